@@ -1,0 +1,455 @@
+/*
+ * hprqp_oracle.c -- plain single-threaded FP64 CPU oracle for HPR-QP
+ * (arXiv 2507.02470).  TEST INFRASTRUCTURE ONLY: see hprqp_oracle.h.
+ *
+ * Written for checkability by eye, not for speed: scalar loops, products
+ * recomputed from the data every time, no blocking, fusion or caching.
+ * Build without -ffast-math (IEEE binary64, round to nearest even).
+ *
+ * Readings of points the paper leaves open (each is listed in the design
+ * notes of the repository as well):
+ *  - Halpern weight 1/(t+2) with the inner counter t of the current epoch
+ *    (Algorithm 4 prints the global counter; Algorithm 3 and the restart
+ *    rationale of Section 3.2 use the per-epoch count).
+ *  - Restart/termination are tested every `check_every` iterations and at
+ *    max_iter; termination is tested before restart.
+ *  - The restart criteria use the R~ of the iteration just completed; the
+ *    epoch reference R~_{r,0} is the R~ of the epoch's first iteration;
+ *    criterion 2 compares with the previous check of the same epoch and is
+ *    skipped at an epoch's first check.
+ *  - The smoothing reference R~_{0,tau_0-1} is the R~ that triggered the
+ *    first restart; alpha_3 drops to 0.2 for good once the ratio used for
+ *    beta is <= 0.1 at a restart.
+ *  - theta_3 is clamped at 0 (only theta_1, theta_2 are clamped at 1e-12 in
+ *    Algorithm 5); the golden-section search runs on log(sigma) over the
+ *    bracket where f' changes sign, to a relative width of 1e-12.
+ *  - The Halpern step is applied to (y, w, x) only: z^{r,t} is never read by
+ *    the updates of Algorithm 4 (zbar is recomputed from (y, w, x)).
+ *  - A term of the dual objective whose bound is infinite counts 0 when its
+ *    multiplier is exactly 0.
+ */
+#include "hprqp_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+/* ------------------------------------------------------------------------ */
+/* Small vector helpers                                                      */
+/* ------------------------------------------------------------------------ */
+static double *vnew(int k) { return (double *)calloc((size_t)(k > 0 ? k : 1), sizeof(double)); }
+static double dot(const double *a, const double *b, int k) {
+  double s = 0.0;
+  for (int i = 0; i < k; ++i) s += a[i] * b[i];
+  return s;
+}
+static double nrm2(const double *a, int k) { return sqrt(dot(a, a, k)); }
+static double nrminf(const double *a, int k) {
+  double s = 0.0;
+  for (int i = 0; i < k; ++i) { double v = fabs(a[i]); if (v > s) s = v; }
+  return s;
+}
+static double clamp(double v, double lo, double hi) {
+  /* projection of one coordinate onto [lo, hi] (lo <= hi, either infinite) */
+  if (v < lo) return lo;
+  if (v > hi) return hi;
+  return v;
+}
+static double now_s(void) {
+  struct timespec ts; clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linear operators                                                          */
+/* ------------------------------------------------------------------------ */
+void orc_apply_Q(const orc_problem *P, const double *x, double *out) {
+  const int n = P->n;
+  if (P->qkind == ORC_Q_ZERO) {
+    for (int i = 0; i < n; ++i) out[i] = 0.0;
+  } else if (P->qkind == ORC_Q_CSR) {
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int k = P->q_rowptr[i]; k < P->q_rowptr[i + 1]; ++k) s += P->q_val[k] * x[P->q_col[k]];
+      out[i] = s;
+    }
+  } else if (P->qkind == ORC_Q_KRON) {
+    /* (B (x) C) vec(X) = vec(C X B^T), X s x p column-major (Section 4.5). */
+    const int p = P->kron_p, s = P->kron_s;
+    const double *B = P->kron_B, *C = P->kron_C;
+    double *T = vnew(s * p);
+    for (int b = 0; b < p; ++b)             /* T = C X */
+      for (int i = 0; i < s; ++i) {
+        double acc = 0.0;
+        for (int a = 0; a < s; ++a) acc += C[i + (size_t)s * a] * x[a + (size_t)s * b];
+        T[i + (size_t)s * b] = acc;
+      }
+    for (int j = 0; j < p; ++j)             /* out = T B^T */
+      for (int i = 0; i < s; ++i) {
+        double acc = 0.0;
+        for (int b = 0; b < p; ++b) acc += T[i + (size_t)s * b] * B[j + (size_t)p * b];
+        out[i + (size_t)s * j] = acc;
+      }
+    free(T);
+  } else { /* ORC_Q_LOWRANK: diag(d) x + F (F^T x) */
+    const int r = P->lr_rank;
+    double *t = vnew(r);
+    for (int k = 0; k < r; ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += P->lr_F[(size_t)j * r + k] * x[j];
+      t[k] = acc;
+    }
+    for (int i = 0; i < n; ++i) {
+      double acc = P->lr_d[i] * x[i];
+      for (int k = 0; k < r; ++k) acc += P->lr_F[(size_t)i * r + k] * t[k];
+      out[i] = acc;
+    }
+    free(t);
+  }
+}
+
+void orc_apply_A(const orc_problem *P, const double *x, double *out) {
+  for (int i = 0; i < P->m; ++i) {
+    double s = 0.0;
+    for (int k = P->a_rowptr[i]; k < P->a_rowptr[i + 1]; ++k) s += P->a_val[k] * x[P->a_col[k]];
+    out[i] = s;
+  }
+}
+
+void orc_apply_AT(const orc_problem *P, const double *y, double *out) {
+  for (int j = 0; j < P->n; ++j) out[j] = 0.0;
+  for (int i = 0; i < P->m; ++i)
+    for (int k = P->a_rowptr[i]; k < P->a_rowptr[i + 1]; ++k) out[P->a_col[k]] += P->a_val[k] * y[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Power method (Section 4.1, parameter setting)                            */
+/* ------------------------------------------------------------------------ */
+double orc_power(const orc_problem *P, int which, const double *start, int maxit,
+                 double tol, int *iters) {
+  const int k = (which == 0) ? P->m : P->n;
+  if (k == 0) { if (iters) *iters = 0; return 0.0; }
+  double *v = vnew(k), *w = vnew(k), *tmp = vnew(P->n);
+  double nv = nrm2(start, k);
+  for (int i = 0; i < k; ++i) v[i] = start[i] / nv;
+  double lam = 0.0, lam_old = 0.0;
+  int it = 0;
+  for (it = 1; it <= maxit; ++it) {
+    if (which == 0) { orc_apply_AT(P, v, tmp); orc_apply_A(P, tmp, w); }   /* A A^T v */
+    else orc_apply_Q(P, v, w);
+    lam = dot(v, w, k);                                                     /* Rayleigh quotient */
+    double nw = nrm2(w, k);
+    if (nw == 0.0) break;
+    if (it > 1 && fabs(lam - lam_old) <= tol * fabs(lam)) break;
+    lam_old = lam;
+    for (int i = 0; i < k; ++i) v[i] = w[i] / nw;
+  }
+  if (iters) *iters = (it > maxit) ? maxit : it;
+  free(v); free(w); free(tmp);
+  return lam;
+}
+
+/* sigma0 = ||b|| / ||c||, b_i = max(|l_i|, |u_i|) with infinite entries read as 0. */
+double orc_sigma0(const orc_problem *P) {
+  double sb = 0.0;
+  for (int i = 0; i < P->m; ++i) {
+    double a = isinf(P->l[i]) ? 0.0 : fabs(P->l[i]);
+    double b = isinf(P->u[i]) ? 0.0 : fabs(P->u[i]);
+    double bi = a > b ? a : b;
+    sb += bi * bi;
+  }
+  double nb = sqrt(sb), nc = nrm2(P->c, P->n);
+  if (nb >= 1e-16 && nb <= 1e16 && nc >= 1e-16 && nc <= 1e16) return nb / nc;
+  return 1.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Metric M (Section 2.3, "eq:metric-M") and the theta's ("eq:theta")       */
+/* ------------------------------------------------------------------------ */
+void orc_thetas(const orc_problem *P, double lamA, double lamQ,
+                const double *dy, const double *dw, const double *dx, double *out) {
+  const int n = P->n, m = P->m;
+  double *Qdw = vnew(n), *ATdy = vnew(n), *QATdy = vnew(n);
+  orc_apply_Q(P, dw, Qdw);
+  orc_apply_AT(P, dy, ATdy);
+  orc_apply_Q(P, ATdy, QATdy);
+  /* theta_1 = lamA ||dy||^2 + lamQ ||dw||_Q^2 - 2 <Q dw, A^T dy> */
+  out[0] = lamA * dot(dy, dy, m) + lamQ * dot(dw, Qdw, n) - 2.0 * dot(Qdw, ATdy, n);
+  /* theta_2 = ||dx||^2 */
+  out[1] = dot(dx, dx, n);
+  /* theta_3 = ||A^T dy||_Q^2 */
+  out[2] = dot(ATdy, QATdy, n);
+  /* cross term of M: <A_Q (dy, dw), dx> = <A^T dy - Q dw, dx> */
+  double cr = 0.0;
+  for (int i = 0; i < n; ++i) cr += (ATdy[i] - Qdw[i]) * dx[i];
+  out[3] = cr;
+  free(Qdw); free(ATdy); free(QATdy);
+}
+
+/* With T_1 = S + S_sGS, S_y = lamA I - A A^*, S_w = Q(lamQ I - Q) and
+ * S_sGS1 = sigma^2 A Q (sigma Q^2 + Q + sigma S_w)^{-1} Q A^* (which on the
+ * range of Q equals sigma^2/(1+sigma lamQ) A Q A^*), the quadratic form of M
+ * splits into the theta's:
+ *   ||du||_M^2 = sigma th1 + th2/sigma + sigma^2 th3/(1+sigma lamQ) + 2 cross. */
+double orc_mnorm2(const orc_problem *P, double sigma, double lamA, double lamQ,
+                  const double *dy, const double *dw, const double *dx) {
+  double th[4];
+  orc_thetas(P, lamA, lamQ, dy, dw, dx, th);
+  return sigma * th[0] + th[1] / sigma + sigma * sigma * th[2] / (1.0 + sigma * lamQ) + 2.0 * th[3];
+}
+
+/* Divided difference (f(a) - f(b)) / (a - b) of f(sigma) = th1 s + th2/s +
+ * s^2 th3/(1 + lamQ s) ("eq:update-sigma-approx"), written without
+ * cancellation:  th1 - th2/(a b) + th3 (a + b + lamQ a b)/((1+lamQ a)(1+lamQ b)). */
+static double f_sigma_slope(double a, double b, double th1, double th2, double th3, double lamQ) {
+  return th1 - th2 / (a * b) + th3 * (a + b + lamQ * a * b) / ((1.0 + lamQ * a) * (1.0 + lamQ * b));
+}
+
+/* argmin_{sigma > 0} f(sigma) by golden-section search (Algorithm 5, step 4).
+ * f' = th1 + (th3/lamQ)(1 - (1+lamQ s)^-2) - th2/s^2, so the minimiser lies in
+ * [sqrt(th2/(th1 + th3/lamQ)), sqrt(th2/th1)]; the search runs on log(sigma).
+ * The comparison f(c) < f(d) (c < d) is taken as the sign of the divided
+ * difference, which keeps it exact down to rounding instead of sqrt(eps). */
+double orc_sigma_argmin(double th1, double th2, double th3, double lamQ) {
+  double hi = sqrt(th2 / th1);
+  if (th3 <= 0.0 || lamQ <= 0.0) return hi;
+  double lo = sqrt(th2 / (th1 + th3 / lamQ));
+  double a = log(lo), b = log(hi);
+  const double g = 0.5 * (sqrt(5.0) - 1.0);
+  for (int it = 0; it < 200 && (b - a) > log1p(1e-12); ++it) {
+    double c = b - g * (b - a), d = a + g * (b - a);
+    /* f(c) < f(d)  <=>  slope(c, d) > 0 since c < d */
+    if (f_sigma_slope(exp(c), exp(d), th1, th2, th3, lamQ) > 0.0) b = d;
+    else a = c;
+  }
+  return exp(0.5 * (a + b));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stopping quantities (Section 4.1, "Termination")                         */
+/* ------------------------------------------------------------------------ */
+void orc_residuals(const orc_problem *P, const double *y, const double *z,
+                   const double *x, double *out) {
+  const int n = P->n, m = P->m;
+  double *Ax = vnew(m), *Qx = vnew(n), *ATy = vnew(n);
+  orc_apply_A(P, x, Ax);
+  orc_apply_Q(P, x, Qx);
+  orc_apply_AT(P, y, ATy);
+  /* primal: ||Ax - Pi_K(Ax)||_inf / (1 + max(||b||_inf, ||Ax||_inf)) */
+  double rp = 0.0, nb = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double d = fabs(Ax[i] - clamp(Ax[i], P->l[i], P->u[i]));
+    if (d > rp) rp = d;
+    double a = isinf(P->l[i]) ? 0.0 : fabs(P->l[i]);
+    double b = isinf(P->u[i]) ? 0.0 : fabs(P->u[i]);
+    if (a > nb) nb = a;
+    if (b > nb) nb = b;
+  }
+  double nAx = nrminf(Ax, m);
+  double eta_p = rp / (1.0 + (nb > nAx ? nb : nAx));
+  /* dual: ||-Qx + A^T y + z - c||_inf / (1 + max(||c||, ||A^T y||, ||Qx||)) */
+  double rd = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double d = fabs(-Qx[j] + ATy[j] + z[j] - P->c[j]);
+    if (d > rd) rd = d;
+  }
+  double den = nrminf(P->c, n);
+  double t1 = nrminf(ATy, n), t2 = nrminf(Qx, n);
+  if (t1 > den) den = t1;
+  if (t2 > den) den = t2;
+  double eta_d = rd / (1.0 + den);
+  /* objectives: P = 1/2 x'Qx + c'x (phi(x) = 0 on the box);
+   * D = -1/2 x'Qx - delta*_K(-y) - delta*_C(-z), where
+   * -delta*_K(-y) = sum_i (l_i y_i^+ + u_i y_i^-), likewise for z with L, U. */
+  double xQx = dot(x, Qx, n), cx = dot(P->c, x, n);
+  double pobj = 0.5 * xQx + cx;
+  double sup = 0.0; int dual_inf = 0;
+  for (int i = 0; i < m; ++i) {
+    if (y[i] > 0.0) { if (isinf(P->l[i])) dual_inf = 1; else sup += P->l[i] * y[i]; }
+    else if (y[i] < 0.0) { if (isinf(P->u[i])) dual_inf = 1; else sup += P->u[i] * y[i]; }
+  }
+  for (int j = 0; j < n; ++j) {
+    if (z[j] > 0.0) { if (isinf(P->L[j])) dual_inf = 1; else sup += P->L[j] * z[j]; }
+    else if (z[j] < 0.0) { if (isinf(P->U[j])) dual_inf = 1; else sup += P->U[j] * z[j]; }
+  }
+  double dobj = dual_inf ? -INFINITY : (-0.5 * xQx + sup);
+  double eta_gap;
+  if (dual_inf) eta_gap = INFINITY;
+  else {
+    double ap = fabs(pobj), ad = fabs(dobj);
+    eta_gap = fabs(pobj - dobj) / (1.0 + (ap > ad ? ap : ad));
+  }
+  out[0] = eta_p; out[1] = eta_d; out[2] = eta_gap; out[3] = pobj; out[4] = dobj;
+  free(Ax); free(Qx); free(ATy);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 4 (HPR-QP) with Algorithm 5 (SigmaUpdate)                      */
+/* ------------------------------------------------------------------------ */
+int orc_solve(const orc_problem *P, const orc_options *opt,
+              const double *y0, const double *w0, const double *x0,
+              double *y_out, double *z_out, double *w_out, double *x_out, orc_info *info) {
+  const int n = P->n, m = P->m;
+  const double t_start = now_s();
+  memset(info, 0, sizeof(*info));
+
+  /* ---- parameters (Section 4.1) ---- */
+  double lamA = opt->lambda_A, lamQ = opt->lambda_Q;
+  if (lamA <= 0.0) {
+    lamA = (m > 0) ? 1.01 * orc_power(P, 0, opt->power_start_A, 5000, 1e-6, NULL) : 0.0;
+  }
+  if (lamQ <= 0.0) {
+    lamQ = (P->qkind == ORC_Q_ZERO) ? 0.0 : 1.01 * orc_power(P, 1, opt->power_start_Q, 5000, 1e-6, NULL);
+  }
+  double sigma = (opt->sigma0 > 0.0) ? opt->sigma0 : orc_sigma0(P);
+  info->lambda_A = lamA; info->lambda_Q = lamQ; info->sigma0 = sigma;
+  const int T = opt->check_every > 0 ? opt->check_every : 1;
+
+  /* ---- state u = (y, w, x), anchor u^{r,0}, bars ---- */
+  double *y = vnew(m), *w = vnew(n), *x = vnew(n);
+  double *ya = vnew(m), *wa = vnew(n), *xa = vnew(n);
+  double *yb = vnew(m), *wb = vnew(n), *xb = vnew(n), *zb = vnew(n);
+  double *ATy = vnew(n), *Qw = vnew(n), *rz = vnew(n), *xh = vnew(n), *wh = vnew(n);
+  double *Qwh = vnew(n), *vv = vnew(n), *ry = vnew(m), *dyv = vnew(m), *ATd = vnew(n);
+  double *dy = vnew(m), *dw = vnew(n), *dx = vnew(n);
+  if (y0) memcpy(y, y0, sizeof(double) * m);
+  if (w0) memcpy(w, w0, sizeof(double) * n);
+  if (x0) memcpy(x, x0, sizeof(double) * n);
+
+  int64_t k = 0;
+  int r = 0, term = -1;
+  double alpha3 = opt->alpha3;
+  double R0ref = -1.0;       /* R~_{0, tau_0 - 1} */
+  double R = 0.0;
+  const int rowlen = 2 * m + 4 * n;
+
+  while (term < 0) {
+    /* ---- new outer iteration r: anchor u^{r,0} ---- */
+    memcpy(ya, y, sizeof(double) * m); memcpy(wa, w, sizeof(double) * n); memcpy(xa, x, sizeof(double) * n);
+    int64_t t = 0;
+    double Rr0 = -1.0, Rprev = -1.0;
+    int restarted = 0;
+    while (!restarted && term < 0) {
+      const double sQ = sigma * lamQ;
+      /* z-step and x-step ("update-z", "update-x"):
+       *   r_z = x + sigma(-Q w + A^T y - c),  xbar = Pi_C(r_z),  zbar = (xbar - r_z)/sigma */
+      orc_apply_AT(P, y, ATy);
+      orc_apply_Q(P, w, Qw);
+      for (int j = 0; j < n; ++j) {
+        rz[j] = x[j] + sigma * (-Qw[j] + ATy[j] - P->c[j]);
+        xb[j] = clamp(rz[j], P->L[j], P->U[j]);
+        zb[j] = (xb[j] - rz[j]) / sigma;
+        xh[j] = 2.0 * xb[j] - x[j];                                   /* xhat */
+      }
+      /* first w-step ("update-w"): w_{1/2} = (sigma lamQ w + xhat)/(1 + sigma lamQ) */
+      for (int j = 0; j < n; ++j) wh[j] = (sQ * w[j] + xh[j]) / (1.0 + sQ);
+      /* y-step ("update-y"): r_y = A(xhat + sigma(Q w - Q w_{1/2})) - sigma lamA y,
+       *   ybar = (Pi_K(r_y) - r_y) / (sigma lamA) */
+      orc_apply_Q(P, wh, Qwh);
+      for (int j = 0; j < n; ++j) vv[j] = xh[j] + sigma * (Qw[j] - Qwh[j]);
+      orc_apply_A(P, vv, ry);
+      for (int i = 0; i < m; ++i) {
+        ry[i] -= sigma * lamA * y[i];
+        yb[i] = (clamp(ry[i], P->l[i], P->u[i]) - ry[i]) / (sigma * lamA);
+      }
+      /* second w-step ("update-w"): wbar = w_{1/2} + sigma/(1+sigma lamQ) A^T(ybar - y) */
+      for (int i = 0; i < m; ++i) dyv[i] = yb[i] - y[i];
+      orc_apply_AT(P, dyv, ATd);
+      for (int j = 0; j < n; ++j) wb[j] = wh[j] + sigma / (1.0 + sQ) * ATd[j];
+
+      /* merit R~ = ||u - ubar||_M of this iteration (needed at the epoch's
+       * first iteration and at every check) */
+      const int is_check = ((k + 1) % T == 0) || (k + 1 >= opt->max_iter);
+      if (t == 0 || is_check) {
+        for (int i = 0; i < m; ++i) dy[i] = y[i] - yb[i];
+        for (int j = 0; j < n; ++j) { dw[j] = w[j] - wb[j]; dx[j] = x[j] - xb[j]; }
+        double m2 = orc_mnorm2(P, sigma, lamA, lamQ, dy, dw, dx);
+        R = sqrt(m2 > 0.0 ? m2 : 0.0);
+      }
+
+      /* Halpern step: u^{r,t+1} = 1/(t+2) u^{r,0} + (t+1)/(t+2) (2 ubar - u) */
+      const double rho = 1.0 / (double)(t + 2);
+      for (int i = 0; i < m; ++i) y[i] = rho * ya[i] + (1.0 - rho) * (2.0 * yb[i] - y[i]);
+      for (int j = 0; j < n; ++j) {
+        w[j] = rho * wa[j] + (1.0 - rho) * (2.0 * wb[j] - w[j]);
+        x[j] = rho * xa[j] + (1.0 - rho) * (2.0 * xb[j] - x[j]);
+      }
+      t += 1; k += 1;
+      if (t == 1) Rr0 = R;
+
+      double sigma_used = sigma;
+      if (is_check) {
+        double res[5];
+        orc_residuals(P, yb, zb, xb, res);
+        info->eta_p = res[0]; info->eta_d = res[1]; info->eta_gap = res[2];
+        info->pobj = res[3]; info->dobj = res[4];
+        double kkt = res[0];
+        if (res[1] > kkt) kkt = res[1];
+        if (res[2] > kkt) kkt = res[2];
+        int do_restart = 0;
+        if (!(kkt == kkt) || !(R == R)) term = ORC_NUMERICAL;        /* NaN guard */
+        else if (kkt <= opt->tol) term = ORC_SOLVED;
+        else if (k >= opt->max_iter) term = ORC_MAX_ITER;
+        else if (opt->time_limit_s > 0.0 && now_s() - t_start >= opt->time_limit_s) term = ORC_TIME_LIMIT;
+        else if (opt->enable_restart) {
+          int c1 = R <= opt->alpha1 * Rr0;
+          int c2 = (Rprev >= 0.0) && (R <= opt->alpha2 * Rr0) && (R > Rprev);
+          int c3 = (double)t >= alpha3 * (double)k;
+          do_restart = c1 || c2 || c3;
+        }
+        Rprev = R;
+        if (term < 0 && do_restart) {
+          if (R0ref < 0.0) R0ref = R;
+          double ratio = R / R0ref;
+          if (opt->enable_sigma_update) {
+            /* Algorithm 5 with dy = ybar - y^{r,0}, dw = wbar - w^{r,0}, dx = xbar - x^{r,0} */
+            double th[4];
+            for (int i = 0; i < m; ++i) dy[i] = yb[i] - ya[i];
+            for (int j = 0; j < n; ++j) { dw[j] = wb[j] - wa[j]; dx[j] = xb[j] - xa[j]; }
+            orc_thetas(P, lamA, lamQ, dy, dw, dx, th);
+            double th1 = th[0] > 1e-12 ? th[0] : 1e-12;
+            double th2 = th[1] > 1e-12 ? th[1] : 1e-12;
+            double th3 = th[2] > 0.0 ? th[2] : 0.0;
+            double snew = orc_sigma_argmin(th1, th2, th3, lamQ);
+            double beta = exp(-ratio);
+            sigma = exp(beta * log(snew) + (1.0 - beta) * log(sigma));
+          }
+          if (ratio <= 0.1) alpha3 = 0.2;
+          /* u^{r+1,0} = ubar^{r,tau_r} */
+          memcpy(y, yb, sizeof(double) * m); memcpy(w, wb, sizeof(double) * n); memcpy(x, xb, sizeof(double) * n);
+          r += 1;
+          restarted = 1;
+        }
+        if (opt->check_log && info->n_log < opt->log_cap) {
+          double *row = opt->check_log + 10 * (size_t)info->n_log;
+          row[0] = (double)k; row[1] = (double)t; row[2] = R; row[3] = res[0]; row[4] = res[1];
+          row[5] = res[2]; row[6] = sigma_used; row[7] = (double)restarted; row[8] = sigma; row[9] = (double)r;
+          info->n_log += 1;
+        }
+      }
+      if (opt->trace && k <= opt->trace_iters) {
+        double *row = opt->trace + (size_t)(k - 1) * rowlen;
+        memcpy(row, y, sizeof(double) * m); row += m;
+        memcpy(row, w, sizeof(double) * n); row += n;
+        memcpy(row, x, sizeof(double) * n); row += n;
+        memcpy(row, yb, sizeof(double) * m); row += m;
+        memcpy(row, wb, sizeof(double) * n); row += n;
+        memcpy(row, xb, sizeof(double) * n);
+      }
+    }
+  }
+
+  /* output ubar of the last iteration (Algorithm 4, "Output") */
+  memcpy(y_out, yb, sizeof(double) * m);
+  memcpy(z_out, zb, sizeof(double) * n);
+  memcpy(w_out, wb, sizeof(double) * n);
+  memcpy(x_out, xb, sizeof(double) * n);
+  info->term = term; info->iters = k; info->restarts = r; info->sigma = sigma; info->R_last = R;
+  info->t_solve_s = now_s() - t_start;
+
+  free(y); free(w); free(x); free(ya); free(wa); free(xa); free(yb); free(wb); free(xb); free(zb);
+  free(ATy); free(Qw); free(rz); free(xh); free(wh); free(Qwh); free(vv); free(ry); free(dyv); free(ATd);
+  free(dy); free(dw); free(dx);
+  return 0;
+}

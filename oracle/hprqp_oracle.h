@@ -1,0 +1,105 @@
+/*
+ * hprqp_oracle.h -- plain single-threaded FP64 CPU oracle for HPR-QP.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library, and the GPU library never
+ * calls it.
+ *
+ * What it computes (arXiv 2507.02470, "HPR-QP"):
+ *   - the CQP of Section 1 (problem "QP-primal-0"): min 1/2<x,Qx> + <c,x>
+ *     s.t. l <= Ax <= u, L <= x <= U;
+ *   - Algorithm 4 (HPR-QP, Section 3) with the closed-form subproblem updates
+ *     of Section 3.1 ("update-z", "update-x", "update-w", "update-y"), the
+ *     restart criteria of Section 3.2 ("eq:restart_1".."eq:restart_3") and
+ *     Algorithm 5 (SigmaUpdate, Section 3.3);
+ *   - the merit R~ = ||u - ubar||_M with M the metric of Section 2.3
+ *     ("eq:metric-M");
+ *   - the stopping quantities eta_p, eta_d, eta_gap of Section 4.1.
+ * Every product A x, A^T y, Q x is recomputed directly from the data each
+ * time it is needed (no cached linear combinations).
+ */
+#ifndef HPRQP_ORACLE_H
+#define HPRQP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_Q_ZERO = 0, ORC_Q_CSR = 1, ORC_Q_KRON = 2, ORC_Q_LOWRANK = 3 };
+enum { ORC_SOLVED = 0, ORC_MAX_ITER = 1, ORC_TIME_LIMIT = 2, ORC_NUMERICAL = 3 };
+
+typedef struct {
+  int n, m;
+  int qkind;
+  const int *q_rowptr, *q_col; const double *q_val;      /* CSR, full symmetric   */
+  int kron_p, kron_s; const double *kron_B, *kron_C;     /* Q = B (x) C, col-major */
+  int lr_rank; const double *lr_d, *lr_F;                /* Q = diag(d) + F F^T, F row-major n x r */
+  const double *c, *L, *U;                               /* box C = [L, U]        */
+  const int *a_rowptr, *a_col; const double *a_val;      /* A, m x n CSR          */
+  const double *l, *u;                                   /* K = [l, u]            */
+} orc_problem;
+
+typedef struct {
+  double tol;             /* stop when max(eta_p, eta_d, eta_gap) <= tol            */
+  int64_t max_iter;
+  int check_every;        /* restart/termination test cadence                        */
+  double time_limit_s;    /* <= 0: none                                               */
+  double sigma0;          /* <= 0: ||b||/||c|| rule                                   */
+  double lambda_A, lambda_Q;  /* <= 0: power method from the given start vectors      */
+  const double *power_start_A;  /* m-vector (start of the power method on A A^T)     */
+  const double *power_start_Q;  /* n-vector (start of the power method on Q)         */
+  double alpha1, alpha2, alpha3;
+  int enable_restart, enable_sigma_update;
+  int trace_iters;        /* record the first K iterations into `trace`               */
+  double *trace;          /* K x (2m + 4n): [y, w, x (carried state), ybar, wbar, xbar] */
+  int log_cap;            /* capacity (rows) of check_log                             */
+  double *check_log;      /* rows of 10: k, t, R, eta_p, eta_d, eta_gap, sigma_used,
+                             restarted, sigma_next, r                                 */
+} orc_options;
+
+typedef struct {
+  int term; int64_t iters; int restarts; int n_log;
+  double sigma, sigma0, lambda_A, lambda_Q;
+  double eta_p, eta_d, eta_gap, pobj, dobj;
+  double R_last, t_solve_s;
+} orc_info;
+
+/* Linear operators (definitions written out). */
+void orc_apply_Q(const orc_problem *P, const double *x, double *out);
+void orc_apply_A(const orc_problem *P, const double *x, double *out);
+void orc_apply_AT(const orc_problem *P, const double *y, double *out);
+
+/* Power method: Rayleigh-quotient estimate of lambda_1(A A^T) (which=0) or
+ * lambda_1(Q) (which=1) from `start`, stopping at relative change <= tol or
+ * after maxit products.  Returns the raw estimate; *iters gets the count.   */
+double orc_power(const orc_problem *P, int which, const double *start, int maxit,
+                 double tol, int *iters);
+
+/* sigma0 rule of Section 4.1 (parameter setting). */
+double orc_sigma0(const orc_problem *P);
+
+/* theta_1, theta_2, theta_3 and the cross term <A^T dy - Q dw, dx> for a
+ * difference (dy, dw, dx); out[4].                                          */
+void orc_thetas(const orc_problem *P, double lamA, double lamQ,
+                const double *dy, const double *dw, const double *dx, double *out);
+/* ||(dy, dw, dz, dx)||_M^2 for the metric M of Algorithm 3 (z-block is 0).  */
+double orc_mnorm2(const orc_problem *P, double sigma, double lamA, double lamQ,
+                  const double *dy, const double *dw, const double *dx);
+/* Algorithm 5 without the smoothing: argmin of f(sigma) by golden section. */
+double orc_sigma_argmin(double th1, double th2, double th3, double lamQ);
+
+/* eta_p, eta_d, eta_gap, pobj, dobj at (y, z, x); out[5]. */
+void orc_residuals(const orc_problem *P, const double *y, const double *z,
+                   const double *x, double *out);
+
+/* Algorithm 4.  y0/w0/x0 may be NULL (origin).  Outputs ubar = (y, z, w, x). */
+int orc_solve(const orc_problem *P, const orc_options *opt,
+              const double *y0, const double *w0, const double *x0,
+              double *y, double *z, double *w, double *x, orc_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,321 @@
+"""Seeded synthetic convex-QP instances for HPR-QP.
+
+This module only *generates* problem data (numpy + scipy.sparse); it holds
+none of the solver's arithmetic.  Both the CPU oracle (``oracle/``) and the
+GPU library (``paper_2507_02470_amd``) consume the :class:`QP` objects built
+here, and neither of them is imported by this module.
+
+Problem form (paper, Section 1, problem (1.2) "QP-primal-0"):
+
+    min  1/2 <x, Q x> + <c, x>   s.t.  l <= A x <= u,   L <= x <= U
+
+with Q self-adjoint PSD given either as an explicit CSR matrix, as the
+Kronecker product B (x) C applied matrix-free, as diag(d) + F F^T, or as 0.
+Infinite bounds are IEEE +-inf.
+
+Workloads (all seeded with ``numpy.random.default_rng``):
+
+* ``make_small_ccqp``   tiny random CCQP (n=200, m=100), explicit sparse Q.
+* ``make_random_large`` OSQP-style "random" class at scale (n=1e6, m=5e5).
+* ``make_kron``          matrix-free Q = B (x) C with assignment constraints
+                         (the QAP-relaxation structure of Section 4.5).
+* ``make_portfolio``     portfolio-style QP, Q = F F^T + D, budget + sector rows.
+* ``make_portfolio_family`` a fixed portfolio instance plus per-sample
+                         perturbations of c and of the sector bounds.
+* ``make_tiny``          very small random QPs for brute-force checks.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+QKINDS = ("zero", "csr", "kron", "lowrank")
+
+
+@dataclass
+class QP:
+    n: int
+    m: int
+    qkind: str
+    c: np.ndarray
+    L: np.ndarray
+    U: np.ndarray
+    a_rowptr: np.ndarray
+    a_col: np.ndarray
+    a_val: np.ndarray
+    l: np.ndarray
+    u: np.ndarray
+    q_rowptr: Optional[np.ndarray] = None
+    q_col: Optional[np.ndarray] = None
+    q_val: Optional[np.ndarray] = None
+    kron_B: Optional[np.ndarray] = None   # p x p (Q = B (x) C)
+    kron_C: Optional[np.ndarray] = None   # s x s
+    lr_d: Optional[np.ndarray] = None     # n
+    lr_F: Optional[np.ndarray] = None     # n x r, row-major
+    meta: dict = field(default_factory=dict)
+
+    # ---- convenience (data plumbing only) ----
+    @property
+    def a_nnz(self) -> int:
+        return int(self.a_rowptr[-1])
+
+    @property
+    def q_nnz(self) -> int:
+        return 0 if self.q_rowptr is None else int(self.q_rowptr[-1])
+
+    def A_scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.a_val, self.a_col, self.a_rowptr), shape=(self.m, self.n))
+
+    def Q_dense(self) -> np.ndarray:
+        """Dense Q (small instances only; used by tests)."""
+        if self.qkind == "zero":
+            return np.zeros((self.n, self.n))
+        if self.qkind == "csr":
+            return sp.csr_matrix((self.q_val, self.q_col, self.q_rowptr),
+                                 shape=(self.n, self.n)).toarray()
+        if self.qkind == "kron":
+            return np.kron(self.kron_B, self.kron_C)
+        if self.qkind == "lowrank":
+            return np.diag(self.lr_d) + self.lr_F @ self.lr_F.T
+        raise ValueError(self.qkind)
+
+    def copy(self) -> "QP":
+        import copy as _c
+        return _c.deepcopy(self)
+
+
+def _csr_arrays(M: sp.spmatrix):
+    M = sp.csr_matrix(M)
+    M.sum_duplicates()
+    M.sort_indices()
+    return (np.ascontiguousarray(M.indptr, dtype=np.int32),
+            np.ascontiguousarray(M.indices, dtype=np.int32),
+            np.ascontiguousarray(M.data, dtype=np.float64))
+
+
+def _bernoulli_sparse(rng, rows, cols, density):
+    """rows x cols matrix, each entry nonzero with prob `density`, N(0,1) values."""
+    mask = rng.random((rows, cols)) < density
+    vals = rng.standard_normal((rows, cols))
+    return sp.csr_matrix(np.where(mask, vals, 0.0))
+
+
+def from_dense(Q, c, L, U, A, l, u, qkind="csr") -> QP:
+    """Build a QP from dense arrays (tests and small cases)."""
+    A = np.atleast_2d(np.asarray(A, dtype=np.float64))
+    n = len(c)
+    if A.size == 0:
+        A = np.zeros((0, n))
+    m = A.shape[0]
+    ar, ac, av = _csr_arrays(sp.csr_matrix(A))
+    kw = {}
+    if qkind == "csr":
+        qr, qc, qv = _csr_arrays(sp.csr_matrix(np.asarray(Q, dtype=np.float64)))
+        kw = dict(q_rowptr=qr, q_col=qc, q_val=qv)
+    elif qkind != "zero":
+        raise ValueError("from_dense supports csr/zero")
+    return QP(n=n, m=m, qkind=qkind, c=np.asarray(c, float).copy(), L=np.asarray(L, float).copy(),
+              U=np.asarray(U, float).copy(), a_rowptr=ar, a_col=ac, a_val=av,
+              l=np.asarray(l, float).reshape(m).copy(), u=np.asarray(u, float).reshape(m).copy(), **kw)
+
+
+# ---------------------------------------------------------------------------
+# Tiny small-CCQP workload: n=200, m=100
+# ---------------------------------------------------------------------------
+def make_small_ccqp(seed: int = 1000, n: int = 200, m: int = 100, nb: int = 50,
+                    density: float = 0.05) -> QP:
+    """Q = B^T B + 0.01 I (B nb x n, 5% N(0,1)); A m x n at 5% N(0,1);
+    x0 ~ U(-5,5); first half rows equality l=u=A x0, second half l=-inf,
+    u = A x0 + U(0,1); box [-10,10]; c ~ N(0,1)."""
+    rng = np.random.default_rng(seed)
+    B = _bernoulli_sparse(rng, nb, n, density)
+    Q = (B.T @ B + 0.01 * sp.identity(n)).tocsr()
+    A = _bernoulli_sparse(rng, m, n, density)
+    x0 = rng.uniform(-5.0, 5.0, n)
+    Ax0 = A @ x0
+    half = m // 2
+    l = np.empty(m); u = np.empty(m)
+    l[:half] = Ax0[:half]; u[:half] = Ax0[:half]
+    l[half:] = -np.inf; u[half:] = Ax0[half:] + rng.uniform(0.0, 1.0, m - half)
+    c = rng.standard_normal(n)
+    qr, qc, qv = _csr_arrays(Q)
+    ar, ac, av = _csr_arrays(A)
+    return QP(n=n, m=m, qkind="csr", c=c, L=np.full(n, -10.0), U=np.full(n, 10.0),
+              a_rowptr=ar, a_col=ac, a_val=av, l=l, u=u, q_rowptr=qr, q_col=qc, q_val=qv,
+              meta=dict(workload="small_ccqp", seed=seed, x_feasible=x0))
+
+
+# ---------------------------------------------------------------------------
+# Large random class: n=1e6, m=5e5, ~10 nnz/row in A, Q = D + S
+# ---------------------------------------------------------------------------
+def make_random_large(seed: int = 1001, n: int = 1_000_000, m: int = 500_000,
+                      nnz_per_row: int = 10, pairs_per_row: int = 2) -> QP:
+    """A: `nnz_per_row` uniformly random columns per row, N(0,1) values.
+    Q = D + S, D ~ U(0.1,1) diagonal, S symmetric with `pairs_per_row`
+    random off-diagonal pairs per row (N(0,1)) and diagonal sum|offdiag|+1e-3,
+    so S is diagonally dominant (PSD) and nnz(Q) ~ 5 n.
+    x0 ~ U(0,10) (inside the box [0,10]); half the rows equality l=u=A x0,
+    the other half l=-inf, u = A x0 + U(0,1); c ~ N(0,1)."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(m, dtype=np.int64), nnz_per_row)
+    cols = rng.integers(0, n, size=m * nnz_per_row, dtype=np.int64)
+    vals = rng.standard_normal(m * nnz_per_row)
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    A.sum_duplicates()
+    # symmetric off-diagonal part
+    i = np.repeat(np.arange(n, dtype=np.int64), pairs_per_row)
+    j = rng.integers(0, n - 1, size=n * pairs_per_row, dtype=np.int64)
+    j = j + (j >= i)                       # j != i
+    v = rng.standard_normal(n * pairs_per_row)
+    S = sp.coo_matrix((np.concatenate([v, v]), (np.concatenate([i, j]), np.concatenate([j, i]))),
+                      shape=(n, n)).tocsr()
+    S.sum_duplicates()
+    rowabs = np.asarray(abs(S).sum(axis=1)).ravel()
+    D = rng.uniform(0.1, 1.0, n)
+    Q = (S + sp.diags(rowabs + 1e-3 + D)).tocsr()
+    x0 = rng.uniform(0.0, 10.0, n)
+    Ax0 = A @ x0
+    half = m // 2
+    l = np.empty(m); u = np.empty(m)
+    l[:half] = Ax0[:half]; u[:half] = Ax0[:half]
+    l[half:] = -np.inf; u[half:] = Ax0[half:] + rng.uniform(0.0, 1.0, m - half)
+    c = rng.standard_normal(n)
+    qr, qc, qv = _csr_arrays(Q)
+    ar, ac, av = _csr_arrays(A)
+    return QP(n=n, m=m, qkind="csr", c=c, L=np.zeros(n), U=np.full(n, 10.0),
+              a_rowptr=ar, a_col=ac, a_val=av, l=l, u=u, q_rowptr=qr, q_col=qc, q_val=qv,
+              meta=dict(workload="random_large", seed=seed, x_feasible=x0))
+
+
+# ---------------------------------------------------------------------------
+# Matrix-free Kronecker Q = B (x) C with assignment constraints
+# ---------------------------------------------------------------------------
+def assignment_A(d: int):
+    """Row sums and column sums of a d x d matrix X stored column-major
+    (x[i + d*j] = X[i, j]): rows 0..d-1 are sum_j X[i,j], rows d..2d-1 are
+    sum_i X[i,j]."""
+    n = d * d
+    idx = np.arange(n, dtype=np.int64)
+    i = idx % d
+    j = idx // d
+    rows = np.concatenate([i, d + j])
+    cols = np.concatenate([idx, idx])
+    A = sp.csr_matrix((np.ones(2 * n), (rows, cols)), shape=(2 * d, n))
+    return A
+
+
+def make_kron(seed: int = 1002, d: int = 300) -> QP:
+    """B, C = G G^T / d with G ~ N(0,1) d x d (each PSD); Q = B (x) C, n = d^2;
+    assignment equalities l = u = 1; box [0,1]; c ~ N(0,1)."""
+    rng = np.random.default_rng(seed)
+    G1 = rng.standard_normal((d, d)); Bm = G1 @ G1.T / d
+    G2 = rng.standard_normal((d, d)); Cm = G2 @ G2.T / d
+    Bm = 0.5 * (Bm + Bm.T); Cm = 0.5 * (Cm + Cm.T)
+    n = d * d
+    A = assignment_A(d)
+    ar, ac, av = _csr_arrays(A)
+    c = rng.standard_normal(n)
+    return QP(n=n, m=2 * d, qkind="kron", c=c, L=np.zeros(n), U=np.ones(n),
+              a_rowptr=ar, a_col=ac, a_val=av, l=np.ones(2 * d), u=np.ones(2 * d),
+              kron_B=Bm, kron_C=Cm,
+              meta=dict(workload="kron_assignment", seed=seed, d=d,
+                        x_feasible=np.full(n, 1.0 / d)))
+
+
+# ---------------------------------------------------------------------------
+# Portfolio-style QP, Q = F F^T + D
+# ---------------------------------------------------------------------------
+def make_portfolio(seed: int, n: Optional[int] = None, nmin: int = 50, nmax: int = 2000,
+                   rank: int = 10, nsectors: int = 20, sector_density: float = 0.05) -> QP:
+    """n ~ U{nmin..nmax} (unless given); F n x rank ~ N(0, 0.1) (std);
+    D ~ U(0.01, 0.1); A = budget row (all ones, l = u = 1) + `nsectors`
+    membership rows (entries 1 with prob 5%, l = -inf, u ~ U(0.2, 0.5));
+    box [0, 0.3]; c = -mu with mu ~ N(0.05, 0.02) (std)."""
+    rng = np.random.default_rng(seed)
+    if n is None:
+        n = int(rng.integers(nmin, nmax + 1))
+    F = rng.normal(0.0, 0.1, (n, rank))
+    D = rng.uniform(0.01, 0.1, n)
+    member = rng.random((nsectors, n)) < sector_density
+    A = np.vstack([np.ones((1, n)), member.astype(np.float64)])
+    m = nsectors + 1
+    l = np.empty(m); u = np.empty(m)
+    l[0] = 1.0; u[0] = 1.0
+    l[1:] = -np.inf; u[1:] = rng.uniform(0.2, 0.5, nsectors)
+    mu = rng.normal(0.05, 0.02, n)
+    ar, ac, av = _csr_arrays(sp.csr_matrix(A))
+    return QP(n=n, m=m, qkind="lowrank", c=-mu, L=np.zeros(n), U=np.full(n, 0.3),
+              a_rowptr=ar, a_col=ac, a_val=av, l=l, u=u,
+              lr_d=D, lr_F=np.ascontiguousarray(F),
+              meta=dict(workload="portfolio", seed=seed, x_feasible=np.full(n, 1.0 / n)))
+
+
+def make_portfolio_batch(count: int = 4096, seed0: int = 10_000, **kw) -> list:
+    """Instance i is ``make_portfolio(seed0 + i)``."""
+    return [make_portfolio(seed0 + i, **kw) for i in range(count)]
+
+
+def make_portfolio_family_base(seed: int = 1004, n: int = 1000) -> QP:
+    """The fixed parametric-family instance (n = 1000, m = 21)."""
+    return make_portfolio(seed, n=n)
+
+
+def portfolio_family_sample(base: QP, seed: int) -> tuple:
+    """One member of the family: c = c0 + N(0, 0.01), sector upper bounds
+    u = u0 * U(0.8, 1.2) (budget row unchanged).  Returns (c, l, u)."""
+    rng = np.random.default_rng(seed)
+    c = base.c + rng.normal(0.0, 0.01, base.n)
+    u = base.u.copy()
+    u[1:] = base.u[1:] * rng.uniform(0.8, 1.2, base.m - 1)
+    return c, base.l.copy(), u
+
+
+def family_member(base: QP, seed: int) -> QP:
+    c, l, u = portfolio_family_sample(base, seed)
+    q = base.copy()
+    q.c, q.l, q.u = c, l, u
+    q.meta = dict(base.meta, sample_seed=seed)
+    return q
+
+
+# ---------------------------------------------------------------------------
+# Tiny random QPs (brute-force checks)
+# ---------------------------------------------------------------------------
+def make_tiny(seed: int, n: int = 4, m: int = 2, psd_rank: Optional[int] = None,
+              n_eq: int = 1, box: float = 2.0, qkind: str = "csr") -> QP:
+    """Random tiny QP with a strictly feasible-ish point x0 in the box.
+    Q = G G^T (+ 0.1 I unless psd_rank is given, then rank-deficient PSD)."""
+    rng = np.random.default_rng(seed)
+    if qkind == "zero":
+        Q = np.zeros((n, n))
+    else:
+        r = n if psd_rank is None else psd_rank
+        G = rng.standard_normal((n, r))
+        Q = G @ G.T + (0.1 * np.eye(n) if psd_rank is None else 0.0)
+        Q = 0.5 * (Q + Q.T)
+    A = rng.standard_normal((m, n)) if m > 0 else np.zeros((0, n))
+    x0 = rng.uniform(-0.5 * box, 0.5 * box, n)
+    Ax0 = A @ x0
+    l = np.empty(m); u = np.empty(m)
+    for i in range(m):
+        if i < n_eq:
+            l[i] = u[i] = Ax0[i]
+        else:
+            kind = rng.integers(0, 3)
+            lo = Ax0[i] - rng.uniform(0.1, 1.0)
+            hi = Ax0[i] + rng.uniform(0.1, 1.0)
+            l[i], u[i] = [(lo, hi), (-np.inf, hi), (lo, np.inf)][kind]
+    L = np.full(n, -box); U = np.full(n, box)
+    # make a couple of bounds infinite to exercise the +-inf paths
+    if n >= 3:
+        L[n - 1] = -np.inf
+    c = rng.standard_normal(n) * 2.0
+    return from_dense(Q, c, L, U, A, l, u, qkind=qkind)
+
+
+def power_start(k: int, seed: int = 0) -> np.ndarray:
+    """Seeded N(0,1) start vector for the power method (length k)."""
+    return np.random.default_rng(seed).standard_normal(k)

@@ -1,0 +1,50 @@
+"""The oracle's pins have teeth: plant one plausible mistake at a time in a
+temporary copy of the oracle's C source (never in the committed file), build
+it, and check that the pin suite fails on it."""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hprqp_oracle.c")
+
+MUTANTS = {
+    "halpern_sign": ("(2.0 * yb[i] - y[i])", "(2.0 * yb[i] + y[i])"),
+    "halpern_index": ("1.0 / (double)(t + 2)", "1.0 / (double)(t + 3)"),
+    "w_half_coef": ("(sQ * w[j] + xh[j]) / (1.0 + sQ)", "(sQ * w[j] + xh[j]) / (1.0 + 2.0 * sQ)"),
+    "ybar_sign": ("(clamp(ry[i], P->l[i], P->u[i]) - ry[i]) / (sigma * lamA)",
+                  "(ry[i] - clamp(ry[i], P->l[i], P->u[i])) / (sigma * lamA)"),
+    "wbar_coef": ("sigma / (1.0 + sQ) * ATd[j]", "1.0 / (1.0 + sQ) * ATd[j]"),
+    "xhat": ("xh[j] = 2.0 * xb[j] - x[j];", "xh[j] = xb[j];"),
+    "rz_c_sign": ("rz[j] = x[j] + sigma * (-Qw[j] + ATy[j] - P->c[j]);",
+                  "rz[j] = x[j] + sigma * (-Qw[j] + ATy[j] + P->c[j]);"),
+    "v_sign": ("vv[j] = xh[j] + sigma * (Qw[j] - Qwh[j]);", "vv[j] = xh[j] + sigma * (Qwh[j] - Qw[j]);"),
+    "theta1_cross": ("- 2.0 * dot(Qdw, ATdy, n);", "+ 2.0 * dot(Qdw, ATdy, n);"),
+    "mnorm_sigma2": ("sigma * sigma * th[2] / (1.0 + sigma * lamQ)", "sigma * th[2] / (1.0 + sigma * lamQ)"),
+    "dual_obj_sign": ("else sup += P->l[i] * y[i];", "else sup -= P->l[i] * y[i];"),
+    "beta_swap": ("exp(beta * log(snew) + (1.0 - beta) * log(sigma))",
+                  "exp((1.0 - beta) * log(snew) + beta * log(sigma))"),
+    "kron_transpose": ("acc += T[i + (size_t)s * b] * B[j + (size_t)p * b];",
+                       "acc += T[i + (size_t)s * b] * B[b + (size_t)p * j];"),
+    "power_no_norm": ("for (int i = 0; i < k; ++i) v[i] = w[i] / nw;", "for (int i = 0; i < k; ++i) v[i] = w[i] / (2.0 * nw);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique/found"
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=199309L", "-fPIC", "-shared",
+                           "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(msrc), "-lm"])
+    env = dict(os.environ, HPRQP_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pin suite"

@@ -1,0 +1,336 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test names the passage of arXiv 2507.02470 it relies on.  None of them
+needs a GPU.
+"""
+import numpy as np
+import pytest
+import scipy.optimize as so
+import scipy.sparse as sp
+
+import oracle
+import qpgen
+from oracle.oracle import split_trace
+from tests import pins
+
+
+def _dense(qp):
+    return qp.Q_dense(), qp.A_scipy().toarray()
+
+
+# ---------------------------------------------------------------------------
+# Linear operators (Section 1: Q may be explicit, Kronecker or structured)
+# ---------------------------------------------------------------------------
+def test_operators_match_scipy_and_kron():
+    rng = np.random.default_rng(7)
+    qp = qpgen.make_small_ccqp(seed=3, n=40, m=20, nb=15, density=0.2)
+    x = rng.standard_normal(qp.n); y = rng.standard_normal(qp.m)
+    Q, A = _dense(qp)
+    np.testing.assert_allclose(oracle.apply_Q(qp, x), Q @ x, rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(oracle.apply_A(qp, x), A @ x, rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(oracle.apply_AT(qp, y), A.T @ y, rtol=1e-13, atol=1e-12)
+    # Kronecker: (B kron C) vec(X) = vec(C X B^T) holds for any factors; use
+    # unsymmetric ones of different sizes so that a transposed factor shows
+    B = rng.standard_normal((5, 5))
+    Cm = rng.standard_normal((3, 3))
+    kq = qpgen.QP(n=15, m=0, qkind="kron", c=np.zeros(15), L=np.zeros(15), U=np.ones(15),
+                  a_rowptr=np.zeros(1, np.int32), a_col=np.zeros(0, np.int32), a_val=np.zeros(0),
+                  l=np.zeros(0), u=np.zeros(0), kron_B=B, kron_C=Cm)
+    xk = rng.standard_normal(15)
+    np.testing.assert_allclose(oracle.apply_Q(kq, xk), np.kron(B, Cm) @ xk, rtol=1e-12, atol=1e-12)
+    # diag + low rank
+    pq = qpgen.make_portfolio(11, n=60)
+    xp = rng.standard_normal(60)
+    np.testing.assert_allclose(oracle.apply_Q(pq, xp), pq.Q_dense() @ xp, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Power method (Section 4.1, parameter setting)
+# ---------------------------------------------------------------------------
+def test_power_method_vs_eigvalsh_and_closed_forms():
+    qp = qpgen.make_small_ccqp()
+    Q, A = _dense(qp)
+    lamA, _ = oracle.power(qp, "A", qpgen.power_start(qp.m))
+    lamQ, _ = oracle.power(qp, "Q", qpgen.power_start(qp.n))
+    assert lamA == pytest.approx(np.linalg.eigvalsh(A @ A.T).max(), rel=1e-5)
+    assert lamQ == pytest.approx(np.linalg.eigvalsh(Q).max(), rel=1e-5)
+    # assignment constraints of a d x d matrix: lambda_1(A A^T) = 2d exactly
+    kq = qpgen.make_kron(d=12)
+    lamAk, _ = oracle.power(kq, "A", qpgen.power_start(kq.m))
+    assert lamAk == pytest.approx(24.0, rel=1e-6)
+    # lambda_1(B kron C) = lambda_1(B) lambda_1(C)
+    lamQk, _ = oracle.power(kq, "Q", qpgen.power_start(kq.n), maxit=20000, tol=1e-10)
+    ref = np.linalg.eigvalsh(kq.kron_B).max() * np.linalg.eigvalsh(kq.kron_C).max()
+    assert lamQk == pytest.approx(ref, rel=1e-6)
+
+
+def test_sigma0_rule_hand_example():
+    # b = max(|l|,|u|) with infinities read as 0: l=[1,-inf], u=[1,3] -> b=[1,3];
+    # c=[3,4,0] -> sigma0 = sqrt(10)/5
+    qp = qpgen.from_dense(np.eye(3), [3.0, 4.0, 0.0], -np.ones(3), np.ones(3),
+                          [[1, 0, 0], [0, 1, 1]], [1.0, -np.inf], [1.0, 3.0])
+    assert oracle.sigma0(qp) == pytest.approx(np.sqrt(10.0) / 5.0, rel=1e-15)
+    qp.c[:] = 0.0
+    assert oracle.sigma0(qp) == 1.0          # ||c|| outside [1e-16, 1e16] -> 1
+
+
+# ---------------------------------------------------------------------------
+# Metric M ("eq:metric-M") assembled densely vs the theta decomposition
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("psd_rank", [None, 2])
+def test_mnorm_matches_dense_metric(psd_rank):
+    qp = qpgen.make_tiny(21, n=5, m=3, psd_rank=psd_rank)
+    Q, A = _dense(qp)
+    lamA = 1.05 * np.linalg.eigvalsh(A @ A.T).max()
+    lamQ = 1.02 * np.linalg.eigvalsh(Q).max()
+    rng = np.random.default_rng(1)
+    for sigma in (0.3, 1.0, 4.0):
+        M, V = pins.dense_metric_M(Q, A, sigma, lamA, lamQ)
+        ev = np.linalg.eigvalsh(0.5 * (M + M.T))
+        assert ev.min() > -1e-9 * ev.max()          # M is PSD
+        for _ in range(3):
+            dy, dw, dx = rng.standard_normal(3), rng.standard_normal(5), rng.standard_normal(5)
+            om = V.T @ dw                              # coordinates of Pi_W(dw)
+            vec = np.concatenate([dy, om, dx])
+            dense = vec @ M @ vec
+            got = oracle.mnorm2(qp, sigma, lamA, lamQ, dy, dw, dx)   # unprojected shadow dw
+            assert got == pytest.approx(dense, rel=1e-10, abs=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Sigma update ("eq:update-sigma-approx", Algorithm 5)
+# ---------------------------------------------------------------------------
+def test_sigma_argmin():
+    # theta_3 = 0: HPR-LP rule sqrt(theta_2/theta_1)
+    assert oracle.sigma_argmin(4.0, 9.0, 0.0, 2.0) == pytest.approx(1.5, rel=1e-14)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        th1, th2, th3 = 10 ** rng.uniform(-3, 3, 3)
+        lamQ = 10 ** rng.uniform(-2, 2)
+        # derivative of f by the quotient rule, root by Brent's method
+        fp = lambda s: th1 - th2 / s ** 2 + th3 * s * (2 + lamQ * s) / (1 + lamQ * s) ** 2
+        ref = so.brentq(fp, 1e-12, 1e12, xtol=1e-300, rtol=1e-15, maxiter=1000)
+        got = oracle.sigma_argmin(th1, th2, th3, lamQ)
+        assert got == pytest.approx(ref, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Final optimum: brute-force active sets (tiny), closed forms, LP, KKT solve
+# ---------------------------------------------------------------------------
+def _solve(qp, **kw):
+    Q, A = _dense(qp)
+    lamA = 1.01 * np.linalg.eigvalsh(A @ A.T).max() if qp.m else 0.0
+    lamQ = 1.01 * np.linalg.eigvalsh(Q).max() if qp.qkind != "zero" else 0.0
+    kw.setdefault("lambda_A", lamA)
+    kw.setdefault("lambda_Q", lamQ)
+    kw.setdefault("max_iter", 200_000)
+    kw.setdefault("check_every", 10)
+    return oracle.solve(qp, **kw)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_bruteforce_active_sets(seed):
+    n = 3 + seed % 3
+    m = 1 + seed % 3
+    qp = qpgen.make_tiny(seed, n=n, m=m, n_eq=seed % 2, psd_rank=(2 if seed % 4 == 3 else None))
+    Q, A = _dense(qp)
+    best = pins.kkt_enumerate(Q, qp.c, qp.L, qp.U, A, qp.l, qp.u)
+    assert best is not None
+    r = _solve(qp, tol=1e-10)
+    assert r.term == "solved" and r.kkt <= 1e-10
+    assert r.pobj == pytest.approx(best[0], rel=1e-7, abs=1e-8)
+    if seed % 4 != 3:           # Q positive definite: x* unique
+        np.testing.assert_allclose(r.x, best[1], atol=1e-6)
+
+
+def test_no_constraints_diag_closed_form():
+    # Remark 2.1: without Ax in K the method cycles z -> x -> w
+    rng = np.random.default_rng(2)
+    n = 30
+    d = rng.uniform(0.1, 2.0, n); c = rng.standard_normal(n) * 3
+    L = -np.ones(n); U = np.ones(n); L[:3] = -np.inf; U[3:6] = np.inf
+    qp = qpgen.from_dense(np.diag(d), c, L, U, np.zeros((0, n)), [], [])
+    r = _solve(qp, tol=1e-11)
+    assert r.term == "solved"
+    np.testing.assert_allclose(r.x, pins.diag_box_closed_form(d, c, L, U), atol=1e-9)
+
+
+def test_diag_budget_bisection():
+    rng = np.random.default_rng(4)
+    n = 50
+    d = rng.uniform(0.01, 0.1, n); c = -rng.normal(0.05, 0.02, n)
+    L = np.zeros(n); U = np.full(n, 0.3)
+    qp = qpgen.from_dense(np.diag(d), c, L, U, np.ones((1, n)), [1.0], [1.0])
+    r = _solve(qp, tol=1e-11)
+    xs, nu = pins.diag_budget_bisect(d, c, L, U)
+    assert r.term == "solved"
+    np.testing.assert_allclose(r.x, xs, atol=1e-8)
+    assert r.y[0] == pytest.approx(nu, rel=1e-6)
+
+
+def test_equality_only_direct_kkt():
+    rng = np.random.default_rng(8)
+    n, m = 12, 4
+    G = rng.standard_normal((n, n)); Q = G @ G.T / n + 0.5 * np.eye(n)
+    A = rng.standard_normal((m, n)); b = rng.standard_normal(m); c = rng.standard_normal(n)
+    qp = qpgen.from_dense(Q, c, np.full(n, -np.inf), np.full(n, np.inf), A, b, b)
+    r = _solve(qp, tol=1e-12)
+    xs, ys = pins.equality_kkt(Q, c, A, b)
+    np.testing.assert_allclose(r.x, xs, atol=1e-8)
+    np.testing.assert_allclose(r.y, ys, atol=1e-7)
+
+
+def test_lp_reduction_matches_highs():
+    # Remark 2.1: Q = 0 and phi = delta_C gives HPR-LP
+    rng = np.random.default_rng(9)
+    n, m = 20, 8
+    A = rng.standard_normal((m, n)); x0 = rng.uniform(0, 1, n)
+    b = A @ x0
+    l = b.copy(); u = b.copy(); l[4:] = -np.inf; u[4:] = b[4:] + 0.5
+    c = rng.uniform(-1, 1, n)
+    L = np.zeros(n); U = np.full(n, 2.0)
+    qp = qpgen.from_dense(np.zeros((n, n)), c, L, U, A, l, u, qkind="zero")
+    r = _solve(qp, tol=1e-10)
+    ref = so.linprog(c, A_ub=A[4:], b_ub=u[4:], A_eq=A[:4], b_eq=b[:4], bounds=list(zip(L, U)), method="highs")
+    assert ref.status == 0
+    assert r.pobj == pytest.approx(ref.fun, rel=1e-7, abs=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Iteration-level pins
+# ---------------------------------------------------------------------------
+def test_fixed_point_at_kkt_solution():
+    # A KKT point u* = (y*, w* = x*, x*) is a fixed point of Algorithm 3.
+    qp = qpgen.make_tiny(30, n=5, m=3, n_eq=1)
+    Q, A = _dense(qp)
+    obj, xs, ys, zs = pins.kkt_enumerate(Q, qp.c, qp.L, qp.U, A, qp.l, qp.u)
+    r = _solve(qp, tol=0.0, max_iter=3, check_every=1000, y0=ys, w0=xs, x0=xs, trace_iters=3)
+    tr = split_trace(r.trace, qp.n, qp.m)
+    for k in range(3):
+        np.testing.assert_allclose(tr["xbar"][k], xs, atol=1e-11)
+        np.testing.assert_allclose(tr["ybar"][k], ys, atol=1e-11)
+        np.testing.assert_allclose(Q @ tr["wbar"][k], Q @ xs, atol=1e-11)
+        np.testing.assert_allclose(tr["x"][k], xs, atol=1e-11)
+
+
+def test_subproblem_optimality_along_trace():
+    """Each step of Algorithm 3 checked from first principles on the trace:
+    Step 1/2: xbar = x + sigma(-Qw + A^T y + zbar - c) lies in argmax_{x in C} <-zbar, x>;
+    Step 3-1/3-3: Q wbar = Q(sigma lamQ w + xbar + sigma(-Qw + A^T ybar + zbar - c))/(1+sigma lamQ);
+    Step 3-2: 0 in d delta*_K(-.)(ybar) + A xbar + sigma A(-Q w_half + A^T ybar + zbar - c) + sigma S_y (ybar - y);
+    Step 5: u^{k+1} = u^0/(k+2) + (k+1)/(k+2) (2 ubar - u^k)."""
+    qp = qpgen.make_small_ccqp(seed=5, n=30, m=12, nb=10, density=0.25)
+    Q, A = _dense(qp)
+    lamA = 1.01 * np.linalg.eigvalsh(A @ A.T).max(); lamQ = 1.01 * np.linalg.eigvalsh(Q).max()
+    sigma = 0.7
+    K = 25
+    r = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10 ** 6, lambda_A=lamA, lambda_Q=lamQ,
+                     sigma0=sigma, trace_iters=K)
+    tr = split_trace(r.trace, qp.n, qp.m)
+    y, w, x = np.zeros(qp.m), np.zeros(qp.n), np.zeros(qp.n)
+    sQ = sigma * lamQ
+    for k in range(K):
+        yb, wb, xb = tr["ybar"][k], tr["wbar"][k], tr["xbar"][k]
+        zb = (xb - x) / sigma + Q @ w - A.T @ y + qp.c                  # Step 2 solved for zbar
+        tol = 1e-9 * (1 + np.abs(xb).max())
+        assert np.all(xb >= qp.L - tol) and np.all(xb <= qp.U + tol)
+        assert np.all(np.abs(xb[zb > 1e-9] - qp.L[zb > 1e-9]) < 1e-8)
+        assert np.all(np.abs(xb[zb < -1e-9] - qp.U[zb < -1e-9]) < 1e-8)
+        wh = (sQ * w + xb + sigma * (-Q @ w + A.T @ y + zb - qp.c)) / (1 + sQ)      # Step 3-1
+        wt = (sQ * w + xb + sigma * (-Q @ w + A.T @ yb + zb - qp.c)) / (1 + sQ)     # Step 3-3
+        np.testing.assert_allclose(Q @ wb, Q @ wt, atol=1e-9 * (1 + np.abs(Q @ wt).max()))
+        Sy = lamA * np.eye(qp.m) - A @ A.T
+        v = A @ xb + sigma * A @ (-Q @ wh + A.T @ yb + zb - qp.c) + sigma * Sy @ (yb - y)
+        # v must be a maximiser of <-ybar, s> over s in K
+        tv = 1e-8 * (1 + np.abs(v).max())
+        assert np.all(v >= qp.l - tv) and np.all(v <= qp.u + tv)
+        pos, neg = yb > 1e-10, yb < -1e-10
+        np.testing.assert_allclose(v[pos], qp.l[pos], atol=tv)
+        np.testing.assert_allclose(v[neg], qp.u[neg], atol=tv)
+        rho = 1.0 / (k + 2)
+        yn = rho * 0 + (1 - rho) * (2 * yb - y)
+        wn = (1 - rho) * (2 * wb - w)
+        xn = (1 - rho) * (2 * xb - x)
+        np.testing.assert_allclose(tr["y"][k], yn, atol=1e-10 * (1 + np.abs(yn).max()))
+        np.testing.assert_allclose(tr["w"][k], wn, atol=1e-10 * (1 + np.abs(wn).max()))
+        np.testing.assert_allclose(tr["x"][k], xn, atol=1e-10 * (1 + np.abs(xn).max()))
+        y, w, x = tr["y"][k], tr["w"][k], tr["x"][k]
+
+
+def test_o_one_over_k_bound_without_restart():
+    """Theorem 2.2: ||u^k - ubar^{k+1}||_M <= ||u^0 - u*||_M / (k+1) with a
+    fixed sigma and no restart."""
+    qp = qpgen.make_tiny(33, n=5, m=3, n_eq=1)
+    Q, A = _dense(qp)
+    obj, xs, ys, zs = pins.kkt_enumerate(Q, qp.c, qp.L, qp.U, A, qp.l, qp.u)
+    lamA = 1.01 * np.linalg.eigvalsh(A @ A.T).max(); lamQ = 1.01 * np.linalg.eigvalsh(Q).max()
+    for sigma in (0.2, 1.0, 5.0):
+        R0 = np.sqrt(oracle.mnorm2(qp, sigma, lamA, lamQ, -ys, -xs, -xs))
+        K = 300
+        r = oracle.solve(qp, tol=0.0, max_iter=K, check_every=1, lambda_A=lamA, lambda_Q=lamQ,
+                         sigma0=sigma, enable_restart=False, enable_sigma_update=False, log_cap=K)
+        k = r.check_log[:, 0]; R = r.check_log[:, 2]
+        assert np.all(R <= R0 / k * (1 + 1e-9) + 1e-13)
+
+
+def test_restart_schedule_with_criterion_three():
+    # eq:restart_3 at the first check of epoch 0 always holds (t = k), and the
+    # sigma update keeps sigma positive and finite.
+    qp = qpgen.make_small_ccqp()
+    r = oracle.solve(qp, tol=1e-8, max_iter=2000, check_every=100, log_cap=100,
+                     power_start_A=qpgen.power_start(qp.m), power_start_Q=qpgen.power_start(qp.n))
+    log = r.check_log
+    assert log[0, 0] == 100 and log[0, 7] == 1.0
+    assert np.all(np.isfinite(log[:, 8])) and np.all(log[:, 8] > 0)
+
+
+def test_small_ccqp_solution_certificate():
+    qp = qpgen.make_small_ccqp()
+    r = oracle.solve(qp, tol=1e-8, max_iter=200_000, power_start_A=qpgen.power_start(qp.m),
+                     power_start_Q=qpgen.power_start(qp.n))
+    assert r.term == "solved"
+    Q, A = _dense(qp)
+    kkt, P, D = pins.kkt_residual_numpy(Q, qp.c, qp.L, qp.U, A, qp.l, qp.u, r.x, r.y, r.z)
+    assert kkt <= 1e-8
+    assert r.pobj == pytest.approx(P, rel=1e-12)
+
+
+def test_residuals_reference_values():
+    qp = qpgen.make_tiny(40, n=4, m=2)
+    Q, A = _dense(qp)
+    rng = np.random.default_rng(0)
+    y, z, x = rng.standard_normal(2), rng.standard_normal(4), rng.standard_normal(4)
+    # z with a finite bound on each side where nonzero keeps the dual finite
+    z[np.isinf(qp.L) & (z > 0)] *= -1
+    got = oracle.residuals(qp, y, z, x)
+    kkt, P, D = pins.kkt_residual_numpy(Q, qp.c, qp.L, qp.U, A, qp.l, qp.u, x, y, z)
+    if np.isfinite(D):
+        assert got["kkt"] == pytest.approx(kkt, rel=1e-12)
+        assert got["pobj"] == pytest.approx(P, rel=1e-13)
+
+
+def test_first_sigma_update_from_dense_thetas():
+    """Algorithm 5 at the first restart: the smoothing ratio is exactly 1, so
+    sigma_1 = exp(e^-1 log sigma_new + (1 - e^-1) log sigma_0), with
+    sigma_new the minimiser of f built from the theta's of "eq:theta"
+    (anchor u^{0,0} = 0).  The theta's are formed densely here and the
+    minimiser found by Brent's method on f'."""
+    qp = qpgen.make_small_ccqp(seed=6, n=40, m=16, nb=12, density=0.2)
+    Q, A = _dense(qp)
+    lamA = 1.01 * np.linalg.eigvalsh(A @ A.T).max(); lamQ = 1.01 * np.linalg.eigvalsh(Q).max()
+    T = 20
+    r = oracle.solve(qp, tol=0.0, max_iter=2 * T, check_every=T, lambda_A=lamA, lambda_Q=lamQ,
+                     trace_iters=T, log_cap=4)
+    tr = split_trace(r.trace, qp.n, qp.m)
+    assert r.check_log[0, 7] == 1.0              # eq:restart_3 fires (t = k)
+    yb, wb, xb = tr["ybar"][T - 1], tr["wbar"][T - 1], tr["xbar"][T - 1]
+    th1 = lamA * yb @ yb + lamQ * wb @ Q @ wb - 2 * (Q @ wb) @ (A.T @ yb)
+    th2 = xb @ xb
+    th3 = (A.T @ yb) @ Q @ (A.T @ yb)
+    fp = lambda s: th1 - th2 / s ** 2 + th3 * s * (2 + lamQ * s) / (1 + lamQ * s) ** 2
+    snew = so.brentq(fp, 1e-9, 1e9, xtol=1e-300, rtol=1e-15)
+    s0 = r.check_log[0, 6]
+    beta = np.exp(-1.0)
+    assert r.check_log[0, 8] == pytest.approx(np.exp(beta * np.log(snew) + (1 - beta) * np.log(s0)), rel=1e-10)
+    # the restarted state is the bar point of the restart iteration
+    np.testing.assert_allclose(tr["x"][T - 1], xb, rtol=0, atol=0)

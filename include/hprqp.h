@@ -1,0 +1,197 @@
+/*
+ * hprqp.h -- C ABI of the MI355X (gfx950) HPR-QP library, libhprqp.so.
+ *
+ * HPR-QP (arXiv 2507.02470) solves the convex QP of Section 1, problem
+ * "QP-primal-0":
+ *
+ *     min_x  1/2 <x, Q x> + <c, x>   s.t.  l <= A x <= u,   L <= x <= U,
+ *
+ * i.e. the composite problem "QP-primal" with phi = indicator of the box
+ * C = [L, U] and K = [l, u].  The library runs the dual Halpern
+ * Peaceman-Rachford iteration of Algorithm 4 on the restricted Wolfe dual
+ * ("QP-dual"), with the restart rule of Section 3.2 and the sigma update of
+ * Algorithm 5, in FP64, entirely in hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array pointer is a DEVICE pointer (memory of the GPU current at
+ *    hprqp_create / hprqp_batch_create) unless its comment says "host".
+ *    Input arrays are borrowed: the caller keeps them alive and unchanged
+ *    for the lifetime of the handle.  Outputs are caller-allocated.
+ *  - Indices are int32, values double.  CSR arrays: rowptr has rows+1
+ *    entries starting at 0 and non-decreasing; columns lie in [0, cols).
+ *  - Infinite bounds are IEEE +-INFINITY; l_i == u_i marks an equality row.
+ *  - All GPU work is enqueued on the stream given at creation; entry points
+ *    return after the results they report are complete.
+ *  - Errors are returned as hprqp_status; a message for the calling thread
+ *    is available from hprqp_last_error().  Non-convergence is not an
+ *    error: it is reported in hprqp_info.term.
+ */
+#ifndef HPRQP_H
+#define HPRQP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPRQP_OK = 0,
+  HPRQP_ERR_ARG = 1,          /* NULL handle/pointer, bad option value          */
+  HPRQP_ERR_SHAPE = 2,        /* bad sizes, CSR not monotone, column out of range */
+  HPRQP_ERR_BOUNDS = 3,       /* l > u, L > U, NaN in a bound, non-finite c      */
+  HPRQP_ERR_HIP = 4,          /* a HIP runtime call failed                       */
+  HPRQP_ERR_OOM = 5,          /* device allocation failed                        */
+  HPRQP_ERR_UNSUPPORTED = 6   /* option or problem kind not supported here       */
+} hprqp_status;
+
+typedef enum {
+  HPRQP_SOLVED = 0,           /* max(eta_p, eta_d, eta_gap) <= tol               */
+  HPRQP_MAX_ITER = 1,
+  HPRQP_TIME_LIMIT = 2,
+  HPRQP_NUMERICAL = 3         /* NaN/Inf met at a check                          */
+} hprqp_term;
+
+typedef enum {
+  HPRQP_Q_ZERO = 0,           /* Q = 0 (the LP case of Remark 2.1)               */
+  HPRQP_Q_CSR = 1,            /* explicit symmetric CSR, both triangles stored   */
+  HPRQP_Q_KRON = 2,           /* matrix-free Q = B (x) C (Section 4.5)           */
+  HPRQP_Q_LOWRANK = 3         /* Q = diag(d) + F F^T                              */
+} hprqp_qkind;
+
+/* Problem data (Section 1, "QP-primal-0").  Q must be self-adjoint PSD. */
+typedef struct {
+  int32_t n, m;               /* variables, rows of A (m may be 0: Remark 2.1)  */
+  int32_t qkind;              /* hprqp_qkind                                      */
+  /* HPRQP_Q_CSR: n x n, full symmetric storage */
+  const int32_t *q_rowptr, *q_col; const double *q_val; int64_t q_nnz;
+  /* HPRQP_Q_KRON: Q vec(X) = vec(C X B^T), X kron_s x kron_p column-major,
+   * n = kron_s * kron_p; B (kron_p x kron_p) and C (kron_s x kron_s) dense
+   * column-major, each symmetric PSD */
+  int32_t kron_p, kron_s; const double *kron_B, *kron_C;
+  /* HPRQP_Q_LOWRANK: Q = diag(lr_d) + F F^T, F n x lr_rank row-major */
+  int32_t lr_rank; const double *lr_d, *lr_F;
+  const double *c, *L, *U;    /* n each: objective and box C = [L, U]          */
+  const int32_t *a_rowptr, *a_col; const double *a_val; int64_t a_nnz;  /* A, m x n */
+  const double *l, *u;        /* m each: K = [l, u]                              */
+} hprqp_problem;
+
+typedef struct {
+  double tol;                 /* stopping tolerance on max(eta_p, eta_d, eta_gap); 1e-8 */
+  int64_t max_iter;           /* iteration cap                                           */
+  double time_limit_s;        /* wall-clock cap checked at each check; <= 0: none; 3600  */
+  int32_t check_every;        /* restart/termination test cadence; 100                   */
+  double sigma0;              /* <= 0: sigma0 = ||b||/||c|| rule of Section 4.1           */
+  double lambda_A, lambda_Q;  /* <= 0: power method (Section 4.1) at create               */
+  const double *power_start_A;  /* device, m: power-method start on A A^T; NULL: all ones */
+  const double *power_start_Q;  /* device, n: power-method start on Q;     NULL: all ones */
+  double alpha1, alpha2, alpha3;  /* restart parameters of Section 3.2; 0.2, 0.8, 0.5     */
+  int32_t enable_restart;     /* 1 */
+  int32_t enable_sigma_update;/* 1 */
+  int32_t use_graph;          /* 1: replay each check segment as a captured HIP graph    */
+  int32_t spmv_autotune;      /* 1: time lanes-per-row choices for A, A^T, Q at create   */
+  int32_t trace_iters;        /* record the first K iterations into trace_host           */
+  double *trace_host;         /* host, K x (2m + 4n) doubles, rows [y, w, x, ybar, wbar, xbar];
+                                 y, w, x is the state carried into the next iteration     */
+  int32_t log_cap;            /* capacity (rows) of check_log_host                       */
+  double *check_log_host;     /* host, rows of 10 doubles: k, t, R~, eta_p, eta_d, eta_gap,
+                                 sigma used, restarted (0/1), sigma next, restart count  */
+  int32_t profile_kernels;    /* 1: time the four per-iteration products with HIP events on
+                                 the solve stream (two iterations per check segment), see
+                                 hprqp_kernel_stats                                        */
+} hprqp_options;
+
+typedef struct {
+  int32_t term;               /* hprqp_term                                        */
+  int64_t iters;              /* iterations done                                   */
+  int32_t restarts;
+  int32_t n_log;              /* rows written to check_log_host                    */
+  double sigma, sigma0, lambda_A, lambda_Q;
+  double eta_p, eta_d, eta_gap; /* at the returned point                          */
+  double pobj, dobj;
+  double R_last;              /* merit R~ at the last check                        */
+  double t_setup_s, t_solve_s;  /* seconds: create (incl. power method), solve    */
+} hprqp_info;
+
+typedef struct hprqp_handle hprqp_handle;
+typedef struct hprqp_batch hprqp_batch;
+
+/* Fills the defaults of Section 4.1 (tol 1e-8, alpha = 0.2/0.8/0.5,
+ * check_every 100, time limit 3600 s, power method, sigma0 rule). */
+void hprqp_default_options(hprqp_options *opt);
+
+/* Validates the problem (bounds, CSR structure, finiteness), builds A^T as
+ * an explicit CSR on the device (rows of A^T ordered by row of A, so every
+ * product is deterministic), runs the power method when lambda_A/lambda_Q
+ * are not given (Section 4.1), computes sigma0 and allocates the workspace
+ * (about 30 n + 12 m doubles plus A^T).  The problem arrays are borrowed.
+ * Returns HPRQP_ERR_BOUNDS / HPRQP_ERR_SHAPE on invalid data. */
+hprqp_status hprqp_create(const hprqp_problem *prob, const hprqp_options *opt,
+                          hipStream_t stream, hprqp_handle **out);
+
+/* Runs Algorithm 4 from (y0, w0, x0) (each may be NULL: origin, Section 4.1)
+ * and writes the last bar iterate ubar = (ybar, zbar, wbar, xbar), the output
+ * of Algorithm 4: y (m), z (n), w (n; the unprojected shadow w_Q of
+ * Proposition 2.4), x (n).  info may be NULL. */
+hprqp_status hprqp_solve(hprqp_handle *h, const double *y0, const double *w0, const double *x0,
+                         double *y, double *z, double *w, double *x, hprqp_info *info);
+
+/* Stopping quantities of Section 4.1 at the point (y, z, x):
+ * out_host[0..4] = eta_p, eta_d, eta_gap, primal objective, dual objective. */
+hprqp_status hprqp_residuals(hprqp_handle *h, const double *y, const double *z, const double *x,
+                             double *out_host);
+
+/* Applies one operator of the handle: op 0: out = Q in (n -> n), op 1:
+ * out = A in (n -> m), op 2: out = A^T in (m -> n, using the stored A^T). */
+hprqp_status hprqp_apply(hprqp_handle *h, int32_t op, const double *in, double *out);
+
+/* The power-method estimates of create (before the 1.01 safety factor),
+ * and the number of products each took; any pointer may be NULL. */
+hprqp_status hprqp_power_info(hprqp_handle *h, double *est_A, int32_t *it_A,
+                              double *est_Q, int32_t *it_Q);
+
+/* Kernel timing of the last hprqp_solve made with profile_kernels = 1:
+ * avg_ms_host[i] = mean duration (ms) and launches_host[i] = number of timed
+ * launches of product i, i = 0: Q xhat (with its epilogue), 1: A v, 2: A^T ybar,
+ * 3: Q A^T(ybar - y) with the Halpern epilogue.  Also reports the
+ * lanes-per-row choice of A, A^T and Q (g_host[3], may be NULL). */
+hprqp_status hprqp_kernel_stats(hprqp_handle *h, double *avg_ms_host, int64_t *launches_host, int32_t *g_host);
+
+void hprqp_destroy(hprqp_handle *h);
+
+/* ---------------------------------------------------------------------
+ * Batched solve: many independent QPs (sizes may differ) solved by one
+ * persistent kernel, one workgroup per instance at a time, with the whole
+ * of Algorithm 4 + 5 (restart, sigma update, termination) on the device.
+ * Supported: qkind HPRQP_Q_LOWRANK with lr_rank <= 16 and n <= 4096,
+ * m <= 64 per instance.
+ * --------------------------------------------------------------------- */
+
+/* probs: host array of `count` problems whose arrays are device pointers;
+ * instances may share arrays (e.g. one Q and A with per-instance c, l, u).
+ * The options apply to every instance (power method per instance when
+ * lambda_A/lambda_Q <= 0, from an all-ones start).  Instances are scheduled
+ * largest first. */
+hprqp_status hprqp_batch_create(int32_t count, const hprqp_problem *probs,
+                                const hprqp_options *opt, hipStream_t stream, hprqp_batch **out);
+
+/* Solves every instance.  Vectors are concatenated in instance order:
+ * y0/y use offsets sum_{j<i} m_j, w0/x0/z/w/x use offsets sum_{j<i} n_j.
+ * y0, w0, x0 may each be NULL (origin for every instance).  infos_host:
+ * host array of `count` hprqp_info (may be NULL). */
+hprqp_status hprqp_solve_batch(hprqp_batch *b, const double *y0, const double *w0, const double *x0,
+                               double *y, double *z, double *w, double *x, hprqp_info *infos_host);
+
+/* Elapsed time of the last hprqp_solve_batch kernel (HIP events), seconds. */
+double hprqp_batch_last_kernel_s(hprqp_batch *b);
+
+void hprqp_batch_destroy(hprqp_batch *b);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char *hprqp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPRQP_H */

@@ -1,0 +1,93 @@
+// common.hpp -- shared device helpers for the HPR-QP kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define HQ_WAVE 64
+#define HQ_BLOCK 256          // threads per block for vector/SpMV kernels (4 waves)
+#define HQ_PCAP 4096          // max partial results per reduction slot
+#define HQ_GRID_CAP 4096      // grid cap of grid-stride kernels (<= HQ_PCAP)
+
+// Iteration scalars kept in device memory so that one captured graph can be
+// replayed for every check segment (sigma changes only at restarts, the
+// inner counter t advances by the segment length).
+struct DevParams {
+  double sigma;     // sigma_r of the current epoch
+  double lamA;      // lambda_A >= lambda_1(A A^T)
+  double lamQ;      // lambda_Q >= lambda_1(Q)
+  int64_t t0;       // inner counter t at the first iteration of the segment
+};
+
+// Scalars derived from DevParams at iteration j of a segment.
+struct IterScalars {
+  double sigma, sQ, kappa, sA, rho;
+  __device__ void load(const DevParams* p, int j) {
+    sigma = p->sigma;
+    sQ = sigma * p->lamQ;             // sigma lambda_Q
+    kappa = sigma / (1.0 + sQ);       // sigma / (1 + sigma lambda_Q)
+    sA = sigma * p->lamA;             // sigma lambda_A
+    rho = 1.0 / (double)(p->t0 + j + 2);   // Halpern weight 1/(t+2)
+  }
+};
+
+// Where a kernel's per-block partial reductions go: acc index s -> global
+// reduction slot slot[s] (-1: skip).  counts[slot] receives gridDim.x.
+struct RedOut {
+  double* partials;   // [slot][HQ_PCAP]
+  int* counts;        // [slot]
+  int8_t slot[16];
+  int active;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Fixed-order block reduction of NR accumulators (sum, or max where bit s of
+// MAXMASK is set) and store of one partial per block.  Deterministic.
+template <int NR, unsigned MAXMASK>
+__device__ __forceinline__ void block_reduce_store(const double* acc, const RedOut& red) {
+  if constexpr (NR > 0) {
+    __shared__ double sh[HQ_BLOCK / HQ_WAVE][NR > 0 ? NR : 1];
+    const int lane = threadIdx.x & (HQ_WAVE - 1), wv = threadIdx.x / HQ_WAVE;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      double v = ((MAXMASK >> s) & 1u) ? wave_max(acc[s]) : wave_sum(acc[s]);
+      if (lane == 0) sh[wv][s] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NR) {
+      const int s = threadIdx.x;
+      double v = sh[0][s];
+      const bool mx = (MAXMASK >> s) & 1u;
+      for (int w = 1; w < (int)(blockDim.x / HQ_WAVE); ++w) v = mx ? fmax(v, sh[w][s]) : v + sh[w][s];
+      const int slot = red.slot[s];
+      if (slot >= 0) {
+        red.partials[(size_t)slot * HQ_PCAP + blockIdx.x] = v;
+        if (blockIdx.x == 0) red.counts[slot] = gridDim.x;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double clampd(double v, double lo, double hi) {
+  return fmin(fmax(v, lo), hi);
+}
+
+// streaming loads for matrix data read once per product
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int ld_stream(const int* p) { return __builtin_nontemporal_load(p); }
+
+static inline int hq_grid(long long work, int per_block) {
+  long long g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > HQ_GRID_CAP) g = HQ_GRID_CAP;
+  return (int)g;
+}

@@ -1,0 +1,105 @@
+// qops.hpp -- matrix-free Q products: Kronecker (FP64 MFMA) and diag + low rank.
+#pragma once
+#include "common.hpp"
+
+typedef double hq_dx4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// D (M x N) = A (M x K, col-major, lda) * op(B); op(B)[k][j] = B[k + ldb j]
+// (TRANSB = false) or B[j + ldb k] (TRANSB = true).  Output element (i, j)
+// goes to the epilogue as vector index i + ldo j.
+//
+// One 16 x 16 output tile per 256-thread block; its four waves split K into
+// four ranges, each accumulating with v_mfma_f64_16x16x4f64, and the four
+// partial tiles are summed in LDS in a fixed order (deterministic).  Operand
+// layout of the 16x16x4 f64 MFMA (measured on gfx950): lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; accumulator register v of lane l holds
+// D[l/16 + 4v][l%16], v = 0..3.
+// ---------------------------------------------------------------------------
+template <bool TRANSB, class Epi>
+__global__ __launch_bounds__(256) void k_dgemm16(int M, int N, int K, const double* __restrict__ A, int lda,
+                                                 const double* __restrict__ B, int ldb, int ldo, Epi epi,
+                                                 const DevParams* __restrict__ prm, int jit, RedOut red) {
+  constexpr int NR = Epi::NR;
+  __shared__ double part[4][16][17];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tiles_m = (M + 15) >> 4, tiles_n = (N + 15) >> 4;
+  const int ksteps = (K + 3) >> 2;
+  const int per = (ksteps + 3) >> 2;
+  const int ks0 = wv * per;
+  const int ks1 = (ks0 + per < ksteps) ? ks0 + per : ksteps;
+  Epi e = epi;
+  e.setup(prm, jit);
+  double acc[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int s = 0; s < (NR > 0 ? NR : 1); ++s) acc[s] = 0.0;
+  for (int tile = blockIdx.x; tile < tiles_m * tiles_n; tile += gridDim.x) {
+    const int i0 = (tile % tiles_m) << 4, j0 = (tile / tiles_m) << 4;
+    const int ia = i0 + li, jb = j0 + li;
+    hq_dx4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int ks = ks0; ks < ks1; ++ks) {
+      const int k = (ks << 2) + lk;
+      const bool kin = k < K;
+      const double a = (ia < M && kin) ? A[ia + (size_t)lda * k] : 0.0;
+      const double b = (jb < N && kin) ? (TRANSB ? B[jb + (size_t)ldb * k] : B[k + (size_t)ldb * jb]) : 0.0;
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[wv][lk + 4 * v][li] = d[v];
+    __syncthreads();
+    const int r = threadIdx.x & 15, cc = threadIdx.x >> 4;
+    const double q = ((part[0][r][cc] + part[1][r][cc]) + part[2][r][cc]) + part[3][r][cc];
+    const int gi = i0 + r, gj = j0 + cc;
+    if (gi < M && gj < N) e(gi + ldo * gj, q, acc);
+    __syncthreads();
+  }
+  if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
+}
+
+// ---------------------------------------------------------------------------
+// Q = diag(d) + F F^T, F n x r row-major (r <= 16).
+// Stage 1: per-block partial sums of t = F^T x (slots red.slot[0..r-1]).
+// Stage 2 (after the final reduction): (Q x)_i = d_i x_i + sum_k F_ik t_k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(HQ_BLOCK) void k_lr_partial(int n, int r, const double* __restrict__ F,
+                                                         const double* __restrict__ x, RedOut red) {
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  for (long long i = (long long)blockIdx.x * HQ_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * HQ_BLOCK) {
+    const double xi = x[i];
+    const double* Fi = F + (size_t)i * r;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < r) acc[k] += Fi[k] * xi;
+  }
+  block_reduce_store<16, 0u>(acc, red);
+}
+
+template <class Epi>
+__global__ __launch_bounds__(HQ_BLOCK) void k_lr_apply(int n, int r, const double* __restrict__ dg,
+                                                       const double* __restrict__ F,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ t, Epi epi,
+                                                       const DevParams* __restrict__ prm, int jit, RedOut red) {
+  constexpr int NR = Epi::NR;
+  Epi e = epi;
+  e.setup(prm, jit);
+  double acc[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int s = 0; s < (NR > 0 ? NR : 1); ++s) acc[s] = 0.0;
+  double tk[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) tk[k] = (k < r) ? t[k] : 0.0;
+  for (long long i = (long long)blockIdx.x * HQ_BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * HQ_BLOCK) {
+    const double* Fi = F + (size_t)i * r;
+    double q = dg[i] * x[i];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < r) q += Fi[k] * tk[k];
+    e((int)i, q, acc);
+  }
+  if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
+}

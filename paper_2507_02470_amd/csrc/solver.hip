@@ -1,0 +1,947 @@
+// solver.hip -- single-instance HPR-QP (Algorithm 4 + Algorithm 5, arXiv
+// 2507.02470) on one MI355X: device kernels for every vector/matrix step,
+// host C++ for the scalar decisions taken at checks (termination, restart
+// criteria of Section 3.2, SigmaUpdate).
+//
+// Per iteration there are four global dependency points
+//   Q xhat  ->  A v  ->  A^T ybar  ->  Q A^T(ybar - y)
+// so an iteration is four launches (a3..a6); the z/x step of the next
+// iteration is fused into the last one.  A "segment" is the run of
+// `check_every` iterations that ends in a check; it can be captured once as
+// a HIP graph and replayed, since sigma and the inner counter live in device
+// memory.  The host reads back ~30 scalars per segment.
+#include "hprqp.h"
+#include "common.hpp"
+#include "epilogues.hpp"
+#include "qops.hpp"
+#include "spmv.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+hipError_t hq_build_transpose(int m, int n, int64_t nnz, const int* rowptr, const int* col, const double* val,
+                              int* t_rowptr, int* t_col, double* t_val, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace hq {
+thread_local std::string g_err;
+
+struct Error {
+  hprqp_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(hprqp_status st, const std::string& msg) { throw Error{st, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) fail(HPRQP_ERR_OOM, std::string(what) + ": out of device memory");
+    fail(HPRQP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+#define HQC(x) ::hq::hip_check((x), #x)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace hq
+
+extern "C" const char* hprqp_last_error(void) { return hq::g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// reduction slots (per-block partials -> final reduce -> host)
+// ---------------------------------------------------------------------------
+enum : int {
+  SL_RF = 0,    // merit of the epoch's first iteration: 7 slots
+  SL_RC = 7,    // merit at the check: 7 slots
+  SL_TH = 14,   // theta~ of Algorithm 5: 5 slots
+  SL_RA = 19,   // primal residual part: 4 slots
+  SL_RQ = 23,   // dual residual part: 7 slots
+  SL_ITER_END = 30,
+  SL_POW = 30,  // power method: 2 slots
+  SL_NRM = 32,  // norms of b and c: 4 slots
+  SL_LR = 36,   // F^T x of the low-rank Q: 16 slots
+  SL_TOTAL = 52
+};
+static constexpr unsigned long long kMaxMask =
+    (1ull << (SL_RA + 0)) | (1ull << (SL_RA + 1)) | (1ull << (SL_RQ + 0)) | (1ull << (SL_RQ + 1)) |
+    (1ull << (SL_RQ + 2)) | (1ull << (SL_NRM + 1)) | (1ull << (SL_NRM + 3));
+
+__global__ __launch_bounds__(256) void k_final_reduce(const double* __restrict__ partials, const int* __restrict__ counts,
+                                                      int slot0, unsigned long long maxmask, double* __restrict__ out) {
+  const int slot = slot0 + blockIdx.x;
+  const int cnt = counts[slot];
+  const bool mx = (maxmask >> slot) & 1ull;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const double p = partials[(size_t)slot * HQ_PCAP + i];
+    v = mx ? fmax(v, p) : v + p;
+  }
+  v = mx ? wave_max(v) : wave_sum(v);
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = mx ? fmax(r, sh[w]) : r + sh[w];
+    out[slot] = r;
+  }
+}
+
+__global__ void k_zero_ints(int n, int* p) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+__global__ void k_fill(long long n, double* p, double v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_copy(long long n, const double* __restrict__ s, double* __restrict__ a, double* __restrict__ b) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double v = s[i];
+    a[i] = v;
+    if (b) b[i] = v;
+  }
+}
+// power method: reduce slots (<v,w>, |w|^2) into the history and the next scale
+__global__ __launch_bounds__(256) void k_pow_final(const double* __restrict__ partials, const int* __restrict__ counts,
+                                                   double* __restrict__ hist, int it, double* __restrict__ scale) {
+  __shared__ double sh[2][4];
+  for (int s = 0; s < 2; ++s) {
+    const int slot = SL_POW + s, cnt = counts[slot];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) v += partials[(size_t)slot * HQ_PCAP + i];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[s][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lam = sh[0][0], nw2 = sh[1][0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) { lam += sh[0][w]; nw2 += sh[1][w]; }
+    hist[2 * it] = lam;
+    hist[2 * it + 1] = nw2;
+    *scale = nw2 > 0.0 ? 1.0 / sqrt(nw2) : 0.0;
+  }
+}
+__global__ void k_scale(long long n, const double* __restrict__ in, const double* __restrict__ s, double* __restrict__ out) {
+  const double f = *s;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = in[i] * f;
+}
+
+struct EpiSumSq {
+  const double* v;
+  static constexpr int NR = 1;
+  static constexpr unsigned MAXMASK = 0u;
+  __device__ void setup(const DevParams*, int) {}
+  __device__ __forceinline__ void operator()(int i, double, double* acc) const { acc[0] += v[i] * v[i]; }
+};
+// ||b||^2, ||c||^2, ||b||_inf, ||c||_inf with b_i = max(|l_i|, |u_i|), infinities read as 0 (Section 4.1)
+struct EpiNormB {
+  const double *l, *u;
+  static constexpr int NR = 2;
+  static constexpr unsigned MAXMASK = 0x2u;
+  __device__ void setup(const DevParams*, int) {}
+  __device__ __forceinline__ void operator()(int i, double, double* acc) const {
+    const double a = isinf(l[i]) ? 0.0 : fabs(l[i]), b = isinf(u[i]) ? 0.0 : fabs(u[i]);
+    const double bi = fmax(a, b);
+    acc[0] += bi * bi;
+    acc[1] = fmax(acc[1], bi);
+  }
+};
+struct EpiNormC {
+  const double* c;
+  static constexpr int NR = 2;
+  static constexpr unsigned MAXMASK = 0x2u;
+  __device__ void setup(const DevParams*, int) {}
+  __device__ __forceinline__ void operator()(int i, double, double* acc) const {
+    acc[0] += c[i] * c[i];
+    acc[1] = fmax(acc[1], fabs(c[i]));
+  }
+};
+
+// input validation (create): bit 0 -> bounds / non-finite data, bit 1 -> CSR structure
+__global__ void k_validate_vec(int n, const double* lo, const double* hi, const double* c, int* flags) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double a = lo[i], b = hi[i];
+    bool bad = !(a <= b) || a == INFINITY || b == -INFINITY;
+    if (c && !isfinite(c[i])) bad = true;
+    if (bad) atomicOr(flags, 1);
+  }
+}
+__global__ void k_validate_finite(long long n, const double* v, int* flags) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    if (!isfinite(v[i])) atomicOr(flags, 1);
+}
+__global__ void k_validate_csr(int rows, int cols, long long nnz, const int* rp, const int* ci, const double* v,
+                               int* flags) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += gridDim.x * blockDim.x) {
+    const int b = rp[i], e = rp[i + 1];
+    // never read columns outside [0, nnz), whatever rowptr holds
+    if ((i == 0 && b != 0) || b < 0 || e < b || (long long)e > nnz || (i == rows - 1 && e != nnz)) {
+      atomicOr(flags, 2);
+      continue;
+    }
+    for (int k = b; k < e; ++k) {
+      if (ci[k] < 0 || ci[k] >= cols) atomicOr(flags, 2);
+      if (!isfinite(v[k])) atomicOr(flags, 1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct Mat {
+  int rows = 0, cols = 0;
+  const int* rp = nullptr;
+  const int* ci = nullptr;
+  const double* v = nullptr;
+  long long nnz = 0;
+  int G = 4;
+};
+
+struct hprqp_handle {
+  int dev = 0;
+  hipStream_t st = nullptr;
+  int n = 0, m = 0, qkind = 0;
+  Mat A, AT, Q;
+  int kp = 0, ks = 0;
+  const double *kB = nullptr, *kC = nullptr;
+  int lr_r = 0;
+  const double *lr_d = nullptr, *lr_F = nullptr;
+  const double *c = nullptr, *L = nullptr, *U = nullptr, *l = nullptr, *u = nullptr;
+  hprqp_options opt{};
+  double lamA = 0, lamQ = 0, sigma0 = 1, binf = 0, cinf = 0;
+  double powA_est = 0, powQ_est = 0;
+  int powA_it = 0, powQ_it = 0;
+  double t_setup = 0;
+  // owned device memory
+  std::vector<void*> owned;
+  int *at_rp = nullptr, *at_ci = nullptr;
+  double* at_v = nullptr;
+  double *y = nullptr, *ya = nullptr, *ybar = nullptr, *tm = nullptr;
+  double *w = nullptr, *wa = nullptr, *x = nullptr, *xa = nullptr, *ATy = nullptr, *ATya = nullptr, *Qw = nullptr,
+         *Qwa = nullptr, *xh = nullptr, *v = nullptr, *q1 = nullptr, *d = nullptr, *g = nullptr, *e = nullptr,
+         *XB = nullptr, *ZB = nullptr, *wbar = nullptr, *qwbar = nullptr, *xbo = nullptr, *zbo = nullptr,
+         *t1 = nullptr, *t2 = nullptr, *kronT = nullptr;
+  double *partials = nullptr, *scalars = nullptr, *hist = nullptr;
+  int* counts = nullptr;
+  int* dflags = nullptr;
+  DevParams* dprm = nullptr;
+  // pinned host
+  double* hs = nullptr;      // scalars
+  DevParams* hp = nullptr;   // params
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_T = 0;
+  // kernel timing (profile_kernels): events around the four products of two
+  // iterations per segment, accumulated over the solve
+  hipEvent_t pev[2][4][2] = {};
+  double prof_ms[4] = {0, 0, 0, 0};
+  long long prof_n[4] = {0, 0, 0, 0};
+  hipStream_t own_st = nullptr;
+
+  template <class T>
+  T* dalloc(size_t count) {
+    void* p = nullptr;
+    HQC(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
+    owned.push_back(p);
+    return (T*)p;
+  }
+  ~hprqp_handle() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    for (void* p : owned) hipFree(p);
+    if (hs) hipHostFree(hs);
+    if (hp) hipHostFree(hp);
+    if (own_st) hipStreamDestroy(own_st);
+    for (auto& a : pev)
+      for (auto& b : a)
+        for (auto& e : b)
+          if (e) hipEventDestroy(e);
+  }
+};
+
+namespace hq {
+
+inline RedOut no_red(hprqp_handle& h) {
+  RedOut r;
+  r.partials = h.partials;
+  r.counts = h.counts;
+  for (int s = 0; s < 16; ++s) r.slot[s] = -1;
+  r.active = 0;
+  return r;
+}
+inline RedOut red_seq(hprqp_handle& h, int slot0, int nr) {
+  RedOut r = no_red(h);
+  for (int s = 0; s < nr; ++s) r.slot[s] = (int8_t)(slot0 + s);
+  r.active = 1;
+  return r;
+}
+
+template <class Epi>
+void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
+  const int grid = hq_grid(M.rows, HQ_BLOCK);
+  hipStream_t st = h.st;
+  switch (M.G) {
+    case 1: k_csr<1, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    case 2: k_csr<2, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    case 4: k_csr<4, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    case 8: k_csr<8, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    case 16: k_csr<16, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    case 32: k_csr<32, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    default: k_csr<64, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+  }
+}
+
+template <class Epi>
+void launch_elem(hprqp_handle& h, int n, const double* q, const Epi& epi, int j, const RedOut& red) {
+  k_elem<Epi><<<hq_grid(n, HQ_BLOCK), HQ_BLOCK, 0, h.st>>>(n, q, epi, h.dprm, j, red);
+}
+
+void final_reduce(hprqp_handle& h, int slot0, int nslot) {
+  k_final_reduce<<<nslot, 256, 0, h.st>>>(h.partials, h.counts, slot0, kMaxMask, h.scalars);
+}
+
+// out-of-place Q product with a fused epilogue: epi(i, (Q x)_i)
+template <class Epi>
+void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedOut& red) {
+  switch (h.qkind) {
+    case HPRQP_Q_ZERO:
+      launch_elem(h, h.n, nullptr, epi, j, red);
+      break;
+    case HPRQP_Q_CSR:
+      launch_csr(h, h.Q, x, epi, j, red);
+      break;
+    case HPRQP_Q_KRON: {
+      // Q vec(X) = vec(C X B^T): T = C X, then Y = T B^T with the epilogue
+      const int s = h.ks, p = h.kp;
+      const int tiles = ((s + 15) / 16) * ((p + 15) / 16);
+      const int grid = std::min(tiles, HQ_GRID_CAP);
+      k_dgemm16<false, EpiStore><<<grid, 256, 0, h.st>>>(s, p, s, h.kC, s, x, s, s, EpiStore{h.kronT}, h.dprm, j,
+                                                         no_red(h));
+      k_dgemm16<true, Epi><<<grid, 256, 0, h.st>>>(s, p, p, h.kronT, s, h.kB, p, s, epi, h.dprm, j, red);
+      break;
+    }
+    case HPRQP_Q_LOWRANK: {
+      const int grid = hq_grid(h.n, HQ_BLOCK);
+      RedOut lr = no_red(h);
+      for (int k = 0; k < h.lr_r; ++k) lr.slot[k] = (int8_t)(SL_LR + k);
+      lr.active = 1;
+      k_lr_partial<<<grid, HQ_BLOCK, 0, h.st>>>(h.n, h.lr_r, h.lr_F, x, lr);
+      final_reduce(h, SL_LR, h.lr_r);
+      k_lr_apply<Epi><<<grid, HQ_BLOCK, 0, h.st>>>(h.n, h.lr_r, h.lr_d, h.lr_F, x, h.scalars + SL_LR, epi, h.dprm, j,
+                                                   red);
+      break;
+    }
+    default:
+      fail(HPRQP_ERR_UNSUPPORTED, "unknown qkind");
+  }
+}
+
+void write_params(hprqp_handle& h, double sigma, long long t0) {
+  h.hp->sigma = sigma;
+  h.hp->lamA = h.lamA;
+  h.hp->lamQ = h.lamQ;
+  h.hp->t0 = t0;
+  HQC(hipMemcpyAsync(h.dprm, h.hp, sizeof(DevParams), hipMemcpyHostToDevice, h.st));
+}
+
+// One iteration (index j of a segment of Tseg iterations; the last one is a check).
+void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace) {
+  const bool check = (j == Tseg - 1);
+  const int rgroup = check ? SL_RC : (j == 0 ? SL_RF : -1);
+  const bool want_r = rgroup >= 0;
+  const bool xb_next = trace || (j >= Tseg - 2);
+  int ps = -1;  // timing sample index of this iteration
+  if (h.opt.profile_kernels && !trace && Tseg >= 4) ps = (j == Tseg / 3) ? 0 : (j == (2 * Tseg) / 3 ? 1 : -1);
+  auto mark = [&](int kind, int edge) {
+    if (ps >= 0) HQC(hipEventRecord(h.pev[ps][kind][edge], h.st));
+  };
+  // a3: q1 = Q xhat, v
+  mark(0, 0);
+  q_apply(h, h.xh, EpiQ1{h.xh, h.Qw, h.v, h.q1, 0.0}, j, no_red(h));
+  mark(0, 1);
+  if (h.m > 0) {
+    // a4: A v, ybar, y+
+    RedOut r4 = no_red(h);
+    if (want_r) r4.slot[0] = (int8_t)rgroup;
+    if (check) r4.slot[1] = (int8_t)SL_TH;
+    r4.active = want_r || check;
+    mark(1, 0);
+    launch_csr(h, h.A, h.v, EpiY{h.l, h.u, h.ya, h.y, h.ybar, want_r, check, 0.0, 0.0}, j, r4);
+    mark(1, 1);
+    // a5: A^T ybar, d, A^T y+
+    mark(2, 0);
+    launch_csr(h, h.AT, h.ybar, EpiAT{h.ATy, h.ATya, h.d, h.g, h.e, check, 0.0}, j, no_red(h));
+    mark(2, 1);
+  }
+  if (check) {
+    // stopping quantities at ubar = (ybar, zbar, xbar) (Section 4.1)
+    if (h.m > 0) launch_csr(h, h.A, h.XB, EpiResA{h.l, h.u, h.ybar}, j, red_seq(h, SL_RA, 4));
+    q_apply(h, h.XB, EpiResQ{h.XB, h.ZB, h.m > 0 ? h.g : nullptr, h.c, h.L, h.U, h.xbo, h.zbo}, j,
+            red_seq(h, SL_RQ, 7));
+  }
+  // a6: Q d, wbar, Halpern, next z/x step
+  EpiQ2 e6;
+  e6.xh = h.xh; e6.w = h.w; e6.Qw = h.Qw; e6.XB = h.XB; e6.ZB = h.ZB;
+  e6.q1 = h.q1; e6.d = h.d; e6.wa = h.wa; e6.Qwa = h.Qwa; e6.xa = h.xa; e6.ATy = h.ATy;
+  e6.c = h.c; e6.L = h.L; e6.U = h.U; e6.e = h.e;
+  e6.wbar = h.wbar; e6.qwbar = h.qwbar; e6.x = h.x; e6.xbar_out = h.xbo;
+  e6.want_r = want_r; e6.check = check; e6.xb_next = xb_next; e6.trace = trace;
+  RedOut r6 = no_red(h);
+  if (want_r)
+    for (int s = 0; s < 6; ++s) r6.slot[s] = (int8_t)(rgroup + 1 + s);
+  if (check)
+    for (int s = 0; s < 3; ++s) r6.slot[6 + s] = (int8_t)(SL_TH + 1 + s);
+  r6.active = want_r || check;
+  mark(3, 0);
+  if (h.m > 0) q_apply(h, h.d, e6, j, r6);
+  else launch_elem(h, h.n, nullptr, e6, j, r6);  // Q A^T(ybar - y) = 0 without constraints
+  mark(3, 1);
+  if (check && h.m > 0 && h.qkind != HPRQP_Q_ZERO)
+    q_apply(h, h.e, EpiTheta3{h.e}, j, red_seq(h, SL_TH + 4, 1));
+}
+
+void enqueue_segment(hprqp_handle& h, int Tseg) {
+  for (int j = 0; j < Tseg; ++j) enqueue_iter(h, j, Tseg, false);
+  final_reduce(h, 0, SL_ITER_END);
+  HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
+}
+
+void stage1(hprqp_handle& h) {
+  launch_elem(h, h.n, nullptr, EpiStage1{h.x, h.Qw, h.ATy, h.c, h.L, h.U, h.xh, h.XB, h.ZB, 0.0}, 0, no_red(h));
+}
+
+// anchor/state <- (y, w, x) buffers; exact A^T y and Q w; z/x step
+void reset_epoch(hprqp_handle& h) {
+  const long long n = h.n, m = h.m;
+  if (m > 0) {
+    k_copy<<<hq_grid(m, 256), 256, 0, h.st>>>(m, h.y, h.ya, nullptr);
+    launch_csr(h, h.AT, h.y, EpiStore2{h.ATy, h.ATya}, 0, no_red(h));
+  }
+  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.w, h.wa, nullptr);
+  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.x, h.xa, nullptr);
+  q_apply(h, h.w, EpiStore2{h.Qw, h.Qwa}, 0, no_red(h));
+  stage1(h);
+}
+
+// ||du||_M^2 from the seven merit slots (theta decomposition of the metric of Algorithm 3)
+double mnorm(const hprqp_handle& h, const double* S, double sigma) {
+  const double th1 = h.lamA * S[0] + h.lamQ * S[1] - 2.0 * S[2];
+  const double th2 = S[3], th3 = S[4], cross = S[5] - S[6];
+  const double m2 = sigma * th1 + th2 / sigma + sigma * sigma * th3 / (1.0 + sigma * h.lamQ) + 2.0 * cross;
+  return std::sqrt(m2 > 0.0 ? m2 : 0.0);
+}
+
+struct Resid {
+  double eta_p, eta_d, eta_gap, pobj, dobj;
+};
+Resid residuals_from(const hprqp_handle& h, const double* S) {
+  Resid r;
+  r.eta_p = (h.m > 0) ? S[SL_RA + 0] / (1.0 + std::max(h.binf, S[SL_RA + 1])) : 0.0;
+  r.eta_d = S[SL_RQ + 0] / (1.0 + std::max(h.cinf, std::max(S[SL_RQ + 1], S[SL_RQ + 2])));
+  const double xQx = S[SL_RQ + 3];
+  r.pobj = 0.5 * xQx + S[SL_RQ + 4];
+  const double dinf = (h.m > 0 ? S[SL_RA + 3] : 0.0) + S[SL_RQ + 6];
+  if (dinf > 0.0) {
+    r.dobj = -INFINITY;
+    r.eta_gap = INFINITY;
+  } else {
+    r.dobj = -0.5 * xQx + (h.m > 0 ? S[SL_RA + 2] : 0.0) + S[SL_RQ + 5];
+    r.eta_gap = std::fabs(r.pobj - r.dobj) / (1.0 + std::max(std::fabs(r.pobj), std::fabs(r.dobj)));
+  }
+  return r;
+}
+
+// Algorithm 5, step 4: argmin of f(s) = th1 s + th2/s + s^2 th3/(1 + lamQ s) by a
+// golden-section search on log s over the interval where f' changes sign; the
+// comparison of f at the two probes uses the divided difference of f.
+double golden_sigma(double th1, double th2, double th3, double lamQ) {
+  const double hi = std::sqrt(th2 / th1);
+  if (th3 <= 0.0 || lamQ <= 0.0) return hi;
+  const double lo = std::sqrt(th2 / (th1 + th3 / lamQ));
+  double a = std::log(lo), b = std::log(hi);
+  const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+  const double stop = std::log1p(1e-12);
+  for (int it = 0; it < 200 && (b - a) > stop; ++it) {
+    const double p = b - gr * (b - a), q = a + gr * (b - a);
+    const double sp = std::exp(p), sq = std::exp(q);
+    const double slope = th1 - th2 / (sp * sq) + th3 * (sp + sq + lamQ * sp * sq) / ((1.0 + lamQ * sp) * (1.0 + lamQ * sq));
+    if (slope > 0.0) b = q;   // f(p) < f(q)
+    else a = p;
+  }
+  return std::exp(0.5 * (a + b));
+}
+
+// ---------------------------------------------------------------------------
+// setup pieces
+// ---------------------------------------------------------------------------
+// Power method on A A^T (which = 0, vectors of length m) or Q (which = 1, length n):
+// v <- start/|start|; repeat w = M v, lambda = <v, w>, v <- w/|w|; stop at the first
+// iteration whose Rayleigh quotient changes by <= tol relative (Section 4.1).
+double power_method(hprqp_handle& h, int which, const double* start, int maxit, double tol, int* iters_out) {
+  const long long k = which == 0 ? h.m : h.n;
+  if (k == 0) { if (iters_out) *iters_out = 0; return 0.0; }
+  double* v = h.t1;   // current unit vector
+  double* wv = h.t2;  // product
+  double* tmpn = h.kronT ? nullptr : nullptr;
+  (void)tmpn;
+  double* mid = (which == 0) ? h.xh : nullptr;  // A^T v (n) for the A A^T case; xh is free at setup
+  if (start) k_copy<<<hq_grid(k, 256), 256, 0, h.st>>>(k, start, v, nullptr);
+  else k_fill<<<hq_grid(k, 256), 256, 0, h.st>>>(k, v, 1.0);
+  launch_elem(h, (int)k, nullptr, EpiSumSq{v}, 0, red_seq(h, SL_POW, 1));
+  final_reduce(h, SL_POW, 1);
+  HQC(hipMemcpyAsync(h.hs, h.scalars + SL_POW, sizeof(double), hipMemcpyDeviceToHost, h.st));
+  HQC(hipStreamSynchronize(h.st));
+  const double s0 = h.hs[0] > 0.0 ? 1.0 / std::sqrt(h.hs[0]) : 0.0;
+  h.hs[1] = s0;
+  HQC(hipMemcpyAsync(h.scalars + SL_TOTAL, h.hs + 1, sizeof(double), hipMemcpyHostToDevice, h.st));
+  k_scale<<<hq_grid(k, 256), 256, 0, h.st>>>(k, v, h.scalars + SL_TOTAL, v);
+  const int chunk = 16;
+  std::vector<double> hist;
+  double lam = 0.0;
+  int stop_it = -1;
+  for (int it0 = 1; it0 <= maxit && stop_it < 0; it0 += chunk) {
+    const int it1 = std::min(maxit, it0 + chunk - 1);
+    for (int it = it0; it <= it1; ++it) {
+      if (which == 0) {
+        launch_csr(h, h.AT, v, EpiStore{mid}, 0, no_red(h));
+        launch_csr(h, h.A, mid, EpiPow{v, wv}, 0, red_seq(h, SL_POW, 2));
+      } else {
+        q_apply(h, v, EpiPow{v, wv}, 0, red_seq(h, SL_POW, 2));
+      }
+      k_pow_final<<<1, 256, 0, h.st>>>(h.partials, h.counts, h.hist, it, h.scalars + SL_TOTAL);
+      k_scale<<<hq_grid(k, 256), 256, 0, h.st>>>(k, wv, h.scalars + SL_TOTAL, v);
+    }
+    std::vector<double> hh(2 * (it1 + 1));
+    HQC(hipMemcpyAsync(hh.data(), h.hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, h.st));
+    HQC(hipStreamSynchronize(h.st));
+    for (int it = it0; it <= it1; ++it) {
+      lam = hh[2 * it];
+      const double nw2 = hh[2 * it + 1];
+      if (nw2 == 0.0) { stop_it = it; break; }
+      if (it > 1 && std::fabs(lam - hh[2 * (it - 1)]) <= tol * std::fabs(lam)) { stop_it = it; break; }
+    }
+  }
+  if (iters_out) *iters_out = stop_it < 0 ? maxit : stop_it;
+  return lam;
+}
+
+void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
+  if (M.rows == 0 || M.nnz == 0) return;
+  const int Gs[] = {1, 2, 4, 8, 16, 32};
+  hipEvent_t e0, e1;
+  HQC(hipEventCreate(&e0));
+  HQC(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bestG = M.G;
+  for (int G : Gs) {
+    M.G = G;
+    launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
+    HQC(hipEventRecord(e0, h.st));
+    for (int r = 0; r < 5; ++r) launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
+    HQC(hipEventRecord(e1, h.st));
+    HQC(hipEventSynchronize(e1));
+    float ms = 0;
+    HQC(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; bestG = G; }
+  }
+  M.G = bestG;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+}
+
+int default_G(long long nnz, int rows) {
+  const double avg = rows > 0 ? (double)nnz / rows : 1.0;
+  int G = 1;
+  while (G < 64 && G * 2 <= avg) G *= 2;
+  return G;
+}
+
+void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t st, hprqp_handle** out) {
+  const double t0 = now_s();
+  if (!P || !opt || !out) fail(HPRQP_ERR_ARG, "NULL argument");
+  if (P->n <= 0 || P->m < 0) fail(HPRQP_ERR_SHAPE, "n must be > 0 and m >= 0");
+  if (!P->c || !P->L || !P->U) fail(HPRQP_ERR_ARG, "c, L, U are required");
+  if (P->m > 0 && (!P->a_rowptr || !P->l || !P->u || (P->a_nnz > 0 && (!P->a_col || !P->a_val))))
+    fail(HPRQP_ERR_ARG, "A, l, u are required when m > 0");
+  if (opt->check_every <= 0 || opt->max_iter <= 0 || !(opt->tol >= 0.0)) fail(HPRQP_ERR_ARG, "bad options");
+  if (P->a_nnz < 0 || P->a_nnz >= (1ll << 31) || P->q_nnz < 0 || P->q_nnz >= (1ll << 31))
+    fail(HPRQP_ERR_SHAPE, "nnz must fit int32");
+  auto hp = new hprqp_handle();
+  try {
+    hprqp_handle& h = *hp;
+    HQC(hipGetDevice(&h.dev));
+    if (!st) {
+      // graphs cannot be captured on the legacy null stream: use a private one
+      HQC(hipStreamCreateWithFlags(&h.own_st, hipStreamNonBlocking));
+      HQC(hipDeviceSynchronize());
+      st = h.own_st;
+    }
+    h.st = st;
+    h.n = P->n; h.m = P->m; h.qkind = P->qkind;
+    h.opt = *opt;
+    if (opt->profile_kernels)
+      for (auto& a : h.pev)
+        for (auto& b : a)
+          for (auto& e : b) HQC(hipEventCreate(&e));
+    h.c = P->c; h.L = P->L; h.U = P->U; h.l = P->l; h.u = P->u;
+    const int n = h.n, m = h.m;
+    switch (P->qkind) {
+      case HPRQP_Q_ZERO: break;
+      case HPRQP_Q_CSR:
+        if (!P->q_rowptr || (P->q_nnz > 0 && (!P->q_col || !P->q_val))) fail(HPRQP_ERR_ARG, "Q CSR arrays required");
+        h.Q = Mat{n, n, P->q_rowptr, P->q_col, P->q_val, P->q_nnz, default_G(P->q_nnz, n)};
+        break;
+      case HPRQP_Q_KRON:
+        if (!P->kron_B || !P->kron_C || P->kron_p <= 0 || P->kron_s <= 0) fail(HPRQP_ERR_ARG, "Kronecker factors required");
+        if ((long long)P->kron_p * P->kron_s != n) fail(HPRQP_ERR_SHAPE, "n must equal kron_p * kron_s");
+        h.kp = P->kron_p; h.ks = P->kron_s; h.kB = P->kron_B; h.kC = P->kron_C;
+        break;
+      case HPRQP_Q_LOWRANK:
+        if (!P->lr_d || (P->lr_rank > 0 && !P->lr_F)) fail(HPRQP_ERR_ARG, "low-rank arrays required");
+        if (P->lr_rank < 0 || P->lr_rank > 16) fail(HPRQP_ERR_UNSUPPORTED, "lr_rank must be in [0, 16]");
+        h.lr_r = P->lr_rank; h.lr_d = P->lr_d; h.lr_F = P->lr_F;
+        break;
+      default: fail(HPRQP_ERR_ARG, "unknown qkind");
+    }
+    // workspace
+    h.partials = h.dalloc<double>((size_t)SL_TOTAL * HQ_PCAP);
+    h.counts = h.dalloc<int>(SL_TOTAL);
+    h.scalars = h.dalloc<double>(SL_TOTAL + 8);
+    h.hist = h.dalloc<double>(2 * 5002);
+    h.dflags = h.dalloc<int>(1);
+    h.dprm = h.dalloc<DevParams>(1);
+    HQC(hipHostMalloc((void**)&h.hs, 64 * sizeof(double), hipHostMallocDefault));
+    HQC(hipHostMalloc((void**)&h.hp, sizeof(DevParams), hipHostMallocDefault));
+    k_zero_ints<<<1, 64, 0, st>>>(SL_TOTAL, h.counts);
+    k_zero_ints<<<1, 64, 0, st>>>(1, h.dflags);
+    double** nv[] = {&h.w, &h.wa, &h.x, &h.xa, &h.ATy, &h.ATya, &h.Qw, &h.Qwa, &h.xh, &h.v, &h.q1, &h.d, &h.g,
+                     &h.e, &h.XB, &h.ZB, &h.wbar, &h.qwbar, &h.xbo, &h.zbo, &h.t1, &h.t2};
+    for (double** p : nv) *p = h.dalloc<double>(n);
+    if (h.qkind == HPRQP_Q_KRON) h.kronT = h.dalloc<double>(n);
+    double** mv[] = {&h.y, &h.ya, &h.ybar, &h.tm};
+    for (double** p : mv) *p = h.dalloc<double>(std::max(m, 1));
+    for (double** p : nv) k_fill<<<hq_grid(n, 256), 256, 0, st>>>(n, *p, 0.0);
+    for (double** p : mv) k_fill<<<hq_grid(std::max(m, 1), 256), 256, 0, st>>>(std::max(m, 1), *p, 0.0);
+    // validation
+    k_validate_vec<<<hq_grid(n, 256), 256, 0, st>>>(n, h.L, h.U, h.c, h.dflags);
+    if (m > 0) {
+      k_validate_vec<<<hq_grid(m, 256), 256, 0, st>>>(m, h.l, h.u, nullptr, h.dflags);
+      k_validate_csr<<<hq_grid(m, 256), 256, 0, st>>>(m, n, P->a_nnz, P->a_rowptr, P->a_col, P->a_val, h.dflags);
+    }
+    if (h.qkind == HPRQP_Q_CSR)
+      k_validate_csr<<<hq_grid(n, 256), 256, 0, st>>>(n, n, P->q_nnz, P->q_rowptr, P->q_col, P->q_val, h.dflags);
+    if (h.qkind == HPRQP_Q_KRON) {
+      k_validate_finite<<<64, 256, 0, st>>>((long long)h.kp * h.kp, h.kB, h.dflags);
+      k_validate_finite<<<64, 256, 0, st>>>((long long)h.ks * h.ks, h.kC, h.dflags);
+    }
+    if (h.qkind == HPRQP_Q_LOWRANK) {
+      k_validate_finite<<<64, 256, 0, st>>>(n, h.lr_d, h.dflags);
+      k_validate_finite<<<256, 256, 0, st>>>((long long)n * h.lr_r, h.lr_F, h.dflags);
+    }
+    int flags = 0;
+    HQC(hipMemcpyAsync(&flags, h.dflags, sizeof(int), hipMemcpyDeviceToHost, st));
+    HQC(hipStreamSynchronize(st));
+    if (flags & 2) fail(HPRQP_ERR_SHAPE, "CSR structure invalid (rowptr not monotone / not ending at nnz, or column out of range)");
+    if (flags & 1) fail(HPRQP_ERR_BOUNDS, "invalid bounds (l > u, L > U, NaN, wrong-sided infinity) or non-finite data");
+    // A and explicit A^T
+    if (m > 0) {
+      h.A = Mat{m, n, P->a_rowptr, P->a_col, P->a_val, P->a_nnz, default_G(P->a_nnz, m)};
+      h.at_rp = h.dalloc<int>(n + 1);
+      h.at_ci = h.dalloc<int>(P->a_nnz);
+      h.at_v = h.dalloc<double>(P->a_nnz);
+      HQC(hq_build_transpose(m, n, P->a_nnz, P->a_rowptr, P->a_col, P->a_val, h.at_rp, h.at_ci, h.at_v, st));
+      h.AT = Mat{n, m, h.at_rp, h.at_ci, h.at_v, P->a_nnz, default_G(P->a_nnz, n)};
+    }
+    // lambda's: needed by the params of every kernel, also during the power method
+    h.lamA = 0; h.lamQ = 0;
+    write_params(h, 1.0, 0);
+    if (opt->spmv_autotune) {
+      if (m > 0) {
+        autotune_csr(h, h.A, h.t1, h.tm);
+        autotune_csr(h, h.AT, h.tm, h.t1);
+      }
+      if (h.qkind == HPRQP_Q_CSR) autotune_csr(h, h.Q, h.t1, h.t2);
+    }
+    if (opt->lambda_A > 0) h.lamA = opt->lambda_A;
+    else if (m > 0) {
+      h.powA_est = power_method(h, 0, opt->power_start_A, 5000, 1e-6, &h.powA_it);
+      h.lamA = 1.01 * h.powA_est;
+    }
+    if (opt->lambda_Q > 0) h.lamQ = opt->lambda_Q;
+    else if (h.qkind != HPRQP_Q_ZERO) {
+      h.powQ_est = power_method(h, 1, opt->power_start_Q, 5000, 1e-6, &h.powQ_it);
+      h.lamQ = 1.01 * h.powQ_est;
+    }
+    if (m > 0 && !(h.lamA > 0.0)) fail(HPRQP_ERR_ARG, "lambda_A must be positive (A = 0?)");
+    // norms of b and c: sigma0 rule and the denominators of eta_p, eta_d
+    if (m > 0) launch_elem(h, m, nullptr, EpiNormB{h.l, h.u}, 0, red_seq(h, SL_NRM, 2));
+    launch_elem(h, n, nullptr, EpiNormC{h.c}, 0, red_seq(h, SL_NRM + 2, 2));
+    // EpiNormC writes (sum c^2, max|c|) into slots NRM+2, NRM+3
+    final_reduce(h, SL_NRM, 4);
+    HQC(hipMemcpyAsync(h.hs, h.scalars + SL_NRM, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HQC(hipStreamSynchronize(st));
+    const double nb = m > 0 ? std::sqrt(h.hs[0]) : 0.0, nc = std::sqrt(h.hs[2]);
+    h.binf = m > 0 ? h.hs[1] : 0.0;
+    h.cinf = h.hs[3];
+    if (opt->sigma0 > 0) h.sigma0 = opt->sigma0;
+    else if (nb >= 1e-16 && nb <= 1e16 && nc >= 1e-16 && nc <= 1e16) h.sigma0 = nb / nc;
+    else h.sigma0 = 1.0;
+    HQC(hipStreamSynchronize(st));
+    h.t_setup = now_s() - t0;
+    *out = hp;
+  } catch (...) {
+    delete hp;
+    throw;
+  }
+}
+
+void copy_or_zero(hprqp_handle& h, long long k, const double* src, double* dst) {
+  if (src) k_copy<<<hq_grid(k, 256), 256, 0, h.st>>>(k, src, dst, nullptr);
+  else k_fill<<<hq_grid(k, 256), 256, 0, h.st>>>(k, dst, 0.0);
+}
+
+void trace_row(hprqp_handle& h, double* row) {
+  const int n = h.n, m = h.m;
+  HQC(hipStreamSynchronize(h.st));
+  HQC(hipMemcpy(row, h.y, m * sizeof(double), hipMemcpyDeviceToHost)); row += m;
+  HQC(hipMemcpy(row, h.w, n * sizeof(double), hipMemcpyDeviceToHost)); row += n;
+  HQC(hipMemcpy(row, h.x, n * sizeof(double), hipMemcpyDeviceToHost)); row += n;
+  HQC(hipMemcpy(row, h.ybar, m * sizeof(double), hipMemcpyDeviceToHost)); row += m;
+  HQC(hipMemcpy(row, h.wbar, n * sizeof(double), hipMemcpyDeviceToHost)); row += n;
+  HQC(hipMemcpy(row, h.xbo, n * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const double* x0, double* yo, double* zo,
+                double* wo, double* xo, hprqp_info* info) {
+  const double tstart = now_s();
+  if (h.own_st) HQC(hipDeviceSynchronize());   // inputs written on other streams
+  for (int kind = 0; kind < 4; ++kind) { h.prof_ms[kind] = 0.0; h.prof_n[kind] = 0; }
+  const hprqp_options& o = h.opt;
+  const int n = h.n, m = h.m;
+  const int T = o.check_every;
+  const bool tracing = o.trace_iters > 0 && o.trace_host;
+  if (!yo && m > 0) fail(HPRQP_ERR_ARG, "output y required");
+  if (!zo || !wo || !xo) fail(HPRQP_ERR_ARG, "outputs z, w, x required");
+  if (m > 0) copy_or_zero(h, m, y0, h.y);
+  copy_or_zero(h, n, w0, h.w);
+  copy_or_zero(h, n, x0, h.x);
+  double sigma = h.sigma0;
+  write_params(h, sigma, 0);
+  reset_epoch(h);
+  long long k = 0, t = 0;
+  int r = 0, term = -1, nlog = 0;
+  double alpha3 = o.alpha3, R0ref = -1.0, Rr0 = -1.0, Rprev = -1.0, R = 0.0;
+  Resid res{};
+  const int rowlen = 2 * m + 4 * n;
+  while (term < 0) {
+    const int Tseg = (int)std::min<long long>(T, o.max_iter - k);
+    write_params(h, sigma, t);
+    if (tracing && k < o.trace_iters) {
+      for (int j = 0; j < Tseg; ++j) {
+        enqueue_iter(h, j, Tseg, true);
+        if (j < Tseg - 1 && k + j + 1 <= o.trace_iters) trace_row(h, o.trace_host + (size_t)(k + j) * rowlen);
+      }
+      final_reduce(h, 0, SL_ITER_END);
+      HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
+    } else if (o.use_graph && Tseg == T) {
+      if (!h.gexec || h.graph_T != T) {
+        if (h.gexec) { hipGraphExecDestroy(h.gexec); h.gexec = nullptr; }
+        if (h.graph) { hipGraphDestroy(h.graph); h.graph = nullptr; }
+        HQC(hipStreamBeginCapture(h.st, hipStreamCaptureModeThreadLocal));
+        enqueue_segment(h, T);
+        HQC(hipStreamEndCapture(h.st, &h.graph));
+        HQC(hipGraphInstantiate(&h.gexec, h.graph, nullptr, nullptr, 0));
+        h.graph_T = T;
+      }
+      HQC(hipGraphLaunch(h.gexec, h.st));
+    } else {
+      enqueue_segment(h, Tseg);
+    }
+    HQC(hipStreamSynchronize(h.st));
+    if (o.profile_kernels && Tseg >= 4 && !(tracing && k < o.trace_iters)) {
+      for (int ps = 0; ps < 2; ++ps)
+        for (int kind = 0; kind < 4; ++kind) {
+          if (m == 0 && (kind == 1 || kind == 2)) continue;
+          float ms = 0.f;
+          HQC(hipEventElapsedTime(&ms, h.pev[ps][kind][0], h.pev[ps][kind][1]));
+          h.prof_ms[kind] += ms;
+          h.prof_n[kind] += 1;
+        }
+    }
+    const double* S = h.hs;
+    if (t == 0) Rr0 = mnorm(h, S + (Tseg == 1 ? SL_RC : SL_RF), sigma);
+    R = mnorm(h, S + SL_RC, sigma);
+    res = residuals_from(h, S);
+    const double th_slots[5] = {S[SL_TH], S[SL_TH + 1], S[SL_TH + 2], S[SL_TH + 3], S[SL_TH + 4]};
+    k += Tseg;
+    t += Tseg;
+    const long long t_check = t;
+    const double kkt = std::max(res.eta_p, std::max(res.eta_d, res.eta_gap));
+    const double sigma_used = sigma;
+    int restarted = 0;
+    bool do_restart = false;
+    if (std::isnan(kkt) || std::isnan(R)) term = HPRQP_NUMERICAL;
+    else if (kkt <= o.tol) term = HPRQP_SOLVED;
+    else if (k >= o.max_iter) term = HPRQP_MAX_ITER;
+    else if (o.time_limit_s > 0 && now_s() - tstart >= o.time_limit_s) term = HPRQP_TIME_LIMIT;
+    else if (o.enable_restart) {
+      const bool c1 = R <= o.alpha1 * Rr0;                                   // eq:restart_1
+      const bool c2 = Rprev >= 0.0 && R <= o.alpha2 * Rr0 && R > Rprev;      // eq:restart_2
+      const bool c3 = (double)t >= alpha3 * (double)k;                       // eq:restart_3
+      do_restart = c1 || c2 || c3;
+    }
+    Rprev = R;
+    if (term < 0 && do_restart) {
+      if (R0ref < 0.0) R0ref = R;
+      const double ratio = R / R0ref;
+      if (o.enable_sigma_update) {
+        double th1 = h.lamA * th_slots[0] + h.lamQ * th_slots[1] - 2.0 * th_slots[2];
+        double th2 = th_slots[3], th3 = th_slots[4];
+        th1 = std::max(th1, 1e-12);
+        th2 = std::max(th2, 1e-12);
+        th3 = std::max(th3, 0.0);
+        const double snew = golden_sigma(th1, th2, th3, h.lamQ);
+        const double beta = std::exp(-ratio);
+        sigma = std::exp(beta * std::log(snew) + (1.0 - beta) * std::log(sigma));
+      }
+      if (ratio <= 0.1) alpha3 = 0.2;
+      // u^{r+1,0} = ubar
+      if (m > 0) k_copy<<<hq_grid(m, 256), 256, 0, h.st>>>(m, h.ybar, h.y, nullptr);
+      k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.wbar, h.w, nullptr);
+      k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.xbo, h.x, nullptr);
+      write_params(h, sigma, 0);
+      reset_epoch(h);
+      t = 0;
+      Rprev = -1.0;
+      r += 1;
+      restarted = 1;
+    }
+    if (tracing && k <= o.trace_iters) trace_row(h, o.trace_host + (size_t)(k - 1) * rowlen);
+    if (o.check_log_host && nlog < o.log_cap) {
+      double* row = o.check_log_host + 10 * (size_t)nlog;
+      row[0] = (double)k; row[1] = (double)t_check;
+      row[2] = R; row[3] = res.eta_p; row[4] = res.eta_d; row[5] = res.eta_gap;
+      row[6] = sigma_used; row[7] = restarted; row[8] = sigma; row[9] = r;
+      ++nlog;
+    }
+  }
+  // output ubar of the last iteration
+  if (m > 0) k_copy<<<hq_grid(m, 256), 256, 0, h.st>>>(m, h.ybar, yo, nullptr);
+  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.zbo, zo, nullptr);
+  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.wbar, wo, nullptr);
+  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.xbo, xo, nullptr);
+  HQC(hipStreamSynchronize(h.st));
+  if (info) {
+    info->term = term; info->iters = k; info->restarts = r; info->n_log = nlog;
+    info->sigma = sigma; info->sigma0 = h.sigma0; info->lambda_A = h.lamA; info->lambda_Q = h.lamQ;
+    info->eta_p = res.eta_p; info->eta_d = res.eta_d; info->eta_gap = res.eta_gap;
+    info->pobj = res.pobj; info->dobj = res.dobj; info->R_last = R;
+    info->t_setup_s = h.t_setup; info->t_solve_s = now_s() - tstart;
+  }
+}
+
+void residuals_impl(hprqp_handle& h, const double* y, const double* z, const double* x, double* out) {
+  if (!z || !x || (h.m > 0 && !y) || !out) fail(HPRQP_ERR_ARG, "NULL argument");
+  write_params(h, h.sigma0, 0);
+  k_zero_ints<<<1, 64, 0, h.st>>>(SL_ITER_END, h.counts);
+  if (h.m > 0) {
+    launch_csr(h, h.AT, y, EpiStore{h.t2}, 0, no_red(h));
+    launch_csr(h, h.A, x, EpiResA{h.l, h.u, y}, 0, red_seq(h, SL_RA, 4));
+  }
+  q_apply(h, x, EpiResQ{x, z, h.m > 0 ? h.t2 : nullptr, h.c, h.L, h.U, nullptr, nullptr}, 0, red_seq(h, SL_RQ, 7));
+  final_reduce(h, 0, SL_ITER_END);
+  HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
+  HQC(hipStreamSynchronize(h.st));
+  const Resid r = residuals_from(h, h.hs);
+  out[0] = r.eta_p; out[1] = r.eta_d; out[2] = r.eta_gap; out[3] = r.pobj; out[4] = r.dobj;
+}
+
+void apply_impl(hprqp_handle& h, int op, const double* in, double* out) {
+  if (!in || !out) fail(HPRQP_ERR_ARG, "NULL argument");
+  write_params(h, h.sigma0, 0);
+  if (op == 0) q_apply(h, in, EpiStore{out}, 0, no_red(h));
+  else if (op == 1 && h.m > 0) launch_csr(h, h.A, in, EpiStore{out}, 0, no_red(h));
+  else if (op == 2 && h.m > 0) launch_csr(h, h.AT, in, EpiStore{out}, 0, no_red(h));
+  else if (op == 2) k_fill<<<hq_grid(h.n, 256), 256, 0, h.st>>>(h.n, out, 0.0);
+  else if (op != 1) fail(HPRQP_ERR_ARG, "op must be 0 (Q), 1 (A) or 2 (A^T)");
+  HQC(hipStreamSynchronize(h.st));
+}
+
+}  // namespace hq
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#define HQ_GUARD(body)                                   \
+  try {                                                  \
+    hq::g_err.clear();                                   \
+    body;                                                \
+    return HPRQP_OK;                                     \
+  } catch (const hq::Error& e) {                         \
+    hq::g_err = e.msg;                                   \
+    return e.st;                                         \
+  } catch (const std::exception& e) {                    \
+    hq::g_err = e.what();                                \
+    return HPRQP_ERR_HIP;                                \
+  }
+
+extern "C" {
+
+void hprqp_default_options(hprqp_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->max_iter = 1000000;
+  o->time_limit_s = 3600.0;
+  o->check_every = 100;
+  o->alpha1 = 0.2; o->alpha2 = 0.8; o->alpha3 = 0.5;
+  o->enable_restart = 1;
+  o->enable_sigma_update = 1;
+  o->use_graph = 1;
+  o->spmv_autotune = 0;
+}
+
+hprqp_status hprqp_create(const hprqp_problem* prob, const hprqp_options* opt, hipStream_t stream,
+                          hprqp_handle** out) {
+  HQ_GUARD(hq::create_impl(prob, opt, stream, out));
+}
+
+hprqp_status hprqp_solve(hprqp_handle* h, const double* y0, const double* w0, const double* x0, double* y, double* z,
+                         double* w, double* x, hprqp_info* info) {
+  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); hq::solve_impl(*h, y0, w0, x0, y, z, w, x, info));
+}
+
+hprqp_status hprqp_residuals(hprqp_handle* h, const double* y, const double* z, const double* x, double* out_host) {
+  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); hq::residuals_impl(*h, y, z, x, out_host));
+}
+
+hprqp_status hprqp_apply(hprqp_handle* h, int32_t op, const double* in, double* out) {
+  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); hq::apply_impl(*h, op, in, out));
+}
+
+hprqp_status hprqp_power_info(hprqp_handle* h, double* est_A, int32_t* it_A, double* est_Q, int32_t* it_Q) {
+  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); if (est_A) *est_A = h->powA_est;
+           if (it_A) *it_A = h->powA_it; if (est_Q) *est_Q = h->powQ_est; if (it_Q) *it_Q = h->powQ_it);
+}
+
+hprqp_status hprqp_kernel_stats(hprqp_handle* h, double* avg_ms, int64_t* launches, int32_t* g) {
+  HQ_GUARD(if (!h || !avg_ms || !launches) hq::fail(HPRQP_ERR_ARG, "NULL argument");
+           for (int k = 0; k < 4; ++k) {
+             launches[k] = h->prof_n[k];
+             avg_ms[k] = h->prof_n[k] ? h->prof_ms[k] / (double)h->prof_n[k] : 0.0;
+           } if (g) { g[0] = h->A.G; g[1] = h->AT.G; g[2] = h->Q.G; });
+}
+
+void hprqp_destroy(hprqp_handle* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""HPR-QP throughput on one MI355X.
+
+Workload (default): the random sparse QP with n = 1,000,000 variables and
+m = 500,000 rows (A: 10 nonzeros per row at uniformly random columns,
+Q = D + S with ~5 nonzeros per row, half the rows equalities, box [0, 10]),
+FP64, seeded synthetic data.
+
+A "step" is one check segment: `check_every` = 100 iterations of
+Algorithm 4 (every product, projection, Halpern update and the merit /
+stopping reductions of the check) plus the host's restart / sigma decision.
+The timed region is one hprqp_solve call of K segments started from the
+origin, inputs already resident in HBM.
+
+Printed: ONE JSON line with iterations/s (value), the roofline of the
+dominant kernel (HIP-event durations measured during the timed region),
+the time to 1e-8 relative KKT, and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+T_CHECK = 100
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(qp) -> dict:
+    """Algorithmic bytes per launch of the four per-iteration products.
+
+    CSR data: 12 B per nonzero (8 B value + 4 B column) + 4 B per row pointer;
+    the gathered input vector counts once (8 B per entry); every streamed
+    vector read or written by the fused epilogue counts 8 B per entry."""
+    n, m = qp.n, qp.m
+    nzA, nzQ = qp.a_nnz, qp.q_nnz
+    return {
+        # Q xhat: Q, xhat (gathered), Qw; writes v, q1
+        "q_xhat": 12 * nzQ + 4 * (n + 1) + 8 * n + 8 * n + 16 * n,
+        # A v: A, v (gathered); reads y, y_a, l, u; writes ybar, y
+        "a_v": 12 * nzA + 4 * (m + 1) + 8 * n + 32 * m + 16 * m,
+        # A^T ybar: A^T, ybar (gathered); reads ATy, ATy_a; writes d, ATy
+        "at_ybar": 12 * nzA + 4 * (n + 1) + 8 * m + 16 * n + 16 * n,
+        # Q d + Halpern + next z/x step: Q, d (gathered); reads xhat, w, Qw, q1,
+        # w_a, Qw_a, x_a, ATy, c, L, U; writes w, Qw, xhat
+        "q_d_halpern": 12 * nzQ + 4 * (n + 1) + 8 * n + 88 * n + 24 * n,
+    }
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2507_02470_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM traffic per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("src_hash") != src_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(qp, lam_A, lam_Q, sigma0, iters):
+    """The oracle as it stands, single thread, on the first `iters` iterations."""
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.solve(qp, tol=0.0, max_iter=iters, check_every=T_CHECK, lambda_A=lam_A, lambda_Q=lam_Q,
+                     sigma0=sigma0)
+    dt = time.perf_counter() - t0
+    return dict(value=r.iters / dt, unit="iterations/s", cores=1, kind="oracle",
+                sample=f"first {r.iters} iterations of the same instance (single-threaded FP64 C, "
+                       f"lambda's and sigma0 given), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="random_large", choices=["random_large", "small_ccqp", "kron"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tol-solve", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--tol-time-limit", type=float, default=120.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the HPR-QP path here is "
+              f"single-GPU, see the multi-GPU design notes", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import qpgen
+    from paper_2507_02470_amd.solver import DeviceProblem, Solver
+
+    t0 = time.perf_counter()
+    if args.workload == "random_large":
+        qp = qpgen.make_random_large()
+        wl = dict(workload="random_large", n=qp.n, m=qp.m, nnz_A=qp.a_nnz, nnz_Q=qp.q_nnz, seed=1001)
+    elif args.workload == "kron":
+        qp = qpgen.make_kron()
+        wl = dict(workload="kron_assignment", n=qp.n, m=qp.m, d=300, seed=1002)
+    else:
+        qp = qpgen.make_small_ccqp()
+        wl = dict(workload="small_ccqp", n=qp.n, m=qp.m, seed=1000)
+    log(f"generated {wl} in {time.perf_counter() - t0:.1f}s")
+    dp = DeviceProblem(qp)
+    torch.cuda.synchronize()
+    s = Solver(dp, power_start_A=qpgen.power_start(qp.m), power_start_Q=qpgen.power_start(qp.n),
+               check_every=T_CHECK, tol=0.0, max_iter=max(1, args.warmup) * T_CHECK, spmv_autotune=1,
+               profile_kernels=0)
+    pi = s.power_info()
+    log(f"create: power A {pi['it_A']} its, Q {pi['it_Q']} its")
+    # warmup (also captures the segment graph)
+    s.solve()
+    torch.cuda.synchronize()
+    # timed region
+    K = args.steps
+    s.set_options(tol=0.0, max_iter=K * T_CHECK, profile_kernels=1, time_limit_s=0.0)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = s.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ta
+    its = r.iters
+    value = its / dt
+    log(f"timed: {its} iterations in {dt:.3f}s -> {value:.1f} it/s (restarts {r.restarts})")
+    ks = s.kernel_stats()
+    log(f"kernel stats: {ks}")
+
+    # roofline of the dominant kernel (largest share of timed kernel time)
+    by = kernel_bytes(qp) if qp.qkind == "csr" else None
+    roofline = None
+    if by is not None:
+        dom = max(ks["avg_ms"], key=lambda k: ks["avg_ms"][k])
+        avg_s = ks["avg_ms"][dom] * 1e-3
+        achieved = by[dom] / avg_s / 1e9
+        traffic = read_traffic(dom, wl["workload"])
+        roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                        algorithmic_bytes_per_launch=by[dom], avg_launch_us=round(avg_s * 1e6, 2),
+                        launches_timed=ks["launches"][dom])
+        iter_bytes = sum(by.values())
+        kern_s = sum(ks["avg_ms"].values()) * 1e-3
+        roofline["iteration"] = dict(algorithmic_bytes=iter_bytes,
+                                     kernel_GBps=round(iter_bytes / kern_s / 1e9, 1),
+                                     wall_GBps=round(iter_bytes * value / 1e9, 1))
+    # time to 1e-8 relative KKT (power method + setup included)
+    tol_run = None
+    if not args.no_tol_solve:
+        s.set_options(tol=1e-8, max_iter=2_000_000, profile_kernels=0, time_limit_s=args.tol_time_limit)
+        rt = s.solve()
+        tol_run = dict(term=rt.term, iterations=rt.iters, kkt=rt.kkt, restarts=rt.restarts,
+                       t_setup_s=round(rt.t_setup_s, 4), t_solve_s=round(rt.t_solve_s, 4),
+                       time_to_tol_s=round(rt.t_setup_s + rt.t_solve_s, 4), pobj=rt.pobj)
+        log(f"to 1e-8: {tol_run}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(qp, r.lambda_A, r.lambda_Q, r.sigma0, args.cpu_iters)
+        log(f"cpu baseline: {cpu}")
+    out = {
+        "metric": "HPR-QP iterations/s (FP64, relative-KKT stopping test every 100 iterations)",
+        "value": round(value, 2),
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator, shapes of the random QP class)",
+        "config": dict(wl, step=f"{T_CHECK} iterations + check", lanes_per_row=ks["lanes_per_row"]),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "time_to_1e-8": tol_run,
+    }
+    print(json.dumps(out))
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

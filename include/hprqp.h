@@ -137,6 +137,12 @@ hprqp_status hprqp_create(const hprqp_problem *prob, const hprqp_options *opt,
 hprqp_status hprqp_solve(hprqp_handle *h, const double *y0, const double *w0, const double *x0,
                          double *y, double *z, double *w, double *x, hprqp_info *info);
 
+/* Replaces the per-solve options of a handle (tol, max_iter, time limit,
+ * check_every, alpha's, restart/sigma switches, graph use, trace/log
+ * buffers, kernel timing).  The setup-time choices made by hprqp_create
+ * (lambda_A, lambda_Q, sigma0, power-method start, SpMV tuning) are kept. */
+hprqp_status hprqp_set_options(hprqp_handle *h, const hprqp_options *opt);
+
 /* Stopping quantities of Section 4.1 at the point (y, z, x):
  * out_host[0..4] = eta_p, eta_d, eta_gap, primal objective, dual objective. */
 hprqp_status hprqp_residuals(hprqp_handle *h, const double *y, const double *z, const double *x,

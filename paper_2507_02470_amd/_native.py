@@ -47,7 +47,7 @@ class hprqp_info(C.Structure):
 
 
 EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_apply",
-           "hprqp_power_info", "hprqp_kernel_stats", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
+           "hprqp_power_info", "hprqp_kernel_stats", "hprqp_set_options", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
            "hprqp_batch_last_kernel_s", "hprqp_batch_destroy", "hprqp_last_error")
 
 _lib = None
@@ -70,6 +70,9 @@ def load():
     lib.hprqp_power_info.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     lib.hprqp_kernel_stats.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    lib.hprqp_kernel_stats.restype = C.c_int
+    lib.hprqp_set_options.argtypes = [_vp, C.POINTER(hprqp_options)]
+    lib.hprqp_set_options.restype = C.c_int
     lib.hprqp_destroy.argtypes = [_vp]
     lib.hprqp_destroy.restype = None
     lib.hprqp_last_error.restype = C.c_char_p

@@ -355,13 +355,13 @@ void write_params(hprqp_handle& h, double sigma, long long t0) {
 }
 
 // One iteration (index j of a segment of Tseg iterations; the last one is a check).
-void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace) {
+void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
   const bool check = (j == Tseg - 1);
   const int rgroup = check ? SL_RC : (j == 0 ? SL_RF : -1);
   const bool want_r = rgroup >= 0;
   const bool xb_next = trace || (j >= Tseg - 2);
   int ps = -1;  // timing sample index of this iteration
-  if (h.opt.profile_kernels && !trace && Tseg >= 4) ps = (j == Tseg / 3) ? 0 : (j == (2 * Tseg) / 3 ? 1 : -1);
+  if (prof && !trace && Tseg >= 4) ps = (j == Tseg / 3) ? 0 : (j == (2 * Tseg) / 3 ? 1 : -1);
   auto mark = [&](int kind, int edge) {
     if (ps >= 0) HQC(hipEventRecord(h.pev[ps][kind][edge], h.st));
   };
@@ -410,8 +410,8 @@ void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace) {
     q_apply(h, h.e, EpiTheta3{h.e}, j, red_seq(h, SL_TH + 4, 1));
 }
 
-void enqueue_segment(hprqp_handle& h, int Tseg) {
-  for (int j = 0; j < Tseg; ++j) enqueue_iter(h, j, Tseg, false);
+void enqueue_segment(hprqp_handle& h, int Tseg, bool prof) {
+  for (int j = 0; j < Tseg; ++j) enqueue_iter(h, j, Tseg, false, prof);
   final_reduce(h, 0, SL_ITER_END);
   HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
 }
@@ -743,32 +743,37 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
   double alpha3 = o.alpha3, R0ref = -1.0, Rr0 = -1.0, Rprev = -1.0, R = 0.0;
   Resid res{};
   const int rowlen = 2 * m + 4 * n;
+  long long seg = 0;
   while (term < 0) {
     const int Tseg = (int)std::min<long long>(T, o.max_iter - k);
+    // kernel timing: every 4th segment is launched directly with HIP events
+    // around the four products (event nodes inside a replayed graph cannot be
+    // read back); the other segments replay the captured graph
+    const bool prof = o.profile_kernels && Tseg >= 4 && (seg++ % 4) == 1 && !(tracing && k < o.trace_iters);
     write_params(h, sigma, t);
     if (tracing && k < o.trace_iters) {
       for (int j = 0; j < Tseg; ++j) {
-        enqueue_iter(h, j, Tseg, true);
+        enqueue_iter(h, j, Tseg, true, false);
         if (j < Tseg - 1 && k + j + 1 <= o.trace_iters) trace_row(h, o.trace_host + (size_t)(k + j) * rowlen);
       }
       final_reduce(h, 0, SL_ITER_END);
       HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
-    } else if (o.use_graph && Tseg == T) {
+    } else if (o.use_graph && Tseg == T && !prof) {
       if (!h.gexec || h.graph_T != T) {
         if (h.gexec) { hipGraphExecDestroy(h.gexec); h.gexec = nullptr; }
         if (h.graph) { hipGraphDestroy(h.graph); h.graph = nullptr; }
         HQC(hipStreamBeginCapture(h.st, hipStreamCaptureModeThreadLocal));
-        enqueue_segment(h, T);
+        enqueue_segment(h, T, false);
         HQC(hipStreamEndCapture(h.st, &h.graph));
         HQC(hipGraphInstantiate(&h.gexec, h.graph, nullptr, nullptr, 0));
         h.graph_T = T;
       }
       HQC(hipGraphLaunch(h.gexec, h.st));
     } else {
-      enqueue_segment(h, Tseg);
+      enqueue_segment(h, Tseg, prof);
     }
     HQC(hipStreamSynchronize(h.st));
-    if (o.profile_kernels && Tseg >= 4 && !(tracing && k < o.trace_iters)) {
+    if (prof) {
       for (int ps = 0; ps < 2; ++ps)
         for (int kind = 0; kind < 4; ++kind) {
           if (m == 0 && (kind == 1 || kind == 2)) continue;
@@ -882,10 +887,10 @@ void apply_impl(hprqp_handle& h, int op, const double* in, double* out) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-#define HQ_GUARD(body)                                   \
+#define HQ_GUARD(...)                                    \
   try {                                                  \
     hq::g_err.clear();                                   \
-    body;                                                \
+    __VA_ARGS__;                                         \
     return HPRQP_OK;                                     \
   } catch (const hq::Error& e) {                         \
     hq::g_err = e.msg;                                   \
@@ -932,6 +937,27 @@ hprqp_status hprqp_apply(hprqp_handle* h, int32_t op, const double* in, double* 
 hprqp_status hprqp_power_info(hprqp_handle* h, double* est_A, int32_t* it_A, double* est_Q, int32_t* it_Q) {
   HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); if (est_A) *est_A = h->powA_est;
            if (it_A) *it_A = h->powA_it; if (est_Q) *est_Q = h->powQ_est; if (it_Q) *it_Q = h->powQ_it);
+}
+
+hprqp_status hprqp_set_options(hprqp_handle* h, const hprqp_options* opt) {
+  HQ_GUARD(
+      if (!h || !opt) hq::fail(HPRQP_ERR_ARG, "NULL argument");
+      if (opt->check_every <= 0 || opt->max_iter <= 0 || !(opt->tol >= 0.0)) hq::fail(HPRQP_ERR_ARG, "bad options");
+      if (opt->profile_kernels && !h->pev[0][0][0])
+        for (auto& a : h->pev)
+          for (auto& b : a)
+            for (auto& e : b) HQC(hipEventCreate(&e));
+      // setup-time choices (lambda's, sigma0, power start, autotune) keep their values
+      const double la = h->opt.lambda_A, lq = h->opt.lambda_Q, s0 = h->opt.sigma0;
+      const double *pa = h->opt.power_start_A, *pq = h->opt.power_start_Q;
+      const int at = h->opt.spmv_autotune;
+      // the captured segment depends on the options (length, timing events): capture again
+      if (h->gexec) { hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+      if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
+      h->graph_T = 0;
+      h->opt = *opt;
+      h->opt.lambda_A = la; h->opt.lambda_Q = lq; h->opt.sigma0 = s0;
+      h->opt.power_start_A = pa; h->opt.power_start_Q = pq; h->opt.spmv_autotune = at);
 }
 
 hprqp_status hprqp_kernel_stats(hprqp_handle* h, double* avg_ms, int64_t* launches, int32_t* g) {

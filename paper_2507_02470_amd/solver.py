@@ -138,6 +138,14 @@ class Solver:
                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
 
+    def set_options(self, **kw):
+        """Change per-solve options (hprqp_set_options); setup choices stay."""
+        for k, v in kw.items():
+            if not hasattr(self.opts, k):
+                raise KeyError(k)
+            setattr(self.opts, k, v)
+        N.check(self.lib.hprqp_set_options(self.h, C.byref(self.opts)))
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.hprqp_destroy(self.h)

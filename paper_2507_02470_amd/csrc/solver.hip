@@ -179,6 +179,11 @@ __global__ void k_validate_finite(long long n, const double* v, int* flags) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     if (!isfinite(v[i])) atomicOr(flags, 1);
 }
+__global__ void k_max_row_len(int rows, const int* rp, int* out) {
+  int mx = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += gridDim.x * blockDim.x) mx = max(mx, rp[i + 1] - rp[i]);
+  atomicMax(out, mx);
+}
 __global__ void k_validate_csr(int rows, int cols, long long nnz, const int* rp, const int* ci, const double* v,
                                int* flags) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += gridDim.x * blockDim.x) {
@@ -291,6 +296,7 @@ void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, 
   const int grid = hq_grid(M.rows, HQ_BLOCK);
   hipStream_t st = h.st;
   switch (M.G) {
+    case 0: k_csr_stream<Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
     case 1: k_csr<1, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
     case 2: k_csr<2, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
     case 4: k_csr<4, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
@@ -537,7 +543,7 @@ double power_method(hprqp_handle& h, int which, const double* start, int maxit, 
 
 void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   if (M.rows == 0 || M.nnz == 0) return;
-  const int Gs[] = {1, 2, 4, 8, 16, 32};
+  const int Gs[] = {0, 2, 4, 8, 16, 32, 64};
   hipEvent_t e0, e1;
   HQC(hipEventCreate(&e0));
   HQC(hipEventCreate(&e1));
@@ -559,8 +565,11 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   hipEventDestroy(e1);
 }
 
-int default_G(long long nnz, int rows) {
+// Lanes per row of the row-split kernel, or 0 for the CSR-stream kernel
+// (short rows: average up to 32 nonzeros and none longer than 4096).
+int default_G(long long nnz, int rows, int maxlen) {
   const double avg = rows > 0 ? (double)nnz / rows : 1.0;
+  if (avg <= 32.0 && maxlen <= 4096) return 0;
   int G = 1;
   while (G < 64 && G * 2 <= avg) G *= 2;
   return G;
@@ -599,7 +608,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       case HPRQP_Q_ZERO: break;
       case HPRQP_Q_CSR:
         if (!P->q_rowptr || (P->q_nnz > 0 && (!P->q_col || !P->q_val))) fail(HPRQP_ERR_ARG, "Q CSR arrays required");
-        h.Q = Mat{n, n, P->q_rowptr, P->q_col, P->q_val, P->q_nnz, default_G(P->q_nnz, n)};
+        h.Q = Mat{n, n, P->q_rowptr, P->q_col, P->q_val, P->q_nnz, 0};
         break;
       case HPRQP_Q_KRON:
         if (!P->kron_B || !P->kron_C || P->kron_p <= 0 || P->kron_s <= 0) fail(HPRQP_ERR_ARG, "Kronecker factors required");
@@ -655,13 +664,25 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
     if (flags & 1) fail(HPRQP_ERR_BOUNDS, "invalid bounds (l > u, L > U, NaN, wrong-sided infinity) or non-finite data");
     // A and explicit A^T
     if (m > 0) {
-      h.A = Mat{m, n, P->a_rowptr, P->a_col, P->a_val, P->a_nnz, default_G(P->a_nnz, m)};
+      h.A = Mat{m, n, P->a_rowptr, P->a_col, P->a_val, P->a_nnz, 0};
       h.at_rp = h.dalloc<int>(n + 1);
       h.at_ci = h.dalloc<int>(P->a_nnz);
       h.at_v = h.dalloc<double>(P->a_nnz);
       HQC(hq_build_transpose(m, n, P->a_nnz, P->a_rowptr, P->a_col, P->a_val, h.at_rp, h.at_ci, h.at_v, st));
-      h.AT = Mat{n, m, h.at_rp, h.at_ci, h.at_v, P->a_nnz, default_G(P->a_nnz, n)};
+      h.AT = Mat{n, m, h.at_rp, h.at_ci, h.at_v, P->a_nnz, 0};
     }
+    // product kernel per matrix from the row-length profile (autotuning may refine it)
+    auto pick = [&](Mat& M) {
+      if (M.rows == 0) return;
+      k_zero_ints<<<1, 64, 0, st>>>(1, h.dflags);
+      k_max_row_len<<<hq_grid(M.rows, 256), 256, 0, st>>>(M.rows, M.rp, h.dflags);
+      int mx = 0;
+      HQC(hipMemcpyAsync(&mx, h.dflags, sizeof(int), hipMemcpyDeviceToHost, st));
+      HQC(hipStreamSynchronize(st));
+      M.G = default_G(M.nnz, M.rows, mx);
+    };
+    if (m > 0) { pick(h.A); pick(h.AT); }
+    if (h.qkind == HPRQP_Q_CSR) pick(h.Q);
     // lambda's: needed by the params of every kernel, also during the power method
     h.lamA = 0; h.lamQ = 0;
     write_params(h, 1.0, 0);

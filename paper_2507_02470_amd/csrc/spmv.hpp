@@ -53,6 +53,54 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr(int nrows, const int* __restri
   if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
 }
 
+// CSR-stream SpMV for short rows.  A block owns HQ_BLOCK consecutive rows; the
+// nonzeros of those rows (a contiguous range of the CSR arrays) are streamed
+// in chunks of HQ_STREAM_CHUNK with fully coalesced loads, each thread forming
+// val[k] * x[col[k]] for k = c0 + tid, c0 + tid + HQ_BLOCK, ... into LDS; then
+// thread t adds up row t's products in CSR order (a fixed summation order)
+// and runs the epilogue for that row.  Loads of the matrix and of the
+// gathered vector are independent of the row structure, which keeps many
+// gathers in flight per wave.
+#define HQ_STREAM_CHUNK 2048
+template <class Epi>
+__global__ __launch_bounds__(HQ_BLOCK) void k_csr_stream(int nrows, const int* __restrict__ rowptr,
+                                                         const int* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ xin, Epi epi,
+                                                         const DevParams* __restrict__ prm, int j, RedOut red) {
+  constexpr int NR = Epi::NR;
+  __shared__ double prod[HQ_STREAM_CHUNK];
+  __shared__ int srp[HQ_BLOCK + 1];
+  Epi e = epi;
+  e.setup(prm, j);
+  double acc[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int s = 0; s < (NR > 0 ? NR : 1); ++s) acc[s] = 0.0;
+  const int t = threadIdx.x;
+  const int nblk = (nrows + HQ_BLOCK - 1) / HQ_BLOCK;
+  for (int rb = blockIdx.x; rb < nblk; rb += gridDim.x) {
+    const int r0 = rb * HQ_BLOCK;
+    const int nr = min(HQ_BLOCK, nrows - r0);
+    for (int i = t; i <= nr; i += HQ_BLOCK) srp[i] = rowptr[r0 + i];   // nr + 1 row pointers
+    __syncthreads();
+    const int kb = srp[0], ke = srp[nr];
+    const int myb = t < nr ? srp[t] : 0, mye = t < nr ? srp[t + 1] : 0;
+    double sum = 0.0;
+    for (int c0 = kb; c0 < ke; c0 += HQ_STREAM_CHUNK) {
+      const int c1 = min(ke, c0 + HQ_STREAM_CHUNK);
+#pragma unroll 4
+      for (int k = c0 + t; k < c1; k += HQ_BLOCK) prod[k - c0] = ld_stream(val + k) * xin[ld_stream(col + k)];
+      __syncthreads();
+      const int lo = max(myb, c0), hi = min(mye, c1);
+      for (int k = lo; k < hi; ++k) sum += prod[k - c0];
+      __syncthreads();
+    }
+    if (t < nr) e(r0 + t, sum, acc);
+    __syncthreads();   // srp is rewritten by the next row block
+  }
+  if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
+}
+
 // Elementwise driver: epi(i, q_i) with a precomputed / zero q.
 template <class Epi>
 __global__ __launch_bounds__(HQ_BLOCK) void k_elem(int n, const double* __restrict__ q, Epi epi,

@@ -1,0 +1,780 @@
+// batch.hip -- many independent HPR-QPs (Algorithm 4 + Algorithm 5 of arXiv
+// 2507.02470) in one persistent kernel on one MI355X.
+//
+// One 512-thread workgroup owns one instance at a time; instances are pulled
+// from a work queue ordered by size (largest first).  Every per-variable
+// vector of the iteration, and the low-rank factor F of Q = diag(d) + F F^T,
+// lives in registers (HB_EPT variables per thread, so n <= 512 * HB_EPT);
+// vectors of length m (<= 64) live in LDS.  The whole method runs on the
+// device in FP64: power method for lambda_A and lambda_Q, the sigma0 rule,
+// the iteration, the merit R~, the stopping test, the restart criteria of
+// Section 3.2 and the golden-section sigma update of Algorithm 5 (thread 0,
+// broadcast through LDS).  No host round trip until every instance is done.
+#include "hprqp.h"
+#include "common.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace hq {
+extern thread_local std::string g_err;
+}
+
+#define HB_BS 512
+#define HB_WAVES (HB_BS / 64)
+#define HB_EPT 4
+#define HB_NMAX (HB_BS * HB_EPT)
+#define HB_MMAX 64
+#define HB_RMAX 16
+
+struct BInst {
+  int n, m, r;
+  int pad;
+  const double *c, *L, *U, *l, *u, *dg, *F;
+  const int *arp, *aci;
+  const double* aval;
+  const int *trp, *tci;   // A^T (n x m) CSR, rows ordered by row of A
+  const double* tval;
+  long long off_n, off_m;
+  long long annz;         // nonzeros of A
+};
+
+struct BOpts {
+  double tol;
+  long long max_iter;
+  int check_every;
+  double sigma0, lamA, lamQ;
+  double alpha1, alpha2, alpha3;
+  int enable_restart, enable_sigma_update;
+};
+
+struct BInfo {
+  int term, restarts;
+  long long iters;
+  double sigma, sigma0, lamA, lamQ, eta_p, eta_d, eta_gap, pobj, dobj, R_last;
+};
+
+// ---------------------------------------------------------------------------
+// block-wide reductions (fixed order: wave butterfly, then waves in order)
+// ---------------------------------------------------------------------------
+struct BShared {
+  double red[HB_WAVES][32];
+  double out[32];
+  double vm[HB_NMAX];          // a length-n vector shared by the block (A v, A xbar)
+  double y[HB_MMAX], ya[HB_MMAX], yb[HB_MMAX], l[HB_MMAX], u[HB_MMAX], ry[HB_MMAX];
+  double yn[HB_MMAX];          // y^{t+1} (Halpern) until the check is done
+  double pw[HB_MMAX];          // power method vector (length m)
+  double t[HB_RMAX];           // F^T (.) of the current product
+  double ctrl[8];
+  int inst;
+};
+
+template <int K>
+__device__ __forceinline__ void bred(BShared& S, double (&v)[K], unsigned maxmask) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const double x = ((maxmask >> s) & 1u) ? wave_max(v[s]) : wave_sum(v[s]);
+    if (lane == 0) S.red[wv][s] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    const int s = threadIdx.x;
+    const bool mx = (maxmask >> s) & 1u;
+    double x = S.red[0][s];
+    for (int w = 1; w < HB_WAVES; ++w) x = mx ? fmax(x, S.red[w][s]) : x + S.red[w][s];
+    S.out[s] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < K; ++s) v[s] = S.out[s];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// the per-instance operator pieces
+// ---------------------------------------------------------------------------
+struct Elem {
+  int n, m, r;
+  double c[HB_EPT], L[HB_EPT], U[HB_EPT], dg[HB_EPT], F[HB_EPT][HB_RMAX];
+  __device__ bool valid(int e) const { return (int)threadIdx.x + e * HB_BS < n; }
+  __device__ int idx(int e) const { return threadIdx.x + e * HB_BS; }
+};
+
+// q = Q p = diag(d) p + F (F^T p)
+__device__ __forceinline__ void q_apply(BShared& S, const Elem& E, const double (&p)[HB_EPT], double (&q)[HB_EPT]) {
+  double t[HB_RMAX];
+#pragma unroll
+  for (int k = 0; k < HB_RMAX; ++k) t[k] = 0.0;
+#pragma unroll
+  for (int e = 0; e < HB_EPT; ++e)
+    if (E.valid(e)) {
+#pragma unroll
+      for (int k = 0; k < HB_RMAX; ++k) t[k] += E.F[e][k] * p[e];
+    }
+  bred<HB_RMAX>(S, t, 0u);
+#pragma unroll
+  for (int e = 0; e < HB_EPT; ++e) {
+    double s = E.dg[e] * p[e];
+#pragma unroll
+    for (int k = 0; k < HB_RMAX; ++k) s += E.F[e][k] * t[k];
+    q[e] = E.valid(e) ? s : 0.0;
+  }
+}
+
+// out[row] = (A p)_row for all rows (LDS S.ry), p staged through S.vm.
+__device__ __forceinline__ void a_apply(BShared& S, const Elem& E, const BInst& I, const double (&p)[HB_EPT]) {
+#pragma unroll
+  for (int e = 0; e < HB_EPT; ++e)
+    if (E.valid(e)) S.vm[E.idx(e)] = p[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int row = wv; row < E.m; row += HB_WAVES) {
+    double s = 0.0;
+    for (int k = I.arp[row] + lane; k < I.arp[row + 1]; k += 64) s += I.aval[k] * S.vm[I.aci[k]];
+    s = wave_sum(s);
+    if (lane == 0) S.ry[row] = s;
+  }
+  __syncthreads();
+}
+
+// g = A^T yv (yv in LDS, length m)
+__device__ __forceinline__ void at_apply(const Elem& E, const BInst& I, const double* yv, double (&g)[HB_EPT]) {
+#pragma unroll
+  for (int e = 0; e < HB_EPT; ++e) {
+    double s = 0.0;
+    if (E.valid(e)) {
+      const int i = E.idx(e);
+      for (int k = I.trp[i]; k < I.trp[i + 1]; ++k) s += I.tval[k] * yv[I.tci[k]];
+    }
+    g[e] = s;
+  }
+}
+
+__device__ double golden_sigma_dev(double th1, double th2, double th3, double lamQ) {
+  const double hi = sqrt(th2 / th1);
+  if (th3 <= 0.0 || lamQ <= 0.0) return hi;
+  const double lo = sqrt(th2 / (th1 + th3 / lamQ));
+  double a = log(lo), b = log(hi);
+  const double gr = 0.5 * (sqrt(5.0) - 1.0);
+  const double stop = log1p(1e-12);
+  for (int it = 0; it < 200 && (b - a) > stop; ++it) {
+    const double p = b - gr * (b - a), q = a + gr * (b - a);
+    const double sp = exp(p), sq = exp(q);
+    const double slope = th1 - th2 / (sp * sq) + th3 * (sp + sq + lamQ * sp * sq) / ((1.0 + lamQ * sp) * (1.0 + lamQ * sq));
+    if (slope > 0.0) b = q;
+    else a = p;
+  }
+  return exp(0.5 * (a + b));
+}
+
+// ---------------------------------------------------------------------------
+// persistent kernel
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__ insts, const int* __restrict__ order,
+                                                      int count, int* __restrict__ queue, BOpts o,
+                                                      const double* __restrict__ y0, const double* __restrict__ w0,
+                                                      const double* __restrict__ x0, double* __restrict__ yo,
+                                                      double* __restrict__ zo, double* __restrict__ wo,
+                                                      double* __restrict__ xo, BInfo* __restrict__ infos) {
+  __shared__ BShared S;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) S.inst = atomicAdd(queue, 1);
+    __syncthreads();
+    const int qi = S.inst;
+    __syncthreads();
+    if (qi >= count) break;                        // every wave leaves together
+    const int ii = order[qi];
+    const BInst I = insts[ii];
+    Elem E;
+    E.n = I.n; E.m = I.m; E.r = I.r;
+    const int n = I.n, m = I.m;
+#pragma unroll
+    for (int e = 0; e < HB_EPT; ++e) {
+      const int i = E.idx(e);
+      const bool ok = i < n;
+      E.c[e] = ok ? I.c[i] : 0.0;
+      E.L[e] = ok ? I.L[i] : 0.0;
+      E.U[e] = ok ? I.U[i] : 0.0;
+      E.dg[e] = ok ? I.dg[i] : 0.0;
+#pragma unroll
+      for (int k = 0; k < HB_RMAX; ++k) E.F[e][k] = (ok && k < I.r) ? I.F[(size_t)i * I.r + k] : 0.0;
+    }
+    if (tid < m) { S.l[tid] = I.l[tid]; S.u[tid] = I.u[tid]; }
+    __syncthreads();
+
+    // ---- lambda_Q: power method on Q from the all-ones start (Section 4.1) ----
+    double lamQ = o.lamQ, lamA = o.lamA;
+    double pv[HB_EPT], qv[HB_EPT];
+    if (!(lamQ > 0.0)) {
+      const double s0 = 1.0 / sqrt((double)n);
+#pragma unroll
+      for (int e = 0; e < HB_EPT; ++e) pv[e] = E.valid(e) ? s0 : 0.0;
+      double lam = 0.0, lam_old = 0.0;
+      for (int it = 1; it <= 5000; ++it) {
+        q_apply(S, E, pv, qv);
+        double rr[2] = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) { rr[0] += pv[e] * qv[e]; rr[1] += qv[e] * qv[e]; }
+        bred<2>(S, rr, 0u);
+        lam = rr[0];
+        if (rr[1] == 0.0) break;
+        if (it > 1 && fabs(lam - lam_old) <= 1e-6 * fabs(lam)) break;
+        lam_old = lam;
+        const double sc = 1.0 / sqrt(rr[1]);
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) pv[e] = qv[e] * sc;
+      }
+      lamQ = 1.01 * lam;
+    }
+    // ---- lambda_A: power method on A A^T from the all-ones start ----
+    if (!(lamA > 0.0) && m > 0) {
+      if (tid < m) S.pw[tid] = 1.0 / sqrt((double)m);
+      __syncthreads();
+      double lam = 0.0, lam_old = 0.0;
+      for (int it = 1; it <= 5000; ++it) {
+        at_apply(E, I, S.pw, pv);                  // u = A^T v
+        a_apply(S, E, I, pv);                      // w = A u  -> S.ry
+        double rr[2] = {0.0, 0.0};
+        if (tid < m) { rr[0] = S.pw[tid] * S.ry[tid]; rr[1] = S.ry[tid] * S.ry[tid]; }
+        bred<2>(S, rr, 0u);
+        lam = rr[0];
+        if (rr[1] == 0.0) break;
+        if (it > 1 && fabs(lam - lam_old) <= 1e-6 * fabs(lam)) break;
+        lam_old = lam;
+        if (tid < m) S.pw[tid] = S.ry[tid] / sqrt(rr[1]);
+        __syncthreads();
+      }
+      lamA = 1.01 * lam;
+    }
+    // ---- sigma0 = ||b|| / ||c|| (Section 4.1); ||b||_inf, ||c||_inf ----
+    double nrm[4] = {0.0, 0.0, 0.0, 0.0};
+    if (tid < m) {
+      const double a = isinf(S.l[tid]) ? 0.0 : fabs(S.l[tid]), b = isinf(S.u[tid]) ? 0.0 : fabs(S.u[tid]);
+      const double bi = fmax(a, b);
+      nrm[0] = bi * bi; nrm[1] = bi;
+    }
+#pragma unroll
+    for (int e = 0; e < HB_EPT; ++e) { nrm[2] += E.c[e] * E.c[e]; nrm[3] = fmax(nrm[3], fabs(E.c[e])); }
+    bred<4>(S, nrm, 0xAu);
+    const double binf = nrm[1], cinf = nrm[3];
+    double sigma;
+    {
+      const double nb = sqrt(nrm[0]), nc = sqrt(nrm[2]);
+      if (o.sigma0 > 0.0) sigma = o.sigma0;
+      else if (nb >= 1e-16 && nb <= 1e16 && nc >= 1e-16 && nc <= 1e16) sigma = nb / nc;
+      else sigma = 1.0;
+    }
+    const double sigma_init = sigma;
+
+    // ---- state: origin or warm start ----
+    double x[HB_EPT], w[HB_EPT], Qw[HB_EPT], ATy[HB_EPT], xa[HB_EPT], wa[HB_EPT], Qwa[HB_EPT], ATya[HB_EPT];
+    double xb[HB_EPT], zb[HB_EPT], wb[HB_EPT], Qwb[HB_EPT], g[HB_EPT];
+#pragma unroll
+    for (int e = 0; e < HB_EPT; ++e) {
+      const int i = E.idx(e);
+      const bool ok = i < n;
+      x[e] = (ok && x0) ? x0[I.off_n + i] : 0.0;
+      w[e] = (ok && w0) ? w0[I.off_n + i] : 0.0;
+      xb[e] = zb[e] = wb[e] = Qwb[e] = g[e] = 0.0;
+    }
+    if (tid < m) S.y[tid] = y0 ? y0[I.off_m + tid] : 0.0;
+    __syncthreads();
+
+    long long k = 0, t = 0;
+    int r = 0, term = -1;
+    double alpha3 = o.alpha3, R0ref = -1.0, Rr0 = -1.0, Rprev = -1.0, R = 0.0;
+    double eta_p = 0, eta_d = 0, eta_gap = 0, pobj = 0, dobj = 0;
+    bool new_epoch = true;
+    while (term < 0) {
+      if (new_epoch) {
+        // anchor u^{r,0} = u; exact A^T y and Q w
+        if (tid < m) S.ya[tid] = S.y[tid];
+        __syncthreads();
+        at_apply(E, I, S.y, ATy);
+        q_apply(S, E, w, Qw);
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) { xa[e] = x[e]; wa[e] = w[e]; Qwa[e] = Qw[e]; ATya[e] = ATy[e]; }
+        t = 0; Rprev = -1.0;
+        new_epoch = false;
+      }
+      const double sQ = sigma * lamQ, kappa = sigma / (1.0 + sQ), sA = sigma * lamA;
+      const double rho = 1.0 / (double)(t + 2);
+      const bool is_check = ((k + 1) % o.check_every == 0) || (k + 1 >= o.max_iter);
+      const bool want_r = (t == 0) || is_check;
+      // z/x step ("update-z", "update-x")
+      double xh[HB_EPT];
+#pragma unroll
+      for (int e = 0; e < HB_EPT; ++e) {
+        const double rz = x[e] + sigma * (-Qw[e] + ATy[e] - E.c[e]);
+        xb[e] = clampd(rz, E.L[e], E.U[e]);
+        zb[e] = (xb[e] - rz) / sigma;
+        xh[e] = E.valid(e) ? 2.0 * xb[e] - x[e] : 0.0;
+      }
+      // Q xhat, v = xhat + kappa (Qw - Q xhat)
+      double q1[HB_EPT], v[HB_EPT];
+      q_apply(S, E, xh, q1);
+#pragma unroll
+      for (int e = 0; e < HB_EPT; ++e) v[e] = E.valid(e) ? xh[e] + kappa * (Qw[e] - q1[e]) : 0.0;
+      // y step ("update-y") and its Halpern update
+      double dy2 = 0.0, th_y = 0.0;
+      if (m > 0) {
+        a_apply(S, E, I, v);
+        if (tid < m) {
+          const double yi = S.y[tid], yai = S.ya[tid];
+          const double rr = S.ry[tid] - sA * yi;
+          const double ybv = (clampd(rr, S.l[tid], S.u[tid]) - rr) / sA;
+          S.yb[tid] = ybv;
+          dy2 = (yi - ybv) * (yi - ybv);
+          th_y = (ybv - yai) * (ybv - yai);
+          S.yn[tid] = rho * yai + (1.0 - rho) * (2.0 * ybv - yi);   // Halpern y+ (applied below)
+        }
+        __syncthreads();
+      }
+      // g = A^T ybar, d = A^T(ybar - y)
+      double d[HB_EPT];
+      at_apply(E, I, S.yb, g);
+#pragma unroll
+      for (int e = 0; e < HB_EPT; ++e) d[e] = m > 0 ? g[e] - ATy[e] : 0.0;
+      double q2[HB_EPT];
+      q_apply(S, E, d, q2);
+      // wbar ("update-w") and Q wbar
+#pragma unroll
+      for (int e = 0; e < HB_EPT; ++e) {
+        const double inv = 1.0 / (1.0 + sQ);
+        wb[e] = (sQ * w[e] + xh[e]) * inv + kappa * d[e];
+        Qwb[e] = (sQ * Qw[e] + q1[e]) * inv + kappa * q2[e];
+      }
+      // merit R~ = ||u - ubar||_M (theta decomposition of the metric of Algorithm 3)
+      if (want_r) {
+        double s7[7] = {dy2, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) {
+          const double dw = w[e] - wb[e], Qdw = Qw[e] - Qwb[e], ATdy = -d[e], QATdy = -q2[e];
+          const double dx = E.valid(e) ? x[e] - xb[e] : 0.0;
+          s7[1] += dw * Qdw; s7[2] += Qdw * ATdy; s7[3] += dx * dx;
+          s7[4] += ATdy * QATdy; s7[5] += ATdy * dx; s7[6] += Qdw * dx;
+        }
+        bred<7>(S, s7, 0u);
+        const double th1 = lamA * s7[0] + lamQ * s7[1] - 2.0 * s7[2];
+        const double m2 = sigma * th1 + s7[3] / sigma + sigma * sigma * s7[4] / (1.0 + sQ) + 2.0 * (s7[5] - s7[6]);
+        R = sqrt(m2 > 0.0 ? m2 : 0.0);
+      }
+      // theta~ of Algorithm 5 and the stopping quantities need the pre-Halpern state
+      double th[5] = {0, 0, 0, 0, 0};
+      double res[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (is_check) {
+        // theta~: D = ubar - u^{r,0}; e = A^T (ybar - y_a) = g - ATy_a
+        double ev[HB_EPT], Qe[HB_EPT];
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) ev[e] = m > 0 ? g[e] - ATya[e] : 0.0;
+        q_apply(S, E, ev, Qe);
+        th[0] = th_y;
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) {
+          const double Dw = wb[e] - wa[e], QDw = Qwb[e] - Qwa[e];
+          const double Dx = E.valid(e) ? xb[e] - xa[e] : 0.0;
+          th[1] += Dw * QDw; th[2] += QDw * ev[e]; th[3] += Dx * Dx; th[4] += ev[e] * Qe[e];
+        }
+        bred<5>(S, th, 0u);
+        // stopping quantities at (ybar, zbar, xbar) (Section 4.1)
+        double Qx[HB_EPT];
+        q_apply(S, E, xb, Qx);
+        if (m > 0) a_apply(S, E, I, xb);            // S.ry = A xbar
+        // res: 0 max|Ax-PiK|, 1 max|Ax|, 2 sum(l y+ + u y-), 3 #inf, 4 max|dual|, 5 max|g|, 6 max|Qx|,
+        //      7 <x,Qx>, 8 <c,x>, 9 sum(L z+ + U z-) (+ #inf folded into 3)
+        if (tid < m) {
+          const double ax = S.ry[tid], li = S.l[tid], ui = S.u[tid], yv = S.yb[tid];
+          res[0] = fabs(ax - clampd(ax, li, ui));
+          res[1] = fabs(ax);
+          if (yv > 0.0) { if (isinf(li)) res[3] += 1.0; else res[2] += li * yv; }
+          else if (yv < 0.0) { if (isinf(ui)) res[3] += 1.0; else res[2] += ui * yv; }
+        }
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) {
+          if (!E.valid(e)) continue;
+          res[4] = fmax(res[4], fabs(-Qx[e] + g[e] + zb[e] - E.c[e]));
+          res[5] = fmax(res[5], fabs(g[e]));
+          res[6] = fmax(res[6], fabs(Qx[e]));
+          res[7] += xb[e] * Qx[e];
+          res[8] += E.c[e] * xb[e];
+          if (zb[e] > 0.0) { if (isinf(E.L[e])) res[3] += 1.0; else res[9] += E.L[e] * zb[e]; }
+          else if (zb[e] < 0.0) { if (isinf(E.U[e])) res[3] += 1.0; else res[9] += E.U[e] * zb[e]; }
+        }
+        bred<10>(S, res, 0x73u);                    // maxes: 0, 1, 4, 5, 6
+        eta_p = m > 0 ? res[0] / (1.0 + fmax(binf, res[1])) : 0.0;
+        eta_d = res[4] / (1.0 + fmax(cinf, fmax(res[5], res[6])));
+        pobj = 0.5 * res[7] + res[8];
+        if (res[3] > 0.0) { dobj = -INFINITY; eta_gap = INFINITY; }
+        else {
+          dobj = -0.5 * res[7] + res[2] + res[9];
+          eta_gap = fabs(pobj - dobj) / (1.0 + fmax(fabs(pobj), fabs(dobj)));
+        }
+      }
+      t += 1; k += 1;
+      if (t == 1) Rr0 = R;
+      // decisions at a check (thread 0, FP64), broadcast through LDS
+      int restart = 0;
+      if (is_check) {
+        if (tid == 0) {
+          const double kkt = fmax(eta_p, fmax(eta_d, eta_gap));
+          int tm = -1, rs = 0;
+          if (isnan(kkt) || isnan(R)) tm = HPRQP_NUMERICAL;
+          else if (kkt <= o.tol) tm = HPRQP_SOLVED;
+          else if (k >= o.max_iter) tm = HPRQP_MAX_ITER;
+          else if (o.enable_restart) {
+            const bool c1 = R <= o.alpha1 * Rr0;                              // eq:restart_1
+            const bool c2 = Rprev >= 0.0 && R <= o.alpha2 * Rr0 && R > Rprev; // eq:restart_2
+            const bool c3 = (double)t >= alpha3 * (double)k;                  // eq:restart_3
+            rs = c1 || c2 || c3;
+          }
+          double sig = sigma, a3 = alpha3, r0 = R0ref;
+          if (tm < 0 && rs) {
+            if (r0 < 0.0) r0 = R;
+            const double ratio = R / r0;
+            if (o.enable_sigma_update) {
+              // Algorithm 5
+              double th1 = lamA * th[0] + lamQ * th[1] - 2.0 * th[2];
+              double th2 = th[3], th3 = th[4];
+              th1 = fmax(th1, 1e-12); th2 = fmax(th2, 1e-12); th3 = fmax(th3, 0.0);
+              const double snew = golden_sigma_dev(th1, th2, th3, lamQ);
+              const double beta = exp(-ratio);
+              sig = exp(beta * log(snew) + (1.0 - beta) * log(sig));
+            }
+            if (ratio <= 0.1) a3 = 0.2;
+          }
+          S.ctrl[0] = tm; S.ctrl[1] = rs; S.ctrl[2] = sig; S.ctrl[3] = a3; S.ctrl[4] = r0;
+        }
+        __syncthreads();
+        term = (int)S.ctrl[0];
+        restart = (term < 0) && (S.ctrl[1] != 0.0);
+        sigma = S.ctrl[2]; alpha3 = S.ctrl[3]; R0ref = S.ctrl[4];
+        Rprev = R;
+        __syncthreads();
+      }
+      if (term >= 0) break;
+      if (restart) {
+        // u^{r+1,0} = ubar
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) { x[e] = xb[e]; w[e] = wb[e]; }
+        if (tid < m) S.y[tid] = S.yb[tid];
+        __syncthreads();
+        r += 1;
+        new_epoch = true;
+      } else {
+        // Halpern step: u^{r,t+1} = rho u^{r,0} + (1 - rho)(2 ubar - u)
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) {
+          const double xn = rho * xa[e] + (1.0 - rho) * (2.0 * xb[e] - x[e]);
+          const double wn = rho * wa[e] + (1.0 - rho) * (2.0 * wb[e] - w[e]);
+          const double Qwn = rho * Qwa[e] + (1.0 - rho) * (2.0 * Qwb[e] - Qw[e]);
+          const double ATyn = rho * ATya[e] + (1.0 - rho) * (2.0 * g[e] - ATy[e]);
+          x[e] = xn; w[e] = wn; Qw[e] = Qwn; ATy[e] = m > 0 ? ATyn : 0.0;
+        }
+        if (tid < m) S.y[tid] = S.yn[tid];
+        __syncthreads();
+      }
+    }
+    // output ubar of the last iteration (Algorithm 4, "Output")
+#pragma unroll
+    for (int e = 0; e < HB_EPT; ++e) {
+      const int i = E.idx(e);
+      if (i < n) {
+        xo[I.off_n + i] = xb[e];
+        zo[I.off_n + i] = zb[e];
+        wo[I.off_n + i] = wb[e];
+      }
+    }
+    if (tid < m) yo[I.off_m + tid] = S.yb[tid];
+    if (tid == 0) {
+      BInfo f;
+      f.term = term; f.restarts = r; f.iters = k; f.sigma = sigma; f.sigma0 = sigma_init;
+      f.lamA = lamA; f.lamQ = lamQ; f.eta_p = eta_p; f.eta_d = eta_d; f.eta_gap = eta_gap;
+      f.pobj = pobj; f.dobj = dobj; f.R_last = R;
+      infos[ii] = f;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+// per-instance validation: bit 0 bounds / non-finite data, bit 1 CSR structure
+__global__ void k_batch_validate(const BInst* __restrict__ insts, int count, int* __restrict__ flags) {
+  const int ii = blockIdx.x;
+  if (ii >= count) return;
+  const BInst I = insts[ii];
+  __shared__ int sflag;
+  if (threadIdx.x == 0) sflag = 0;
+  __syncthreads();
+  int f = 0;
+  for (int i = threadIdx.x; i < I.n; i += blockDim.x) {
+    if (!(I.L[i] <= I.U[i]) || I.L[i] == INFINITY || I.U[i] == -INFINITY || !isfinite(I.c[i]) || !isfinite(I.dg[i]))
+      f |= 1;
+    for (int k = 0; k < I.r; ++k)
+      if (!isfinite(I.F[(size_t)i * I.r + k])) f |= 1;
+  }
+  for (int i = threadIdx.x; i < I.m; i += blockDim.x) {
+    if (!(I.l[i] <= I.u[i]) || I.l[i] == INFINITY || I.u[i] == -INFINITY) f |= 1;
+    const int b = I.arp[i], e = I.arp[i + 1];
+    if ((i == 0 && b != 0) || b < 0 || e < b || (long long)e > I.annz || (i == I.m - 1 && e != I.annz)) f |= 2;
+  }
+  if (f) atomicOr(&sflag, f);
+  __syncthreads();
+  // columns, only once every row pointer lies in [0, nnz]
+  if ((sflag & 2) == 0 && I.m > 0) {
+    const int nnz = I.arp[I.m];
+    int g = 0;
+    for (int k = threadIdx.x; k < nnz; k += blockDim.x)
+      if (I.aci[k] < 0 || I.aci[k] >= I.n || !isfinite(I.aval[k])) g |= 2;
+    if (g) atomicOr(&sflag, g);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) flags[ii] = sflag;
+}
+
+// A^T of one instance per block (rows of A^T ordered by row of A): LDS
+// histogram, then one thread scans and scatters in CSR order (deterministic).
+__global__ void k_batch_transpose(const BInst* __restrict__ insts, const int* __restrict__ rep, int nrep,
+                                  int* __restrict__ trp_all, int* __restrict__ tci_all, double* __restrict__ tval_all,
+                                  const long long* __restrict__ toff) {
+  const int q = blockIdx.x;
+  if (q >= nrep) return;
+  const BInst I = insts[rep[q]];
+  __shared__ int cnt[HB_NMAX + 1];
+  for (int i = threadIdx.x; i <= I.n; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const int nnz = I.m > 0 ? I.arp[I.m] : 0;
+  for (int k = threadIdx.x; k < nnz; k += blockDim.x) atomicAdd(&cnt[I.aci[k] + 1], 1);
+  __syncthreads();
+  int* trp = trp_all + toff[2 * q];
+  int* tci = tci_all + toff[2 * q + 1];
+  double* tv = tval_all + toff[2 * q + 1];
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < I.n; ++i) cnt[i + 1] += cnt[i];
+    for (int i = 0; i <= I.n; ++i) trp[i] = cnt[i];
+    for (int row = 0; row < I.m; ++row)
+      for (int k = I.arp[row]; k < I.arp[row + 1]; ++k) {
+        const int p = cnt[I.aci[k]]++;
+        tci[p] = row;
+        tv[p] = I.aval[k];
+      }
+  }
+}
+
+__global__ void k_zero_int1(int* p) { *p = 0; }
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct hprqp_batch {
+  int count = 0;
+  hipStream_t st = nullptr, own_st = nullptr;
+  BOpts o{};
+  BInst* d_insts = nullptr;
+  int* d_order = nullptr;
+  int* d_queue = nullptr;
+  int* d_flags = nullptr;
+  BInfo* d_infos = nullptr;
+  int *trp = nullptr, *tci = nullptr;
+  double* tval = nullptr;
+  long long* d_toff = nullptr;
+  int* d_rep = nullptr;
+  long long total_n = 0, total_m = 0;
+  int grid = 0;
+  double last_kernel_s = 0.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~hprqp_batch() {
+    void* ps[] = {d_insts, d_order, d_queue, d_flags, d_infos, trp, tci, tval, d_toff, d_rep};
+    for (void* p : ps)
+      if (p) hipFree(p);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (own_st) hipStreamDestroy(own_st);
+  }
+};
+
+namespace {
+struct BErr {
+  hprqp_status st;
+  std::string msg;
+};
+[[noreturn]] void bfail(hprqp_status st, const std::string& m) { throw BErr{st, m}; }
+void bcheck(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) bfail(HPRQP_ERR_OOM, std::string(what) + ": out of device memory");
+    bfail(HPRQP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+#define HBC(x) bcheck((x), #x)
+
+void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_options* opt, hipStream_t st,
+                       hprqp_batch** out) {
+  if (count <= 0 || !probs || !opt || !out) bfail(HPRQP_ERR_ARG, "bad arguments");
+  if (opt->check_every <= 0 || opt->max_iter <= 0 || !(opt->tol >= 0.0)) bfail(HPRQP_ERR_ARG, "bad options");
+  auto* b = new hprqp_batch();
+  try {
+    b->count = count;
+    if (!st) {
+      HBC(hipStreamCreateWithFlags(&b->own_st, hipStreamNonBlocking));
+      HBC(hipDeviceSynchronize());
+      st = b->own_st;
+    }
+    b->st = st;
+    b->o.tol = opt->tol; b->o.max_iter = opt->max_iter; b->o.check_every = opt->check_every;
+    b->o.sigma0 = opt->sigma0; b->o.lamA = opt->lambda_A; b->o.lamQ = opt->lambda_Q;
+    b->o.alpha1 = opt->alpha1; b->o.alpha2 = opt->alpha2; b->o.alpha3 = opt->alpha3;
+    b->o.enable_restart = opt->enable_restart; b->o.enable_sigma_update = opt->enable_sigma_update;
+    std::vector<BInst> hi(count);
+    // unique A matrices (instances may share one) -> one A^T each
+    std::vector<int> rep_of(count);
+    std::vector<int> reps;
+    std::vector<long long> toff;
+    long long tn = 0, tz = 0;
+    for (int i = 0; i < count; ++i) {
+      const hprqp_problem& P = probs[i];
+      if (P.qkind != HPRQP_Q_LOWRANK) bfail(HPRQP_ERR_UNSUPPORTED, "batched solve supports qkind HPRQP_Q_LOWRANK only");
+      if (P.n <= 0 || P.n > HB_NMAX || P.m < 0 || P.m > HB_MMAX || P.lr_rank < 0 || P.lr_rank > HB_RMAX)
+        bfail(HPRQP_ERR_UNSUPPORTED, "batched solve needs 0 < n <= 2048, 0 <= m <= 64, lr_rank <= 16 (instance " +
+                                         std::to_string(i) + ")");
+      if (!P.c || !P.L || !P.U || !P.lr_d || (P.lr_rank > 0 && !P.lr_F) ||
+          (P.m > 0 && (!P.l || !P.u || !P.a_rowptr || (P.a_nnz > 0 && (!P.a_col || !P.a_val)))))
+        bfail(HPRQP_ERR_ARG, "missing array in instance " + std::to_string(i));
+      BInst& I = hi[i];
+      std::memset(&I, 0, sizeof(I));
+      I.n = P.n; I.m = P.m; I.r = P.lr_rank;
+      I.c = P.c; I.L = P.L; I.U = P.U; I.l = P.l; I.u = P.u; I.dg = P.lr_d; I.F = P.lr_F;
+      I.arp = P.a_rowptr; I.aci = P.a_col; I.aval = P.a_val;
+      I.off_n = b->total_n; I.off_m = b->total_m;
+      I.annz = P.m > 0 ? P.a_nnz : 0;
+      if (P.a_nnz < 0 || P.a_nnz > (1ll << 30)) bfail(HPRQP_ERR_SHAPE, "bad a_nnz in instance " + std::to_string(i));
+      b->total_n += P.n; b->total_m += P.m;
+      int found = -1;
+      for (size_t q = 0; q < reps.size() && found < 0; ++q) {
+        const hprqp_problem& R = probs[reps[q]];
+        if (R.a_rowptr == P.a_rowptr && R.a_col == P.a_col && R.a_val == P.a_val && R.n == P.n && R.m == P.m) found = (int)q;
+      }
+      if (found < 0) {
+        found = (int)reps.size();
+        reps.push_back(i);
+        toff.push_back(tn);
+        toff.push_back(tz);
+        tn += P.n + 1;
+        tz += std::max<long long>(P.a_nnz, 0);
+      }
+      rep_of[i] = found;
+    }
+    HBC(hipMalloc(&b->trp, std::max<long long>(tn, 1) * sizeof(int)));
+    HBC(hipMalloc(&b->tci, std::max<long long>(tz, 1) * sizeof(int)));
+    HBC(hipMalloc(&b->tval, std::max<long long>(tz, 1) * sizeof(double)));
+    for (int i = 0; i < count; ++i) {
+      const int q = rep_of[i];
+      hi[i].trp = b->trp + toff[2 * q];
+      hi[i].tci = b->tci + toff[2 * q + 1];
+      hi[i].tval = b->tval + toff[2 * q + 1];
+    }
+    HBC(hipMalloc(&b->d_insts, count * sizeof(BInst)));
+    HBC(hipMemcpyAsync(b->d_insts, hi.data(), count * sizeof(BInst), hipMemcpyHostToDevice, st));
+    HBC(hipMalloc(&b->d_flags, count * sizeof(int)));
+    HBC(hipMemsetAsync(b->d_flags, 0, count * sizeof(int), st));
+    k_batch_validate<<<count, 256, 0, st>>>(b->d_insts, count, b->d_flags);
+    std::vector<int> flags(count);
+    HBC(hipMemcpyAsync(flags.data(), b->d_flags, count * sizeof(int), hipMemcpyDeviceToHost, st));
+    HBC(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i) {
+      if (flags[i] & 2) bfail(HPRQP_ERR_SHAPE, "CSR structure of A invalid in instance " + std::to_string(i));
+      if (flags[i] & 1) bfail(HPRQP_ERR_BOUNDS, "invalid bounds or non-finite data in instance " + std::to_string(i));
+    }
+    HBC(hipMalloc(&b->d_rep, reps.size() * sizeof(int)));
+    HBC(hipMalloc(&b->d_toff, toff.size() * sizeof(long long)));
+    HBC(hipMemcpyAsync(b->d_rep, reps.data(), reps.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HBC(hipMemcpyAsync(b->d_toff, toff.data(), toff.size() * sizeof(long long), hipMemcpyHostToDevice, st));
+    k_batch_transpose<<<(int)reps.size(), 256, 0, st>>>(b->d_insts, b->d_rep, (int)reps.size(), b->trp, b->tci,
+                                                         b->tval, b->d_toff);
+    // largest instances first
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return hi[a].n > hi[c].n; });
+    HBC(hipMalloc(&b->d_order, count * sizeof(int)));
+    HBC(hipMemcpyAsync(b->d_order, order.data(), count * sizeof(int), hipMemcpyHostToDevice, st));
+    HBC(hipMalloc(&b->d_queue, sizeof(int)));
+    HBC(hipMalloc(&b->d_infos, count * sizeof(BInfo)));
+    int dev = 0, ncu = 0, per_cu = 0;
+    HBC(hipGetDevice(&dev));
+    HBC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_solve, HB_BS, 0));
+    b->grid = std::max(1, std::min(count, ncu * std::max(per_cu, 1)));
+    HBC(hipEventCreate(&b->e0));
+    HBC(hipEventCreate(&b->e1));
+    HBC(hipStreamSynchronize(st));
+    *out = b;
+  } catch (...) {
+    delete b;
+    throw;
+  }
+}
+
+void solve_batch_impl(hprqp_batch* b, const double* y0, const double* w0, const double* x0, double* y, double* z,
+                      double* w, double* x, hprqp_info* infos) {
+  if (!b || !z || !w || !x || (b->total_m > 0 && !y)) bfail(HPRQP_ERR_ARG, "NULL argument");
+  if (b->own_st) HBC(hipDeviceSynchronize());
+  k_zero_int1<<<1, 1, 0, b->st>>>(b->d_queue);
+  HBC(hipEventRecord(b->e0, b->st));
+  k_batch_solve<<<b->grid, HB_BS, 0, b->st>>>(b->d_insts, b->d_order, b->count, b->d_queue, b->o, y0, w0, x0, y, z,
+                                               w, x, b->d_infos);
+  HBC(hipGetLastError());
+  HBC(hipEventRecord(b->e1, b->st));
+  std::vector<BInfo> hi(b->count);
+  HBC(hipMemcpyAsync(hi.data(), b->d_infos, b->count * sizeof(BInfo), hipMemcpyDeviceToHost, b->st));
+  HBC(hipStreamSynchronize(b->st));
+  float ms = 0.f;
+  HBC(hipEventElapsedTime(&ms, b->e0, b->e1));
+  b->last_kernel_s = ms * 1e-3;
+  if (infos)
+    for (int i = 0; i < b->count; ++i) {
+      hprqp_info& f = infos[i];
+      std::memset(&f, 0, sizeof(f));
+      f.term = hi[i].term; f.iters = hi[i].iters; f.restarts = hi[i].restarts;
+      f.sigma = hi[i].sigma; f.sigma0 = hi[i].sigma0; f.lambda_A = hi[i].lamA; f.lambda_Q = hi[i].lamQ;
+      f.eta_p = hi[i].eta_p; f.eta_d = hi[i].eta_d; f.eta_gap = hi[i].eta_gap;
+      f.pobj = hi[i].pobj; f.dobj = hi[i].dobj; f.R_last = hi[i].R_last;
+    }
+}
+}  // namespace
+
+#define HB_GUARD(...)                 \
+  try {                               \
+    hq::g_err.clear();                \
+    __VA_ARGS__;                      \
+    return HPRQP_OK;                  \
+  } catch (const BErr& e) {           \
+    hq::g_err = e.msg;                \
+    return e.st;                      \
+  } catch (const std::exception& e) { \
+    hq::g_err = e.what();             \
+    return HPRQP_ERR_HIP;             \
+  }
+
+extern "C" {
+
+hprqp_status hprqp_batch_create(int32_t count, const hprqp_problem* probs, const hprqp_options* opt,
+                                hipStream_t stream, hprqp_batch** out) {
+  HB_GUARD(batch_create_impl(count, probs, opt, stream, out));
+}
+
+hprqp_status hprqp_solve_batch(hprqp_batch* b, const double* y0, const double* w0, const double* x0, double* y,
+                               double* z, double* w, double* x, hprqp_info* infos_host) {
+  HB_GUARD(solve_batch_impl(b, y0, w0, x0, y, z, w, x, infos_host));
+}
+
+double hprqp_batch_last_kernel_s(hprqp_batch* b) { return b ? b->last_kernel_s : 0.0; }
+
+void hprqp_batch_destroy(hprqp_batch* b) { delete b; }
+
+}  // extern "C"

@@ -95,6 +95,131 @@ def cpu_baseline(qp, lam_A, lam_Q, sigma0, iters):
                        f"lambda's and sigma0 given), {dt:.1f} s")
 
 
+FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 MFMA, published
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA, published
+
+
+def extra_kron(steps, cpu):
+    """Matrix-free Q = B (x) C (d = 300, n = 90,000) with assignment rows."""
+    import torch
+    import qpgen
+    from paper_2507_02470_amd.solver import DeviceProblem, Solver
+    qp = qpgen.make_kron()
+    s = Solver(DeviceProblem(qp), power_start_A=qpgen.power_start(qp.m), power_start_Q=qpgen.power_start(qp.n),
+               check_every=T_CHECK, tol=0.0, max_iter=T_CHECK, spmv_autotune=1)
+    s.solve()
+    s.set_options(tol=0.0, max_iter=steps * T_CHECK, profile_kernels=1, time_limit_s=0.0)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = s.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ta
+    ks = s.kernel_stats()
+    d = qp.kron_B.shape[0]
+    q_flop = 2 * 2.0 * d * d * d            # two d x d x d GEMMs per Q product
+    q_ms = 0.5 * (ks["avg_ms"]["q_xhat"] + ks["avg_ms"]["q_d_halpern"])
+    out = dict(workload="kron_assignment", n=qp.n, m=qp.m, d=d, iterations_per_s=round(r.iters / dt, 1),
+               us_per_iteration=round(dt / r.iters * 1e6, 2), kernel_avg_us={k: round(v * 1e3, 2) for k, v in
+                                                                              ks["avg_ms"].items()},
+               q_product=dict(flop=q_flop, avg_us=round(q_ms * 1e3, 2),
+                              tflops=round(q_flop / (q_ms * 1e-3) / 1e12, 2),
+                              fp64_mfma_util=round(q_flop / (q_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)))
+    s.set_options(tol=1e-8, max_iter=2_000_000, profile_kernels=0, time_limit_s=60.0)
+    rt = s.solve()
+    out["time_to_1e-8"] = dict(term=rt.term, iterations=rt.iters, kkt=rt.kkt,
+                               time_s=round(rt.t_setup_s + rt.t_solve_s, 4))
+    if cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ro = oracle.solve(qp, tol=0.0, max_iter=3, check_every=T_CHECK, lambda_A=r.lambda_A, lambda_Q=r.lambda_Q,
+                          sigma0=r.sigma0)
+        out["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
+    s.close()
+    return out
+
+
+def extra_batch(count, cpu):
+    """`count` independent portfolio QPs (n ~ U{50..2000}) in one persistent launch."""
+    import numpy as np
+    import torch
+    import qpgen
+    from paper_2507_02470_amd.batch import BatchSolver
+    qps = qpgen.make_portfolio_batch(count)
+    b = BatchSolver(qps, tol=1e-8, max_iter=200_000)
+    b.solve(split=False)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = b.solve(split=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ta
+    it = r.iters
+    terms = [f["term"] for f in r.infos]
+    out = dict(workload="portfolio_batch", instances=count, sum_n=int(sum(q.n for q in qps)),
+               solved=terms.count("solved"), wall_s=round(dt, 4), kernel_s=round(r.kernel_s, 4),
+               instances_per_s=round(count / dt, 1), instance_iterations_per_s=round(float(it.sum()) / dt, 1),
+               iterations_mean=round(float(it.mean()), 1), iterations_max=int(it.max()),
+               max_kkt=float(max(f["kkt"] for f in r.infos)))
+    b.close()
+    if cpu:
+        import oracle
+        sample = sorted(range(count), key=lambda i: qps[i].n)[::max(1, count // 16)][:16]
+        t0 = time.perf_counter()
+        its = 0
+        for i in sample:
+            its += oracle.solve(qps[i], tol=1e-8, max_iter=200_000).iters
+        tc = time.perf_counter() - t0
+        out["cpu_oracle"] = dict(instances_per_s=round(len(sample) / tc, 2),
+                                 instance_iterations_per_s=round(its / tc, 1), cores=1,
+                                 sample=f"{len(sample)} instances stratified by n, solved one after another")
+    return out
+
+
+def extra_warm_cold(n_train, n_eval, epochs):
+    """Learned warm start on the parametric portfolio family (n = 1000, m = 21)."""
+    import numpy as np
+    import torch
+    import qpgen
+    from paper_2507_02470_amd.surrogate import (WarmStartSurrogate, family_features, solve_family, targets_from,
+                                                warm_vs_cold)
+    base = qpgen.make_portfolio_family_base()
+    t0 = time.perf_counter()
+    train = [qpgen.portfolio_family_sample(base, 100_000 + j) for j in range(n_train)]
+    held = [qpgen.portfolio_family_sample(base, 200_000 + j) for j in range(n_eval)]
+    tg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = solve_family(base, train)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    X = np.stack([family_features(c, u) for (c, l, u) in train])
+    T = targets_from(r, n_train, base.n, base.m)
+    sur = WarmStartSurrogate(base, hidden=512, max_batch=512, seed=0)
+    t0 = time.perf_counter()
+    hist = sur.fit(X, T, epochs=epochs, batch=256, lr=1e-3, lr_final=1e-5, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    # BF16 MFMA throughput of the forward GEMMs on one evaluation batch
+    Xe = np.stack([family_features(c, u) for (c, l, u) in held[:512]])
+    sur.net.forward(Xe)
+    ms, fl = sur.net.gemm_stats()
+    res = warm_vs_cold(sur, held)
+    ic, iw = res["iters_cold"], res["iters_warm"]
+    return dict(workload="portfolio_family", n=base.n, m=base.m, train_samples=n_train, eval_samples=n_eval,
+                epochs=epochs, t_generate_s=round(tg, 2), t_solve_training_set_s=round(t_data, 2),
+                t_train_s=round(t_train, 2), loss_first=hist[0], loss_last=hist[-1],
+                cold=dict(iterations_mean=round(float(ic.mean()), 1), iterations_median=float(np.median(ic)),
+                          wall_s=round(res["t_cold_s"], 4), kernel_s=round(res["kernel_cold_s"], 4)),
+                warm=dict(iterations_mean=round(float(iw.mean()), 1), iterations_median=float(np.median(iw)),
+                          wall_s=round(res["t_warm_s"], 4), kernel_s=round(res["kernel_warm_s"], 4),
+                          fallback=res["fallback"]),
+                fewer_iterations_frac=round(float(np.mean(iw < ic)), 4),
+                max_kkt_warm=float(res["kkt_warm"].max()),
+                max_obj_rel_diff=float(np.max(np.abs(res["obj_warm"] - res["obj_cold"]) /
+                                              np.maximum(1.0, np.abs(res["obj_cold"])))),
+                prediction_rel_err_w=round(res["pred_rel_err_w"], 4),
+                mlp_forward_gemm=dict(batch=512, ms=round(ms, 4), tflops=round(fl / (ms * 1e-3) / 1e12, 2),
+                                      bf16_mfma_util=round(fl / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 5)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +230,11 @@ def main():
     ap.add_argument("--no-tol-solve", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--tol-time-limit", type=float, default=120.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the Kronecker, batch and warm-start workloads")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--train-samples", type=int, default=50_000)
+    ap.add_argument("--eval-samples", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the HPR-QP path here is "
@@ -181,6 +311,16 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(qp, r.lambda_A, r.lambda_Q, r.sigma0, args.cpu_iters)
         log(f"cpu baseline: {cpu}")
+    s.close()
+    extras = None
+    if not args.no_extras and args.workload == "random_large":
+        extras = {}
+        extras["kron"] = extra_kron(max(5, args.steps // 2), not args.no_cpu_baseline)
+        log(f"kron: {extras['kron']}")
+        extras["batch"] = extra_batch(args.batch_count, not args.no_cpu_baseline)
+        log(f"batch: {extras['batch']}")
+        extras["warm_vs_cold"] = extra_warm_cold(args.train_samples, args.eval_samples, args.epochs)
+        log(f"warm vs cold: {extras['warm_vs_cold']}")
     out = {
         "metric": "HPR-QP iterations/s (FP64, relative-KKT stopping test every 100 iterations)",
         "value": round(value, 2),
@@ -198,9 +338,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_1e-8": tol_run,
+        "extras": extras,
     }
     print(json.dumps(out))
-    s.close()
 
 
 if __name__ == "__main__":

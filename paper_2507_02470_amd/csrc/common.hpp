@@ -55,7 +55,7 @@ __device__ __forceinline__ double wave_max(double v) {
 template <int NR, unsigned MAXMASK>
 __device__ __forceinline__ void block_reduce_store(const double* acc, const RedOut& red) {
   if constexpr (NR > 0) {
-    __shared__ double sh[HQ_BLOCK / HQ_WAVE][NR > 0 ? NR : 1];
+    __shared__ double sh[16][NR > 0 ? NR : 1];   // up to 1024-thread blocks
     const int lane = threadIdx.x & (HQ_WAVE - 1), wv = threadIdx.x / HQ_WAVE;
 #pragma unroll
     for (int s = 0; s < NR; ++s) {

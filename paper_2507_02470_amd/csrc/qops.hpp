@@ -9,24 +9,27 @@ typedef double hq_dx4 __attribute__((ext_vector_type(4)));
 // (TRANSB = false) or B[j + ldb k] (TRANSB = true).  Output element (i, j)
 // goes to the epilogue as vector index i + ldo j.
 //
-// One 16 x 16 output tile per 256-thread block; its four waves split K into
-// four ranges, each accumulating with v_mfma_f64_16x16x4f64, and the four
-// partial tiles are summed in LDS in a fixed order (deterministic).  Operand
-// layout of the 16x16x4 f64 MFMA (measured on gfx950): lane l supplies
-// A[l%16][l/16] and B[l/16][l%16]; accumulator register v of lane l holds
-// D[l/16 + 4v][l%16], v = 0..3.
+// One 16 x 16 output tile per block of HQ_KSPLIT waves; the waves split K
+// into HQ_KSPLIT ranges, each accumulating with v_mfma_f64_16x16x4f64, and
+// the partial tiles are summed in LDS in a fixed order (deterministic).  A
+// short K range per wave keeps the chain of dependent loads and MFMAs short:
+// at these sizes (d ~ 300) the product is latency-bound, not MFMA-bound.
+// Operand layout of the 16x16x4 f64 MFMA (measured on gfx950): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register v of lane l
+// holds D[l/16 + 4v][l%16], v = 0..3.
 // ---------------------------------------------------------------------------
+#define HQ_KSPLIT 8
 template <bool TRANSB, class Epi>
-__global__ __launch_bounds__(256) void k_dgemm16(int M, int N, int K, const double* __restrict__ A, int lda,
-                                                 const double* __restrict__ B, int ldb, int ldo, Epi epi,
-                                                 const DevParams* __restrict__ prm, int jit, RedOut red) {
+__global__ __launch_bounds__(64 * HQ_KSPLIT) void k_dgemm16(int M, int N, int K, const double* __restrict__ A, int lda,
+                                                            const double* __restrict__ B, int ldb, int ldo, Epi epi,
+                                                            const DevParams* __restrict__ prm, int jit, RedOut red) {
   constexpr int NR = Epi::NR;
-  __shared__ double part[4][16][17];
+  __shared__ double part[HQ_KSPLIT][16][17];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int tiles_m = (M + 15) >> 4, tiles_n = (N + 15) >> 4;
   const int ksteps = (K + 3) >> 2;
-  const int per = (ksteps + 3) >> 2;
+  const int per = (ksteps + HQ_KSPLIT - 1) / HQ_KSPLIT;
   const int ks0 = wv * per;
   const int ks1 = (ks0 + per < ksteps) ? ks0 + per : ksteps;
   Epi e = epi;
@@ -38,7 +41,7 @@ __global__ __launch_bounds__(256) void k_dgemm16(int M, int N, int K, const doub
     const int i0 = (tile % tiles_m) << 4, j0 = (tile / tiles_m) << 4;
     const int ia = i0 + li, jb = j0 + li;
     hq_dx4 d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+#pragma unroll 8
     for (int ks = ks0; ks < ks1; ++ks) {
       const int k = (ks << 2) + lk;
       const bool kin = k < K;
@@ -49,10 +52,14 @@ __global__ __launch_bounds__(256) void k_dgemm16(int M, int N, int K, const doub
 #pragma unroll
     for (int v = 0; v < 4; ++v) part[wv][lk + 4 * v][li] = d[v];
     __syncthreads();
-    const int r = threadIdx.x & 15, cc = threadIdx.x >> 4;
-    const double q = ((part[0][r][cc] + part[1][r][cc]) + part[2][r][cc]) + part[3][r][cc];
-    const int gi = i0 + r, gj = j0 + cc;
-    if (gi < M && gj < N) e(gi + ldo * gj, q, acc);
+    if (threadIdx.x < 256) {
+      const int r = threadIdx.x & 15, cc = threadIdx.x >> 4;
+      double q = part[0][r][cc];
+#pragma unroll
+      for (int w = 1; w < HQ_KSPLIT; ++w) q += part[w][r][cc];
+      const int gi = i0 + r, gj = j0 + cc;
+      if (gi < M && gj < N) e(gi + ldo * gj, q, acc);
+    }
     __syncthreads();
   }
   if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);

@@ -293,7 +293,8 @@ inline RedOut red_seq(hprqp_handle& h, int slot0, int nr) {
 
 template <class Epi>
 void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
-  const int grid = hq_grid(M.rows, HQ_BLOCK);
+  // stream kernel: HQ_BLOCK rows per block; row-split kernel: HQ_BLOCK / G rows per block
+  const int grid = M.G == 0 ? hq_grid(M.rows, HQ_BLOCK) : hq_grid(M.rows, HQ_BLOCK / M.G);
   hipStream_t st = h.st;
   switch (M.G) {
     case 0: k_csr_stream<Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
@@ -331,9 +332,9 @@ void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedO
       const int s = h.ks, p = h.kp;
       const int tiles = ((s + 15) / 16) * ((p + 15) / 16);
       const int grid = std::min(tiles, HQ_GRID_CAP);
-      k_dgemm16<false, EpiStore><<<grid, 256, 0, h.st>>>(s, p, s, h.kC, s, x, s, s, EpiStore{h.kronT}, h.dprm, j,
-                                                         no_red(h));
-      k_dgemm16<true, Epi><<<grid, 256, 0, h.st>>>(s, p, p, h.kronT, s, h.kB, p, s, epi, h.dprm, j, red);
+      k_dgemm16<false, EpiStore><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, s, h.kC, s, x, s, s, EpiStore{h.kronT},
+                                                                    h.dprm, j, no_red(h));
+      k_dgemm16<true, Epi><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, p, h.kronT, s, h.kB, p, s, epi, h.dprm, j, red);
       break;
     }
     case HPRQP_Q_LOWRANK: {

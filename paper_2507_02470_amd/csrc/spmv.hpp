@@ -1,54 +1,40 @@
-// spmv.hpp -- row-split CSR SpMV for gfx950 with a fused per-row epilogue.
-//
-// A wave owns 64 consecutive rows.  It walks them in G passes; in each pass
-// groups of G lanes reduce one row each (lanes stride over the row's
-// nonzeros, then a butterfly over the group), and a cross-lane shuffle hands
-// each row's sum to the lane whose index matches the row.  The epilogue then
-// runs with all 64 lanes on 64 consecutive rows, so its vector traffic is
-// fully coalesced.  No atomics; the summation order depends only on G.
+// spmv.hpp -- CSR SpMV kernels for gfx950 with a fused per-row epilogue.
 #pragma once
 #include "common.hpp"
 
+// Row-split kernel for long rows: groups of G lanes each own one row (a
+// block covers HQ_BLOCK / G rows per pass); the lanes stride over the row's
+// nonzeros, a butterfly over the group adds the partial sums, and the
+// group's first lane runs the epilogue.  Rows are dealt out in grid-stride
+// order, so a matrix with a few hundred long rows still spreads over
+// hundreds of waves.  No atomics; the summation order depends only on G.
 template <int G, class Epi>
 __global__ __launch_bounds__(HQ_BLOCK) void k_csr(int nrows, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
                                                   const double* __restrict__ val,
                                                   const double* __restrict__ xin, Epi epi,
                                                   const DevParams* __restrict__ prm, int j, RedOut red) {
-  constexpr int RPW = HQ_WAVE / G;  // rows per wave per pass
+  constexpr int RPB = HQ_BLOCK / G;  // rows per block per pass
   constexpr int NR = Epi::NR;
-  const int lane = threadIdx.x & (HQ_WAVE - 1);
-  const int wv = threadIdx.x / HQ_WAVE;
-  const int gl = lane % G;
-  const int gi = lane / G;
+  const int gl = threadIdx.x % G;
+  const int gi = threadIdx.x / G;
   Epi e = epi;
   e.setup(prm, j);
   double acc[NR > 0 ? NR : 1];
 #pragma unroll
   for (int s = 0; s < (NR > 0 ? NR : 1); ++s) acc[s] = 0.0;
-  const long long wstride = (long long)gridDim.x * (HQ_BLOCK / HQ_WAVE) * HQ_WAVE;
-  for (long long base = ((long long)blockIdx.x * (HQ_BLOCK / HQ_WAVE) + wv) * HQ_WAVE; base < nrows;
-       base += wstride) {
-    double mine = 0.0;
-#pragma unroll
-    for (int s = 0; s < G; ++s) {
-      const long long row = base + (long long)s * RPW + gi;
-      double sum = 0.0;
-      if (row < nrows) {
-        const int b = rowptr[row], en = rowptr[row + 1];
-        for (int k = b + gl; k < en; k += G) sum += ld_stream(val + k) * xin[ld_stream(col + k)];
-      }
-      if constexpr (G > 1) {
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-        const double v = __shfl(sum, (lane % RPW) * G);
-        if (lane / RPW == s) mine = v;
-      } else {
-        mine = sum;
-      }
+  for (long long r0 = (long long)blockIdx.x * RPB; r0 < nrows; r0 += (long long)gridDim.x * RPB) {
+    const long long row = r0 + gi;
+    double sum = 0.0;
+    if (row < nrows) {
+      const int b = rowptr[row], en = rowptr[row + 1];
+      for (int k = b + gl; k < en; k += G) sum += ld_stream(val + k) * xin[ld_stream(col + k)];
     }
-    const long long row = base + lane;
-    if (row < nrows) e((int)row, mine, acc);
+    if constexpr (G > 1) {
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    }
+    if (row < nrows && gl == 0) e((int)row, sum, acc);
   }
   if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
 }

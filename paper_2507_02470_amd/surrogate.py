@@ -228,7 +228,11 @@ class WarmStartSurrogate:
         return hist
 
     def starts(self, X):
-        return self.net.warm_start(X, self.n, self.m, self.base.L, self.base.U)
+        """Warm starts (y0, w0, x0, bad) for the rows of X, in chunks of the network's max batch."""
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device)
+        parts = [self.net.warm_start(X[b0:b0 + self.net.max_batch], self.n, self.m, self.base.L, self.base.U)
+                 for b0 in range(0, X.shape[0], self.net.max_batch)]
+        return tuple(torch.cat([p[k] for p in parts], dim=0) for k in range(4))
 
 
 def warm_vs_cold(sur: WarmStartSurrogate, samples, tol=1e-8, max_iter=200_000):

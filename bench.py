@@ -231,6 +231,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--tol-time-limit", type=float, default=120.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the Kronecker, batch and warm-start workloads")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default SpMV kernel choice")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 512 MiB device copy (reference dispatch for hardware byte counters)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--train-samples", type=int, default=50_000)
     ap.add_argument("--eval-samples", type=int, default=4096)
@@ -260,7 +263,7 @@ def main():
     dp = DeviceProblem(qp)
     torch.cuda.synchronize()
     s = Solver(dp, power_start_A=qpgen.power_start(qp.m), power_start_Q=qpgen.power_start(qp.n),
-               check_every=T_CHECK, tol=0.0, max_iter=max(1, args.warmup) * T_CHECK, spmv_autotune=1,
+               check_every=T_CHECK, tol=0.0, max_iter=max(1, args.warmup) * T_CHECK, spmv_autotune=0 if args.no_autotune else 1,
                profile_kernels=0)
     pi = s.power_info()
     log(f"create: power A {pi['it_A']} its, Q {pi['it_Q']} its")
@@ -312,6 +315,15 @@ def main():
         cpu = cpu_baseline(qp, r.lambda_A, r.lambda_Q, r.sigma0, args.cpu_iters)
         log(f"cpu baseline: {cpu}")
     s.close()
+    if args.calibrate_copy:
+        a = torch.rand(64 << 20, dtype=torch.float64, device="cuda")
+        flush = torch.empty(128 << 20, dtype=torch.float64, device="cuda").fill_(1.0)   # evict caches
+        del flush
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 536870912 bytes read, 536870912 bytes written")
+        del a, b
     extras = None
     if not args.no_extras and args.workload == "random_large":
         extras = {}

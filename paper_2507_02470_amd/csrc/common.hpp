@@ -81,9 +81,12 @@ __device__ __forceinline__ double clampd(double v, double lo, double hi) {
   return fmin(fmax(v, lo), hi);
 }
 
-// streaming loads for matrix data read once per product
+// streaming loads/stores for data touched once per product (matrix entries,
+// single-use vector streams): marked non-temporal so they do not evict the
+// vector being gathered from L2
 __device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ int ld_stream(const int* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
 static inline int hq_grid(long long work, int per_block) {
   long long g = (work + per_block - 1) / per_block;

@@ -28,8 +28,8 @@ struct EpiQ1 {
   static constexpr unsigned MAXMASK = 0u;
   __device__ void setup(const DevParams* p, int j) { IterScalars s; s.load(p, j); kappa = s.kappa; }
   __device__ __forceinline__ void operator()(int i, double q, double*) const {
-    q1[i] = q;
-    v[i] = xh[i] + kappa * (Qw[i] - q);
+    st_stream(q1 + i, q);                                   // read once, by Q-apply #2
+    v[i] = xh[i] + kappa * (ld_stream(Qw + i) - q);          // v is gathered next: keep it cached
   }
 };
 
@@ -45,11 +45,11 @@ struct EpiY {
   static constexpr unsigned MAXMASK = 0u;
   __device__ void setup(const DevParams* p, int j) { IterScalars s; s.load(p, j); sA = s.sA; rho = s.rho; }
   __device__ __forceinline__ void operator()(int i, double q, double* acc) const {
-    const double yi = y[i], yai = ya[i];
+    const double yi = ld_stream(y + i), yai = ld_stream(ya + i);
     const double r = q - sA * yi;
-    const double yb = (clampd(r, l[i], u[i]) - r) / sA;
-    ybar[i] = yb;
-    y[i] = rho * yai + (1.0 - rho) * (2.0 * yb - yi);
+    const double yb = (clampd(r, ld_stream(l + i), ld_stream(u + i)) - r) / sA;
+    ybar[i] = yb;                                            // gathered next by A^T
+    st_stream(y + i, rho * yai + (1.0 - rho) * (2.0 * yb - yi));
     if (want_r) { const double t = yi - yb; acc[0] += t * t; }
     if (want_th) { const double t = yb - yai; acc[1] += t * t; }
   }
@@ -66,9 +66,9 @@ struct EpiAT {
   static constexpr unsigned MAXMASK = 0u;
   __device__ void setup(const DevParams* p, int j) { IterScalars s; s.load(p, j); rho = s.rho; }
   __device__ __forceinline__ void operator()(int i, double q, double*) const {
-    const double aty = ATy[i], atya = ATya[i];
-    d[i] = q - aty;
-    ATy[i] = rho * atya + (1.0 - rho) * (2.0 * q - aty);
+    const double aty = ld_stream(ATy + i), atya = ld_stream(ATya + i);
+    d[i] = q - aty;                                          // gathered next by Q-apply #2
+    st_stream(ATy + i, rho * atya + (1.0 - rho) * (2.0 * q - aty));
     if (check) { g[i] = q; e[i] = q - atya; }
   }
 };
@@ -99,11 +99,11 @@ struct EpiQ2 {
     sigma = s.sigma; sQ = s.sQ; kappa = s.kappa; rho = s.rho;
   }
   __device__ __forceinline__ void operator()(int i, double q2, double* acc) const {
-    const double xhi = xh[i], wi = w[i], Qwi = Qw[i], di = d[i];
+    const double xhi = ld_stream(xh + i), wi = ld_stream(w + i), Qwi = ld_stream(Qw + i), di = d[i];
     const double inv = 1.0 / (1.0 + sQ);
     const double wb = (sQ * wi + xhi) * inv + kappa * di;
-    const double Qwb = (sQ * Qwi + q1[i]) * inv + kappa * q2;
-    const double wai = wa[i], Qwai = Qwa[i], xai = xa[i];
+    const double Qwb = (sQ * Qwi + ld_stream(q1 + i)) * inv + kappa * q2;
+    const double wai = ld_stream(wa + i), Qwai = ld_stream(Qwa + i), xai = ld_stream(xa + i);
     if (want_r || check || trace) {
       const double xb = XB[i];
       if (want_r) {
@@ -121,11 +121,11 @@ struct EpiQ2 {
     const double xn = rho * xai + (1.0 - rho) * xhi;
     const double wn = rho * wai + (1.0 - rho) * (2.0 * wb - wi);
     const double Qwn = rho * Qwai + (1.0 - rho) * (2.0 * Qwb - Qwi);
-    w[i] = wn; Qw[i] = Qwn;
+    st_stream(w + i, wn); st_stream(Qw + i, Qwn);
     if (trace) x[i] = xn;
-    const double rz = xn + sigma * (-Qwn + ATy[i] - c[i]);
-    const double xbn = clampd(rz, L[i], U[i]);
-    xh[i] = 2.0 * xbn - xn;
+    const double rz = xn + sigma * (-Qwn + ld_stream(ATy + i) - ld_stream(c + i));
+    const double xbn = clampd(rz, ld_stream(L + i), ld_stream(U + i));
+    xh[i] = 2.0 * xbn - xn;                                  // gathered next by Q-apply #1
     if (xb_next) { XB[i] = xbn; ZB[i] = (xbn - rz) / sigma; }
   }
 };

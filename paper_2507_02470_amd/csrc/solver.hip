@@ -548,8 +548,11 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   hipEvent_t e0, e1;
   HQC(hipEventCreate(&e0));
   HQC(hipEventCreate(&e1));
-  float best = 1e30f;
-  int bestG = M.G;
+  // the default choice is kept unless another is at least 5% faster, so that
+  // near-ties do not flip between runs
+  const int G0 = M.G;
+  float best = 1e30f, t_default = 1e30f;
+  int bestG = G0;
   for (int G : Gs) {
     M.G = G;
     launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
@@ -559,9 +562,10 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
     HQC(hipEventSynchronize(e1));
     float ms = 0;
     HQC(hipEventElapsedTime(&ms, e0, e1));
+    if (G == G0) t_default = ms;
     if (ms < best) { best = ms; bestG = G; }
   }
-  M.G = bestG;
+  M.G = best < 0.95f * t_default ? bestG : G0;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
 }

@@ -212,6 +212,8 @@ struct Mat {
   int G = 4;
 };
 
+#define HQ_PROF_ITERS 64
+
 struct hprqp_handle {
   int dev = 0;
   hipStream_t st = nullptr;
@@ -246,9 +248,10 @@ struct hprqp_handle {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   int graph_T = 0;
-  // kernel timing (profile_kernels): events around the four products of two
-  // iterations per segment, accumulated over the solve
-  hipEvent_t pev[2][4][2] = {};
+  // kernel timing (profile_kernels): events around the four products of the
+  // plain iterations 1..HQ_PROF_ITERS of a timed segment, accumulated over the
+  // solve (the first and the check iteration carry extra reductions)
+  hipEvent_t pev[HQ_PROF_ITERS][4][2] = {};
   double prof_ms[4] = {0, 0, 0, 0};
   long long prof_n[4] = {0, 0, 0, 0};
   hipStream_t own_st = nullptr;
@@ -368,7 +371,7 @@ void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
   const bool want_r = rgroup >= 0;
   const bool xb_next = trace || (j >= Tseg - 2);
   int ps = -1;  // timing sample index of this iteration
-  if (prof && !trace && Tseg >= 4) ps = (j == Tseg / 3) ? 0 : (j == (2 * Tseg) / 3 ? 1 : -1);
+  if (prof && !trace && j >= 1 && j <= HQ_PROF_ITERS && j < Tseg - 1) ps = j - 1;
   auto mark = [&](int kind, int edge) {
     if (ps >= 0) HQC(hipEventRecord(h.pev[ps][kind][edge], h.st));
   };
@@ -800,7 +803,7 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
     }
     HQC(hipStreamSynchronize(h.st));
     if (prof) {
-      for (int ps = 0; ps < 2; ++ps)
+      for (int ps = 0; ps < HQ_PROF_ITERS && ps + 1 < Tseg - 1; ++ps)
         for (int kind = 0; kind < 4; ++kind) {
           if (m == 0 && (kind == 1 || kind == 2)) continue;
           float ms = 0.f;

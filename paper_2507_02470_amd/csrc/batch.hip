@@ -2,10 +2,11 @@
 // 2507.02470) in one persistent kernel on one MI355X.
 //
 // One 512-thread workgroup owns one instance at a time; instances are pulled
-// from a work queue ordered by size (largest first).  Every per-variable
-// vector of the iteration, and the low-rank factor F of Q = diag(d) + F F^T,
-// lives in registers (HB_EPT variables per thread, so n <= 512 * HB_EPT);
-// vectors of length m (<= 64) live in LDS.  The whole method runs on the
+// from a work queue ordered by size (largest first).  The iterate, the
+// per-iteration vectors and the low-rank factor F of Q = diag(d) + F F^T
+// live in registers (HB_EPT variables per thread, so n <= 512 * HB_EPT; F
+// padded to rank 10 or 16 by template); the Halpern anchors and vectors of
+// length m (<= 64) live in LDS.  The whole method runs on the
 // device in FP64: power method for lambda_A and lambda_Q, the sigma0 rule,
 // the iteration, the merit R~, the stopping test, the restart criteria of
 // Section 3.2 and the golden-section sigma update of Algorithm 5 (thread 0,
@@ -30,6 +31,8 @@ extern thread_local std::string g_err;
 #define HB_NMAX (HB_BS * HB_EPT)
 #define HB_MMAX 64
 #define HB_RMAX 16
+#define HB_APIECE 256                                  // nonzeros of A per wave work item
+#define HB_PMAX (HB_MMAX + HB_MMAX * HB_NMAX / HB_APIECE)  // pieces of A at most
 
 struct BInst {
   int n, m, r;
@@ -39,6 +42,7 @@ struct BInst {
   const double* aval;
   const int *trp, *tci;   // A^T (n x m) CSR, rows ordered by row of A
   const double* tval;
+  const double* FT;       // F with rows padded to the kernel's rank RM (entries k >= r zero)
   long long off_n, off_m;
   long long annz;         // nonzeros of A
 };
@@ -59,97 +63,196 @@ struct BInfo {
 };
 
 // ---------------------------------------------------------------------------
-// block-wide reductions (fixed order: wave butterfly, then waves in order)
+// LDS of one instance
 // ---------------------------------------------------------------------------
+#define HB_RED 16   // most values reduced at once
+
 struct BShared {
-  double red[HB_WAVES][32];
-  double out[32];
-  double vm[HB_NMAX];          // a length-n vector shared by the block (A v, A xbar)
+  alignas(16) double red[2][HB_RED][HB_WAVES];   // wave partials, two buffers used in turn
+  double vm[HB_NMAX];                // a length-n vector shared by the block (A v, A xbar)
+  // Halpern anchors u^{r,0} and their images (read once per iteration)
+  double xa[HB_NMAX], wa[HB_NMAX], Qwa[HB_NMAX], ATya[HB_NMAX];
+  // iterate u^{r,t} = (x, w) with the images Q w and A^T y kept by linearity
+  double xs[HB_NMAX], ws[HB_NMAX], Qws[HB_NMAX], ATys[HB_NMAX];
   double y[HB_MMAX], ya[HB_MMAX], yb[HB_MMAX], l[HB_MMAX], u[HB_MMAX], ry[HB_MMAX];
-  double yn[HB_MMAX];          // y^{t+1} (Halpern) until the check is done
-  double pw[HB_MMAX];          // power method vector (length m)
-  double t[HB_RMAX];           // F^T (.) of the current product
+  double yn[HB_MMAX];                // y^{t+1} (Halpern) until the check is done
+  double pw[HB_MMAX];                // power method vector (length m)
+  // A products: row r of A is cut into pieces of HB_APIECE nonzeros; piece
+  // q belongs to row prow[q] and pieces pstart[r] .. pstart[r+1]-1 to row r
+  double part[HB_PMAX];
+  short prow[HB_PMAX];
+  int pstart[HB_MMAX + 1];
+  int np;
   double ctrl[8];
   int inst;
 };
 
+// DPP move of a double (both 32-bit halves with the same control); lanes
+// without a source read 0, the identity of the sums and of the maxima of
+// non-negative values reduced here.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave reduction with DPP (fixed pattern: quad swaps, row shifts by 4 and 8,
+// row broadcasts 15 and 31); the result is exact in lane 63 only.
+template <bool MX>
+__device__ __forceinline__ double wave_reduce63(double v) {
+  auto op = [](double a, double b) { return MX ? fmax(a, b) : a + b; };
+  v = op(v, dpp_mov<0xb1>(v));          // quad_perm [1,0,3,2]
+  v = op(v, dpp_mov<0x4e>(v));          // quad_perm [2,3,0,1]
+  v = op(v, dpp_mov<0x114>(v));         // row_shr:4
+  v = op(v, dpp_mov<0x118>(v));         // row_shr:8
+  v = op(v, dpp_mov<0x142, 0xa>(v));    // row_bcast:15
+  v = op(v, dpp_mov<0x143, 0xc>(v));    // row_bcast:31
+  return v;
+}
+
+// Block-wide reduction of K values (sum, or max where bit s of maxmask is
+// set; maxima only of non-negative values) with one barrier: DPP wave
+// reductions, lane 63 of each wave stores its partials, then every wave
+// combines the partials of value s on lanes 8s..8s+7 with a fixed butterfly
+// and broadcasts the result.  Fixed order, deterministic.  The two partial
+// buffers alternate between calls, so a buffer is rewritten only after every
+// thread has passed the barrier of the call in between.
 template <int K>
-__device__ __forceinline__ void bred(BShared& S, double (&v)[K], unsigned maxmask) {
+__device__ __forceinline__ void bred(BShared& S, int& par, double (&v)[K], unsigned maxmask) {
+  static_assert(K <= HB_RED && HB_WAVES == 8, "reduction layout");
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int s = 0; s < K; ++s) {
-    const double x = ((maxmask >> s) & 1u) ? wave_max(v[s]) : wave_sum(v[s]);
-    if (lane == 0) S.red[wv][s] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < K) {
-    const int s = threadIdx.x;
-    const bool mx = (maxmask >> s) & 1u;
-    double x = S.red[0][s];
-    for (int w = 1; w < HB_WAVES; ++w) x = mx ? fmax(x, S.red[w][s]) : x + S.red[w][s];
-    S.out[s] = x;
+    const double x = ((maxmask >> s) & 1u) ? wave_reduce63<true>(v[s]) : wave_reduce63<false>(v[s]);
+    if (lane == 63) S.red[par][s][wv] = x;
   }
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < K; ++s) v[s] = S.out[s];
-  __syncthreads();
+  for (int s0 = 0; s0 < K; s0 += 8) {
+    const int s = s0 + (lane >> 3), w = lane & 7;
+    const bool mx = (maxmask >> s) & 1u;
+    double x = s < K ? S.red[par][s][w] : 0.0;
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      const double y = __shfl_xor(x, off);
+      x = mx ? fmax(x, y) : x + y;
+    }
+#pragma unroll
+    for (int q = s0; q < K && q < s0 + 8; ++q) v[q] = __shfl(x, (q - s0) * 8);
+  }
+  par ^= 1;
 }
 
 // ---------------------------------------------------------------------------
 // the per-instance operator pieces
 // ---------------------------------------------------------------------------
+template <int RM>
 struct Elem {
   int n, m, r;
-  double c[HB_EPT], L[HB_EPT], U[HB_EPT], dg[HB_EPT], F[HB_EPT][HB_RMAX];
+  const double* FT;       // F with rows padded to RM: F(i, k) = FT[i RM + k], zero for k >= r
+  const double *c, *L, *U, *dg;
   __device__ bool valid(int e) const { return (int)threadIdx.x + e * HB_BS < n; }
   __device__ int idx(int e) const { return threadIdx.x + e * HB_BS; }
 };
 
-// q = Q p = diag(d) p + F (F^T p)
-__device__ __forceinline__ void q_apply(BShared& S, const Elem& E, const double (&p)[HB_EPT], double (&q)[HB_EPT]) {
-  double t[HB_RMAX];
+// q = Q p = diag(d) p + F (F^T p).  F is read from the library's copy with
+// rows padded to RM entries (16-byte loads at fixed offsets from one address
+// per entry; L2-resident while the instance is solved).
+template <int RM>
+__device__ __forceinline__ void q_apply(BShared& S, int& par, const Elem<RM>& E, const double (&p)[HB_EPT],
+                                        double (&q)[HB_EPT]) {
+  static_assert(RM % 2 == 0, "rows are read in pairs");
+  double t[RM];
 #pragma unroll
-  for (int k = 0; k < HB_RMAX; ++k) t[k] = 0.0;
+  for (int k = 0; k < RM; ++k) t[k] = 0.0;
 #pragma unroll
   for (int e = 0; e < HB_EPT; ++e)
     if (E.valid(e)) {
+      const double2* f = reinterpret_cast<const double2*>(E.FT + (size_t)E.idx(e) * RM);
 #pragma unroll
-      for (int k = 0; k < HB_RMAX; ++k) t[k] += E.F[e][k] * p[e];
+      for (int k = 0; k < RM / 2; ++k) {
+        const double2 v = f[k];
+        t[2 * k] += v.x * p[e];
+        t[2 * k + 1] += v.y * p[e];
+      }
     }
-  bred<HB_RMAX>(S, t, 0u);
+  bred<RM>(S, par, t, 0u);
 #pragma unroll
   for (int e = 0; e < HB_EPT; ++e) {
-    double s = E.dg[e] * p[e];
+    double s = 0.0;
+    if (E.valid(e)) {
+      s = E.dg[E.idx(e)] * p[e];
+      const double2* f = reinterpret_cast<const double2*>(E.FT + (size_t)E.idx(e) * RM);
 #pragma unroll
-    for (int k = 0; k < HB_RMAX; ++k) s += E.F[e][k] * t[k];
-    q[e] = E.valid(e) ? s : 0.0;
+      for (int k = 0; k < RM / 2; ++k) {
+        const double2 v = f[k];
+        s += v.x * t[2 * k];
+        s += v.y * t[2 * k + 1];
+      }
+    }
+    q[e] = s;
   }
 }
 
-// out[row] = (A p)_row for all rows (LDS S.ry), p staged through S.vm.
-__device__ __forceinline__ void a_apply(BShared& S, const Elem& E, const BInst& I, const double (&p)[HB_EPT]) {
+// Pieces of the rows of A for a_apply (thread 0, once per instance).
+__device__ void a_pieces(BShared& S, const BInst& I) {
+  int q = 0;
+  for (int r = 0; r < I.m; ++r) {
+    S.pstart[r] = q;
+    const int len = I.arp[r + 1] - I.arp[r];
+    for (int c = 0; c * HB_APIECE < len; ++c) S.prow[q++] = (short)r;
+  }
+  S.pstart[I.m] = q;
+  S.np = q;
+}
+
+// S.ry[row] = (A p)_row, p staged through S.vm.  The waves share the pieces
+// of all rows (a dense row does not serialise on one wave); thread row < m
+// then adds its row's pieces in order and is the only reader of S.ry[row].
+template <int RM>
+__device__ __forceinline__ void a_apply(BShared& S, const Elem<RM>& E, const BInst& I, const double (&p)[HB_EPT]) {
 #pragma unroll
   for (int e = 0; e < HB_EPT; ++e)
     if (E.valid(e)) S.vm[E.idx(e)] = p[e];
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int row = wv; row < E.m; row += HB_WAVES) {
+  for (int q = wv; q < S.np; q += HB_WAVES) {
+    const int row = S.prow[q];
+    const int b = I.arp[row] + (q - S.pstart[row]) * HB_APIECE;
+    const int e = min(I.arp[row + 1], b + HB_APIECE);
     double s = 0.0;
-    for (int k = I.arp[row] + lane; k < I.arp[row + 1]; k += 64) s += I.aval[k] * S.vm[I.aci[k]];
+#pragma unroll
+    for (int u = 0; u < HB_APIECE / 64; ++u) {
+      const int k = b + lane + 64 * u;
+      if (k < e) s += I.aval[k] * S.vm[I.aci[k]];
+    }
     s = wave_sum(s);
-    if (lane == 0) S.ry[row] = s;
+    if (lane == 0) S.part[q] = s;
   }
   __syncthreads();
+  if ((int)threadIdx.x < E.m) {
+    double s = 0.0;
+    for (int q = S.pstart[threadIdx.x]; q < S.pstart[threadIdx.x + 1]; ++q) s += S.part[q];
+    S.ry[threadIdx.x] = s;
+  }
 }
 
-// g = A^T yv (yv in LDS, length m)
-__device__ __forceinline__ void at_apply(const Elem& E, const BInst& I, const double* yv, double (&g)[HB_EPT]) {
+// g = A^T yv (yv in LDS, length m); tb/te: the entries' ranges in A^T,
+// loaded once per instance.  Two entries per step keep two loads in flight.
+template <int RM>
+__device__ __forceinline__ void at_apply(const Elem<RM>& E, const BInst& I, const int (&tb)[HB_EPT],
+                                         const int (&te)[HB_EPT], const double* yv, double (&g)[HB_EPT]) {
 #pragma unroll
   for (int e = 0; e < HB_EPT; ++e) {
     double s = 0.0;
-    if (E.valid(e)) {
-      const int i = E.idx(e);
-      for (int k = I.trp[i]; k < I.trp[i + 1]; ++k) s += I.tval[k] * yv[I.tci[k]];
+    for (int k = tb[e]; k < te[e]; k += 2) {
+      const bool two = k + 1 < te[e];
+      const double v0 = I.tval[k], v1 = two ? I.tval[k + 1] : 0.0;
+      const int c0 = I.tci[k], c1 = two ? I.tci[k + 1] : c0;
+      s += v0 * yv[c0];
+      if (two) s += v1 * yv[c1];
     }
     g[e] = s;
   }
@@ -172,17 +275,73 @@ __device__ double golden_sigma_dev(double th1, double th2, double th3, double la
   return exp(0.5 * (a + b));
 }
 
+// Halpern step for entry i: u^{r,t+1} = rho u^{r,0} + (1 - rho)(2 ubar - u),
+// with Q w and A^T y carried along by linearity
+__device__ __forceinline__ void halpern(BShared& S, int i, double rho, bool has_rows, double xb, double wb,
+                                        double Qwb, double g) {
+  const double xn = rho * S.xa[i] + (1.0 - rho) * (2.0 * xb - S.xs[i]);
+  const double wn = rho * S.wa[i] + (1.0 - rho) * (2.0 * wb - S.ws[i]);
+  const double Qwn = rho * S.Qwa[i] + (1.0 - rho) * (2.0 * Qwb - S.Qws[i]);
+  const double ATyn = rho * S.ATya[i] + (1.0 - rho) * (2.0 * g - S.ATys[i]);
+  S.xs[i] = xn; S.ws[i] = wn; S.Qws[i] = Qwn; S.ATys[i] = has_rows ? ATyn : 0.0;
+}
+
+// Stopping test, restart criteria (Section 3.2) and the sigma update of
+// Algorithm 5 at a check; thread 0 only, results in S.ctrl.  Kept out of
+// line: it runs once per check and its golden section needs registers the
+// iteration does not.
+__device__ __noinline__ void check_decision(BShared& S, const BOpts& o, double eta_p, double eta_d, double eta_gap,
+                                            double R, double Rr0, double Rprev, long long t, long long k, double lamA,
+                                            double lamQ, double thy, double thw, double thq, double th2, double th3,
+                                            double sigma, double alpha3, double R0ref) {
+  const double kkt = fmax(eta_p, fmax(eta_d, eta_gap));
+  int tm = -1, rs = 0;
+  if (isnan(kkt) || isnan(R)) tm = HPRQP_NUMERICAL;
+  else if (kkt <= o.tol) tm = HPRQP_SOLVED;
+  else if (k >= o.max_iter) tm = HPRQP_MAX_ITER;
+  else if (o.enable_restart) {
+    const bool c1 = R <= o.alpha1 * Rr0;                              // eq:restart_1
+    const bool c2 = Rprev >= 0.0 && R <= o.alpha2 * Rr0 && R > Rprev; // eq:restart_2
+    const bool c3 = (double)t >= alpha3 * (double)k;                  // eq:restart_3
+    rs = c1 || c2 || c3;
+  }
+  double sig = sigma, a3 = alpha3, r0 = R0ref;
+  if (tm < 0 && rs) {
+    if (r0 < 0.0) r0 = R;
+    const double ratio = R / r0;
+    if (o.enable_sigma_update) {
+      // Algorithm 5
+      double th1 = lamA * thy + lamQ * thw - 2.0 * thq;
+      th1 = fmax(th1, 1e-12); th2 = fmax(th2, 1e-12); th3 = fmax(th3, 0.0);
+      const double snew = golden_sigma_dev(th1, th2, th3, lamQ);
+      const double beta = exp(-ratio);
+      sig = exp(beta * log(snew) + (1.0 - beta) * log(sig));
+    }
+    if (ratio <= 0.1) a3 = 0.2;
+  }
+  S.ctrl[0] = tm; S.ctrl[1] = rs; S.ctrl[2] = sig; S.ctrl[3] = a3; S.ctrl[4] = r0;
+}
+
 // ---------------------------------------------------------------------------
-// persistent kernel
+// persistent kernel (RM: largest rank of F handled, F rows padded with zeros)
 // ---------------------------------------------------------------------------
+template <int RM>
 __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__ insts, const int* __restrict__ order,
                                                       int count, int* __restrict__ queue, BOpts o,
                                                       const double* __restrict__ y0, const double* __restrict__ w0,
                                                       const double* __restrict__ x0, double* __restrict__ yo,
                                                       double* __restrict__ zo, double* __restrict__ wo,
-                                                      double* __restrict__ xo, BInfo* __restrict__ infos) {
+                                                      double* __restrict__ xo, BInfo* __restrict__ infos,
+                                                      double* __restrict__ hbuf) {
   __shared__ BShared S;
   const int tid = threadIdx.x;
+  int par = 0;
+  // the block's check buffer: xbar, wbar, Q wbar, A^T ybar, zbar (entries owned per thread)
+  double* const Hx = hbuf + (size_t)blockIdx.x * 5 * HB_NMAX;
+  double* const Hw = Hx + HB_NMAX;
+  double* const HQw = Hx + 2 * HB_NMAX;
+  double* const Hg = Hx + 3 * HB_NMAX;
+  double* const Hz = Hx + 4 * HB_NMAX;   // reduction buffer in turn (uniform over the block)
   for (;;) {
     if (tid == 0) S.inst = atomicAdd(queue, 1);
     __syncthreads();
@@ -191,37 +350,35 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
     if (qi >= count) break;                        // every wave leaves together
     const int ii = order[qi];
     const BInst I = insts[ii];
-    Elem E;
-    E.n = I.n; E.m = I.m; E.r = I.r;
+    Elem<RM> E;
+    E.n = I.n; E.m = I.m; E.r = I.r; E.FT = I.FT;
+    E.c = I.c; E.L = I.L; E.U = I.U; E.dg = I.dg;
     const int n = I.n, m = I.m;
+    if (tid < m) { S.l[tid] = I.l[tid]; S.u[tid] = I.u[tid]; }
+    if (tid == 0) a_pieces(S, I);
+    int tb[HB_EPT], te[HB_EPT];   // A^T ranges of the thread's entries (empty when invalid)
 #pragma unroll
     for (int e = 0; e < HB_EPT; ++e) {
       const int i = E.idx(e);
-      const bool ok = i < n;
-      E.c[e] = ok ? I.c[i] : 0.0;
-      E.L[e] = ok ? I.L[i] : 0.0;
-      E.U[e] = ok ? I.U[i] : 0.0;
-      E.dg[e] = ok ? I.dg[i] : 0.0;
-#pragma unroll
-      for (int k = 0; k < HB_RMAX; ++k) E.F[e][k] = (ok && k < I.r) ? I.F[(size_t)i * I.r + k] : 0.0;
+      tb[e] = i < n ? I.trp[i] : 0;
+      te[e] = i < n ? I.trp[i + 1] : 0;
     }
-    if (tid < m) { S.l[tid] = I.l[tid]; S.u[tid] = I.u[tid]; }
     __syncthreads();
 
     // ---- lambda_Q: power method on Q from the all-ones start (Section 4.1) ----
     double lamQ = o.lamQ, lamA = o.lamA;
-    double pv[HB_EPT], qv[HB_EPT];
     if (!(lamQ > 0.0)) {
+      double pv[HB_EPT], qv[HB_EPT];
       const double s0 = 1.0 / sqrt((double)n);
 #pragma unroll
       for (int e = 0; e < HB_EPT; ++e) pv[e] = E.valid(e) ? s0 : 0.0;
       double lam = 0.0, lam_old = 0.0;
       for (int it = 1; it <= 5000; ++it) {
-        q_apply(S, E, pv, qv);
+        q_apply(S, par, E, pv, qv);
         double rr[2] = {0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) { rr[0] += pv[e] * qv[e]; rr[1] += qv[e] * qv[e]; }
-        bred<2>(S, rr, 0u);
+        bred<2>(S, par, rr, 0u);
         lam = rr[0];
         if (rr[1] == 0.0) break;
         if (it > 1 && fabs(lam - lam_old) <= 1e-6 * fabs(lam)) break;
@@ -234,15 +391,16 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
     }
     // ---- lambda_A: power method on A A^T from the all-ones start ----
     if (!(lamA > 0.0) && m > 0) {
+      double pv[HB_EPT];
       if (tid < m) S.pw[tid] = 1.0 / sqrt((double)m);
       __syncthreads();
       double lam = 0.0, lam_old = 0.0;
       for (int it = 1; it <= 5000; ++it) {
-        at_apply(E, I, S.pw, pv);                  // u = A^T v
+        at_apply(E, I, tb, te, S.pw, pv);          // u = A^T v
         a_apply(S, E, I, pv);                      // w = A u  -> S.ry
         double rr[2] = {0.0, 0.0};
         if (tid < m) { rr[0] = S.pw[tid] * S.ry[tid]; rr[1] = S.ry[tid] * S.ry[tid]; }
-        bred<2>(S, rr, 0u);
+        bred<2>(S, par, rr, 0u);
         lam = rr[0];
         if (rr[1] == 0.0) break;
         if (it > 1 && fabs(lam - lam_old) <= 1e-6 * fabs(lam)) break;
@@ -260,8 +418,11 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
       nrm[0] = bi * bi; nrm[1] = bi;
     }
 #pragma unroll
-    for (int e = 0; e < HB_EPT; ++e) { nrm[2] += E.c[e] * E.c[e]; nrm[3] = fmax(nrm[3], fabs(E.c[e])); }
-    bred<4>(S, nrm, 0xAu);
+    for (int e = 0; e < HB_EPT; ++e) {
+      const double ce = E.valid(e) ? E.c[E.idx(e)] : 0.0;
+      nrm[2] += ce * ce; nrm[3] = fmax(nrm[3], fabs(ce));
+    }
+    bred<4>(S, par, nrm, 0xAu);
     const double binf = nrm[1], cinf = nrm[3];
     double sigma;
     {
@@ -273,15 +434,14 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
     const double sigma_init = sigma;
 
     // ---- state: origin or warm start ----
-    double x[HB_EPT], w[HB_EPT], Qw[HB_EPT], ATy[HB_EPT], xa[HB_EPT], wa[HB_EPT], Qwa[HB_EPT], ATya[HB_EPT];
-    double xb[HB_EPT], zb[HB_EPT], wb[HB_EPT], Qwb[HB_EPT], g[HB_EPT];
+    // the iterate lives in LDS; thread t owns entries t + 512 e (no other
+    // thread reads them), so updates need no barrier
 #pragma unroll
     for (int e = 0; e < HB_EPT; ++e) {
       const int i = E.idx(e);
       const bool ok = i < n;
-      x[e] = (ok && x0) ? x0[I.off_n + i] : 0.0;
-      w[e] = (ok && w0) ? w0[I.off_n + i] : 0.0;
-      xb[e] = zb[e] = wb[e] = Qwb[e] = g[e] = 0.0;
+      S.xs[i] = (ok && x0) ? x0[I.off_n + i] : 0.0;
+      S.ws[i] = (ok && w0) ? w0[I.off_n + i] : 0.0;
     }
     if (tid < m) S.y[tid] = y0 ? y0[I.off_m + tid] : 0.0;
     __syncthreads();
@@ -293,13 +453,21 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
     bool new_epoch = true;
     while (term < 0) {
       if (new_epoch) {
-        // anchor u^{r,0} = u; exact A^T y and Q w
+        // anchor u^{r,0} = u; exact A^T y and Q w.  Each thread keeps the
+        // anchors of its own variables in LDS (no other thread reads them).
         if (tid < m) S.ya[tid] = S.y[tid];
         __syncthreads();
-        at_apply(E, I, S.y, ATy);
-        q_apply(S, E, w, Qw);
+        double ATy[HB_EPT], Qw[HB_EPT], w[HB_EPT];
 #pragma unroll
-        for (int e = 0; e < HB_EPT; ++e) { xa[e] = x[e]; wa[e] = w[e]; Qwa[e] = Qw[e]; ATya[e] = ATy[e]; }
+        for (int e = 0; e < HB_EPT; ++e) w[e] = S.ws[E.idx(e)];
+        at_apply(E, I, tb, te, S.y, ATy);
+        q_apply(S, par, E, w, Qw);
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) {
+          const int i = E.idx(e);
+          S.Qws[i] = Qw[e]; S.ATys[i] = ATy[e];
+          S.xa[i] = S.xs[i]; S.wa[i] = w[e]; S.Qwa[i] = Qw[e]; S.ATya[i] = ATy[e];
+        }
         t = 0; Rprev = -1.0;
         new_epoch = false;
       }
@@ -307,23 +475,26 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
       const double rho = 1.0 / (double)(t + 2);
       const bool is_check = ((k + 1) % o.check_every == 0) || (k + 1 >= o.max_iter);
       const bool want_r = (t == 0) || is_check;
-      // z/x step ("update-z", "update-x")
-      double xh[HB_EPT];
+      // z/x step ("update-z", "update-x"); zbar itself is formed at checks only
+      double xh[HB_EPT], xb[HB_EPT];
 #pragma unroll
       for (int e = 0; e < HB_EPT; ++e) {
-        const double rz = x[e] + sigma * (-Qw[e] + ATy[e] - E.c[e]);
-        xb[e] = clampd(rz, E.L[e], E.U[e]);
-        zb[e] = (xb[e] - rz) / sigma;
-        xh[e] = E.valid(e) ? 2.0 * xb[e] - x[e] : 0.0;
+        const int i = E.idx(e);
+        const bool ok = E.valid(e);
+        const double xe = S.xs[i];
+        const double rz = xe + sigma * (-S.Qws[i] + S.ATys[i] - (ok ? E.c[i] : 0.0));
+        xb[e] = ok ? clampd(rz, E.L[i], E.U[i]) : 0.0;
+        xh[e] = ok ? 2.0 * xb[e] - xe : 0.0;
       }
       // Q xhat, v = xhat + kappa (Qw - Q xhat)
-      double q1[HB_EPT], v[HB_EPT];
-      q_apply(S, E, xh, q1);
-#pragma unroll
-      for (int e = 0; e < HB_EPT; ++e) v[e] = E.valid(e) ? xh[e] + kappa * (Qw[e] - q1[e]) : 0.0;
+      double q1[HB_EPT];
+      q_apply(S, par, E, xh, q1);
       // y step ("update-y") and its Halpern update
       double dy2 = 0.0, th_y = 0.0;
       if (m > 0) {
+        double v[HB_EPT];
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) v[e] = E.valid(e) ? xh[e] + kappa * (S.Qws[E.idx(e)] - q1[e]) : 0.0;
         a_apply(S, E, I, v);
         if (tid < m) {
           const double yi = S.y[tid], yai = S.ya[tid];
@@ -337,55 +508,86 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
         __syncthreads();
       }
       // g = A^T ybar, d = A^T(ybar - y)
-      double d[HB_EPT];
-      at_apply(E, I, S.yb, g);
+      double d[HB_EPT], g[HB_EPT];
+      at_apply(E, I, tb, te, S.yb, g);
 #pragma unroll
-      for (int e = 0; e < HB_EPT; ++e) d[e] = m > 0 ? g[e] - ATy[e] : 0.0;
+      for (int e = 0; e < HB_EPT; ++e) d[e] = m > 0 ? g[e] - S.ATys[E.idx(e)] : 0.0;
       double q2[HB_EPT];
-      q_apply(S, E, d, q2);
+      q_apply(S, par, E, d, q2);
       // wbar ("update-w") and Q wbar
+      double wb[HB_EPT], Qwb[HB_EPT];
 #pragma unroll
       for (int e = 0; e < HB_EPT; ++e) {
         const double inv = 1.0 / (1.0 + sQ);
-        wb[e] = (sQ * w[e] + xh[e]) * inv + kappa * d[e];
-        Qwb[e] = (sQ * Qw[e] + q1[e]) * inv + kappa * q2[e];
+        const int i = E.idx(e);
+        wb[e] = (sQ * S.ws[i] + xh[e]) * inv + kappa * d[e];
+        Qwb[e] = (sQ * S.Qws[i] + q1[e]) * inv + kappa * q2[e];
       }
       // merit R~ = ||u - ubar||_M (theta decomposition of the metric of Algorithm 3)
       if (want_r) {
         double s7[7] = {dy2, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) {
-          const double dw = w[e] - wb[e], Qdw = Qw[e] - Qwb[e], ATdy = -d[e], QATdy = -q2[e];
-          const double dx = E.valid(e) ? x[e] - xb[e] : 0.0;
+          const int i = E.idx(e);
+          const double dw = S.ws[i] - wb[e], Qdw = S.Qws[i] - Qwb[e], ATdy = -d[e], QATdy = -q2[e];
+          const double dx = E.valid(e) ? S.xs[i] - xb[e] : 0.0;
           s7[1] += dw * Qdw; s7[2] += Qdw * ATdy; s7[3] += dx * dx;
           s7[4] += ATdy * QATdy; s7[5] += ATdy * dx; s7[6] += Qdw * dx;
         }
-        bred<7>(S, s7, 0u);
+        bred<7>(S, par, s7, 0u);
         const double th1 = lamA * s7[0] + lamQ * s7[1] - 2.0 * s7[2];
         const double m2 = sigma * th1 + s7[3] / sigma + sigma * sigma * s7[4] / (1.0 + sQ) + 2.0 * (s7[5] - s7[6]);
         R = sqrt(m2 > 0.0 ? m2 : 0.0);
       }
-      // theta~ of Algorithm 5 and the stopping quantities need the pre-Halpern state
-      double th[5] = {0, 0, 0, 0, 0};
-      double res[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      if (is_check) {
-        // theta~: D = ubar - u^{r,0}; e = A^T (ybar - y_a) = g - ATy_a
-        double ev[HB_EPT], Qe[HB_EPT];
-#pragma unroll
-        for (int e = 0; e < HB_EPT; ++e) ev[e] = m > 0 ? g[e] - ATya[e] : 0.0;
-        q_apply(S, E, ev, Qe);
-        th[0] = th_y;
+      t += 1; k += 1;
+      if (t == 1) Rr0 = R;
+      if (!is_check) {
+        // Halpern step: u^{r,t+1} = rho u^{r,0} + (1 - rho)(2 ubar - u)
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) {
-          const double Dw = wb[e] - wa[e], QDw = Qwb[e] - Qwa[e];
-          const double Dx = E.valid(e) ? xb[e] - xa[e] : 0.0;
+          if (!E.valid(e)) continue;
+          const int i = E.idx(e);
+          halpern(S, i, rho, m > 0, xb[e], wb[e], Qwb[e], g[e]);
+        }
+        if (tid < m) S.y[tid] = S.yn[tid];
+        __syncthreads();
+        continue;
+      }
+
+      // ---- check iteration (every check_every iterations): the bar values go
+      // to the block's buffer H so that the registers of the loop above are
+      // free for the stopping test and Algorithm 5
+#pragma unroll
+      for (int e = 0; e < HB_EPT; ++e) {
+        const int i = E.idx(e);
+        Hx[i] = xb[e]; Hw[i] = wb[e]; HQw[i] = Qwb[e]; Hg[i] = g[e];
+      }
+      // theta~ of Algorithm 5: D = ubar - u^{r,0}; e = A^T (ybar - y_a) = g - ATy_a
+      double th[5] = {th_y, 0, 0, 0, 0};
+      {
+        double ev[HB_EPT], Qe[HB_EPT];
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) ev[e] = (m > 0 && E.valid(e)) ? Hg[E.idx(e)] - S.ATya[E.idx(e)] : 0.0;
+        q_apply(S, par, E, ev, Qe);
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) {
+          if (!E.valid(e)) continue;
+          const int i = E.idx(e);
+          const double Dw = Hw[i] - S.wa[i], QDw = HQw[i] - S.Qwa[i];
+          const double Dx = Hx[i] - S.xa[i];
           th[1] += Dw * QDw; th[2] += QDw * ev[e]; th[3] += Dx * Dx; th[4] += ev[e] * Qe[e];
         }
-        bred<5>(S, th, 0u);
-        // stopping quantities at (ybar, zbar, xbar) (Section 4.1)
-        double Qx[HB_EPT];
-        q_apply(S, E, xb, Qx);
-        if (m > 0) a_apply(S, E, I, xb);            // S.ry = A xbar
+        bred<5>(S, par, th, 0u);
+      }
+      // stopping quantities at (ybar, zbar, xbar) (Section 4.1), with
+      // zbar = (xbar - r_z) / sigma formed here
+      {
+        double res[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double xbv[HB_EPT], Qx[HB_EPT];
+#pragma unroll
+        for (int e = 0; e < HB_EPT; ++e) xbv[e] = Hx[E.idx(e)];
+        q_apply(S, par, E, xbv, Qx);
+        if (m > 0) a_apply(S, E, I, xbv);           // S.ry = A xbar
         // res: 0 max|Ax-PiK|, 1 max|Ax|, 2 sum(l y+ + u y-), 3 #inf, 4 max|dual|, 5 max|g|, 6 max|Qx|,
         //      7 <x,Qx>, 8 <c,x>, 9 sum(L z+ + U z-) (+ #inf folded into 3)
         if (tid < m) {
@@ -398,15 +600,20 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) {
           if (!E.valid(e)) continue;
-          res[4] = fmax(res[4], fabs(-Qx[e] + g[e] + zb[e] - E.c[e]));
-          res[5] = fmax(res[5], fabs(g[e]));
+          const int i = E.idx(e);
+          const double ce = E.c[i], Le = E.L[i], Ue = E.U[i], ge = Hg[i];
+          const double rz = S.xs[i] + sigma * (-S.Qws[i] + S.ATys[i] - ce);
+          const double zbe = (xbv[e] - rz) / sigma;
+          Hz[i] = zbe;
+          res[4] = fmax(res[4], fabs(-Qx[e] + ge + zbe - ce));
+          res[5] = fmax(res[5], fabs(ge));
           res[6] = fmax(res[6], fabs(Qx[e]));
-          res[7] += xb[e] * Qx[e];
-          res[8] += E.c[e] * xb[e];
-          if (zb[e] > 0.0) { if (isinf(E.L[e])) res[3] += 1.0; else res[9] += E.L[e] * zb[e]; }
-          else if (zb[e] < 0.0) { if (isinf(E.U[e])) res[3] += 1.0; else res[9] += E.U[e] * zb[e]; }
+          res[7] += xbv[e] * Qx[e];
+          res[8] += ce * xbv[e];
+          if (zbe > 0.0) { if (isinf(Le)) res[3] += 1.0; else res[9] += Le * zbe; }
+          else if (zbe < 0.0) { if (isinf(Ue)) res[3] += 1.0; else res[9] += Ue * zbe; }
         }
-        bred<10>(S, res, 0x73u);                    // maxes: 0, 1, 4, 5, 6
+        bred<10>(S, par, res, 0x73u);               // maxes: 0, 1, 4, 5, 6
         eta_p = m > 0 ? res[0] / (1.0 + fmax(binf, res[1])) : 0.0;
         eta_d = res[4] / (1.0 + fmax(cinf, fmax(res[5], res[6])));
         pobj = 0.5 * res[7] + res[8];
@@ -416,78 +623,43 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
           eta_gap = fabs(pobj - dobj) / (1.0 + fmax(fabs(pobj), fabs(dobj)));
         }
       }
-      t += 1; k += 1;
-      if (t == 1) Rr0 = R;
-      // decisions at a check (thread 0, FP64), broadcast through LDS
-      int restart = 0;
-      if (is_check) {
-        if (tid == 0) {
-          const double kkt = fmax(eta_p, fmax(eta_d, eta_gap));
-          int tm = -1, rs = 0;
-          if (isnan(kkt) || isnan(R)) tm = HPRQP_NUMERICAL;
-          else if (kkt <= o.tol) tm = HPRQP_SOLVED;
-          else if (k >= o.max_iter) tm = HPRQP_MAX_ITER;
-          else if (o.enable_restart) {
-            const bool c1 = R <= o.alpha1 * Rr0;                              // eq:restart_1
-            const bool c2 = Rprev >= 0.0 && R <= o.alpha2 * Rr0 && R > Rprev; // eq:restart_2
-            const bool c3 = (double)t >= alpha3 * (double)k;                  // eq:restart_3
-            rs = c1 || c2 || c3;
+      // decisions (thread 0, FP64), broadcast through LDS
+      if (tid == 0)
+        check_decision(S, o, eta_p, eta_d, eta_gap, R, Rr0, Rprev, t, k, lamA, lamQ, th[0], th[1], th[2], th[3], th[4],
+                       sigma, alpha3, R0ref);
+      __syncthreads();
+      term = (int)S.ctrl[0];
+      const int restart = (term < 0) && (S.ctrl[1] != 0.0);
+      sigma = S.ctrl[2]; alpha3 = S.ctrl[3]; R0ref = S.ctrl[4];
+      Rprev = R;
+      __syncthreads();
+      if (term >= 0) {
+        // output ubar of the last iteration (Algorithm 4, "Output")
+        for (int e = 0; e < HB_EPT; ++e) {
+          const int i = E.idx(e);
+          if (i < n) {
+            xo[I.off_n + i] = Hx[i];
+            zo[I.off_n + i] = Hz[i];
+            wo[I.off_n + i] = Hw[i];
           }
-          double sig = sigma, a3 = alpha3, r0 = R0ref;
-          if (tm < 0 && rs) {
-            if (r0 < 0.0) r0 = R;
-            const double ratio = R / r0;
-            if (o.enable_sigma_update) {
-              // Algorithm 5
-              double th1 = lamA * th[0] + lamQ * th[1] - 2.0 * th[2];
-              double th2 = th[3], th3 = th[4];
-              th1 = fmax(th1, 1e-12); th2 = fmax(th2, 1e-12); th3 = fmax(th3, 0.0);
-              const double snew = golden_sigma_dev(th1, th2, th3, lamQ);
-              const double beta = exp(-ratio);
-              sig = exp(beta * log(snew) + (1.0 - beta) * log(sig));
-            }
-            if (ratio <= 0.1) a3 = 0.2;
-          }
-          S.ctrl[0] = tm; S.ctrl[1] = rs; S.ctrl[2] = sig; S.ctrl[3] = a3; S.ctrl[4] = r0;
         }
-        __syncthreads();
-        term = (int)S.ctrl[0];
-        restart = (term < 0) && (S.ctrl[1] != 0.0);
-        sigma = S.ctrl[2]; alpha3 = S.ctrl[3]; R0ref = S.ctrl[4];
-        Rprev = R;
-        __syncthreads();
+        break;
       }
-      if (term >= 0) break;
       if (restart) {
         // u^{r+1,0} = ubar
-#pragma unroll
-        for (int e = 0; e < HB_EPT; ++e) { x[e] = xb[e]; w[e] = wb[e]; }
+        for (int e = 0; e < HB_EPT; ++e) { S.xs[E.idx(e)] = Hx[E.idx(e)]; S.ws[E.idx(e)] = Hw[E.idx(e)]; }
         if (tid < m) S.y[tid] = S.yb[tid];
         __syncthreads();
         r += 1;
         new_epoch = true;
       } else {
-        // Halpern step: u^{r,t+1} = rho u^{r,0} + (1 - rho)(2 ubar - u)
-#pragma unroll
         for (int e = 0; e < HB_EPT; ++e) {
-          const double xn = rho * xa[e] + (1.0 - rho) * (2.0 * xb[e] - x[e]);
-          const double wn = rho * wa[e] + (1.0 - rho) * (2.0 * wb[e] - w[e]);
-          const double Qwn = rho * Qwa[e] + (1.0 - rho) * (2.0 * Qwb[e] - Qw[e]);
-          const double ATyn = rho * ATya[e] + (1.0 - rho) * (2.0 * g[e] - ATy[e]);
-          x[e] = xn; w[e] = wn; Qw[e] = Qwn; ATy[e] = m > 0 ? ATyn : 0.0;
+          if (!E.valid(e)) continue;
+          const int i = E.idx(e);
+          halpern(S, i, rho, m > 0, Hx[i], Hw[i], HQw[i], Hg[i]);
         }
         if (tid < m) S.y[tid] = S.yn[tid];
         __syncthreads();
-      }
-    }
-    // output ubar of the last iteration (Algorithm 4, "Output")
-#pragma unroll
-    for (int e = 0; e < HB_EPT; ++e) {
-      const int i = E.idx(e);
-      if (i < n) {
-        xo[I.off_n + i] = xb[e];
-        zo[I.off_n + i] = zb[e];
-        wo[I.off_n + i] = wb[e];
       }
     }
     if (tid < m) yo[I.off_m + tid] = S.yb[tid];
@@ -568,6 +740,21 @@ __global__ void k_batch_transpose(const BInst* __restrict__ insts, const int* __
   }
 }
 
+// F of every instance with rows padded to the kernel's rank RM:
+// FT[i RM + k] = F(i, k) for k < r, 0 for r <= k < RM
+__global__ void k_batch_ft(const BInst* __restrict__ insts, int count, int RM, double* __restrict__ ft_all,
+                           const long long* __restrict__ ft_off) {
+  const int ii = blockIdx.x;
+  if (ii >= count) return;
+  const BInst I = insts[ii];
+  double* ft = ft_all + ft_off[ii];
+  const long long tot = (long long)RM * I.n;
+  for (long long q = threadIdx.x; q < tot; q += blockDim.x) {
+    const int i = (int)(q / RM), k = (int)(q % RM);
+    ft[q] = k < I.r ? I.F[(size_t)i * I.r + k] : 0.0;
+  }
+}
+
 __global__ void k_zero_int1(int* p) { *p = 0; }
 
 // ---------------------------------------------------------------------------
@@ -586,12 +773,16 @@ struct hprqp_batch {
   double* tval = nullptr;
   long long* d_toff = nullptr;
   int* d_rep = nullptr;
+  double* ft = nullptr;        // F of every instance, rows padded to rank_max
+  long long* d_ftoff = nullptr;
+  double* hbuf = nullptr;      // per-block check buffers
   long long total_n = 0, total_m = 0;
   int grid = 0;
+  int rank_max = 0;       // 10 or 16: the kernel instantiation used
   double last_kernel_s = 0.0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ~hprqp_batch() {
-    void* ps[] = {d_insts, d_order, d_queue, d_flags, d_infos, trp, tci, tval, d_toff, d_rep};
+    void* ps[] = {d_insts, d_order, d_queue, d_flags, d_infos, trp, tci, tval, d_toff, d_rep, ft, d_ftoff, hbuf};
     for (void* p : ps)
       if (p) hipFree(p);
     if (e0) hipEventDestroy(e0);
@@ -679,6 +870,17 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
       hi[i].tci = b->tci + toff[2 * q + 1];
       hi[i].tval = b->tval + toff[2 * q + 1];
     }
+    // padded copy of F: rank class of the kernel (10 or 16)
+    int maxr = 0;
+    for (int i = 0; i < count; ++i) maxr = std::max(maxr, hi[i].r);
+    b->rank_max = maxr <= 10 ? 10 : 16;
+    std::vector<long long> ftoff(count);
+    long long tf = 0;
+    for (int i = 0; i < count; ++i) { ftoff[i] = tf; tf += (long long)b->rank_max * hi[i].n; }
+    HBC(hipMalloc(&b->ft, std::max<long long>(tf, 1) * sizeof(double)));
+    HBC(hipMalloc(&b->d_ftoff, count * sizeof(long long)));
+    HBC(hipMemcpyAsync(b->d_ftoff, ftoff.data(), count * sizeof(long long), hipMemcpyHostToDevice, st));
+    for (int i = 0; i < count; ++i) hi[i].FT = b->ft + ftoff[i];
     HBC(hipMalloc(&b->d_insts, count * sizeof(BInst)));
     HBC(hipMemcpyAsync(b->d_insts, hi.data(), count * sizeof(BInst), hipMemcpyHostToDevice, st));
     HBC(hipMalloc(&b->d_flags, count * sizeof(int)));
@@ -697,6 +899,7 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     HBC(hipMemcpyAsync(b->d_toff, toff.data(), toff.size() * sizeof(long long), hipMemcpyHostToDevice, st));
     k_batch_transpose<<<(int)reps.size(), 256, 0, st>>>(b->d_insts, b->d_rep, (int)reps.size(), b->trp, b->tci,
                                                          b->tval, b->d_toff);
+    k_batch_ft<<<count, 256, 0, st>>>(b->d_insts, count, b->rank_max, b->ft, b->d_ftoff);
     // largest instances first
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -708,8 +911,10 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     int dev = 0, ncu = 0, per_cu = 0;
     HBC(hipGetDevice(&dev));
     HBC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_solve, HB_BS, 0));
+    if (b->rank_max == 10) HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_solve<10>, HB_BS, 0));
+    else HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_solve<16>, HB_BS, 0));
     b->grid = std::max(1, std::min(count, ncu * std::max(per_cu, 1)));
+    HBC(hipMalloc(&b->hbuf, (size_t)b->grid * 5 * HB_NMAX * sizeof(double)));
     HBC(hipEventCreate(&b->e0));
     HBC(hipEventCreate(&b->e1));
     HBC(hipStreamSynchronize(st));
@@ -726,8 +931,12 @@ void solve_batch_impl(hprqp_batch* b, const double* y0, const double* w0, const 
   if (b->own_st) HBC(hipDeviceSynchronize());
   k_zero_int1<<<1, 1, 0, b->st>>>(b->d_queue);
   HBC(hipEventRecord(b->e0, b->st));
-  k_batch_solve<<<b->grid, HB_BS, 0, b->st>>>(b->d_insts, b->d_order, b->count, b->d_queue, b->o, y0, w0, x0, y, z,
-                                               w, x, b->d_infos);
+  if (b->rank_max == 10)
+    k_batch_solve<10><<<b->grid, HB_BS, 0, b->st>>>(b->d_insts, b->d_order, b->count, b->d_queue, b->o, y0, w0, x0,
+                                                    y, z, w, x, b->d_infos, b->hbuf);
+  else
+    k_batch_solve<16><<<b->grid, HB_BS, 0, b->st>>>(b->d_insts, b->d_order, b->count, b->d_queue, b->o, y0, w0, x0,
+                                                    y, z, w, x, b->d_infos, b->hbuf);
   HBC(hipGetLastError());
   HBC(hipEventRecord(b->e1, b->st));
   std::vector<BInfo> hi(b->count);

@@ -59,12 +59,16 @@ def kernel_bytes(qp) -> dict:
     }
 
 
+# sources of the single-instance solver's kernels and launches (the batched
+# solver and the MLP do not enter the dominant kernel)
+SOLVER_SOURCES = ("common.hpp", "spmv.hpp", "epilogues.hpp", "qops.hpp", "solver.hip")
+
+
 def src_hash() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2507_02470_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in SOLVER_SOURCES:
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -5,10 +5,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 shares no code with it.
 
 * ``hprqp_oracle.c`` -- plain single-threaded FP64 C: Algorithm 4 + 5, the
-  metric M, the stopping quantities, the power method.  Loaded via ctypes.
+  metric M, the stopping quantities, the power method, the diagonal
+  preconditioning of Section 4.1.  Loaded via ctypes.
 * ``mlp.py``         -- numpy FP64 forward/backward of the warm-start MLP.
 """
 from .oracle import (  # noqa: F401
     build_oracle, solve, residuals, apply_Q, apply_A, apply_AT, power, sigma0,
-    thetas, mnorm2, sigma_argmin, OracleResult, TERM_NAMES,
+    thetas, mnorm2, sigma_argmin, scaling, OracleResult, TERM_NAMES,
 )

@@ -227,6 +227,58 @@ double orc_sigma_argmin(double th1, double th2, double th3, double lamQ) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Diagonal preconditioning (Section 4.1, "Preconditioning")               */
+/* ------------------------------------------------------------------------ */
+/* Row norms of the scaled K = diag(D, E) [[Q, A^T], [A, 0]] diag(D, E):
+ * p = 0: inf-norm, p = 1: 1-norm.  For variable j the row holds row j of
+ * D Q D and column j of E A D; for constraint i, row i of E A D.          */
+static void scaled_row_norms(const orc_problem *P, const double *D, const double *E, int p,
+                             double *nx, double *ny) {
+  const int n = P->n, m = P->m;
+  double *nq = vnew(n), *na = vnew(n);
+  if (P->qkind == ORC_Q_CSR)
+    for (int i = 0; i < n; ++i)
+      for (int k = P->q_rowptr[i]; k < P->q_rowptr[i + 1]; ++k) {
+        const double a = fabs(D[i] * P->q_val[k] * D[P->q_col[k]]);
+        if (p == 0) { if (a > nq[i]) nq[i] = a; } else nq[i] += a;
+      }
+  for (int i = 0; i < m; ++i) {
+    ny[i] = 0.0;
+    for (int k = P->a_rowptr[i]; k < P->a_rowptr[i + 1]; ++k) {
+      const int j = P->a_col[k];
+      const double a = fabs(E[i] * P->a_val[k] * D[j]);
+      if (p == 0) { if (a > ny[i]) ny[i] = a; if (a > na[j]) na[j] = a; }
+      else { ny[i] += a; na[j] += a; }
+    }
+  }
+  for (int j = 0; j < n; ++j) nx[j] = (p == 0) ? (nq[j] > na[j] ? nq[j] : na[j]) : nq[j] + na[j];
+  free(nq); free(na);
+}
+
+static void divide_by_sqrt(double *f, const double *nrm, int k) {
+  for (int i = 0; i < k; ++i)
+    if (nrm[i] > 0.0) f[i] /= sqrt(nrm[i]);
+}
+
+void orc_scaling(const orc_problem *P, int ruiz_iters, int pock_chambolle, double *D, double *E) {
+  const int n = P->n, m = P->m;
+  double *nx = vnew(n), *ny = vnew(m);
+  for (int j = 0; j < n; ++j) D[j] = 1.0;
+  for (int i = 0; i < m; ++i) E[i] = 1.0;
+  for (int it = 0; it < ruiz_iters; ++it) {          /* Ruiz equilibration */
+    scaled_row_norms(P, D, E, 0, nx, ny);
+    divide_by_sqrt(D, nx, n);
+    divide_by_sqrt(E, ny, m);
+  }
+  if (pock_chambolle) {                              /* Pock-Chambolle, alpha = 1 */
+    scaled_row_norms(P, D, E, 1, nx, ny);
+    divide_by_sqrt(D, nx, n);
+    divide_by_sqrt(E, ny, m);
+  }
+  free(nx); free(ny);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Stopping quantities (Section 4.1, "Termination")                         */
 /* ------------------------------------------------------------------------ */
 void orc_residuals(const orc_problem *P, const double *y, const double *z,
@@ -287,9 +339,12 @@ void orc_residuals(const orc_problem *P, const double *y, const double *z,
 /* ------------------------------------------------------------------------ */
 /* Algorithm 4 (HPR-QP) with Algorithm 5 (SigmaUpdate)                      */
 /* ------------------------------------------------------------------------ */
-int orc_solve(const orc_problem *P, const orc_options *opt,
-              const double *y0, const double *w0, const double *x0,
-              double *y_out, double *z_out, double *w_out, double *x_out, orc_info *info) {
+/* P: the problem iterated on; P0, D, E (when D != NULL): the given problem
+ * whose residuals at the unscaled point (E ybar, zbar / D, D xbar) decide
+ * termination (P is then the scaled problem of orc_scaling).              */
+static int solve_core(const orc_problem *P, const orc_problem *P0, const double *D, const double *E,
+                      const orc_options *opt, const double *y0, const double *w0, const double *x0,
+                      double *y_out, double *z_out, double *w_out, double *x_out, orc_info *info) {
   const int n = P->n, m = P->m;
   const double t_start = now_s();
   memset(info, 0, sizeof(*info));
@@ -381,7 +436,13 @@ int orc_solve(const orc_problem *P, const orc_options *opt,
       double sigma_used = sigma;
       if (is_check) {
         double res[5];
-        orc_residuals(P, yb, zb, xb, res);
+        if (D) {
+          for (int i = 0; i < m; ++i) dy[i] = E[i] * yb[i];
+          for (int j = 0; j < n; ++j) { dw[j] = zb[j] / D[j]; dx[j] = D[j] * xb[j]; }
+          orc_residuals(P0, dy, dw, dx, res);
+        } else {
+          orc_residuals(P, yb, zb, xb, res);
+        }
         info->eta_p = res[0]; info->eta_d = res[1]; info->eta_gap = res[2];
         info->pobj = res[3]; info->dobj = res[4];
         double kkt = res[0];
@@ -452,4 +513,37 @@ int orc_solve(const orc_problem *P, const orc_options *opt,
   free(ATy); free(Qw); free(rz); free(xh); free(wh); free(Qwh); free(vv); free(ry); free(dyv); free(ATd);
   free(dy); free(dw); free(dx);
   return 0;
+}
+
+int orc_solve(const orc_problem *P, const orc_options *opt,
+              const double *y0, const double *w0, const double *x0,
+              double *y_out, double *z_out, double *w_out, double *x_out, orc_info *info) {
+  if (!opt->precondition || (P->qkind != ORC_Q_CSR && P->qkind != ORC_Q_ZERO))
+    return solve_core(P, NULL, NULL, NULL, opt, y0, w0, x0, y_out, z_out, w_out, x_out, info);
+  /* Section 4.1: solve the scaled problem, stop on the given one */
+  const int n = P->n, m = P->m;
+  const int nq = (P->qkind == ORC_Q_CSR) ? P->q_rowptr[n] : 0;
+  const int na = (m > 0) ? P->a_rowptr[m] : 0;
+  double *D = vnew(n), *E = vnew(m);
+  orc_scaling(P, opt->ruiz_iters, 1, D, E);
+  double *qv = vnew(nq), *av = vnew(na), *c = vnew(n), *L = vnew(n), *U = vnew(n), *l = vnew(m), *u = vnew(m);
+  for (int i = 0; i < n && P->qkind == ORC_Q_CSR; ++i)
+    for (int k = P->q_rowptr[i]; k < P->q_rowptr[i + 1]; ++k) qv[k] = D[i] * P->q_val[k] * D[P->q_col[k]];
+  for (int i = 0; i < m; ++i)
+    for (int k = P->a_rowptr[i]; k < P->a_rowptr[i + 1]; ++k) av[k] = E[i] * P->a_val[k] * D[P->a_col[k]];
+  for (int j = 0; j < n; ++j) { c[j] = D[j] * P->c[j]; L[j] = P->L[j] / D[j]; U[j] = P->U[j] / D[j]; }
+  for (int i = 0; i < m; ++i) { l[i] = E[i] * P->l[i]; u[i] = E[i] * P->u[i]; }
+  orc_problem S = *P;
+  S.q_val = qv; S.a_val = av; S.c = c; S.L = L; S.U = U; S.l = l; S.u = u;
+  /* a warm start given in the original variables enters scaled */
+  double *ys = NULL, *ws = NULL, *xs = NULL;
+  if (y0) { ys = vnew(m); for (int i = 0; i < m; ++i) ys[i] = y0[i] / E[i]; }
+  if (w0) { ws = vnew(n); for (int j = 0; j < n; ++j) ws[j] = w0[j] / D[j]; }
+  if (x0) { xs = vnew(n); for (int j = 0; j < n; ++j) xs[j] = x0[j] / D[j]; }
+  int rc = solve_core(&S, P, D, E, opt, ys, ws, xs, y_out, z_out, w_out, x_out, info);
+  for (int i = 0; i < m; ++i) y_out[i] *= E[i];
+  for (int j = 0; j < n; ++j) { z_out[j] /= D[j]; w_out[j] *= D[j]; x_out[j] *= D[j]; }
+  free(D); free(E); free(qv); free(av); free(c); free(L); free(U); free(l); free(u);
+  free(ys); free(ws); free(xs);
+  return rc;
 }

@@ -57,6 +57,9 @@ typedef struct {
   int log_cap;            /* capacity (rows) of check_log                             */
   double *check_log;      /* rows of 10: k, t, R, eta_p, eta_d, eta_gap, sigma_used,
                              restarted, sigma_next, r                                 */
+  int precondition;       /* explicit Q (CSR or zero) only: solve the diagonally
+                             scaled problem, stop on the residuals of the given one   */
+  int ruiz_iters;         /* Ruiz passes of the scaling (Section 4.1: 10)             */
 } orc_options;
 
 typedef struct {
@@ -89,6 +92,17 @@ double orc_mnorm2(const orc_problem *P, double sigma, double lamA, double lamQ,
                   const double *dy, const double *dw, const double *dx);
 /* Algorithm 5 without the smoothing: argmin of f(sigma) by golden section. */
 double orc_sigma_argmin(double th1, double th2, double th3, double lamQ);
+
+/* Diagonal preconditioning (Section 4.1, "Preconditioning"): scale factors
+ * D (n, variables) and E (m, rows of A) of the symmetric scaling of
+ * K = [[Q, A^T], [A, 0]]: `ruiz_iters` Ruiz passes (each scale divided by the
+ * square root of the inf-norm of its row of the currently scaled K), then,
+ * if pock_chambolle, one Pock-Chambolle pass with alpha = 1 (divided by the
+ * square root of the 1-norm of the row).  Explicit Q (CSR or zero) only.
+ * The scaled problem is  Q~ = D Q D, A~ = E A D, c~ = D c, [L, U]~ = [L, U]/D,
+ * [l, u]~ = E [l, u];  its solution maps back as x = D x~, w = D w~,
+ * z = z~ / D, y = E y~.                                                      */
+void orc_scaling(const orc_problem *P, int ruiz_iters, int pock_chambolle, double *D, double *E);
 
 /* eta_p, eta_d, eta_gap, pobj, dobj at (y, z, x); out[5]. */
 void orc_residuals(const orc_problem *P, const double *y, const double *z,

@@ -40,7 +40,8 @@ class _Options(C.Structure):
                 ("alpha1", C.c_double), ("alpha2", C.c_double), ("alpha3", C.c_double),
                 ("enable_restart", C.c_int), ("enable_sigma_update", C.c_int),
                 ("trace_iters", C.c_int), ("trace", _dp),
-                ("log_cap", C.c_int), ("check_log", _dp)]
+                ("log_cap", C.c_int), ("check_log", _dp),
+                ("precondition", C.c_int), ("ruiz_iters", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -83,6 +84,7 @@ def _L():
         _lib.orc_mnorm2.restype = C.c_double
         _lib.orc_sigma_argmin.argtypes = [C.c_double] * 4
         _lib.orc_sigma_argmin.restype = C.c_double
+        _lib.orc_scaling.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int, _dp, _dp]
     return _lib
 
 
@@ -154,7 +156,7 @@ class OracleResult:
 def solve(qp, tol=1e-8, max_iter=100_000, check_every=100, time_limit_s=0.0, sigma0=0.0,
           lambda_A=0.0, lambda_Q=0.0, alpha=(0.2, 0.8, 0.5), enable_restart=True,
           enable_sigma_update=True, trace_iters=0, log_cap=0, y0=None, w0=None, x0=None,
-          power_start_A=None, power_start_Q=None) -> OracleResult:
+          power_start_A=None, power_start_Q=None, precondition=False, ruiz_iters=10) -> OracleResult:
     L = _L()
     M = _Marshal(qp)
     O = _Options()
@@ -165,6 +167,7 @@ def solve(qp, tol=1e-8, max_iter=100_000, check_every=100, time_limit_s=0.0, sig
     O.power_start_A, O.power_start_Q = _d(psA), _d(psQ)
     O.alpha1, O.alpha2, O.alpha3 = alpha
     O.enable_restart, O.enable_sigma_update = int(enable_restart), int(enable_sigma_update)
+    O.precondition, O.ruiz_iters = int(precondition), int(ruiz_iters)
     trace = None
     if trace_iters > 0:
         trace = np.zeros((trace_iters, 2 * qp.m + 4 * qp.n))
@@ -242,6 +245,14 @@ def power(qp, which: str, start, maxit=5000, tol=1e-6):
     it = C.c_int(0)
     lam = _L().orc_power(C.byref(M.P), 0 if which == "A" else 1, _d(s), maxit, tol, C.byref(it))
     return lam, it.value
+
+
+def scaling(qp, ruiz_iters=10, pock_chambolle=True):
+    """Scale factors (D, E) of the diagonal preconditioning (Section 4.1)."""
+    M = _Marshal(qp)
+    D, E = np.zeros(qp.n), np.zeros(max(qp.m, 1))
+    _L().orc_scaling(C.byref(M.P), int(ruiz_iters), int(pock_chambolle), _d(D), _d(E))
+    return D, E[:qp.m].copy()
 
 
 def sigma0(qp) -> float:

@@ -30,6 +30,12 @@ MUTANTS = {
     "kron_transpose": ("acc += T[i + (size_t)s * b] * B[j + (size_t)p * b];",
                        "acc += T[i + (size_t)s * b] * B[b + (size_t)p * j];"),
     "power_no_norm": ("for (int i = 0; i < k; ++i) v[i] = w[i] / nw;", "for (int i = 0; i < k; ++i) v[i] = w[i] / (2.0 * nw);"),
+    "precond_box_unscaled": ("L[j] = P->L[j] / D[j]; U[j] = P->U[j] / D[j];", "L[j] = P->L[j]; U[j] = P->U[j];"),
+    "precond_y_unscale": ("for (int i = 0; i < m; ++i) y_out[i] *= E[i];", "for (int i = 0; i < m; ++i) y_out[i] /= E[i];"),
+    "ruiz_no_sqrt": ("if (nrm[i] > 0.0) f[i] /= sqrt(nrm[i]);", "if (nrm[i] > 0.0) f[i] /= nrm[i];"),
+    "precond_stop_on_scaled": ("        if (D) {\n", "        if (0) {\n"),
+    "ruiz_col_part": ("if (p == 0) { if (a > ny[i]) ny[i] = a; if (a > na[j]) na[j] = a; }",
+                      "if (p == 0) { if (a > ny[i]) ny[i] = a; }"),
 }
 
 

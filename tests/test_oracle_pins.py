@@ -334,3 +334,83 @@ def test_first_sigma_update_from_dense_thetas():
     assert r.check_log[0, 8] == pytest.approx(np.exp(beta * np.log(snew) + (1 - beta) * np.log(s0)), rel=1e-10)
     # the restarted state is the bar point of the restart iteration
     np.testing.assert_allclose(tr["x"][T - 1], xb, rtol=0, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Diagonal preconditioning (Section 4.1, "Preconditioning": Ruiz x10, then
+# Pock-Chambolle with alpha = 1, Q explicit; termination on the given problem)
+# ---------------------------------------------------------------------------
+def _scaled_K(qp, D, E):
+    """Dense D-E scaled K = [[Q, A^T], [A, 0]] (the matrix the scaling equilibrates)."""
+    Q, A = _dense(qp)
+    n, m = qp.n, qp.m
+    K = np.zeros((n + m, n + m))
+    K[:n, :n] = Q
+    K[n:, :n] = A
+    K[:n, n:] = A.T
+    s = np.concatenate([D, E])
+    return s[:, None] * K * s[None, :]
+
+
+def _badly_scaled(qp, seed):
+    """The same kind of QP with variables and rows rescaled by 10^U(-2, 2)."""
+    rng = np.random.default_rng(seed)
+    Q, A = _dense(qp)
+    s = 10.0 ** rng.uniform(-2, 2, qp.n)
+    r = 10.0 ** rng.uniform(-2, 2, qp.m)
+    return qpgen.from_dense(s[:, None] * Q * s[None, :], s * qp.c, qp.L / s, qp.U / s,
+                            r[:, None] * A * s[None, :], r * qp.l, r * qp.u)
+
+
+def test_scaling_closed_forms():
+    rng = np.random.default_rng(21)
+    n = 20
+    # diagonal Q and no rows: one Ruiz pass gives D = q^(-1/2) and the unit
+    # diagonal, which later passes and Pock-Chambolle leave unchanged
+    q = 10.0 ** rng.uniform(-2, 2, n)
+    qp = qpgen.from_dense(np.diag(q), rng.standard_normal(n), -np.ones(n), np.ones(n), np.zeros((0, n)), [], [])
+    D, E = oracle.scaling(qp, ruiz_iters=10)
+    np.testing.assert_allclose(D, q ** -0.5, rtol=1e-14)
+    # Q = 0 and one row alpha 1^T: Ruiz gives D = E = alpha^(-1/2) (all entries 1);
+    # Pock-Chambolle then divides E by the square root of the row's 1-norm n
+    alpha = 37.0
+    qp = qpgen.from_dense(np.zeros((n, n)), rng.standard_normal(n), -np.ones(n), np.ones(n),
+                          alpha * np.ones((1, n)), [-1.0], [1.0])
+    D, E = oracle.scaling(qp, ruiz_iters=10)
+    np.testing.assert_allclose(D, alpha ** -0.5, rtol=1e-14)
+    np.testing.assert_allclose(E, alpha ** -0.5 / np.sqrt(n), rtol=1e-14)
+
+
+def test_ruiz_equilibrates_and_pock_chambolle_bound():
+    qp = _badly_scaled(qpgen.make_small_ccqp(), 5)
+    # Ruiz's iteration converges to rows of unit inf-norm (Ruiz 2001)
+    D, E = oracle.scaling(qp, ruiz_iters=60, pock_chambolle=False)
+    K = _scaled_K(qp, D, E)
+    rmax = np.abs(K).max(axis=1)
+    nz = rmax > 0
+    np.testing.assert_allclose(rmax[nz], 1.0, atol=1e-6)
+    # Pock-Chambolle with alpha = 1 bounds the scaled operator: ||D K D||_2 <= 1
+    # (Pock & Chambolle 2011, Lemma 2), alone and after the Ruiz passes
+    for ruiz in (0, 10):
+        D, E = oracle.scaling(qp, ruiz_iters=ruiz, pock_chambolle=True)
+        assert np.linalg.norm(_scaled_K(qp, D, E), 2) <= 1.0 + 1e-12
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_preconditioned_solve_bruteforce(seed):
+    n = 3 + seed % 3
+    m = 1 + seed % 3
+    qp = _badly_scaled(qpgen.make_tiny(100 + seed, n=n, m=m, n_eq=seed % 2), seed)
+    Q, A = _dense(qp)
+    best = pins.kkt_enumerate(Q, qp.c, qp.L, qp.U, A, qp.l, qp.u)
+    assert best is not None
+    r = oracle.solve(qp, tol=1e-10, max_iter=400_000, check_every=10, precondition=True)
+    assert r.term == "solved"
+    assert r.pobj == pytest.approx(best[0], rel=1e-7, abs=1e-8)
+    xs = np.maximum(np.abs(best[1]), 1.0)
+    np.testing.assert_allclose(r.x / xs, best[1] / xs, atol=1e-6)
+    # the stopping test was taken on the given problem at the returned point
+    res = oracle.residuals(qp, r.y, r.z, r.x)
+    assert res["kkt"] <= 1e-10
+    for k in ("eta_p", "eta_d", "eta_gap"):
+        assert getattr(r, k) == pytest.approx(res[k], rel=1e-9, abs=1e-15)

@@ -142,6 +142,41 @@ def extra_kron(steps, cpu):
     return out
 
 
+def extra_precond(qp_large, dp_large, cpu):
+    """Diagonal preconditioning (Ruiz x10 + Pock-Chambolle): the random QP to
+    1e-8 with it, and a badly scaled small QP (variables and rows rescaled by
+    10^U(-2,2)) with and without it.  Solve times follow the paper's protocol:
+    power method counted, preconditioning reported apart."""
+    import qpgen
+    from paper_2507_02470_amd.solver import DeviceProblem, Solver
+    out = {}
+    s = Solver(dp_large, power_start_A=qpgen.power_start(qp_large.m), power_start_Q=qpgen.power_start(qp_large.n),
+               check_every=T_CHECK, tol=1e-8, max_iter=2_000_000, time_limit_s=60.0, precondition=1,
+               spmv_autotune=1)
+    r = s.solve()
+    s.close()
+    out["random_large"] = dict(term=r.term, iterations=r.iters, restarts=r.restarts, kkt=r.kkt,
+                               t_precond_s=round(r.t_precond_s, 4),
+                               time_to_tol_s=round(r.t_setup_s - r.t_precond_s + r.t_solve_s, 4), pobj=r.pobj)
+    qp = qpgen.rescale(qpgen.make_small_ccqp(), 3)
+    dp = DeviceProblem(qp)
+    res = {}
+    for pc in (1, 0):
+        s = Solver(dp, check_every=T_CHECK, tol=1e-8, max_iter=200_000, precondition=pc)
+        r = s.solve()
+        s.close()
+        res["with" if pc else "without"] = dict(term=r.term, iterations=r.iters, kkt=r.kkt,
+                                                time_s=round(r.t_setup_s - r.t_precond_s + r.t_solve_s, 4))
+    out["badly_scaled_small_ccqp"] = dict(n=qp.n, m=qp.m, **res)
+    if cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ro = oracle.solve(qp, tol=1e-8, max_iter=200_000, precondition=True)
+        out["badly_scaled_small_ccqp"]["cpu_oracle_with"] = dict(term=ro.term, iterations=ro.iters,
+                                                                 time_s=round(time.perf_counter() - t0, 3))
+    return out
+
+
 def extra_batch(count, cpu):
     """`count` independent portfolio QPs (n ~ U{50..2000}) in one persistent launch."""
     import numpy as np
@@ -331,6 +366,8 @@ def main():
     extras = None
     if not args.no_extras and args.workload == "random_large":
         extras = {}
+        extras["precond"] = extra_precond(qp, dp, not args.no_cpu_baseline)
+        log(f"precond: {extras['precond']}")
         extras["kron"] = extra_kron(max(5, args.steps // 2), not args.no_cpu_baseline)
         log(f"kron: {extras['kron']}")
         extras["batch"] = extra_batch(args.batch_count, not args.no_cpu_baseline)

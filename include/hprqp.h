@@ -93,13 +93,24 @@ typedef struct {
   int32_t spmv_autotune;      /* 1: time lanes-per-row choices for A, A^T, Q at create   */
   int32_t trace_iters;        /* record the first K iterations into trace_host           */
   double *trace_host;         /* host, K x (2m + 4n) doubles, rows [y, w, x, ybar, wbar, xbar];
-                                 y, w, x is the state carried into the next iteration     */
+                                 y, w, x is the state carried into the next iteration
+                                 (in the scaled variables when preconditioned)            */
   int32_t log_cap;            /* capacity (rows) of check_log_host                       */
   double *check_log_host;     /* host, rows of 10 doubles: k, t, R~, eta_p, eta_d, eta_gap,
                                  sigma used, restarted (0/1), sigma next, restart count  */
   int32_t profile_kernels;    /* 1: time the four per-iteration products with HIP events on
-                                 the solve stream (two iterations per check segment), see
-                                 hprqp_kernel_stats                                        */
+                                 the solve stream (the plain iterations of every 4th check
+                                 segment, launched without a graph), see hprqp_kernel_stats */
+  int32_t precondition;       /* 1: diagonal preconditioning of Section 4.1 at create, for
+                                 explicit Q (HPRQP_Q_CSR, HPRQP_Q_ZERO; ignored otherwise,
+                                 as the paper applies none to a matrix-free Q): symmetric
+                                 scaling of K = [[Q, A^T], [A, 0]] by ruiz_iters Ruiz passes
+                                 (divide each scale by the square root of the inf-norm of
+                                 its row) and one Pock-Chambolle pass with alpha = 1 (the
+                                 1-norm).  The method runs on Q~ = DQD, A~ = EAD, c~ = Dc,
+                                 [L,U]/D, E[l,u]; termination is tested on the given problem
+                                 and inputs/outputs stay in the given variables.  0          */
+  int32_t ruiz_iters;         /* Ruiz passes of the preconditioning; 10                  */
 } hprqp_options;
 
 typedef struct {
@@ -112,6 +123,7 @@ typedef struct {
   double pobj, dobj;
   double R_last;              /* merit R~ at the last check                        */
   double t_setup_s, t_solve_s;  /* seconds: create (incl. power method), solve    */
+  double t_precond_s;         /* seconds of create spent on the preconditioning   */
 } hprqp_info;
 
 typedef struct hprqp_handle hprqp_handle;
@@ -157,6 +169,11 @@ hprqp_status hprqp_apply(hprqp_handle *h, int32_t op, const double *in, double *
 hprqp_status hprqp_power_info(hprqp_handle *h, double *est_A, int32_t *it_A,
                               double *est_Q, int32_t *it_Q);
 
+/* Scale factors of the preconditioning (precondition = 1 at create): D (n)
+ * for the variables and E (m) for the rows of A, written to the device arrays
+ * D and E (either may be NULL).  Without preconditioning both are all ones. */
+hprqp_status hprqp_scaling(hprqp_handle *h, double *D, double *E);
+
 /* Kernel timing of the last hprqp_solve made with profile_kernels = 1:
  * avg_ms_host[i] = mean duration (ms) and launches_host[i] = number of timed
  * launches of product i, i = 0: Q xhat (with its epilogue), 1: A v, 2: A^T ybar,
@@ -170,8 +187,8 @@ void hprqp_destroy(hprqp_handle *h);
  * Batched solve: many independent QPs (sizes may differ) solved by one
  * persistent kernel, one workgroup per instance at a time, with the whole
  * of Algorithm 4 + 5 (restart, sigma update, termination) on the device.
- * Supported: qkind HPRQP_Q_LOWRANK with lr_rank <= 16 and n <= 4096,
- * m <= 64 per instance.
+ * Supported: qkind HPRQP_Q_LOWRANK with lr_rank <= 16 and n <= 2048,
+ * m <= 64 per instance (no preconditioning: Q is matrix-free).
  * --------------------------------------------------------------------- */
 
 /* probs: host array of `count` problems whose arrays are device pointers;

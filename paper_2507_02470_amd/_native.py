@@ -35,7 +35,7 @@ class hprqp_options(C.Structure):
                 ("use_graph", C.c_int32), ("spmv_autotune", C.c_int32),
                 ("trace_iters", C.c_int32), ("trace_host", C.POINTER(C.c_double)),
                 ("log_cap", C.c_int32), ("check_log_host", C.POINTER(C.c_double)),
-                ("profile_kernels", C.c_int32)]
+                ("profile_kernels", C.c_int32), ("precondition", C.c_int32), ("ruiz_iters", C.c_int32)]
 
 
 class hprqp_info(C.Structure):
@@ -43,11 +43,12 @@ class hprqp_info(C.Structure):
                 ("sigma", C.c_double), ("sigma0", C.c_double), ("lambda_A", C.c_double),
                 ("lambda_Q", C.c_double), ("eta_p", C.c_double), ("eta_d", C.c_double),
                 ("eta_gap", C.c_double), ("pobj", C.c_double), ("dobj", C.c_double),
-                ("R_last", C.c_double), ("t_setup_s", C.c_double), ("t_solve_s", C.c_double)]
+                ("R_last", C.c_double), ("t_setup_s", C.c_double), ("t_solve_s", C.c_double),
+                ("t_precond_s", C.c_double)]
 
 
 EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_apply",
-           "hprqp_power_info", "hprqp_kernel_stats", "hprqp_set_options", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
+           "hprqp_power_info", "hprqp_scaling", "hprqp_kernel_stats", "hprqp_set_options", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
            "hprqp_batch_last_kernel_s", "hprqp_batch_destroy", "hprqp_last_error")
 
 _lib = None
@@ -69,6 +70,8 @@ def load():
     lib.hprqp_apply.argtypes = [_vp, C.c_int32, _vp, _vp]
     lib.hprqp_power_info.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    lib.hprqp_scaling.argtypes = [_vp, _vp, _vp]
+    lib.hprqp_scaling.restype = C.c_int
     lib.hprqp_kernel_stats.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
     lib.hprqp_kernel_stats.restype = C.c_int
     lib.hprqp_set_options.argtypes = [_vp, C.POINTER(hprqp_options)]

@@ -149,15 +149,19 @@ struct EpiStage1 {
 // Primal residual and the y-part of the dual objective at (x, y) from A x:
 //   acc[0] = max |Ax - Pi_K(Ax)|, acc[1] = max |Ax|,
 //   acc[2] = sum_i (l_i y_i^+ + u_i y_i^-), acc[3] = #(nonzero y_i against an infinite bound)
+// With diagonal preconditioning, ie = 1/E turns the scaled row (A~ x~)_i into
+// the given problem's (A x)_i; the objective terms are invariant.
 struct EpiResA {
   const double *l, *u, *y;
+  const double* ie;   // NULL: no preconditioning
   static constexpr int NR = 4;
   static constexpr unsigned MAXMASK = 0x3u;
   __device__ void setup(const DevParams*, int) {}
   __device__ __forceinline__ void operator()(int i, double ax, double* acc) const {
     const double li = l[i], ui = u[i], yi = y[i];
-    acc[0] = fmax(acc[0], fabs(ax - clampd(ax, li, ui)));
-    acc[1] = fmax(acc[1], fabs(ax));
+    const double s = ie ? ie[i] : 1.0;
+    acc[0] = fmax(acc[0], fabs(ax - clampd(ax, li, ui)) * s);
+    acc[1] = fmax(acc[1], fabs(ax) * s);
     if (yi > 0.0) { if (isinf(li)) acc[3] += 1.0; else acc[2] += li * yi; }
     else if (yi < 0.0) { if (isinf(ui)) acc[3] += 1.0; else acc[2] += ui * yi; }
   }
@@ -167,17 +171,21 @@ struct EpiResA {
 //   acc[0] = max |-Qx + g + z - c|, acc[1] = max |g|, acc[2] = max |Qx|,
 //   acc[3] = <x, Qx>, acc[4] = <c, x>, acc[5] = sum_j (L_j z_j^+ + U_j z_j^-),
 //   acc[6] = #(nonzero z_j against an infinite bound).
-// Optionally copies x, z to the output buffers.
+// Optionally copies x, z to the output buffers.  With diagonal
+// preconditioning, id = 1/D maps the scaled dual quantities back (the dual
+// residual, A^T y and Q x of the given problem are 1/D times the scaled ones).
 struct EpiResQ {
   const double *x, *z, *g, *c, *L, *U; double *xo, *zo;
+  const double* id;   // NULL: no preconditioning
   static constexpr int NR = 7;
   static constexpr unsigned MAXMASK = 0x7u;
   __device__ void setup(const DevParams*, int) {}
   __device__ __forceinline__ void operator()(int i, double qx, double* acc) const {
     const double xi = x[i], zi = z[i], gi = g ? g[i] : 0.0, ci = c[i];
-    acc[0] = fmax(acc[0], fabs(-qx + gi + zi - ci));
-    acc[1] = fmax(acc[1], fabs(gi));
-    acc[2] = fmax(acc[2], fabs(qx));
+    const double s = id ? id[i] : 1.0;
+    acc[0] = fmax(acc[0], fabs(-qx + gi + zi - ci) * s);
+    acc[1] = fmax(acc[1], fabs(gi) * s);
+    acc[2] = fmax(acc[2], fabs(qx) * s);
     acc[3] += xi * qx;
     acc[4] += ci * xi;
     const double Li = L[i], Ui = U[i];

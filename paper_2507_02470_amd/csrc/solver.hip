@@ -15,6 +15,7 @@
 #include "epilogues.hpp"
 #include "qops.hpp"
 #include "spmv.hpp"
+#include "precond.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -25,7 +26,7 @@
 #include <vector>
 
 hipError_t hq_build_transpose(int m, int n, int64_t nnz, const int* rowptr, const int* col, const double* val,
-                              int* t_rowptr, int* t_col, double* t_val, hipStream_t st);
+                              int* t_rowptr, int* t_col, double* t_val, int* t_perm, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // errors
@@ -102,6 +103,16 @@ __global__ void k_fill(long long n, double* p, double v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
 }
+__global__ void k_mul(long long n, const double* __restrict__ s, const double* __restrict__ f, double* __restrict__ o) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    o[i] = s[i] * f[i];
+}
+
+__global__ void k_recip(long long n, const double* __restrict__ s, double* __restrict__ o) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    o[i] = 1.0 / s[i];
+}
+
 __global__ void k_copy(long long n, const double* __restrict__ s, double* __restrict__ a, double* __restrict__ b) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const double v = s[i];
@@ -224,11 +235,18 @@ struct hprqp_handle {
   int lr_r = 0;
   const double *lr_d = nullptr, *lr_F = nullptr;
   const double *c = nullptr, *L = nullptr, *U = nullptr, *l = nullptr, *u = nullptr;
+  // diagonal preconditioning (Section 4.1): the method runs on the scaled data
+  // above; A0, AT0, Q0 and c0..u0 are the problem as given
+  bool pre = false;
+  double *Ds = nullptr, *Es = nullptr, *iDs = nullptr, *iEs = nullptr;
+  Mat A0, AT0, Q0;
+  const double *c0 = nullptr, *L0 = nullptr, *U0 = nullptr, *l0 = nullptr, *u0 = nullptr;
+  int* at_perm = nullptr;
   hprqp_options opt{};
   double lamA = 0, lamQ = 0, sigma0 = 1, binf = 0, cinf = 0;
   double powA_est = 0, powQ_est = 0;
   int powA_it = 0, powQ_it = 0;
-  double t_setup = 0;
+  double t_setup = 0, t_precond = 0;
   // owned device memory
   std::vector<void*> owned;
   int *at_rp = nullptr, *at_ci = nullptr;
@@ -395,8 +413,8 @@ void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
   }
   if (check) {
     // stopping quantities at ubar = (ybar, zbar, xbar) (Section 4.1)
-    if (h.m > 0) launch_csr(h, h.A, h.XB, EpiResA{h.l, h.u, h.ybar}, j, red_seq(h, SL_RA, 4));
-    q_apply(h, h.XB, EpiResQ{h.XB, h.ZB, h.m > 0 ? h.g : nullptr, h.c, h.L, h.U, h.xbo, h.zbo}, j,
+    if (h.m > 0) launch_csr(h, h.A, h.XB, EpiResA{h.l, h.u, h.ybar, h.iEs}, j, red_seq(h, SL_RA, 4));
+    q_apply(h, h.XB, EpiResQ{h.XB, h.ZB, h.m > 0 ? h.g : nullptr, h.c, h.L, h.U, h.xbo, h.zbo, h.iDs}, j,
             red_seq(h, SL_RQ, 7));
   }
   // a6: Q d, wbar, Halpern, next z/x step
@@ -676,8 +694,45 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       h.at_rp = h.dalloc<int>(n + 1);
       h.at_ci = h.dalloc<int>(P->a_nnz);
       h.at_v = h.dalloc<double>(P->a_nnz);
-      HQC(hq_build_transpose(m, n, P->a_nnz, P->a_rowptr, P->a_col, P->a_val, h.at_rp, h.at_ci, h.at_v, st));
+      const bool want_perm = opt->precondition && (h.qkind == HPRQP_Q_CSR || h.qkind == HPRQP_Q_ZERO);
+      if (want_perm) h.at_perm = h.dalloc<int>(P->a_nnz);
+      HQC(hq_build_transpose(m, n, P->a_nnz, P->a_rowptr, P->a_col, P->a_val, h.at_rp, h.at_ci, h.at_v, h.at_perm,
+                             st));
       h.AT = Mat{n, m, h.at_rp, h.at_ci, h.at_v, P->a_nnz, 0};
+    }
+    h.A0 = h.A; h.AT0 = h.AT; h.Q0 = h.Q;
+    h.c0 = h.c; h.L0 = h.L; h.U0 = h.U; h.l0 = h.l; h.u0 = h.u;
+    // diagonal preconditioning (Section 4.1), explicit Q only
+    if (opt->precondition && (h.qkind == HPRQP_Q_CSR || h.qkind == HPRQP_Q_ZERO)) {
+      if (opt->ruiz_iters < 0) fail(HPRQP_ERR_ARG, "ruiz_iters must be >= 0");
+      h.pre = true;
+      h.Ds = h.dalloc<double>(n); h.iDs = h.dalloc<double>(n);
+      h.Es = h.dalloc<double>(std::max(m, 1)); h.iEs = h.dalloc<double>(std::max(m, 1));
+      HqPrecondIn pin{};
+      pin.m = m; pin.n = n;
+      pin.a_rp = P->a_rowptr; pin.a_ci = P->a_col; pin.a_v = P->a_val; pin.a_nnz = m > 0 ? P->a_nnz : 0;
+      pin.at_rp = h.at_rp; pin.at_ci = h.at_ci; pin.at_perm = h.at_perm; pin.at_v = h.at_v;
+      if (h.qkind == HPRQP_Q_CSR) { pin.q_rp = P->q_rowptr; pin.q_ci = P->q_col; pin.q_v = P->q_val; }
+      pin.c = P->c; pin.L = P->L; pin.U = P->U; pin.l = P->l; pin.u = P->u;
+      pin.ruiz_iters = opt->ruiz_iters;
+      HqPrecondOut pout{};
+      pout.D = h.Ds; pout.E = h.Es;
+      pout.q_v = h.qkind == HPRQP_Q_CSR ? h.dalloc<double>(std::max<long long>(P->q_nnz, 1)) : nullptr;
+      pout.a_v = m > 0 ? h.dalloc<double>(std::max<long long>(P->a_nnz, 1)) : nullptr;
+      pout.at_v = m > 0 ? h.dalloc<double>(std::max<long long>(P->a_nnz, 1)) : nullptr;
+      pout.c = h.dalloc<double>(n); pout.L = h.dalloc<double>(n); pout.U = h.dalloc<double>(n);
+      pout.l = m > 0 ? h.dalloc<double>(m) : nullptr; pout.u = m > 0 ? h.dalloc<double>(m) : nullptr;
+      pout.work_n = h.t1; pout.work_n2 = h.t2; pout.work_m = h.tm;
+      HQC(hipStreamSynchronize(st));
+      const double tp = now_s();
+      HQC(hq_precondition(pin, pout, st));
+      k_recip<<<hq_grid(n, 256), 256, 0, st>>>(n, h.Ds, h.iDs);
+      if (m > 0) k_recip<<<hq_grid(m, 256), 256, 0, st>>>(m, h.Es, h.iEs);
+      if (h.qkind == HPRQP_Q_CSR) h.Q.v = pout.q_v;
+      if (m > 0) { h.A.v = pout.a_v; h.AT.v = pout.at_v; h.l = pout.l; h.u = pout.u; }
+      h.c = pout.c; h.L = pout.L; h.U = pout.U;
+      HQC(hipStreamSynchronize(st));
+      h.t_precond = now_s() - tp;
     }
     // product kernel per matrix from the row-length profile (autotuning may refine it)
     auto pick = [&](Mat& M) {
@@ -722,6 +777,17 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
     const double nb = m > 0 ? std::sqrt(h.hs[0]) : 0.0, nc = std::sqrt(h.hs[2]);
     h.binf = m > 0 ? h.hs[1] : 0.0;
     h.cinf = h.hs[3];
+    if (h.pre) {
+      // sigma0 uses the scaled b and c (the problem the method runs on); the
+      // stopping test uses the norms of the given problem
+      if (m > 0) launch_elem(h, m, nullptr, EpiNormB{h.l0, h.u0}, 0, red_seq(h, SL_NRM, 2));
+      launch_elem(h, n, nullptr, EpiNormC{h.c0}, 0, red_seq(h, SL_NRM + 2, 2));
+      final_reduce(h, SL_NRM, 4);
+      HQC(hipMemcpyAsync(h.hs, h.scalars + SL_NRM, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HQC(hipStreamSynchronize(st));
+      h.binf = m > 0 ? h.hs[1] : 0.0;
+      h.cinf = h.hs[3];
+    }
     if (opt->sigma0 > 0) h.sigma0 = opt->sigma0;
     else if (nb >= 1e-16 && nb <= 1e16 && nc >= 1e-16 && nc <= 1e16) h.sigma0 = nb / nc;
     else h.sigma0 = 1.0;
@@ -734,8 +800,10 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
   }
 }
 
-void copy_or_zero(hprqp_handle& h, long long k, const double* src, double* dst) {
-  if (src) k_copy<<<hq_grid(k, 256), 256, 0, h.st>>>(k, src, dst, nullptr);
+// dst = src (times f elementwise when f is given), or 0 without src
+void copy_or_zero(hprqp_handle& h, long long k, const double* src, double* dst, const double* f = nullptr) {
+  if (src && f) k_mul<<<hq_grid(k, 256), 256, 0, h.st>>>(k, src, f, dst);
+  else if (src) k_copy<<<hq_grid(k, 256), 256, 0, h.st>>>(k, src, dst, nullptr);
   else k_fill<<<hq_grid(k, 256), 256, 0, h.st>>>(k, dst, 0.0);
 }
 
@@ -761,9 +829,10 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
   const bool tracing = o.trace_iters > 0 && o.trace_host;
   if (!yo && m > 0) fail(HPRQP_ERR_ARG, "output y required");
   if (!zo || !wo || !xo) fail(HPRQP_ERR_ARG, "outputs z, w, x required");
-  if (m > 0) copy_or_zero(h, m, y0, h.y);
-  copy_or_zero(h, n, w0, h.w);
-  copy_or_zero(h, n, x0, h.x);
+  // a warm start in the given variables enters scaled: y/E, w/D, x/D
+  if (m > 0) copy_or_zero(h, m, y0, h.y, h.pre ? h.iEs : nullptr);
+  copy_or_zero(h, n, w0, h.w, h.pre ? h.iDs : nullptr);
+  copy_or_zero(h, n, x0, h.x, h.pre ? h.iDs : nullptr);
   double sigma = h.sigma0;
   write_params(h, sigma, 0);
   reset_epoch(h);
@@ -869,18 +938,19 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
       ++nlog;
     }
   }
-  // output ubar of the last iteration
-  if (m > 0) k_copy<<<hq_grid(m, 256), 256, 0, h.st>>>(m, h.ybar, yo, nullptr);
-  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.zbo, zo, nullptr);
-  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.wbar, wo, nullptr);
-  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.xbo, xo, nullptr);
+  // output ubar of the last iteration, in the given variables when
+  // preconditioned: y = E y~, z = z~ / D, w = D w~, x = D x~
+  if (m > 0) copy_or_zero(h, m, h.ybar, yo, h.pre ? h.Es : nullptr);
+  copy_or_zero(h, n, h.zbo, zo, h.pre ? h.iDs : nullptr);
+  copy_or_zero(h, n, h.wbar, wo, h.pre ? h.Ds : nullptr);
+  copy_or_zero(h, n, h.xbo, xo, h.pre ? h.Ds : nullptr);
   HQC(hipStreamSynchronize(h.st));
   if (info) {
     info->term = term; info->iters = k; info->restarts = r; info->n_log = nlog;
     info->sigma = sigma; info->sigma0 = h.sigma0; info->lambda_A = h.lamA; info->lambda_Q = h.lamQ;
     info->eta_p = res.eta_p; info->eta_d = res.eta_d; info->eta_gap = res.eta_gap;
     info->pobj = res.pobj; info->dobj = res.dobj; info->R_last = R;
-    info->t_setup_s = h.t_setup; info->t_solve_s = now_s() - tstart;
+    info->t_setup_s = h.t_setup; info->t_solve_s = now_s() - tstart; info->t_precond_s = h.t_precond;
   }
 }
 
@@ -888,11 +958,20 @@ void residuals_impl(hprqp_handle& h, const double* y, const double* z, const dou
   if (!z || !x || (h.m > 0 && !y) || !out) fail(HPRQP_ERR_ARG, "NULL argument");
   write_params(h, h.sigma0, 0);
   k_zero_ints<<<1, 64, 0, h.st>>>(SL_ITER_END, h.counts);
+  if (h.pre) {
+    // the point is given in the original variables: scale it (y/E, z D, x/D)
+    // and take the stopping quantities as at a check
+    if (h.m > 0) k_mul<<<hq_grid(h.m, 256), 256, 0, h.st>>>(h.m, y, h.iEs, h.tm);
+    k_mul<<<hq_grid(h.n, 256), 256, 0, h.st>>>(h.n, z, h.Ds, h.q1);
+    k_mul<<<hq_grid(h.n, 256), 256, 0, h.st>>>(h.n, x, h.iDs, h.v);
+    y = h.m > 0 ? h.tm : y; z = h.q1; x = h.v;
+  }
   if (h.m > 0) {
     launch_csr(h, h.AT, y, EpiStore{h.t2}, 0, no_red(h));
-    launch_csr(h, h.A, x, EpiResA{h.l, h.u, y}, 0, red_seq(h, SL_RA, 4));
+    launch_csr(h, h.A, x, EpiResA{h.l, h.u, y, h.iEs}, 0, red_seq(h, SL_RA, 4));
   }
-  q_apply(h, x, EpiResQ{x, z, h.m > 0 ? h.t2 : nullptr, h.c, h.L, h.U, nullptr, nullptr}, 0, red_seq(h, SL_RQ, 7));
+  q_apply(h, x, EpiResQ{x, z, h.m > 0 ? h.t2 : nullptr, h.c, h.L, h.U, nullptr, nullptr, h.iDs}, 0,
+          red_seq(h, SL_RQ, 7));
   final_reduce(h, 0, SL_ITER_END);
   HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
   HQC(hipStreamSynchronize(h.st));
@@ -903,9 +982,11 @@ void residuals_impl(hprqp_handle& h, const double* y, const double* z, const dou
 void apply_impl(hprqp_handle& h, int op, const double* in, double* out) {
   if (!in || !out) fail(HPRQP_ERR_ARG, "NULL argument");
   write_params(h, h.sigma0, 0);
-  if (op == 0) q_apply(h, in, EpiStore{out}, 0, no_red(h));
-  else if (op == 1 && h.m > 0) launch_csr(h, h.A, in, EpiStore{out}, 0, no_red(h));
-  else if (op == 2 && h.m > 0) launch_csr(h, h.AT, in, EpiStore{out}, 0, no_red(h));
+  // the operators of the problem as given (the unscaled copies when preconditioned)
+  if (op == 0 && h.pre && h.qkind == HPRQP_Q_CSR) launch_csr(h, h.Q0, in, EpiStore{out}, 0, no_red(h));
+  else if (op == 0) q_apply(h, in, EpiStore{out}, 0, no_red(h));
+  else if (op == 1 && h.m > 0) launch_csr(h, h.A0, in, EpiStore{out}, 0, no_red(h));
+  else if (op == 2 && h.m > 0) launch_csr(h, h.AT0, in, EpiStore{out}, 0, no_red(h));
   else if (op == 2) k_fill<<<hq_grid(h.n, 256), 256, 0, h.st>>>(h.n, out, 0.0);
   else if (op != 1) fail(HPRQP_ERR_ARG, "op must be 0 (Q), 1 (A) or 2 (A^T)");
   HQC(hipStreamSynchronize(h.st));
@@ -943,6 +1024,8 @@ void hprqp_default_options(hprqp_options* o) {
   o->enable_sigma_update = 1;
   o->use_graph = 1;
   o->spmv_autotune = 0;
+  o->precondition = 0;
+  o->ruiz_iters = 10;
 }
 
 hprqp_status hprqp_create(const hprqp_problem* prob, const hprqp_options* opt, hipStream_t stream,
@@ -976,17 +1059,31 @@ hprqp_status hprqp_set_options(hprqp_handle* h, const hprqp_options* opt) {
         for (auto& a : h->pev)
           for (auto& b : a)
             for (auto& e : b) HQC(hipEventCreate(&e));
-      // setup-time choices (lambda's, sigma0, power start, autotune) keep their values
+      // setup-time choices (lambda's, sigma0, power start, autotune, preconditioning) keep their values
       const double la = h->opt.lambda_A, lq = h->opt.lambda_Q, s0 = h->opt.sigma0;
       const double *pa = h->opt.power_start_A, *pq = h->opt.power_start_Q;
-      const int at = h->opt.spmv_autotune;
+      const int at = h->opt.spmv_autotune, pc = h->opt.precondition, ri = h->opt.ruiz_iters;
       // the captured segment depends on the options (length, timing events): capture again
       if (h->gexec) { hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
       if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
       h->graph_T = 0;
       h->opt = *opt;
       h->opt.lambda_A = la; h->opt.lambda_Q = lq; h->opt.sigma0 = s0;
-      h->opt.power_start_A = pa; h->opt.power_start_Q = pq; h->opt.spmv_autotune = at);
+      h->opt.power_start_A = pa; h->opt.power_start_Q = pq; h->opt.spmv_autotune = at;
+      h->opt.precondition = pc; h->opt.ruiz_iters = ri);
+}
+
+hprqp_status hprqp_scaling(hprqp_handle* h, double* D, double* E) {
+  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle");
+           if (D) {
+             if (h->pre) HQC(hipMemcpyAsync(D, h->Ds, h->n * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+             else k_fill<<<hq_grid(h->n, 256), 256, 0, h->st>>>(h->n, D, 1.0);
+           }
+           if (E && h->m > 0) {
+             if (h->pre) HQC(hipMemcpyAsync(E, h->Es, h->m * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+             else k_fill<<<hq_grid(h->m, 256), 256, 0, h->st>>>(h->m, E, 1.0);
+           }
+           HQC(hipStreamSynchronize(h->st)));
 }
 
 hprqp_status hprqp_kernel_stats(hprqp_handle* h, double* avg_ms, int64_t* launches, int32_t* g) {

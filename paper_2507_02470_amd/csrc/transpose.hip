@@ -30,11 +30,13 @@ __global__ void k_hist(int64_t nnz, const int* __restrict__ col, int* __restrict
 }
 
 __global__ void k_gather_t(int64_t nnz, const int* __restrict__ perm, const int* __restrict__ rid,
-                           const double* __restrict__ val, int* __restrict__ tcol, double* __restrict__ tval) {
+                           const double* __restrict__ val, int* __restrict__ tcol, double* __restrict__ tval,
+                           int* __restrict__ tperm) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x) {
     const int p = perm[k];
     tcol[k] = rid[p];
     tval[k] = val[p];
+    if (tperm) tperm[k] = p;
   }
 }
 
@@ -47,9 +49,10 @@ int grid_for(int64_t work) {
 
 }  // namespace
 
-// t_rowptr: n+1 ints, t_col: nnz ints, t_val: nnz doubles (device).
+// t_rowptr: n+1 ints, t_col: nnz ints, t_val: nnz doubles (device);
+// t_perm (nnz ints, may be NULL): position in A of each entry of A^T.
 hipError_t hq_build_transpose(int m, int n, int64_t nnz, const int* rowptr, const int* col, const double* val,
-                              int* t_rowptr, int* t_col, double* t_val, hipStream_t st) {
+                              int* t_rowptr, int* t_col, double* t_val, int* t_perm, hipStream_t st) {
   hipError_t err = hipSuccess;
   k_zero_int<<<grid_for(n + 1), 256, 0, st>>>(n + 1, t_rowptr);
   if (nnz == 0) return hipGetLastError();
@@ -73,7 +76,7 @@ hipError_t hq_build_transpose(int m, int n, int64_t nnz, const int* rowptr, cons
   HQ_TRY(hipMalloc(&tmp, tmp_bytes));
   HQ_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys_in, keys_out, vals_in, vals_out,
                                             (int)nnz, 0, bits, st));
-  k_gather_t<<<grid_for(nnz), 256, 0, st>>>(nnz, vals_out, rid, val, t_col, t_val);
+  k_gather_t<<<grid_for(nnz), 256, 0, st>>>(nnz, vals_out, rid, val, t_col, t_val, t_perm);
   k_hist<<<grid_for(nnz), 256, 0, st>>>(nnz, col, t_rowptr);
   {
     size_t b = tmp_bytes;

@@ -97,6 +97,7 @@ class Result:
     R_last: float
     t_setup_s: float
     t_solve_s: float
+    t_precond_s: float = 0.0
     trace: np.ndarray | None = None
     check_log: np.ndarray | None = None
 
@@ -170,7 +171,7 @@ class Solver:
                       restarts=int(info.restarts), sigma=info.sigma, sigma0=info.sigma0,
                       lambda_A=info.lambda_A, lambda_Q=info.lambda_Q, eta_p=info.eta_p, eta_d=info.eta_d,
                       eta_gap=info.eta_gap, pobj=info.pobj, dobj=info.dobj, R_last=info.R_last,
-                      t_setup_s=info.t_setup_s, t_solve_s=info.t_solve_s,
+                      t_setup_s=info.t_setup_s, t_solve_s=info.t_solve_s, t_precond_s=info.t_precond_s,
                       trace=None if self.trace is None else self.trace.copy(),
                       check_log=None if self.log is None else self.log[:info.n_log].copy())
 
@@ -201,6 +202,13 @@ class Solver:
         return dict(avg_ms={k: avg[i] for i, k in enumerate(names)},
                     launches={k: cnt[i] for i, k in enumerate(names)},
                     lanes_per_row=dict(A=g[0], AT=g[1], Q=g[2]))
+
+    def scaling(self):
+        """Scale factors (D, E) of the diagonal preconditioning (ones without it)."""
+        f64 = dict(dtype=torch.float64, device=self.device)
+        D = torch.empty(self.dp.n, **f64); E = torch.empty(max(self.dp.m, 1), **f64)
+        N.check(self.lib.hprqp_scaling(self.h, _ptr(D), _ptr(E)))
+        return D, E[:self.dp.m]
 
     def power_info(self):
         ea, eq = C.c_double(), C.c_double()

@@ -319,3 +319,16 @@ def make_tiny(seed: int, n: int = 4, m: int = 2, psd_rank: Optional[int] = None,
 def power_start(k: int, seed: int = 0) -> np.ndarray:
     """Seeded N(0,1) start vector for the power method (length k)."""
     return np.random.default_rng(seed).standard_normal(k)
+
+def rescale(qp: QP, seed: int, decades: float = 2.0) -> QP:
+    """The same QP after a change of variables x = S x' and a scaling R of the
+    rows of A, with S, R diagonal and entries 10^U(-decades, decades): a badly
+    scaled instance with the same optimal value (dense; small instances)."""
+    rng = np.random.default_rng(seed)
+    Q, A = qp.Q_dense(), qp.A_scipy().toarray()
+    s = 10.0 ** rng.uniform(-decades, decades, qp.n)
+    r = 10.0 ** rng.uniform(-decades, decades, qp.m)
+    out = from_dense(s[:, None] * Q * s[None, :], s * qp.c, qp.L / s, qp.U / s,
+                     r[:, None] * A * s[None, :], r * qp.l, r * qp.u)
+    out.meta = dict(workload=qp.meta.get("workload"), rescaled=seed)
+    return out

@@ -1,0 +1,148 @@
+"""GPU parity of the diagonal preconditioning (Section 4.1: Ruiz passes, then
+Pock-Chambolle with alpha = 1, explicit Q; termination on the given problem)
+against the CPU oracle, through the C ABI.
+
+Tolerances: scale factors 1e-13 relative (same products and sums, different
+rounding order at most); iterates over the first 50 iterations and final
+solutions as in the unpreconditioned tests (1e-10 of the largest entry;
+objective 1e-6 relative).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import qpgen
+from oracle.oracle import split_trace
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_02470_amd import load
+    load()
+
+
+def _S():
+    from paper_2507_02470_amd.solver import DeviceProblem, Solver
+    return DeviceProblem, Solver
+
+
+def _max_rel(a, b):
+    return np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b)))
+
+
+def _badly_scaled(qp, seed):
+    """The same QP with variables and rows rescaled by 10^U(-2, 2)."""
+    rng = np.random.default_rng(seed)
+    Q, A = qp.Q_dense(), qp.A_scipy().toarray()
+    s = 10.0 ** rng.uniform(-2, 2, qp.n)
+    r = 10.0 ** rng.uniform(-2, 2, qp.m)
+    return qpgen.from_dense(s[:, None] * Q * s[None, :], s * qp.c, qp.L / s, qp.U / s,
+                            r[:, None] * A * s[None, :], r * qp.l, r * qp.u)
+
+
+def _scaled_lams(qp, D, E):
+    """lambda's of the scaled problem (dense), from the oracle's scale factors."""
+    Q, A = qp.Q_dense(), qp.A_scipy().toarray()
+    As = E[:, None] * A * D[None, :]
+    Qs = D[:, None] * Q * D[None, :]
+    lamA = 1.01 * np.linalg.eigvalsh(As @ As.T).max() if qp.m else 0.0
+    lamQ = 1.01 * np.linalg.eigvalsh(Qs).max()
+    return lamA, lamQ
+
+
+def _cases():
+    return [_badly_scaled(qpgen.make_small_ccqp(), 3),
+            _badly_scaled(qpgen.make_small_ccqp(seed=7, n=300, m=140, nb=60, density=0.04), 4)]
+
+
+def test_scale_factors_match_oracle():
+    DP, Solver = _S()
+    for qp in _cases():
+        for ruiz in (0, 1, 10):
+            D0, E0 = oracle.scaling(qp, ruiz_iters=ruiz)
+            s = Solver(DP(qp), precondition=1, ruiz_iters=ruiz, max_iter=1)
+            D, E = s.scaling()
+            s.close()
+            assert _max_rel(D.cpu().numpy(), D0) < 1e-13
+            assert _max_rel(E.cpu().numpy(), E0) < 1e-13
+
+
+def test_preconditioned_iterates_match_oracle():
+    DP, Solver = _S()
+    K = 50
+    for qp in _cases():
+        D0, E0 = oracle.scaling(qp)
+        lamA, lamQ = _scaled_lams(qp, D0, E0)
+        ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_A=lamA, lambda_Q=lamQ,
+                          trace_iters=K, log_cap=K, precondition=True)
+        s = Solver(DP(qp), lambda_A=lamA, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10,
+                   trace_iters=K, log_cap=K, precondition=1)
+        rg = s.solve()
+        s.close()
+        np.testing.assert_array_equal(rg.check_log[:, 7], ro.check_log[:, 7])
+        for col in (2, 3, 4, 5):   # R, eta_p, eta_d, eta_gap of the given problem
+            np.testing.assert_allclose(rg.check_log[:, col], ro.check_log[:, col], rtol=1e-9, atol=1e-15)
+        to = split_trace(ro.trace, qp.n, qp.m)
+        tg = split_trace(rg.trace, qp.n, qp.m)
+        for k in range(K):
+            for name in ("y", "w", "x", "ybar", "wbar", "xbar"):
+                e = _max_rel(tg[name][k], to[name][k])
+                assert e <= 1e-10, (k, name, e)
+        for name in ("y", "z", "w", "x"):
+            assert _max_rel(getattr(rg, name).cpu().numpy(), getattr(ro, name)) <= 1e-10, name
+
+
+def test_preconditioned_full_solve_and_given_problem_entry_points():
+    DP, Solver = _S()
+    qp = _cases()[0]
+    ro = oracle.solve(qp, tol=1e-8, max_iter=400_000, precondition=True)
+    s = Solver(DP(qp), tol=1e-8, max_iter=400_000, precondition=1)
+    rg = s.solve()
+    assert rg.term == ro.term == "solved"
+    assert rg.kkt <= 1e-8
+    assert abs(rg.pobj - ro.pobj) <= 1e-6 * max(1.0, abs(ro.pobj))
+    # the returned point is in the given variables: the given problem's
+    # residuals (oracle, CPU) agree with what the solver reported
+    res = oracle.residuals(qp, rg.y.cpu().numpy(), rg.z.cpu().numpy(), rg.x.cpu().numpy())
+    assert res["kkt"] <= 1e-8
+    for k in ("eta_p", "eta_d", "eta_gap"):
+        assert getattr(rg, k) == pytest.approx(res[k], rel=1e-6, abs=1e-14)
+    # hprqp_residuals and hprqp_apply act on the given problem
+    g = s.residuals(rg.y, rg.z, rg.x)
+    for k in ("eta_p", "eta_d", "eta_gap", "pobj", "dobj"):
+        assert g[k] == pytest.approx(res[k], rel=1e-9, abs=1e-14), k
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(qp.n); y = rng.standard_normal(qp.m)
+    A = qp.A_scipy()
+    assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13
+    assert _max_rel(s.apply("AT", y).cpu().numpy(), A.T @ y) < 1e-13
+    assert _max_rel(s.apply("Q", x).cpu().numpy(), qp.Q_dense() @ x) < 1e-13
+    # a warm start in the given variables from the solution stops at the first check
+    s.set_options(max_iter=400_000)
+    rw = s.solve(y0=rg.y, w0=rg.w, x0=rg.x)
+    assert rw.term == "solved" and rw.iters <= 100
+    s.close()
+    # the badly scaled QP is a change of variables of the well-scaled one: same
+    # optimal value (the badly scaled one is not solved in 4e5 iterations
+    # without preconditioning)
+    r0 = oracle.solve(qpgen.make_small_ccqp(), tol=1e-8, max_iter=400_000)
+    assert abs(rg.pobj - r0.pobj) <= 1e-6 * max(1.0, abs(r0.pobj))
+
+
+def test_matrix_free_q_ignores_preconditioning():
+    DP, Solver = _S()
+    qp = qpgen.make_portfolio(12, n=300)
+    s0 = Solver(DP(qp), tol=1e-8, max_iter=100_000)
+    s1 = Solver(DP(qp), tol=1e-8, max_iter=100_000, precondition=1)
+    D, E = s1.scaling()
+    assert torch.all(D == 1.0) and torch.all(E == 1.0)
+    r0, r1 = s0.solve(), s1.solve()
+    assert r0.iters == r1.iters
+    assert torch.equal(r0.x, r1.x)
+    s0.close(); s1.close()

@@ -92,6 +92,19 @@ void orc_apply_Q(const orc_problem *P, const double *x, double *out) {
         out[i + (size_t)s * j] = acc;
       }
     free(T);
+  } else if (P->qkind == ORC_Q_GRAM) {
+    /* Q x = Ahat^T (Ahat x) */
+    const int p = P->gram_p;
+    double *t = vnew(p);
+    for (int i = 0; i < p; ++i) {
+      double acc = 0.0;
+      for (int k = P->gram_rowptr[i]; k < P->gram_rowptr[i + 1]; ++k) acc += P->gram_val[k] * x[P->gram_col[k]];
+      t[i] = acc;
+    }
+    for (int j = 0; j < n; ++j) out[j] = 0.0;
+    for (int i = 0; i < p; ++i)
+      for (int k = P->gram_rowptr[i]; k < P->gram_rowptr[i + 1]; ++k) out[P->gram_col[k]] += P->gram_val[k] * t[i];
+    free(t);
   } else { /* ORC_Q_LOWRANK: diag(d) x + F (F^T x) */
     const int r = P->lr_rank;
     double *t = vnew(r);
@@ -279,6 +292,33 @@ void orc_scaling(const orc_problem *P, int ruiz_iters, int pock_chambolle, doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* phi(x) = lambda ||x||_1 + delta_[L,U](x): prox and conjugate              */
+/* ------------------------------------------------------------------------ */
+double orc_prox(const orc_problem *P, int j, double sigma, double r) {
+  const double t = sigma * P->l1_weight;
+  double v = r;
+  if (t > 0.0) v = (r > t) ? r - t : ((r < -t) ? r + t : 0.0);   /* soft threshold */
+  return clamp(v, P->L[j], P->U[j]);
+}
+
+/* -phi_j^*(-z) for phi_j(x) = lambda |x| + delta_[L_j,U_j](x):
+ * phi_j^*(s) = sup_{L <= x <= U} (s x - lambda |x|), attained at L, U or 0.
+ * It is +inf (dual objective -inf) when L = -inf and z > lambda, or when
+ * U = +inf and z < -lambda.  With lambda > 0 a multiplier that exceeds
+ * lambda by rounding only (by at most 1e-12 max(1, lambda)) counts as
+ * lambda.  Sets *inf and returns 0 in the infinite case.                  */
+static double neg_conj_phi(const orc_problem *P, int j, double z, int *inf) {
+  const double lam = P->l1_weight, L = P->L[j], U = P->U[j];
+  const double slack = lam > 0.0 ? 1e-12 * (lam > 1.0 ? lam : 1.0) : 0.0;
+  if ((isinf(L) && z > lam + slack) || (isinf(U) && z < -lam - slack)) { *inf = 1; return 0.0; }
+  double best = -INFINITY;
+  if (!isinf(L)) { double v = -z * L - lam * fabs(L); if (v > best) best = v; }
+  if (!isinf(U)) { double v = -z * U - lam * fabs(U); if (v > best) best = v; }
+  if (L <= 0.0 && 0.0 <= U && best < 0.0) best = 0.0;
+  return -best;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Stopping quantities (Section 4.1, "Termination")                         */
 /* ------------------------------------------------------------------------ */
 void orc_residuals(const orc_problem *P, const double *y, const double *z,
@@ -311,20 +351,19 @@ void orc_residuals(const orc_problem *P, const double *y, const double *z,
   if (t1 > den) den = t1;
   if (t2 > den) den = t2;
   double eta_d = rd / (1.0 + den);
-  /* objectives: P = 1/2 x'Qx + c'x (phi(x) = 0 on the box);
-   * D = -1/2 x'Qx - delta*_K(-y) - delta*_C(-z), where
-   * -delta*_K(-y) = sum_i (l_i y_i^+ + u_i y_i^-), likewise for z with L, U. */
+  /* objectives: P = 1/2 x'Qx + c'x + phi(x);
+   * D = -1/2 x'Qx - delta*_K(-y) - phi*(-z), where
+   * -delta*_K(-y) = sum_i (l_i y_i^+ + u_i y_i^-). */
   double xQx = dot(x, Qx, n), cx = dot(P->c, x, n);
-  double pobj = 0.5 * xQx + cx;
+  double l1 = 0.0;
+  for (int j = 0; j < n; ++j) l1 += fabs(x[j]);
+  double pobj = 0.5 * xQx + cx + P->l1_weight * l1;          /* phi(x) on the box */
   double sup = 0.0; int dual_inf = 0;
   for (int i = 0; i < m; ++i) {
     if (y[i] > 0.0) { if (isinf(P->l[i])) dual_inf = 1; else sup += P->l[i] * y[i]; }
     else if (y[i] < 0.0) { if (isinf(P->u[i])) dual_inf = 1; else sup += P->u[i] * y[i]; }
   }
-  for (int j = 0; j < n; ++j) {
-    if (z[j] > 0.0) { if (isinf(P->L[j])) dual_inf = 1; else sup += P->L[j] * z[j]; }
-    else if (z[j] < 0.0) { if (isinf(P->U[j])) dual_inf = 1; else sup += P->U[j] * z[j]; }
-  }
+  for (int j = 0; j < n; ++j) sup += neg_conj_phi(P, j, z[j], &dual_inf);   /* -phi^*(-z) */
   double dobj = dual_inf ? -INFINITY : (-0.5 * xQx + sup);
   double eta_gap;
   if (dual_inf) eta_gap = INFINITY;
@@ -393,7 +432,7 @@ static int solve_core(const orc_problem *P, const orc_problem *P0, const double 
       orc_apply_Q(P, w, Qw);
       for (int j = 0; j < n; ++j) {
         rz[j] = x[j] + sigma * (-Qw[j] + ATy[j] - P->c[j]);
-        xb[j] = clamp(rz[j], P->L[j], P->U[j]);
+        xb[j] = orc_prox(P, j, sigma, rz[j]);
         zb[j] = (xb[j] - rz[j]) / sigma;
         xh[j] = 2.0 * xb[j] - x[j];                                   /* xhat */
       }

@@ -7,8 +7,9 @@
  * calls it.
  *
  * What it computes (arXiv 2507.02470, "HPR-QP"):
- *   - the CQP of Section 1 (problem "QP-primal-0"): min 1/2<x,Qx> + <c,x>
- *     s.t. l <= Ax <= u, L <= x <= U;
+ *   - the CCQP of Section 1 (problem "QP-primal"): min 1/2<x,Qx> + <c,x> + phi(x)
+ *     s.t. l <= Ax <= u, with phi(x) = lambda ||x||_1 + delta_[L,U](x) (lambda = 0:
+ *     the CQP "QP-primal-0"; m = 0, Q = Ahat^T Ahat: the Lasso of Section 4.4);
  *   - Algorithm 4 (HPR-QP, Section 3) with the closed-form subproblem updates
  *     of Section 3.1 ("update-z", "update-x", "update-w", "update-y"), the
  *     restart criteria of Section 3.2 ("eq:restart_1".."eq:restart_3") and
@@ -27,7 +28,7 @@
 extern "C" {
 #endif
 
-enum { ORC_Q_ZERO = 0, ORC_Q_CSR = 1, ORC_Q_KRON = 2, ORC_Q_LOWRANK = 3 };
+enum { ORC_Q_ZERO = 0, ORC_Q_CSR = 1, ORC_Q_KRON = 2, ORC_Q_LOWRANK = 3, ORC_Q_GRAM = 4 };
 enum { ORC_SOLVED = 0, ORC_MAX_ITER = 1, ORC_TIME_LIMIT = 2, ORC_NUMERICAL = 3 };
 
 typedef struct {
@@ -39,6 +40,9 @@ typedef struct {
   const double *c, *L, *U;                               /* box C = [L, U]        */
   const int *a_rowptr, *a_col; const double *a_val;      /* A, m x n CSR          */
   const double *l, *u;                                   /* K = [l, u]            */
+  double l1_weight;       /* lambda >= 0: phi(x) = lambda ||x||_1 + delta_[L,U](x)   */
+  int gram_p; const int *gram_rowptr, *gram_col; const double *gram_val;
+                          /* Q = Ahat^T Ahat, Ahat p x n CSR (matrix-free Q)          */
 } orc_problem;
 
 typedef struct {
@@ -103,6 +107,10 @@ double orc_sigma_argmin(double th1, double th2, double th3, double lamQ);
  * [l, u]~ = E [l, u];  its solution maps back as x = D x~, w = D w~,
  * z = z~ / D, y = E y~.                                                      */
 void orc_scaling(const orc_problem *P, int ruiz_iters, int pock_chambolle, double *D, double *E);
+
+/* Prox of sigma phi for phi(x) = lambda ||x||_1 + delta_[L,U](x), entry j:
+ * the soft threshold of r at sigma lambda, clamped to [L_j, U_j].           */
+double orc_prox(const orc_problem *P, int j, double sigma, double r);
 
 /* eta_p, eta_d, eta_gap, pobj, dobj at (y, z, x); out[5]. */
 void orc_residuals(const orc_problem *P, const double *y, const double *z,

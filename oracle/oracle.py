@@ -29,7 +29,9 @@ class _Problem(C.Structure):
                 ("lr_rank", C.c_int), ("lr_d", _dp), ("lr_F", _dp),
                 ("c", _dp), ("L", _dp), ("U", _dp),
                 ("a_rowptr", _ip), ("a_col", _ip), ("a_val", _dp),
-                ("l", _dp), ("u", _dp)]
+                ("l", _dp), ("u", _dp),
+                ("l1_weight", C.c_double),
+                ("gram_p", C.c_int), ("gram_rowptr", _ip), ("gram_col", _ip), ("gram_val", _dp)]
 
 
 class _Options(C.Structure):
@@ -99,7 +101,7 @@ def _i(a):
 class _Marshal:
     """Keeps contiguous copies alive while the C struct points at them."""
 
-    QK = {"zero": 0, "csr": 1, "kron": 2, "lowrank": 3}
+    QK = {"zero": 0, "csr": 1, "kron": 2, "lowrank": 3, "gram": 4}
 
     def __init__(self, qp):
         f64 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
@@ -118,6 +120,11 @@ class _Marshal:
         if qp.qkind == "lowrank":
             P.lr_rank = qp.lr_F.shape[1]
             P.lr_d = _d(k(f64(qp.lr_d))); P.lr_F = _d(k(f64(qp.lr_F)))
+        if qp.qkind == "gram":
+            P.gram_p = qp.gram_p
+            P.gram_rowptr = _i(k(i32(qp.gram_rowptr))); P.gram_col = _i(k(i32(qp.gram_col)))
+            P.gram_val = _d(k(f64(qp.gram_val) if qp.gram_val.size else np.zeros(1)))
+        P.l1_weight = float(getattr(qp, "l1_weight", 0.0))
         P.c = _d(k(f64(qp.c))); P.L = _d(k(f64(qp.L))); P.U = _d(k(f64(qp.U)))
         P.a_rowptr = _i(k(i32(qp.a_rowptr))); P.a_col = _i(k(i32(qp.a_col)))
         P.a_val = _d(k(f64(qp.a_val) if qp.a_val.size else np.zeros(1)))

@@ -5,13 +5,15 @@ none of the solver's arithmetic.  Both the CPU oracle (``oracle/``) and the
 GPU library (``paper_2507_02470_amd``) consume the :class:`QP` objects built
 here, and neither of them is imported by this module.
 
-Problem form (paper, Section 1, problem (1.2) "QP-primal-0"):
+Problem form (paper, Section 1, problem "QP-primal"):
 
-    min  1/2 <x, Q x> + <c, x>   s.t.  l <= A x <= u,   L <= x <= U
+    min  1/2 <x, Q x> + <c, x> + lambda ||x||_1   s.t.  l <= A x <= u,   L <= x <= U
 
 with Q self-adjoint PSD given either as an explicit CSR matrix, as the
-Kronecker product B (x) C applied matrix-free, as diag(d) + F F^T, or as 0.
-Infinite bounds are IEEE +-inf.
+Kronecker product B (x) C applied matrix-free, as diag(d) + F F^T, as the
+Gram matrix Ahat^T Ahat of a sparse Ahat (applied matrix-free), or as 0;
+lambda = ``l1_weight`` (0 for the CQP "QP-primal-0").  Infinite bounds are
+IEEE +-inf.
 
 Workloads (all seeded with ``numpy.random.default_rng``):
 
@@ -23,6 +25,8 @@ Workloads (all seeded with ``numpy.random.default_rng``):
 * ``make_portfolio_family`` a fixed portfolio instance plus per-sample
                          perturbations of c and of the sector bounds.
 * ``make_tiny``          very small random QPs for brute-force checks.
+* ``make_lasso``         Lasso 1/2||Ahat x - bhat||^2 + lambda ||x||_1 (Section
+                         4.4), Q = Ahat^T Ahat matrix-free, c = -Ahat^T bhat, m = 0.
 """
 from __future__ import annotations
 
@@ -32,7 +36,7 @@ from typing import Optional
 import numpy as np
 import scipy.sparse as sp
 
-QKINDS = ("zero", "csr", "kron", "lowrank")
+QKINDS = ("zero", "csr", "kron", "lowrank", "gram")
 
 
 @dataclass
@@ -55,6 +59,11 @@ class QP:
     kron_C: Optional[np.ndarray] = None   # s x s
     lr_d: Optional[np.ndarray] = None     # n
     lr_F: Optional[np.ndarray] = None     # n x r, row-major
+    gram_rowptr: Optional[np.ndarray] = None   # Ahat (p x n) CSR, Q = Ahat^T Ahat
+    gram_col: Optional[np.ndarray] = None
+    gram_val: Optional[np.ndarray] = None
+    gram_p: int = 0
+    l1_weight: float = 0.0                # lambda of phi(x) = lambda ||x||_1 + box
     meta: dict = field(default_factory=dict)
 
     # ---- convenience (data plumbing only) ----
@@ -80,7 +89,13 @@ class QP:
             return np.kron(self.kron_B, self.kron_C)
         if self.qkind == "lowrank":
             return np.diag(self.lr_d) + self.lr_F @ self.lr_F.T
+        if self.qkind == "gram":
+            Ah = self.Ahat_scipy().toarray()
+            return Ah.T @ Ah
         raise ValueError(self.qkind)
+
+    def Ahat_scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.gram_val, self.gram_col, self.gram_rowptr), shape=(self.gram_p, self.n))
 
     def copy(self) -> "QP":
         import copy as _c
@@ -332,3 +347,26 @@ def rescale(qp: QP, seed: int, decades: float = 2.0) -> QP:
                      r[:, None] * A * s[None, :], r * qp.l, r * qp.u)
     out.meta = dict(workload=qp.meta.get("workload"), rescaled=seed)
     return out
+
+
+def make_lasso(seed: int = 1005, p: int = 200, q: int = 600, density: float = 0.15,
+               lam_frac: float = 0.2) -> QP:
+    """Lasso  min 1/2 ||Ahat x - bhat||^2 + lambda ||x||_1  (Section 4.4) as the
+    CCQP  1/2 <x, Ahat^T Ahat x> - <Ahat^T bhat, x> + lambda ||x||_1, m = 0,
+    no box (the constant 1/2 ||bhat||^2 is dropped).  The random class the
+    paper scales up: Ahat p x q with `density` N(0,1) entries, bhat = Ahat
+    x_true + noise, x_true with half of its entries zero and the rest
+    N(0, 1/q), noise N(0, 1), lambda = lam_frac ||Ahat^T bhat||_inf."""
+    rng = np.random.default_rng(seed)
+    Ah = sp.random(p, q, density=density, format="csr", random_state=rng,
+                   data_rvs=lambda k: rng.standard_normal(k))
+    xt = np.where(rng.random(q) < 0.5, 0.0, rng.standard_normal(q) / np.sqrt(q))
+    bh = Ah @ xt + rng.standard_normal(p)
+    g = np.asarray(Ah.T @ bh).ravel()
+    rp, ci, vv = _csr_arrays(Ah)
+    qp = QP(n=q, m=0, qkind="gram", c=-g, L=np.full(q, -np.inf), U=np.full(q, np.inf),
+            a_rowptr=np.zeros(1, dtype=np.int32), a_col=np.zeros(0, dtype=np.int32),
+            a_val=np.zeros(0), l=np.zeros(0), u=np.zeros(0),
+            gram_rowptr=rp, gram_col=ci, gram_val=vv, gram_p=p, l1_weight=lam_frac * np.abs(g).max(),
+            meta=dict(workload="lasso", seed=seed, p=p, q=q, density=density, bhat=bh))
+    return qp

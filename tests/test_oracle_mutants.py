@@ -34,6 +34,10 @@ MUTANTS = {
     "precond_y_unscale": ("for (int i = 0; i < m; ++i) y_out[i] *= E[i];", "for (int i = 0; i < m; ++i) y_out[i] /= E[i];"),
     "ruiz_no_sqrt": ("if (nrm[i] > 0.0) f[i] /= sqrt(nrm[i]);", "if (nrm[i] > 0.0) f[i] /= nrm[i];"),
     "precond_stop_on_scaled": ("        if (D) {\n", "        if (0) {\n"),
+    "soft_threshold_sign": ("(r > t) ? r - t :", "(r > t) ? r + t :"),
+    "l1_missing_in_pobj": ("double pobj = 0.5 * xQx + cx + P->l1_weight * l1;", "double pobj = 0.5 * xQx + cx;"),
+    "gram_abs_values": ("acc += P->gram_val[k] * x[P->gram_col[k]];", "acc += fabs(P->gram_val[k]) * x[P->gram_col[k]];"),
+    "conj_ignores_lambda": ("(isinf(L) && z > lam + slack)", "(isinf(L) && z > slack)"),
     "ruiz_col_part": ("if (p == 0) { if (a > ny[i]) ny[i] = a; if (a > na[j]) na[j] = a; }",
                       "if (p == 0) { if (a > ny[i]) ny[i] = a; }"),
 }

@@ -414,3 +414,69 @@ def test_preconditioned_solve_bruteforce(seed):
     assert res["kkt"] <= 1e-10
     for k in ("eta_p", "eta_d", "eta_gap"):
         assert getattr(r, k) == pytest.approx(res[k], rel=1e-9, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# phi(x) = lambda ||x||_1 (+ box) and the matrix-free Gram Q = Ahat^T Ahat:
+# the Lasso of Section 4.4 (m = 0: the z -> x -> w cycle of Remark 2.1)
+# ---------------------------------------------------------------------------
+def test_lasso_subgradient_optimality():
+    qp = qpgen.make_lasso()
+    r = oracle.solve(qp, tol=1e-10, max_iter=200_000)
+    assert r.term == "solved"
+    Ah, bh, lam = qp.Ahat_scipy(), qp.meta["bhat"], qp.l1_weight
+    g = Ah.T @ (Ah @ r.x - bh)                 # gradient of 1/2||Ahat x - bhat||^2
+    on = np.abs(r.x) > 1e-12
+    assert on.any() and (~on).any()
+    np.testing.assert_allclose(g[on], -lam * np.sign(r.x[on]), atol=1e-8 * lam)
+    assert np.abs(g[~on]).max() <= lam * (1 + 1e-8)
+    # primal objective of the Lasso itself (constant 1/2||bhat||^2 dropped in the QP)
+    f = 0.5 * np.sum((Ah @ r.x - bh) ** 2) + lam * np.abs(r.x).sum()
+    assert r.pobj + 0.5 * bh @ bh == pytest.approx(f, rel=1e-12)
+
+
+def test_lasso_orthonormal_design_closed_form():
+    # Ahat with orthonormal columns: Q = I and x* = soft(Ahat^T bhat, lambda)
+    rng = np.random.default_rng(8)
+    p, q = 60, 25
+    Ah = np.linalg.qr(rng.standard_normal((p, q)))[0]
+    bh = rng.standard_normal(p) * 3
+    g = Ah.T @ bh
+    lam = 0.5 * np.abs(g).max()
+    qp = qpgen.make_lasso(seed=1, p=4, q=q)    # then replace the data
+    rp, ci, vv = (np.asarray(a) for a in (sp.csr_matrix(Ah).indptr, sp.csr_matrix(Ah).indices,
+                                          sp.csr_matrix(Ah).data))
+    qp.gram_rowptr, qp.gram_col, qp.gram_val, qp.gram_p = rp.astype(np.int32), ci.astype(np.int32), vv, p
+    qp.c, qp.l1_weight = -g, lam
+    r = oracle.solve(qp, tol=1e-11, max_iter=100_000)
+    assert r.term == "solved"
+    np.testing.assert_allclose(r.x, np.sign(g) * np.maximum(np.abs(g) - lam, 0.0), atol=1e-9)
+    # lambda >= ||Ahat^T bhat||_inf: the solution is 0
+    qp.l1_weight = 1.01 * np.abs(g).max()
+    r0 = oracle.solve(qp, tol=1e-11, max_iter=100_000)
+    assert r0.term == "solved" and np.abs(r0.x).max() <= 1e-9
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_l1_with_box_and_rows_bruteforce(seed):
+    # lambda ||x||_1 + box with rows, against the split QP in (x+, x-) >= 0:
+    # min 1/2 (x+ - x-)'Q(x+ - x-) + c'(x+ - x-) + lambda 1'(x+ + x-),
+    # L <= x+ - x- <= U and l <= A(x+ - x-) <= u as rows, by active sets
+    n, m = 3, 1 + seed % 2
+    qp = qpgen.make_tiny(200 + seed, n=n, m=m, n_eq=seed % 2)
+    Q, A = _dense(qp)
+    lam = 0.7
+    qp.l1_weight = lam
+    I = np.eye(n)
+    Q2 = np.block([[Q, -Q], [-Q, Q]])
+    c2 = np.concatenate([qp.c + lam, -qp.c + lam])
+    fin = np.isfinite(qp.L) | np.isfinite(qp.U)
+    A2 = np.vstack([np.hstack([A, -A]), np.hstack([I, -I])[fin]])
+    l2 = np.concatenate([qp.l, qp.L[fin]]); u2 = np.concatenate([qp.u, qp.U[fin]])
+    best = pins.kkt_enumerate(Q2, c2, np.zeros(2 * n), np.full(2 * n, np.inf), A2, l2, u2)
+    assert best is not None
+    r = oracle.solve(qp, tol=1e-10, max_iter=400_000, check_every=10)
+    assert r.term == "solved"
+    assert r.pobj == pytest.approx(best[0], rel=1e-7, abs=1e-8)
+    xb = best[1][:n] - best[1][n:]
+    np.testing.assert_allclose(r.x, xb, atol=1e-6)

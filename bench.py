@@ -177,6 +177,47 @@ def extra_precond(qp_large, dp_large, cpu):
     return out
 
 
+def extra_lasso(steps, cpu):
+    """Lasso 1/2||Ahat x - bhat||^2 + lambda ||x||_1 (Section 4.4) at the first size
+    of the paper's random Lasso table (p = 1e4 rows, q = 5e5 variables), Ahat with
+    1% N(0,1) entries, lambda = ||Ahat^T bhat||_inf / 5; Q = Ahat^T Ahat matrix-free."""
+    import torch
+    import qpgen
+    from paper_2507_02470_amd.solver import DeviceProblem, Solver
+    qp = qpgen.make_lasso(seed=1006, p=10_000, q=500_000, density=0.01)
+    nnz = int(qp.gram_rowptr[-1])
+    dp = DeviceProblem(qp)
+    s = Solver(dp, power_start_Q=qpgen.power_start(qp.n), check_every=T_CHECK, tol=0.0, max_iter=T_CHECK,
+               spmv_autotune=1)
+    s.solve()
+    s.set_options(tol=0.0, max_iter=steps * T_CHECK, profile_kernels=1, time_limit_s=0.0)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = s.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ta
+    ks = s.kernel_stats()
+    q_us = ks["avg_ms"]["q_xhat"] * 1e3
+    # Q xhat = Ahat^T (Ahat xhat) with its epilogue: both matrices once (12 B per
+    # nonzero + row pointers), xhat and Ahat xhat gathered once, Qw read, v and q1 written
+    q_bytes = 2 * 12 * nnz + 4 * (qp.gram_p + 1) + 4 * (qp.n + 1) + 8 * qp.n + 8 * qp.gram_p * 2 + 8 * qp.n * 3
+    out = dict(workload="lasso", p=qp.gram_p, q=qp.n, nnz=nnz, l1_weight=qp.l1_weight,
+               iterations_per_s=round(r.iters / dt, 1), us_per_iteration=round(dt / r.iters * 1e6, 2),
+               q_product=dict(avg_us=round(q_us, 2), algorithmic_bytes=q_bytes,
+                              GBps=round(q_bytes / (q_us * 1e-6) / 1e9, 1)))
+    s.set_options(tol=1e-8, max_iter=2_000_000, profile_kernels=0, time_limit_s=60.0)
+    rt = s.solve()
+    out["time_to_1e-8"] = dict(term=rt.term, iterations=rt.iters, restarts=rt.restarts, kkt=rt.kkt,
+                               time_s=round(rt.t_setup_s + rt.t_solve_s, 4), pobj=rt.pobj)
+    s.close()
+    if cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ro = oracle.solve(qp, tol=0.0, max_iter=5, check_every=T_CHECK, lambda_Q=rt.lambda_Q, sigma0=rt.sigma0)
+        out["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
+    return out
+
+
 def extra_batch(count, cpu):
     """`count` independent portfolio QPs (n ~ U{50..2000}) in one persistent launch."""
     import numpy as np
@@ -368,6 +409,8 @@ def main():
         extras = {}
         extras["precond"] = extra_precond(qp, dp, not args.no_cpu_baseline)
         log(f"precond: {extras['precond']}")
+        extras["lasso"] = extra_lasso(max(5, args.steps // 2), not args.no_cpu_baseline)
+        log(f"lasso: {extras['lasso']}")
         extras["kron"] = extra_kron(max(5, args.steps // 2), not args.no_cpu_baseline)
         log(f"kron: {extras['kron']}")
         extras["batch"] = extra_batch(args.batch_count, not args.no_cpu_baseline)

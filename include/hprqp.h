@@ -57,10 +57,13 @@ typedef enum {
   HPRQP_Q_ZERO = 0,           /* Q = 0 (the LP case of Remark 2.1)               */
   HPRQP_Q_CSR = 1,            /* explicit symmetric CSR, both triangles stored   */
   HPRQP_Q_KRON = 2,           /* matrix-free Q = B (x) C (Section 4.5)           */
-  HPRQP_Q_LOWRANK = 3         /* Q = diag(d) + F F^T                              */
+  HPRQP_Q_LOWRANK = 3,        /* Q = diag(d) + F F^T                              */
+  HPRQP_Q_GRAM = 4            /* matrix-free Q = Ahat^T Ahat, Ahat sparse (Lasso) */
 } hprqp_qkind;
 
-/* Problem data (Section 1, "QP-primal-0").  Q must be self-adjoint PSD. */
+/* Problem data (Section 1, "QP-primal"): min 1/2<x,Qx> + <c,x> + phi(x)
+ * s.t. l <= Ax <= u, with phi(x) = l1_weight ||x||_1 + delta_[L,U](x)
+ * (l1_weight = 0: the CQP "QP-primal-0").  Q must be self-adjoint PSD. */
 typedef struct {
   int32_t n, m;               /* variables, rows of A (m may be 0: Remark 2.1)  */
   int32_t qkind;              /* hprqp_qkind                                      */
@@ -75,6 +78,9 @@ typedef struct {
   const double *c, *L, *U;    /* n each: objective and box C = [L, U]          */
   const int32_t *a_rowptr, *a_col; const double *a_val; int64_t a_nnz;  /* A, m x n */
   const double *l, *u;        /* m each: K = [l, u]                              */
+  double l1_weight;           /* >= 0: weight of ||x||_1 in phi (Lasso, Section 4.4) */
+  /* HPRQP_Q_GRAM: Q = Ahat^T Ahat applied as two products; Ahat gram_p x n CSR */
+  int32_t gram_p; const int32_t *gram_rowptr, *gram_col; const double *gram_val; int64_t gram_nnz;
 } hprqp_problem;
 
 typedef struct {
@@ -102,8 +108,9 @@ typedef struct {
                                  the solve stream (the plain iterations of every 4th check
                                  segment, launched without a graph), see hprqp_kernel_stats */
   int32_t precondition;       /* 1: diagonal preconditioning of Section 4.1 at create, for
-                                 explicit Q (HPRQP_Q_CSR, HPRQP_Q_ZERO; ignored otherwise,
-                                 as the paper applies none to a matrix-free Q): symmetric
+                                 explicit Q (HPRQP_Q_CSR, HPRQP_Q_ZERO) with l1_weight = 0;
+                                 ignored otherwise (the paper applies none to a matrix-free
+                                 Q, and a scaled ||x||_1 needs per-variable weights): symmetric
                                  scaling of K = [[Q, A^T], [A, 0]] by ruiz_iters Ruiz passes
                                  (divide each scale by the square root of the inf-norm of
                                  its row) and one Pock-Chambolle pass with alpha = 1 (the

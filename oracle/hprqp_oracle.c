@@ -557,7 +557,7 @@ static int solve_core(const orc_problem *P, const orc_problem *P0, const double 
 int orc_solve(const orc_problem *P, const orc_options *opt,
               const double *y0, const double *w0, const double *x0,
               double *y_out, double *z_out, double *w_out, double *x_out, orc_info *info) {
-  if (!opt->precondition || (P->qkind != ORC_Q_CSR && P->qkind != ORC_Q_ZERO))
+  if (!opt->precondition || (P->qkind != ORC_Q_CSR && P->qkind != ORC_Q_ZERO) || P->l1_weight != 0.0)
     return solve_core(P, NULL, NULL, NULL, opt, y0, w0, x0, y_out, z_out, w_out, x_out, info);
   /* Section 4.1: solve the scaled problem, stop on the given one */
   const int n = P->n, m = P->m;

@@ -61,8 +61,9 @@ typedef struct {
   int log_cap;            /* capacity (rows) of check_log                             */
   double *check_log;      /* rows of 10: k, t, R, eta_p, eta_d, eta_gap, sigma_used,
                              restarted, sigma_next, r                                 */
-  int precondition;       /* explicit Q (CSR or zero) only: solve the diagonally
-                             scaled problem, stop on the residuals of the given one   */
+  int precondition;       /* explicit Q (CSR or zero) and phi a box indicator only:
+                             solve the diagonally scaled problem, stop on the
+                             residuals of the given one                               */
   int ruiz_iters;         /* Ruiz passes of the scaling (Section 4.1: 10)             */
 } orc_options;
 

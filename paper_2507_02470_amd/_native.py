@@ -22,7 +22,10 @@ class hprqp_problem(C.Structure):
                 ("lr_rank", C.c_int32), ("lr_d", _vp), ("lr_F", _vp),
                 ("c", _vp), ("L", _vp), ("U", _vp),
                 ("a_rowptr", _vp), ("a_col", _vp), ("a_val", _vp), ("a_nnz", C.c_int64),
-                ("l", _vp), ("u", _vp)]
+                ("l", _vp), ("u", _vp),
+                ("l1_weight", C.c_double),
+                ("gram_p", C.c_int32), ("gram_rowptr", _vp), ("gram_col", _vp), ("gram_val", _vp),
+                ("gram_nnz", C.c_int64)]
 
 
 class hprqp_options(C.Structure):

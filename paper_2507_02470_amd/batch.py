@@ -101,6 +101,7 @@ class BatchSolver:
                 p.lr_d, p.lr_F = ptr("d", 8), ptr("F", 8)
                 p.a_rowptr, p.a_col, p.a_val = ptr("arp", 4), ptr("aci", 4), ptr("aval", 8)
                 p.a_nnz = int(q.a_rowptr[-1])
+                p.l1_weight = float(getattr(q, "l1_weight", 0.0))
         self.P = P
         self.ns = np.array(ns, dtype=np.int64)
         self.ms = np.array(ms, dtype=np.int64)

@@ -831,6 +831,7 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     for (int i = 0; i < count; ++i) {
       const hprqp_problem& P = probs[i];
       if (P.qkind != HPRQP_Q_LOWRANK) bfail(HPRQP_ERR_UNSUPPORTED, "batched solve supports qkind HPRQP_Q_LOWRANK only");
+      if (P.l1_weight != 0.0) bfail(HPRQP_ERR_UNSUPPORTED, "batched solve supports phi = box indicator only (l1_weight 0)");
       if (P.n <= 0 || P.n > HB_NMAX || P.m < 0 || P.m > HB_MMAX || P.lr_rank < 0 || P.lr_rank > HB_RMAX)
         bfail(HPRQP_ERR_UNSUPPORTED, "batched solve needs 0 < n <= 2048, 0 <= m <= 64, lr_rank <= 16 (instance " +
                                          std::to_string(i) + ")");

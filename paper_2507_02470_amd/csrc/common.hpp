@@ -81,6 +81,27 @@ __device__ __forceinline__ double clampd(double v, double lo, double hi) {
   return fmin(fmax(v, lo), hi);
 }
 
+// Prox of sigma phi for phi(x) = lambda |x| + delta_[L,U](x), t = sigma lambda:
+// soft threshold at t, then the clamp to [L, U] (t = 0: the projection).
+__device__ __forceinline__ double prox_phi(double r, double t, double L, double U) {
+  const double v = r > t ? r - t : (r < -t ? r + t : 0.0);
+  return clampd(v, L, U);
+}
+
+// -phi^*(-z) for phi(x) = lambda |x| + delta_[L,U](x): phi^*(s) is the max of
+// s x - lambda |x| over x in {L, U, 0 if L <= 0 <= U}; it is +inf when L = -inf
+// and z > lambda or U = +inf and z < -lambda (then *inf is set).  With
+// lambda > 0 an excess of at most 1e-12 max(1, lambda) counts as rounding.
+__device__ __forceinline__ double neg_conj_phi(double z, double lam, double L, double U, bool* inf) {
+  const double slack = lam > 0.0 ? 1e-12 * fmax(lam, 1.0) : 0.0;
+  if ((isinf(L) && z > lam + slack) || (isinf(U) && z < -lam - slack)) { *inf = true; return 0.0; }
+  double best = -INFINITY;
+  if (!isinf(L)) best = fmax(best, -z * L - lam * fabs(L));
+  if (!isinf(U)) best = fmax(best, -z * U - lam * fabs(U));
+  if (L <= 0.0 && 0.0 <= U) best = fmax(best, 0.0);
+  return -best;
+}
+
 // streaming loads/stores for data touched once per product (matrix entries,
 // single-use vector streams): marked non-temporal so they do not evict the
 // vector being gathered from L2

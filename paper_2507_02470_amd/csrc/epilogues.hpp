@@ -91,6 +91,7 @@ struct EpiQ2 {
   const double *q1, *d, *wa, *Qwa, *xa, *ATy, *c, *L, *U, *e;
   double *wbar, *qwbar, *x, *xbar_out;
   int want_r, check, xb_next, trace;
+  double l1;                      // lambda of phi (0: the box projection)
   double sigma, sQ, kappa, rho;
   static constexpr int NR = 9;
   static constexpr unsigned MAXMASK = 0u;
@@ -124,7 +125,7 @@ struct EpiQ2 {
     st_stream(w + i, wn); st_stream(Qw + i, Qwn);
     if (trace) x[i] = xn;
     const double rz = xn + sigma * (-Qwn + ld_stream(ATy + i) - ld_stream(c + i));
-    const double xbn = clampd(rz, ld_stream(L + i), ld_stream(U + i));
+    const double xbn = prox_phi(rz, sigma * l1, ld_stream(L + i), ld_stream(U + i));
     xh[i] = 2.0 * xbn - xn;                                  // gathered next by Q-apply #1
     if (xb_next) { XB[i] = xbn; ZB[i] = (xbn - rz) / sigma; }
   }
@@ -134,6 +135,7 @@ struct EpiQ2 {
 //   r_z = x + sigma(-Qw + A^T y - c); xbar = Pi_C(r_z); zbar = (xbar - r_z)/sigma; xh = 2 xbar - x.
 struct EpiStage1 {
   const double *x, *Qw, *ATy, *c, *L, *U; double *xh, *XB, *ZB;
+  double l1;
   double sigma;
   static constexpr int NR = 0;
   static constexpr unsigned MAXMASK = 0u;
@@ -141,7 +143,7 @@ struct EpiStage1 {
   __device__ __forceinline__ void operator()(int i, double, double*) const {
     const double xi = x[i];
     const double rz = xi + sigma * (-Qw[i] + ATy[i] - c[i]);
-    const double xb = clampd(rz, L[i], U[i]);
+    const double xb = prox_phi(rz, sigma * l1, L[i], U[i]);
     xh[i] = 2.0 * xb - xi; XB[i] = xb; ZB[i] = (xb - rz) / sigma;
   }
 };
@@ -169,14 +171,15 @@ struct EpiResA {
 
 // Dual residual and the rest of the objectives at (x, z) from Q x and g = A^T y:
 //   acc[0] = max |-Qx + g + z - c|, acc[1] = max |g|, acc[2] = max |Qx|,
-//   acc[3] = <x, Qx>, acc[4] = <c, x>, acc[5] = sum_j (L_j z_j^+ + U_j z_j^-),
-//   acc[6] = #(nonzero z_j against an infinite bound).
+//   acc[3] = <x, Qx>, acc[4] = <c, x> + lambda ||x||_1, acc[5] = -phi^*(-z) (for
+//   lambda = 0: sum_j (L_j z_j^+ + U_j z_j^-)), acc[6] = #(z_j making phi^*(-z) infinite).
 // Optionally copies x, z to the output buffers.  With diagonal
 // preconditioning, id = 1/D maps the scaled dual quantities back (the dual
 // residual, A^T y and Q x of the given problem are 1/D times the scaled ones).
 struct EpiResQ {
   const double *x, *z, *g, *c, *L, *U; double *xo, *zo;
   const double* id;   // NULL: no preconditioning
+  double l1;          // lambda of phi: acc[4] also holds lambda ||x||_1
   static constexpr int NR = 7;
   static constexpr unsigned MAXMASK = 0x7u;
   __device__ void setup(const DevParams*, int) {}
@@ -187,10 +190,10 @@ struct EpiResQ {
     acc[1] = fmax(acc[1], fabs(gi) * s);
     acc[2] = fmax(acc[2], fabs(qx) * s);
     acc[3] += xi * qx;
-    acc[4] += ci * xi;
-    const double Li = L[i], Ui = U[i];
-    if (zi > 0.0) { if (isinf(Li)) acc[6] += 1.0; else acc[5] += Li * zi; }
-    else if (zi < 0.0) { if (isinf(Ui)) acc[6] += 1.0; else acc[5] += Ui * zi; }
+    acc[4] += ci * xi + l1 * fabs(xi);
+    bool inf = false;
+    acc[5] += neg_conj_phi(zi, l1, L[i], U[i], &inf);
+    if (inf) acc[6] += 1.0;
     if (xo) { xo[i] = xi; zo[i] = zi; }
   }
 };

@@ -234,6 +234,9 @@ struct hprqp_handle {
   const double *kB = nullptr, *kC = nullptr;
   int lr_r = 0;
   const double *lr_d = nullptr, *lr_F = nullptr;
+  Mat G, GT;                 // Q = Ahat^T Ahat: Ahat (p x n) and its stored transpose
+  double* gtmp = nullptr;    // Ahat x (p)
+  double l1 = 0.0;           // lambda of phi(x) = lambda ||x||_1 + delta_[L,U](x)
   const double *c = nullptr, *L = nullptr, *U = nullptr, *l = nullptr, *u = nullptr;
   // diagonal preconditioning (Section 4.1): the method runs on the scaled data
   // above; A0, AT0, Q0 and c0..u0 are the problem as given
@@ -358,6 +361,11 @@ void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedO
       k_dgemm16<true, Epi><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, p, h.kronT, s, h.kB, p, s, epi, h.dprm, j, red);
       break;
     }
+    case HPRQP_Q_GRAM:
+      // Q x = Ahat^T (Ahat x): a plain product into gtmp, then the epilogue product
+      launch_csr(h, h.G, x, EpiStore{h.gtmp}, j, no_red(h));
+      launch_csr(h, h.GT, h.gtmp, epi, j, red);
+      break;
     case HPRQP_Q_LOWRANK: {
       const int grid = hq_grid(h.n, HQ_BLOCK);
       RedOut lr = no_red(h);
@@ -414,7 +422,7 @@ void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
   if (check) {
     // stopping quantities at ubar = (ybar, zbar, xbar) (Section 4.1)
     if (h.m > 0) launch_csr(h, h.A, h.XB, EpiResA{h.l, h.u, h.ybar, h.iEs}, j, red_seq(h, SL_RA, 4));
-    q_apply(h, h.XB, EpiResQ{h.XB, h.ZB, h.m > 0 ? h.g : nullptr, h.c, h.L, h.U, h.xbo, h.zbo, h.iDs}, j,
+    q_apply(h, h.XB, EpiResQ{h.XB, h.ZB, h.m > 0 ? h.g : nullptr, h.c, h.L, h.U, h.xbo, h.zbo, h.iDs, h.l1}, j,
             red_seq(h, SL_RQ, 7));
   }
   // a6: Q d, wbar, Halpern, next z/x step
@@ -424,6 +432,7 @@ void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
   e6.c = h.c; e6.L = h.L; e6.U = h.U; e6.e = h.e;
   e6.wbar = h.wbar; e6.qwbar = h.qwbar; e6.x = h.x; e6.xbar_out = h.xbo;
   e6.want_r = want_r; e6.check = check; e6.xb_next = xb_next; e6.trace = trace;
+  e6.l1 = h.l1;
   RedOut r6 = no_red(h);
   if (want_r)
     for (int s = 0; s < 6; ++s) r6.slot[s] = (int8_t)(rgroup + 1 + s);
@@ -445,7 +454,8 @@ void enqueue_segment(hprqp_handle& h, int Tseg, bool prof) {
 }
 
 void stage1(hprqp_handle& h) {
-  launch_elem(h, h.n, nullptr, EpiStage1{h.x, h.Qw, h.ATy, h.c, h.L, h.U, h.xh, h.XB, h.ZB, 0.0}, 0, no_red(h));
+  launch_elem(h, h.n, nullptr, EpiStage1{h.x, h.Qw, h.ATy, h.c, h.L, h.U, h.xh, h.XB, h.ZB, h.l1, 0.0}, 0,
+              no_red(h));
 }
 
 // anchor/state <- (y, w, x) buffers; exact A^T y and Q w; z/x step
@@ -629,6 +639,8 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         for (auto& b : a)
           for (auto& e : b) HQC(hipEventCreate(&e));
     h.c = P->c; h.L = P->L; h.U = P->U; h.l = P->l; h.u = P->u;
+    if (!(P->l1_weight >= 0.0) || std::isinf(P->l1_weight)) fail(HPRQP_ERR_ARG, "l1_weight must be finite and >= 0");
+    h.l1 = P->l1_weight;
     const int n = h.n, m = h.m;
     switch (P->qkind) {
       case HPRQP_Q_ZERO: break;
@@ -640,6 +652,12 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         if (!P->kron_B || !P->kron_C || P->kron_p <= 0 || P->kron_s <= 0) fail(HPRQP_ERR_ARG, "Kronecker factors required");
         if ((long long)P->kron_p * P->kron_s != n) fail(HPRQP_ERR_SHAPE, "n must equal kron_p * kron_s");
         h.kp = P->kron_p; h.ks = P->kron_s; h.kB = P->kron_B; h.kC = P->kron_C;
+        break;
+      case HPRQP_Q_GRAM:
+        if (P->gram_p <= 0 || !P->gram_rowptr || (P->gram_nnz > 0 && (!P->gram_col || !P->gram_val)))
+          fail(HPRQP_ERR_ARG, "Gram factor Ahat (gram_p > 0, CSR arrays) required");
+        if (P->gram_nnz < 0 || P->gram_nnz >= (1ll << 31)) fail(HPRQP_ERR_SHAPE, "gram_nnz must fit int32");
+        h.G = Mat{P->gram_p, n, P->gram_rowptr, P->gram_col, P->gram_val, P->gram_nnz, 0};
         break;
       case HPRQP_Q_LOWRANK:
         if (!P->lr_d || (P->lr_rank > 0 && !P->lr_F)) fail(HPRQP_ERR_ARG, "low-rank arrays required");
@@ -683,6 +701,9 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       k_validate_finite<<<64, 256, 0, st>>>(n, h.lr_d, h.dflags);
       k_validate_finite<<<256, 256, 0, st>>>((long long)n * h.lr_r, h.lr_F, h.dflags);
     }
+    if (h.qkind == HPRQP_Q_GRAM)
+      k_validate_csr<<<hq_grid(h.G.rows, 256), 256, 0, st>>>(h.G.rows, n, P->gram_nnz, P->gram_rowptr, P->gram_col,
+                                                             P->gram_val, h.dflags);
     int flags = 0;
     HQC(hipMemcpyAsync(&flags, h.dflags, sizeof(int), hipMemcpyDeviceToHost, st));
     HQC(hipStreamSynchronize(st));
@@ -694,16 +715,27 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       h.at_rp = h.dalloc<int>(n + 1);
       h.at_ci = h.dalloc<int>(P->a_nnz);
       h.at_v = h.dalloc<double>(P->a_nnz);
-      const bool want_perm = opt->precondition && (h.qkind == HPRQP_Q_CSR || h.qkind == HPRQP_Q_ZERO);
+      const bool want_perm = opt->precondition && (h.qkind == HPRQP_Q_CSR || h.qkind == HPRQP_Q_ZERO) && h.l1 == 0.0;
       if (want_perm) h.at_perm = h.dalloc<int>(P->a_nnz);
       HQC(hq_build_transpose(m, n, P->a_nnz, P->a_rowptr, P->a_col, P->a_val, h.at_rp, h.at_ci, h.at_v, h.at_perm,
                              st));
       h.AT = Mat{n, m, h.at_rp, h.at_ci, h.at_v, P->a_nnz, 0};
     }
+    // Gram factor: explicit Ahat^T for the second product of Q x = Ahat^T (Ahat x)
+    if (h.qkind == HPRQP_Q_GRAM) {
+      const int p = h.G.rows;
+      int* grp = h.dalloc<int>(n + 1);
+      int* gci = h.dalloc<int>(std::max<long long>(P->gram_nnz, 1));
+      double* gv = h.dalloc<double>(std::max<long long>(P->gram_nnz, 1));
+      HQC(hq_build_transpose(p, n, P->gram_nnz, P->gram_rowptr, P->gram_col, P->gram_val, grp, gci, gv, nullptr, st));
+      h.GT = Mat{n, p, grp, gci, gv, P->gram_nnz, 0};
+      h.gtmp = h.dalloc<double>(p);
+    }
     h.A0 = h.A; h.AT0 = h.AT; h.Q0 = h.Q;
     h.c0 = h.c; h.L0 = h.L; h.U0 = h.U; h.l0 = h.l; h.u0 = h.u;
-    // diagonal preconditioning (Section 4.1), explicit Q only
-    if (opt->precondition && (h.qkind == HPRQP_Q_CSR || h.qkind == HPRQP_Q_ZERO)) {
+    // diagonal preconditioning (Section 4.1): explicit Q and phi a box indicator
+    // only (a scaled ||x||_1 would need per-variable weights)
+    if (opt->precondition && (h.qkind == HPRQP_Q_CSR || h.qkind == HPRQP_Q_ZERO) && h.l1 == 0.0) {
       if (opt->ruiz_iters < 0) fail(HPRQP_ERR_ARG, "ruiz_iters must be >= 0");
       h.pre = true;
       h.Ds = h.dalloc<double>(n); h.iDs = h.dalloc<double>(n);
@@ -746,6 +778,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
     };
     if (m > 0) { pick(h.A); pick(h.AT); }
     if (h.qkind == HPRQP_Q_CSR) pick(h.Q);
+    if (h.qkind == HPRQP_Q_GRAM) { pick(h.G); pick(h.GT); }
     // lambda's: needed by the params of every kernel, also during the power method
     h.lamA = 0; h.lamQ = 0;
     write_params(h, 1.0, 0);
@@ -755,6 +788,10 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         autotune_csr(h, h.AT, h.tm, h.t1);
       }
       if (h.qkind == HPRQP_Q_CSR) autotune_csr(h, h.Q, h.t1, h.t2);
+      if (h.qkind == HPRQP_Q_GRAM) {
+        autotune_csr(h, h.G, h.t1, h.gtmp);
+        autotune_csr(h, h.GT, h.gtmp, h.t1);
+      }
     }
     if (opt->lambda_A > 0) h.lamA = opt->lambda_A;
     else if (m > 0) {
@@ -970,7 +1007,7 @@ void residuals_impl(hprqp_handle& h, const double* y, const double* z, const dou
     launch_csr(h, h.AT, y, EpiStore{h.t2}, 0, no_red(h));
     launch_csr(h, h.A, x, EpiResA{h.l, h.u, y, h.iEs}, 0, red_seq(h, SL_RA, 4));
   }
-  q_apply(h, x, EpiResQ{x, z, h.m > 0 ? h.t2 : nullptr, h.c, h.L, h.U, nullptr, nullptr, h.iDs}, 0,
+  q_apply(h, x, EpiResQ{x, z, h.m > 0 ? h.t2 : nullptr, h.c, h.L, h.U, nullptr, nullptr, h.iDs, h.l1}, 0,
           red_seq(h, SL_RQ, 7));
   final_reduce(h, 0, SL_ITER_END);
   HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));

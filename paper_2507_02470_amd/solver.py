@@ -12,7 +12,7 @@ import torch
 
 from . import _native as N
 
-QKIND = {"zero": 0, "csr": 1, "kron": 2, "lowrank": 3}
+QKIND = {"zero": 0, "csr": 1, "kron": 2, "lowrank": 3, "gram": 4}
 
 
 def _dev(a, dtype, device):
@@ -59,6 +59,15 @@ class DeviceProblem:
             t["lr_F"] = _dev(qp.lr_F, f64, device)
             P.lr_rank = qp.lr_F.shape[1]
             P.lr_d, P.lr_F = t["lr_d"].data_ptr(), t["lr_F"].data_ptr()
+        elif qp.qkind == "gram":
+            t["gram_rowptr"] = _dev(qp.gram_rowptr, i32, device)
+            t["gram_col"] = _dev(qp.gram_col if len(qp.gram_col) else np.zeros(1), i32, device)
+            t["gram_val"] = _dev(qp.gram_val if len(qp.gram_val) else np.zeros(1), f64, device)
+            P.gram_p = int(qp.gram_p)
+            P.gram_rowptr, P.gram_col, P.gram_val = (t["gram_rowptr"].data_ptr(), t["gram_col"].data_ptr(),
+                                                     t["gram_val"].data_ptr())
+            P.gram_nnz = int(qp.gram_rowptr[-1])
+        P.l1_weight = float(getattr(qp, "l1_weight", 0.0))
         P.c, P.L, P.U = t["c"].data_ptr(), t["L"].data_ptr(), t["U"].data_ptr()
         P.a_rowptr, P.a_col, P.a_val = t["a_rowptr"].data_ptr(), t["a_col"].data_ptr(), t["a_val"].data_ptr()
         P.a_nnz = int(qp.a_rowptr[-1])

@@ -199,8 +199,9 @@ def extra_lasso(steps, cpu):
     ks = s.kernel_stats()
     q_us = ks["avg_ms"]["q_xhat"] * 1e3
     # Q xhat = Ahat^T (Ahat xhat) with its epilogue: both matrices once (12 B per
-    # nonzero + row pointers), xhat and Ahat xhat gathered once, Qw read, v and q1 written
-    q_bytes = 2 * 12 * nnz + 4 * (qp.gram_p + 1) + 4 * (qp.n + 1) + 8 * qp.n + 8 * qp.gram_p * 2 + 8 * qp.n * 3
+    # nonzero + row pointers); Ahat xhat written and gathered once (16 p); xhat
+    # gathered once, xhat and Qw read, v and q1 written (40 n)
+    q_bytes = 2 * 12 * nnz + 4 * (qp.gram_p + 1) + 4 * (qp.n + 1) + 16 * qp.gram_p + 40 * qp.n
     out = dict(workload="lasso", p=qp.gram_p, q=qp.n, nnz=nnz, l1_weight=qp.l1_weight,
                iterations_per_s=round(r.iters / dt, 1), us_per_iteration=round(dt / r.iters * 1e6, 2),
                q_product=dict(avg_us=round(q_us, 2), algorithmic_bytes=q_bytes,

@@ -118,6 +118,9 @@ typedef struct {
                                  [L,U]/D, E[l,u]; termination is tested on the given problem
                                  and inputs/outputs stay in the given variables.  0          */
   int32_t ruiz_iters;         /* Ruiz passes of the preconditioning; 10                  */
+  int32_t spmv_lanes;         /* -1: SpMV kernel per matrix from its row lengths (and the
+                                 autotuner); 0: the CSR-stream kernel; 1, 2, 4, ..., 256:
+                                 that many lanes per row, for every matrix; -1          */
 } hprqp_options;
 
 typedef struct {

@@ -221,6 +221,7 @@ struct Mat {
   const double* v = nullptr;
   long long nnz = 0;
   int G = 4;
+  int maxlen = -1;    // longest row (-1: not measured)
 };
 
 #define HQ_PROF_ITERS 64
@@ -328,7 +329,9 @@ void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, 
     case 8: k_csr<8, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
     case 16: k_csr<16, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
     case 32: k_csr<32, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
-    default: k_csr<64, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    case 64: k_csr<64, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    case 128: k_csr<128, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
+    default: k_csr<256, Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
   }
 }
 
@@ -575,7 +578,7 @@ double power_method(hprqp_handle& h, int which, const double* start, int maxit, 
 
 void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   if (M.rows == 0 || M.nnz == 0) return;
-  const int Gs[] = {0, 2, 4, 8, 16, 32, 64};
+  const int Gs[] = {0, 2, 4, 8, 16, 32, 64, 128, 256};
   hipEvent_t e0, e1;
   HQC(hipEventCreate(&e0));
   HQC(hipEventCreate(&e1));
@@ -585,6 +588,8 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   float best = 1e30f, t_default = 1e30f;
   int bestG = G0;
   for (int G : Gs) {
+    // the CSR-stream kernel adds a row serially: not a candidate for very long rows
+    if (G == 0 && M.maxlen > 4096 && G0 != 0) continue;
     M.G = G;
     launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
     HQC(hipEventRecord(e0, h.st));
@@ -607,7 +612,7 @@ int default_G(long long nnz, int rows, int maxlen) {
   const double avg = rows > 0 ? (double)nnz / rows : 1.0;
   if (avg <= 32.0 && maxlen <= 4096) return 0;
   int G = 1;
-  while (G < 64 && G * 2 <= avg) G *= 2;
+  while (G < HQ_BLOCK && G * 2 <= avg) G *= 2;
   return G;
 }
 
@@ -775,6 +780,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       HQC(hipMemcpyAsync(&mx, h.dflags, sizeof(int), hipMemcpyDeviceToHost, st));
       HQC(hipStreamSynchronize(st));
       M.G = default_G(M.nnz, M.rows, mx);
+      M.maxlen = mx;
     };
     if (m > 0) { pick(h.A); pick(h.AT); }
     if (h.qkind == HPRQP_Q_CSR) pick(h.Q);
@@ -792,6 +798,11 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         autotune_csr(h, h.G, h.t1, h.gtmp);
         autotune_csr(h, h.GT, h.gtmp, h.t1);
       }
+    }
+    if (opt->spmv_lanes >= 0) {
+      const int g = opt->spmv_lanes;
+      if (g > HQ_BLOCK || (g & (g - 1)) != 0) fail(HPRQP_ERR_ARG, "spmv_lanes must be -1, 0 or a power of 2 <= 256");
+      for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT}) M->G = g;
     }
     if (opt->lambda_A > 0) h.lamA = opt->lambda_A;
     else if (m > 0) {
@@ -1063,6 +1074,7 @@ void hprqp_default_options(hprqp_options* o) {
   o->spmv_autotune = 0;
   o->precondition = 0;
   o->ruiz_iters = 10;
+  o->spmv_lanes = -1;
 }
 
 hprqp_status hprqp_create(const hprqp_problem* prob, const hprqp_options* opt, hipStream_t stream,

@@ -4,16 +4,19 @@
 
 // Row-split kernel for long rows: groups of G lanes each own one row (a
 // block covers HQ_BLOCK / G rows per pass); the lanes stride over the row's
-// nonzeros, a butterfly over the group adds the partial sums, and the
-// group's first lane runs the epilogue.  Rows are dealt out in grid-stride
-// order, so a matrix with a few hundred long rows still spreads over
-// hundreds of waves.  No atomics; the summation order depends only on G.
+// nonzeros, the group's partial sums are added by a butterfly (G <= 64) or by
+// wave sums combined in LDS in wave order (G = 128, 256: one row spans 2 or 4
+// waves), and the group's first lane runs the epilogue.  Rows are dealt out
+// in grid-stride order, so a matrix with a few hundred long rows still
+// spreads over hundreds of waves.  No atomics; the summation order depends
+// only on G.
 template <int G, class Epi>
 __global__ __launch_bounds__(HQ_BLOCK) void k_csr(int nrows, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
                                                   const double* __restrict__ val,
                                                   const double* __restrict__ xin, Epi epi,
                                                   const DevParams* __restrict__ prm, int j, RedOut red) {
+  static_assert(G >= 1 && G <= HQ_BLOCK && (HQ_BLOCK % G) == 0, "lanes per row");
   constexpr int RPB = HQ_BLOCK / G;  // rows per block per pass
   constexpr int NR = Epi::NR;
   const int gl = threadIdx.x % G;
@@ -28,9 +31,22 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr(int nrows, const int* __restri
     double sum = 0.0;
     if (row < nrows) {
       const int b = rowptr[row], en = rowptr[row + 1];
+#pragma unroll 4
       for (int k = b + gl; k < en; k += G) sum += ld_stream(val + k) * xin[ld_stream(col + k)];
     }
-    if constexpr (G > 1) {
+    if constexpr (G > 64) {
+      __shared__ double wpart[HQ_BLOCK / HQ_WAVE];
+      sum = wave_sum(sum);
+      if ((threadIdx.x & (HQ_WAVE - 1)) == 0) wpart[threadIdx.x / HQ_WAVE] = sum;
+      __syncthreads();
+      if (gl == 0) {
+        const int w0 = (gi * G) / HQ_WAVE;
+        sum = wpart[w0];
+#pragma unroll
+        for (int w = 1; w < G / HQ_WAVE; ++w) sum += wpart[w0 + w];
+      }
+      __syncthreads();   // wpart is rewritten by the next pass
+    } else if constexpr (G > 1) {
 #pragma unroll
       for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
     }

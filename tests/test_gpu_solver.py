@@ -84,6 +84,30 @@ def test_operators_large_csr_all_lane_groups():
     s = Solver(DP(qp), lambda_Q=1.0, spmv_autotune=1)
     assert _max_rel(s.apply("Q", x).cpu().numpy(), ref) < 1e-13
     s.close()
+    dp = DP(qp)
+    for g in (0, 1, 2, 4, 8, 16, 32, 64, 128, 256):
+        s = Solver(dp, lambda_Q=1.0, spmv_lanes=g)
+        assert _max_rel(s.apply("Q", x).cpu().numpy(), ref) < 1e-13, g
+        s.close()
+
+
+def test_long_rows_and_every_kernel_in_the_iteration():
+    """A Gram Q with rows of thousands of nonzeros (the Lasso shape) through the
+    whole iteration with every SpMV kernel: iterates agree with the oracle."""
+    DP, Solver = _S()
+    qp = qpgen.make_lasso(seed=5, p=40, q=9000, density=0.3)     # 2700 nonzeros per row of Ahat
+    lamQ = 1.01 * oracle.power(qp, "Q", qpgen.power_start(qp.n), maxit=5000, tol=1e-10)[0]
+    K = 30
+    ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_Q=lamQ, trace_iters=K)
+    to = split_trace(ro.trace, qp.n, qp.m)
+    dp = DP(qp)
+    for g in (0, 1, 8, 64, 128, 256):
+        s = Solver(dp, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K, spmv_lanes=g)
+        rg = s.solve()
+        s.close()
+        tg = split_trace(rg.trace, qp.n, qp.m)
+        for name in ("w", "x", "wbar", "xbar"):
+            assert _max_rel(tg[name][K - 1], to[name][K - 1]) <= 1e-10, (g, name)
 
 
 def test_power_method_matches_oracle():

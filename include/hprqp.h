@@ -119,8 +119,10 @@ typedef struct {
                                  and inputs/outputs stay in the given variables.  0          */
   int32_t ruiz_iters;         /* Ruiz passes of the preconditioning; 10                  */
   int32_t spmv_lanes;         /* -1: SpMV kernel per matrix from its row lengths (and the
-                                 autotuner); 0: the CSR-stream kernel; 1, 2, 4, ..., 256:
-                                 that many lanes per row, for every matrix; -1          */
+                                 autotuner); 0: the CSR-stream kernel; -2: the CSR-stream
+                                 kernel gathering from an LDS copy of the input vector
+                                 (matrices with at most 16384 columns, else 0); 1, 2, 4,
+                                 ..., 256: that many lanes per row, for every matrix; -1  */
 } hprqp_options;
 
 typedef struct {

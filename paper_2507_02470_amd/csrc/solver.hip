@@ -228,6 +228,7 @@ struct Mat {
 
 struct hprqp_handle {
   int dev = 0;
+  int ncu = 256;     // compute units of the device
   hipStream_t st = nullptr;
   int n = 0, m = 0, qkind = 0;
   Mat A, AT, Q;
@@ -316,8 +317,31 @@ inline RedOut red_seq(hprqp_handle& h, int slot0, int nr) {
   return r;
 }
 
+// Lanes-per-row code of the stream kernel that gathers from an LDS copy of the
+// input vector (matrices with at most HQ_XLDS_MAX columns).
+#define HQ_G_XLDS (-1)
+
+template <class Epi>
+void launch_csr_xlds(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
+  constexpr int BS = HQ_XLDS_BLOCK;
+  const size_t lds = (size_t)M.cols * sizeof(double);
+  static bool attr_set = false;   // one per epilogue type: dynamic LDS above 64 KB must be enabled
+  if (!attr_set) {
+    HQC(hipFuncSetAttribute((const void*)k_csr_stream<Epi, true, BS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(HQ_XLDS_MAX * sizeof(double))));
+    attr_set = true;
+  }
+  // persistent grid of 1024-thread blocks: as many as fit on the CUs at this LDS size
+  const size_t per_block = lds + 2 * HQ_STREAM_CHUNK * sizeof(double) + (BS + 1) * sizeof(int) + 2048;
+  const int per_cu = std::max(1, (int)((160 * 1024) / per_block));
+  const int nblk = (M.rows + BS - 1) / BS;
+  const int grid = std::max(1, std::min(nblk, std::min(h.ncu * per_cu, HQ_GRID_CAP)));
+  k_csr_stream<Epi, true, BS><<<grid, BS, lds, h.st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red, M.cols);
+}
+
 template <class Epi>
 void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
+  if (M.G == HQ_G_XLDS) { launch_csr_xlds(h, M, x, epi, j, red); return; }
   // stream kernel: HQ_BLOCK rows per block; row-split kernel: HQ_BLOCK / G rows per block
   const int grid = M.G == 0 ? hq_grid(M.rows, HQ_BLOCK) : hq_grid(M.rows, HQ_BLOCK / M.G);
   hipStream_t st = h.st;
@@ -578,7 +602,7 @@ double power_method(hprqp_handle& h, int which, const double* start, int maxit, 
 
 void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   if (M.rows == 0 || M.nnz == 0) return;
-  const int Gs[] = {0, 2, 4, 8, 16, 32, 64, 128, 256};
+  const int Gs[] = {0, HQ_G_XLDS, 2, 4, 8, 16, 32, 64, 128, 256};
   hipEvent_t e0, e1;
   HQC(hipEventCreate(&e0));
   HQC(hipEventCreate(&e1));
@@ -588,8 +612,9 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   float best = 1e30f, t_default = 1e30f;
   int bestG = G0;
   for (int G : Gs) {
-    // the CSR-stream kernel adds a row serially: not a candidate for very long rows
-    if (G == 0 && M.maxlen > 4096 && G0 != 0) continue;
+    // the CSR-stream kernels add a row serially: not candidates for very long rows
+    if ((G == 0 || G == HQ_G_XLDS) && M.maxlen > 4096 && G0 != 0) continue;
+    if (G == HQ_G_XLDS && M.cols > HQ_XLDS_MAX) continue;
     M.G = G;
     launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
     HQC(hipEventRecord(e0, h.st));
@@ -607,9 +632,13 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
 }
 
 // Lanes per row of the row-split kernel, or 0 for the CSR-stream kernel
-// (short rows: average up to 32 nonzeros and none longer than 4096).
-int default_G(long long nnz, int rows, int maxlen) {
+// (short rows: average up to 32 nonzeros and none longer than 4096).  The
+// variant gathering from an LDS copy of the vector is left to the autotuner:
+// measured on a 5e7-nonzero A^T with an 80 KB vector it was slower (322 us vs
+// 262 us) than gathering through the L2.
+int default_G(long long nnz, int rows, int maxlen, int cols) {
   const double avg = rows > 0 ? (double)nnz / rows : 1.0;
+  (void)cols;
   if (avg <= 32.0 && maxlen <= 4096) return 0;
   int G = 1;
   while (G < HQ_BLOCK && G * 2 <= avg) G *= 2;
@@ -630,6 +659,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
   try {
     hprqp_handle& h = *hp;
     HQC(hipGetDevice(&h.dev));
+    HQC(hipDeviceGetAttribute(&h.ncu, hipDeviceAttributeMultiprocessorCount, h.dev));
     if (!st) {
       // graphs cannot be captured on the legacy null stream: use a private one
       HQC(hipStreamCreateWithFlags(&h.own_st, hipStreamNonBlocking));
@@ -779,7 +809,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       int mx = 0;
       HQC(hipMemcpyAsync(&mx, h.dflags, sizeof(int), hipMemcpyDeviceToHost, st));
       HQC(hipStreamSynchronize(st));
-      M.G = default_G(M.nnz, M.rows, mx);
+      M.G = default_G(M.nnz, M.rows, mx, M.cols);
       M.maxlen = mx;
     };
     if (m > 0) { pick(h.A); pick(h.AT); }
@@ -799,10 +829,12 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         autotune_csr(h, h.GT, h.gtmp, h.t1);
       }
     }
-    if (opt->spmv_lanes >= 0) {
-      const int g = opt->spmv_lanes;
-      if (g > HQ_BLOCK || (g & (g - 1)) != 0) fail(HPRQP_ERR_ARG, "spmv_lanes must be -1, 0 or a power of 2 <= 256");
-      for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT}) M->G = g;
+    if (opt->spmv_lanes >= 0 || opt->spmv_lanes == -2) {
+      const int g = opt->spmv_lanes == -2 ? HQ_G_XLDS : opt->spmv_lanes;
+      if (g != HQ_G_XLDS && (g > HQ_BLOCK || (g & (g - 1)) != 0))
+        fail(HPRQP_ERR_ARG, "spmv_lanes must be -2, -1, 0 or a power of 2 <= 256");
+      for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT})
+        M->G = (g == HQ_G_XLDS && M->cols > HQ_XLDS_MAX) ? 0 : g;   // the LDS copy needs a small vector
     }
     if (opt->lambda_A > 0) h.lamA = opt->lambda_A;
     else if (m > 0) {

@@ -63,35 +63,52 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr(int nrows, const int* __restri
 // and runs the epilogue for that row.  Loads of the matrix and of the
 // gathered vector are independent of the row structure, which keeps many
 // gathers in flight per wave.
+//
+// XLDS: the whole input vector (ncols entries) is first copied into LDS
+// (dynamic shared memory) and gathered from there: for vectors that fit
+// (up to HQ_XLDS_MAX entries) the gathers then cost no L2 requests.  The grid
+// is persistent (a few blocks per CU), so the copy is made once per block.
+// BS: threads (= rows) per block; the chunk is 2048 products (4096 for
+// 1024-thread blocks, keeping 32 KB of LDS beside the vector's copy).
 #define HQ_STREAM_CHUNK 2048
-template <class Epi>
-__global__ __launch_bounds__(HQ_BLOCK) void k_csr_stream(int nrows, const int* __restrict__ rowptr,
-                                                         const int* __restrict__ col,
-                                                         const double* __restrict__ val,
-                                                         const double* __restrict__ xin, Epi epi,
-                                                         const DevParams* __restrict__ prm, int j, RedOut red) {
+#define HQ_XLDS_MAX 14336
+#define HQ_XLDS_BLOCK 1024
+template <class Epi, bool XLDS = false, int BS = HQ_BLOCK>
+__global__ __launch_bounds__(BS) void k_csr_stream(int nrows, const int* __restrict__ rowptr,
+                                                   const int* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ xin, Epi epi,
+                                                   const DevParams* __restrict__ prm, int j, RedOut red,
+                                                   int ncols = 0) {
   constexpr int NR = Epi::NR;
-  __shared__ double prod[HQ_STREAM_CHUNK];
-  __shared__ int srp[HQ_BLOCK + 1];
+  constexpr int CH = BS > HQ_BLOCK ? 2 * HQ_STREAM_CHUNK : HQ_STREAM_CHUNK;
+  __shared__ double prod[CH];
+  __shared__ int srp[BS + 1];
+  extern __shared__ double xs[];
   Epi e = epi;
   e.setup(prm, j);
   double acc[NR > 0 ? NR : 1];
 #pragma unroll
   for (int s = 0; s < (NR > 0 ? NR : 1); ++s) acc[s] = 0.0;
   const int t = threadIdx.x;
-  const int nblk = (nrows + HQ_BLOCK - 1) / HQ_BLOCK;
+  if constexpr (XLDS) {
+    for (int i = t; i < ncols; i += BS) xs[i] = xin[i];
+    __syncthreads();
+  }
+  const double* xg = XLDS ? xs : xin;
+  const int nblk = (nrows + BS - 1) / BS;
   for (int rb = blockIdx.x; rb < nblk; rb += gridDim.x) {
-    const int r0 = rb * HQ_BLOCK;
-    const int nr = min(HQ_BLOCK, nrows - r0);
-    for (int i = t; i <= nr; i += HQ_BLOCK) srp[i] = rowptr[r0 + i];   // nr + 1 row pointers
+    const int r0 = rb * BS;
+    const int nr = min(BS, nrows - r0);
+    for (int i = t; i <= nr; i += BS) srp[i] = rowptr[r0 + i];   // nr + 1 row pointers
     __syncthreads();
     const int kb = srp[0], ke = srp[nr];
     const int myb = t < nr ? srp[t] : 0, mye = t < nr ? srp[t + 1] : 0;
     double sum = 0.0;
-    for (int c0 = kb; c0 < ke; c0 += HQ_STREAM_CHUNK) {
-      const int c1 = min(ke, c0 + HQ_STREAM_CHUNK);
+    for (int c0 = kb; c0 < ke; c0 += CH) {
+      const int c1 = min(ke, c0 + CH);
 #pragma unroll 4
-      for (int k = c0 + t; k < c1; k += HQ_BLOCK) prod[k - c0] = ld_stream(val + k) * xin[ld_stream(col + k)];
+      for (int k = c0 + t; k < c1; k += BS) prod[k - c0] = ld_stream(val + k) * xg[ld_stream(col + k)];
       __syncthreads();
       const int lo = max(myb, c0), hi = min(mye, c1);
       for (int k = lo; k < hi; ++k) sum += prod[k - c0];

@@ -53,16 +53,18 @@ def test_operators_csr_kron_lowrank():
              qpgen.make_portfolio(12, n=777)]
     for qp in cases:
         print("operators:", qp.meta.get("workload"), qp.n, qp.m, flush=True)
-        s = Solver(DP(qp), lambda_A=1.0, lambda_Q=1.0)
         x = rng.standard_normal(qp.n); y = rng.standard_normal(qp.m)
-        Qd = qp.Q_dense() if qp.n <= 4000 else None
-        ref_q = Qd @ x
-        got = s.apply("Q", x).cpu().numpy()
-        assert _max_rel(got, ref_q) < 1e-13
-        A = qp.A_scipy()
-        assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13
-        assert _max_rel(s.apply("AT", y).cpu().numpy(), A.T @ y) < 1e-13
-        s.close()
+        dp = DP(qp)
+        for lanes in (-1, 0, -2):    # default choice, CSR-stream, CSR-stream gathering from LDS
+            s = Solver(dp, lambda_A=1.0, lambda_Q=1.0, spmv_lanes=lanes)
+            Qd = qp.Q_dense() if qp.n <= 4000 else None
+            ref_q = Qd @ x
+            got = s.apply("Q", x).cpu().numpy()
+            assert _max_rel(got, ref_q) < 1e-13, lanes
+            A = qp.A_scipy()
+            assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13, lanes
+            assert _max_rel(s.apply("AT", y).cpu().numpy(), A.T @ y) < 1e-13, lanes
+            s.close()
 
 
 def test_operators_large_csr_all_lane_groups():
@@ -101,7 +103,7 @@ def test_long_rows_and_every_kernel_in_the_iteration():
     ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_Q=lamQ, trace_iters=K)
     to = split_trace(ro.trace, qp.n, qp.m)
     dp = DP(qp)
-    for g in (0, 1, 8, 64, 128, 256):
+    for g in (-2, 0, 1, 8, 64, 128, 256):
         s = Solver(dp, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K, spmv_lanes=g)
         rg = s.solve()
         s.close()

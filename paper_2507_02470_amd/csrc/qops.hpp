@@ -12,13 +12,14 @@ typedef double hq_dx4 __attribute__((ext_vector_type(4)));
 // One 16 x 16 output tile per block of HQ_KSPLIT waves; the waves split K
 // into HQ_KSPLIT ranges, each accumulating with v_mfma_f64_16x16x4f64, and
 // the partial tiles are summed in LDS in a fixed order (deterministic).  A
-// short K range per wave keeps the chain of dependent loads and MFMAs short:
+// short K range per wave keeps the chain of loads and MFMAs short:
 // at these sizes (d ~ 300) the product is latency-bound, not MFMA-bound.
 // Operand layout of the 16x16x4 f64 MFMA (measured on gfx950): lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register v of lane l
 // holds D[l/16 + 4v][l%16], v = 0..3.
 // ---------------------------------------------------------------------------
 #define HQ_KSPLIT 8
+#define HQ_KUNROLL 5
 template <bool TRANSB, class Epi>
 __global__ __launch_bounds__(64 * HQ_KSPLIT) void k_dgemm16(int M, int N, int K, const double* __restrict__ A, int lda,
                                                             const double* __restrict__ B, int ldb, int ldo, Epi epi,
@@ -41,13 +42,26 @@ __global__ __launch_bounds__(64 * HQ_KSPLIT) void k_dgemm16(int M, int N, int K,
     const int i0 = (tile % tiles_m) << 4, j0 = (tile / tiles_m) << 4;
     const int ia = i0 + li, jb = j0 + li;
     hq_dx4 d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-    for (int ks = ks0; ks < ks1; ++ks) {
-      const int k = (ks << 2) + lk;
-      const bool kin = k < K;
-      const double a = (ia < M && kin) ? A[ia + (size_t)lda * k] : 0.0;
-      const double b = (jb < N && kin) ? (TRANSB ? B[jb + (size_t)ldb * k] : B[k + (size_t)ldb * jb]) : 0.0;
-      d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+    // the operands of HQ_KUNROLL k-steps are loaded first (all in flight at
+    // once: the MFMA chain would otherwise wait a full load latency per
+    // step), then multiplied; out-of-range operands are read from a clamped
+    // index and replaced by 0
+    for (int kc = ks0; kc < ks1; kc += HQ_KUNROLL) {
+      double av[HQ_KUNROLL], bv[HQ_KUNROLL];
+#pragma unroll
+      for (int u = 0; u < HQ_KUNROLL; ++u) {
+        const int ks = kc + u;
+        const int k = (ks << 2) + lk;
+        const bool kin = ks < ks1 && k < K;
+        const int kk = kin ? k : 0;
+        const int ic = ia < M ? ia : M - 1, jc = jb < N ? jb : N - 1;
+        const double a = A[ic + (size_t)lda * kk];
+        const double b = TRANSB ? B[jc + (size_t)ldb * kk] : B[kk + (size_t)ldb * jc];
+        av[u] = (ia < M && kin) ? a : 0.0;
+        bv[u] = (jb < N && kin) ? b : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < HQ_KUNROLL; ++u) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], d, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) part[wv][lk + 4 * v][li] = d[v];

@@ -41,6 +41,7 @@ static inline int rup8(int v) { return (v + 7) & ~7; }
 // (resp. b_rs == 1) and the row start is 16-byte aligned the 8 values come
 // from one vector load.
 // ---------------------------------------------------------------------------
+#define HM_KUNROLL 8
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, long long a_rs,
                                                   long long a_cs, const uint16_t* __restrict__ B, long long b_rs,
                                                   long long b_cs, float* __restrict__ C, long long ldc, int accumulate) {
@@ -52,23 +53,40 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   const bool a_vec = (a_cs == 1) && ((a_rs & 7) == 0) && ((((uintptr_t)A) & 15) == 0);
   const bool b_vec = (b_rs == 1) && ((b_cs & 7) == 0) && ((((uintptr_t)B) & 15) == 0);
   hm_f32x16 acc = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const int kb = k0 + 8 * lh;
-    hm_u16x8 au, bu;
+  auto frag_a = [&](int kb) {
+    hm_u16x8 au;
     if (a_vec && ia < M && kb + 8 <= K) {
       au = *reinterpret_cast<const hm_u16x8*>(A + (long long)ia * a_rs + kb);
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) au[e] = (ia < M && kb + e < K) ? A[(long long)ia * a_rs + (long long)(kb + e) * a_cs] : 0;
     }
+    return au;
+  };
+  auto frag_b = [&](int kb) {
+    hm_u16x8 bu;
     if (b_vec && jb < N && kb + 8 <= K) {
       bu = *reinterpret_cast<const hm_u16x8*>(B + (long long)jb * b_cs + kb);
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) bu[e] = (jb < N && kb + e < K) ? B[(long long)(kb + e) * b_rs + (long long)jb * b_cs] : 0;
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(hm_bf16x8, au), __builtin_bit_cast(hm_bf16x8, bu),
-                                                  acc, 0, 0, 0);
+    return bu;
+  };
+  // the fragments of HM_KUNROLL k-steps are loaded first (all in flight at
+  // once), then multiplied: the MFMA chain does not wait a load per step
+  for (int k0 = 0; k0 < K; k0 += 16 * HM_KUNROLL) {
+    hm_u16x8 au[HM_KUNROLL], bu[HM_KUNROLL];
+#pragma unroll
+    for (int u = 0; u < HM_KUNROLL; ++u) {
+      const int kb = k0 + 16 * u + 8 * lh;
+      au[u] = frag_a(kb);
+      bu[u] = frag_b(kb);
+    }
+#pragma unroll
+    for (int u = 0; u < HM_KUNROLL; ++u)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(hm_bf16x8, au[u]),
+                                                    __builtin_bit_cast(hm_bf16x8, bu[u]), acc, 0, 0, 0);
   }
 #pragma unroll
   for (int v = 0; v < 16; ++v) {

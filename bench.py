@@ -100,6 +100,7 @@ def cpu_baseline(qp, lam_A, lam_Q, sigma0, iters):
 
 
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 MFMA, published
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, published
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA, published
 
 
@@ -235,23 +236,64 @@ def extra_batch(count, cpu):
     dt = time.perf_counter() - ta
     it = r.iters
     terms = [f["term"] for f in r.infos]
+    # FP64 vector work per iteration of an instance (n variables, rank r, nnz(A)):
+    # two Q products of 4nr + 2n, A v and A^T ybar 2 nnz(A) each, about 40n of
+    # elementwise updates; the persistent kernel is latency-bound, so this is
+    # reported against the FP64 vector peak as an ALU roofline
+    flops = sum(float(it[i]) * (2 * (4 * q.n * q.lr_F.shape[1] + 2 * q.n) + 4 * q.a_nnz + 40 * q.n)
+                for i, q in enumerate(qps))
+    achieved = flops / r.kernel_s / 1e12
     out = dict(workload="portfolio_batch", instances=count, sum_n=int(sum(q.n for q in qps)),
                solved=terms.count("solved"), wall_s=round(dt, 4), kernel_s=round(r.kernel_s, 4),
                instances_per_s=round(count / dt, 1), instance_iterations_per_s=round(float(it.sum()) / dt, 1),
                iterations_mean=round(float(it.mean()), 1), iterations_max=int(it.max()),
-               max_kkt=float(max(f["kkt"] for f in r.infos)))
+               max_kkt=float(max(f["kkt"] for f in r.infos)),
+               roofline=dict(bound="alu", achieved=round(achieved, 3), peak=FP64_VECTOR_PEAK_TFLOPS,
+                             unit="TFLOP/s", frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                             flop_per_batch=flops))
     b.close()
     if cpu:
         import oracle
-        sample = sorted(range(count), key=lambda i: qps[i].n)[::max(1, count // 16)][:16]
+        sample = sorted(range(count), key=lambda i: qps[i].n)[::max(1, count // 64)][:64]
         t0 = time.perf_counter()
         its = 0
         for i in sample:
             its += oracle.solve(qps[i], tol=1e-8, max_iter=200_000).iters
         tc = time.perf_counter() - t0
+        cores = os.cpu_count() or 1
         out["cpu_oracle"] = dict(instances_per_s=round(len(sample) / tc, 2),
                                  instance_iterations_per_s=round(its / tc, 1), cores=1,
-                                 sample=f"{len(sample)} instances stratified by n, solved one after another")
+                                 sample=f"{len(sample)} instances stratified by n, solved one after another",
+                                 projected_all_cores=dict(instances_per_s=round(cores * len(sample) / tc, 1),
+                                                          cores=cores, kind="projected (independent instances)"))
+    return out
+
+
+def extra_small(cpu):
+    """The small CCQP (n = 200, m = 100): launch-latency bound, graph replay."""
+    import torch
+    import qpgen
+    from paper_2507_02470_amd.solver import DeviceProblem, Solver
+    qp = qpgen.make_small_ccqp()
+    s = Solver(DeviceProblem(qp), check_every=T_CHECK, tol=0.0, max_iter=T_CHECK)
+    s.solve()
+    s.set_options(tol=0.0, max_iter=20 * T_CHECK)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    r = s.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ta
+    s.set_options(tol=1e-8, max_iter=1_000_000)
+    rt = s.solve()
+    s.close()
+    out = {"workload": "small_ccqp", "n": qp.n, "m": qp.m, "us_per_iteration": round(dt / r.iters * 1e6, 2),
+           "time_to_1e-8": dict(term=rt.term, iterations=rt.iters, time_s=round(rt.t_setup_s + rt.t_solve_s, 4))}
+    if cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ro = oracle.solve(qp, tol=1e-8, max_iter=1_000_000)
+        out["cpu_oracle_full_solve"] = dict(term=ro.term, iterations=ro.iters, time_s=round(time.perf_counter() - t0, 4),
+                                            cores=1)
     return out
 
 
@@ -408,6 +450,8 @@ def main():
     extras = None
     if not args.no_extras and args.workload == "random_large":
         extras = {}
+        extras["small_ccqp"] = extra_small(not args.no_cpu_baseline)
+        log(f"small: {extras['small_ccqp']}")
         extras["precond"] = extra_precond(qp, dp, not args.no_cpu_baseline)
         log(f"precond: {extras['precond']}")
         extras["lasso"] = extra_lasso(max(5, args.steps // 2), not args.no_cpu_baseline)

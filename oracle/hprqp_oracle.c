@@ -27,6 +27,14 @@
  *    the updates of Algorithm 4 (zbar is recomputed from (y, w, x)).
  *  - A term of the dual objective whose bound is infinite counts 0 when its
  *    multiplier is exactly 0.
+ *  - HPR on the primal reformulations (Appendix A, method 1 and 2): the
+ *    paper says only that they use restart and sigma strategies similar to
+ *    HPR-QP's.  Here: the same restart criteria on R~ = ||u - ubar||_M with
+ *    the metric M of the reformulation (derived from the steps, see
+ *    orc_primal_mnorm2); sigma <- minimiser of the sigma-dependent part of
+ *    ||ubar - u^{r,0}||_M^2, smoothed as in Algorithm 5; sigma0 = ||c||/||b||;
+ *    the multiplier t of x = v starts at 0; s is read by no step and is not
+ *    carried.
  */
 #include "hprqp_oracle.h"
 
@@ -554,11 +562,248 @@ static int solve_core(const orc_problem *P, const orc_problem *P0, const double 
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* HPR on the primal reformulations (Appendix A): the two baselines of       */
+/* Table 1.  Variant 1 splits Ax = s ("QP-primal-s", Algorithm 6), variant 2  */
+/* also x = v ("QP-primal-sv", Algorithm 7).                                 */
+/* ------------------------------------------------------------------------ */
+/* One pass of Steps 1-3 from the state (x, v, y, t) (v, t: variant 2 only;
+ * s is read by no step, so it is not part of the state):
+ *   Step 1/2:  sbar = Pi_K(r), r = Ax - y/sigma (the minimiser of L_sigma
+ *              over s), ybar = y + sigma (sbar - Ax) = sigma (sbar - r);
+ *   variant 2: vbar = (sigma x - t + lamQ v - Q v)/(lamQ + sigma)  (the v-part
+ *              of Step 1 with the proximal term S_v = lamQ I - Q),
+ *              tbar = t + sigma (vbar - x);
+ *   Step 3, variant 1 (S_x = lamQ I - Q + sigma(lamA I - A^T A)): the quadratic
+ *              part of the subproblem becomes tau/2 ||x||^2, tau = lamQ + sigma lamA,
+ *              so xbar = prox_{phi/tau}(x - (Q x + c - A^T(2 ybar - y))/tau);
+ *   Step 3, variant 2 (S_x = sigma(lamA I - A^T A)): kappa = sigma (1 + lamA),
+ *              xbar = prox_{phi/kappa}((sigma lamA x + sigma vbar + tbar
+ *                                        + A^T(2 ybar - y) - c)/kappa).
+ * zbar = tau (xbar - r) (kappa for variant 2), r the prox argument: the
+ * multiplier with -zbar in the subdifferential of phi at xbar.            */
+void orc_primal_step(const orc_problem *P, int variant, double sigma, double lamA, double lamQ,
+                     const double *x, const double *v, const double *y, const double *t,
+                     double *sb, double *yb, double *vb, double *tb, double *xb, double *zb) {
+  const int n = P->n, m = P->m;
+  double *Ax = vnew(m), *e = vnew(m), *g = vnew(n), *Qin = vnew(n);
+  orc_apply_A(P, x, Ax);
+  for (int i = 0; i < m; ++i) {
+    /* ybar = y + sigma (sbar - Ax) written as sigma (sbar - r), r = Ax - y/sigma
+     * (the same number up to rounding): ybar is exactly 0 where the
+     * projection is inactive, so its sign always matches the active bound */
+    const double r = Ax[i] - y[i] / sigma;
+    sb[i] = clamp(r, P->l[i], P->u[i]);
+    yb[i] = sigma * (sb[i] - r);
+    e[i] = 2.0 * yb[i] - y[i];
+  }
+  orc_apply_AT(P, e, g);
+  if (variant == 1) {
+    const double tau = lamQ + sigma * lamA;
+    orc_apply_Q(P, x, Qin);
+    for (int j = 0; j < n; ++j) {
+      double r = x[j] - (Qin[j] + P->c[j] - g[j]) / tau;
+      xb[j] = orc_prox(P, j, 1.0 / tau, r);
+      zb[j] = tau * (xb[j] - r);
+    }
+  } else {
+    const double kap = sigma * (1.0 + lamA);
+    orc_apply_Q(P, v, Qin);
+    for (int j = 0; j < n; ++j) {
+      vb[j] = (sigma * x[j] - t[j] + lamQ * v[j] - Qin[j]) / (lamQ + sigma);
+      tb[j] = t[j] + sigma * (vb[j] - x[j]);
+      double r = (sigma * lamA * x[j] + sigma * vb[j] + tb[j] + g[j] - P->c[j]) / kap;
+      xb[j] = orc_prox(P, j, 1.0 / kap, r);
+      zb[j] = kap * (xb[j] - r);
+    }
+  }
+  free(Ax); free(e); free(g); free(Qin);
+}
+
+/* ||du||_M^2 for the metric of the preconditioned proximal-point form of
+ * Algorithms 6 and 7 (0 in T(ubar) + M(ubar - u), T the KKT operator of the
+ * reformulation; the s-block of M is 0):
+ *   variant 1: <dx, (tau I - Q) dx> - 2 <A dx, dy> + ||dy||^2 / sigma;
+ *   variant 2: kappa ||dx||^2 - 2 <A dx, dy> - 2 <dx, dt> + (||dy||^2 + ||dt||^2)/sigma
+ *              + <dv, (lamQ I - Q) dv>.                                    */
+double orc_primal_mnorm2(const orc_problem *P, int variant, double sigma, double lamA, double lamQ,
+                         const double *dx, const double *dv, const double *dy, const double *dt) {
+  const int n = P->n, m = P->m;
+  double *Adx = vnew(m), *Qd = vnew(n);
+  orc_apply_A(P, dx, Adx);
+  double r = -2.0 * dot(Adx, dy, m) + dot(dy, dy, m) / sigma;
+  if (variant == 1) {
+    orc_apply_Q(P, dx, Qd);
+    r += (lamQ + sigma * lamA) * dot(dx, dx, n) - dot(dx, Qd, n);
+  } else {
+    orc_apply_Q(P, dv, Qd);
+    r += sigma * (1.0 + lamA) * dot(dx, dx, n) - 2.0 * dot(dx, dt, n) + dot(dt, dt, n) / sigma
+         + lamQ * dot(dv, dv, n) - dot(dv, Qd, n);
+  }
+  free(Adx); free(Qd);
+  return r;
+}
+
+/* Algorithms 6/7 with the restart and sigma strategy carried over from
+ * HPR-QP (readings listed in the header comment of this file):
+ *   merit R~ = ||u - ubar||_M (metric above), restart criteria of Section 3.2;
+ *   sigma update: the minimiser of the sigma-dependent part of
+ *   ||ubar - u^{r,0}||_M^2, i.e. sqrt(th2/th1) with th1 = lamA ||Dx||^2
+ *   (variant 2: (1 + lamA) ||Dx||^2) and th2 = ||Dy||^2 (+ ||Dt||^2), both
+ *   clamped at 1e-12, then the smoothing of Algorithm 5 with beta = exp(-ratio);
+ *   sigma0 = ||c|| / ||b|| (the reciprocal of the HPR-QP rule: here sigma
+ *   multiplies the primal residual);  state (x, v, y, t) from (x0, w0, y0, 0).
+ * Output: ubar with w = xbar (variant 1) or vbar (variant 2).              */
+static int solve_primal(const orc_problem *P, const orc_problem *P0, const double *D, const double *E,
+                        const orc_options *opt, const double *y0, const double *w0, const double *x0,
+                        double *y_out, double *z_out, double *w_out, double *x_out, orc_info *info) {
+  const int n = P->n, m = P->m, var = opt->method;
+  const double t_start = now_s();
+  memset(info, 0, sizeof(*info));
+  double lamA = opt->lambda_A, lamQ = opt->lambda_Q;
+  if (lamA <= 0.0) lamA = (m > 0) ? 1.01 * orc_power(P, 0, opt->power_start_A, 5000, 1e-6, NULL) : 0.0;
+  if (lamQ <= 0.0)
+    lamQ = (P->qkind == ORC_Q_ZERO) ? 0.0 : 1.01 * orc_power(P, 1, opt->power_start_Q, 5000, 1e-6, NULL);
+  double sigma = opt->sigma0;
+  if (sigma <= 0.0) {
+    double d = orc_sigma0(P);
+    sigma = (d == 1.0) ? 1.0 : 1.0 / d;
+  }
+  info->lambda_A = lamA; info->lambda_Q = lamQ; info->sigma0 = sigma;
+  const int T = opt->check_every > 0 ? opt->check_every : 1;
+
+  double *x = vnew(n), *v = vnew(n), *y = vnew(m), *t = vnew(n);
+  double *xa = vnew(n), *va = vnew(n), *ya = vnew(m), *ta = vnew(n);
+  double *xb = vnew(n), *vb = vnew(n), *yb = vnew(m), *tb = vnew(n), *sb = vnew(m), *zb = vnew(n);
+  double *dx = vnew(n), *dv = vnew(n), *dy = vnew(m), *dt = vnew(n);
+  if (x0) memcpy(x, x0, sizeof(double) * n);
+  if (w0 && var == 2) memcpy(v, w0, sizeof(double) * n);
+  if (y0) memcpy(y, y0, sizeof(double) * m);
+
+  int64_t k = 0;
+  int r = 0, term = -1;
+  double alpha3 = opt->alpha3, R0ref = -1.0, R = 0.0;
+  const int rowlen = 2 * m + 4 * n;
+  while (term < 0) {
+    memcpy(xa, x, sizeof(double) * n); memcpy(va, v, sizeof(double) * n);
+    memcpy(ya, y, sizeof(double) * m); memcpy(ta, t, sizeof(double) * n);
+    int64_t it = 0;
+    double Rr0 = -1.0, Rprev = -1.0;
+    int restarted = 0;
+    while (!restarted && term < 0) {
+      orc_primal_step(P, var, sigma, lamA, lamQ, x, v, y, t, sb, yb, vb, tb, xb, zb);
+      const int is_check = ((k + 1) % T == 0) || (k + 1 >= opt->max_iter);
+      if (it == 0 || is_check) {
+        for (int j = 0; j < n; ++j) { dx[j] = x[j] - xb[j]; dv[j] = v[j] - vb[j]; dt[j] = t[j] - tb[j]; }
+        for (int i = 0; i < m; ++i) dy[i] = y[i] - yb[i];
+        double m2 = orc_primal_mnorm2(P, var, sigma, lamA, lamQ, dx, dv, dy, dt);
+        R = sqrt(m2 > 0.0 ? m2 : 0.0);
+      }
+      /* Steps 4-5: u <- 1/(t+2) u^{r,0} + (t+1)/(t+2) (2 ubar - u) */
+      const double rho = 1.0 / (double)(it + 2);
+      for (int j = 0; j < n; ++j) {
+        x[j] = rho * xa[j] + (1.0 - rho) * (2.0 * xb[j] - x[j]);
+        if (var == 2) {
+          v[j] = rho * va[j] + (1.0 - rho) * (2.0 * vb[j] - v[j]);
+          t[j] = rho * ta[j] + (1.0 - rho) * (2.0 * tb[j] - t[j]);
+        }
+      }
+      for (int i = 0; i < m; ++i) y[i] = rho * ya[i] + (1.0 - rho) * (2.0 * yb[i] - y[i]);
+      it += 1; k += 1;
+      if (it == 1) Rr0 = R;
+      double sigma_used = sigma;
+      if (is_check) {
+        double res[5];
+        if (D) {
+          for (int i = 0; i < m; ++i) dy[i] = E[i] * yb[i];
+          for (int j = 0; j < n; ++j) { dv[j] = zb[j] / D[j]; dx[j] = D[j] * xb[j]; }
+          orc_residuals(P0, dy, dv, dx, res);
+        } else {
+          orc_residuals(P, yb, zb, xb, res);
+        }
+        info->eta_p = res[0]; info->eta_d = res[1]; info->eta_gap = res[2];
+        info->pobj = res[3]; info->dobj = res[4];
+        double kkt = res[0];
+        if (res[1] > kkt) kkt = res[1];
+        if (res[2] > kkt) kkt = res[2];
+        int do_restart = 0;
+        if (!(kkt == kkt) || !(R == R)) term = ORC_NUMERICAL;
+        else if (kkt <= opt->tol) term = ORC_SOLVED;
+        else if (k >= opt->max_iter) term = ORC_MAX_ITER;
+        else if (opt->time_limit_s > 0.0 && now_s() - t_start >= opt->time_limit_s) term = ORC_TIME_LIMIT;
+        else if (opt->enable_restart) {
+          int c1 = R <= opt->alpha1 * Rr0;
+          int c2 = (Rprev >= 0.0) && (R <= opt->alpha2 * Rr0) && (R > Rprev);
+          int c3 = (double)it >= alpha3 * (double)k;
+          do_restart = c1 || c2 || c3;
+        }
+        Rprev = R;
+        if (term < 0 && do_restart) {
+          if (R0ref < 0.0) R0ref = R;
+          double ratio = R / R0ref;
+          if (opt->enable_sigma_update && !(var == 1 && m == 0)) {
+            double nx = 0.0, ny = 0.0, nt = 0.0;
+            for (int j = 0; j < n; ++j) {
+              nx += (xb[j] - xa[j]) * (xb[j] - xa[j]);
+              if (var == 2) nt += (tb[j] - ta[j]) * (tb[j] - ta[j]);
+            }
+            for (int i = 0; i < m; ++i) ny += (yb[i] - ya[i]) * (yb[i] - ya[i]);
+            double th1 = (var == 1 ? lamA : 1.0 + lamA) * nx, th2 = ny + nt;
+            if (th1 < 1e-12) th1 = 1e-12;
+            if (th2 < 1e-12) th2 = 1e-12;
+            double snew = sqrt(th2 / th1);
+            double beta = exp(-ratio);
+            sigma = exp(beta * log(snew) + (1.0 - beta) * log(sigma));
+          }
+          if (ratio <= 0.1) alpha3 = 0.2;
+          memcpy(x, xb, sizeof(double) * n); memcpy(y, yb, sizeof(double) * m);
+          if (var == 2) { memcpy(v, vb, sizeof(double) * n); memcpy(t, tb, sizeof(double) * n); }
+          r += 1;
+          restarted = 1;
+        }
+        if (opt->check_log && info->n_log < opt->log_cap) {
+          double *row = opt->check_log + 10 * (size_t)info->n_log;
+          row[0] = (double)k; row[1] = (double)it; row[2] = R; row[3] = res[0]; row[4] = res[1];
+          row[5] = res[2]; row[6] = sigma_used; row[7] = (double)restarted; row[8] = sigma; row[9] = (double)r;
+          info->n_log += 1;
+        }
+      }
+      if (opt->trace && k <= opt->trace_iters) {
+        /* [y, v, x, ybar, vbar, xbar]; variant 1 has no v: x stands in its place */
+        double *row = opt->trace + (size_t)(k - 1) * rowlen;
+        memcpy(row, y, sizeof(double) * m); row += m;
+        memcpy(row, var == 2 ? v : x, sizeof(double) * n); row += n;
+        memcpy(row, x, sizeof(double) * n); row += n;
+        memcpy(row, yb, sizeof(double) * m); row += m;
+        memcpy(row, var == 2 ? vb : xb, sizeof(double) * n); row += n;
+        memcpy(row, xb, sizeof(double) * n);
+      }
+    }
+  }
+  memcpy(y_out, yb, sizeof(double) * m);
+  memcpy(z_out, zb, sizeof(double) * n);
+  memcpy(w_out, var == 2 ? vb : xb, sizeof(double) * n);
+  memcpy(x_out, xb, sizeof(double) * n);
+  info->term = term; info->iters = k; info->restarts = r; info->sigma = sigma; info->R_last = R;
+  info->t_solve_s = now_s() - t_start;
+  free(x); free(v); free(y); free(t); free(xa); free(va); free(ya); free(ta);
+  free(xb); free(vb); free(yb); free(tb); free(sb); free(zb); free(dx); free(dv); free(dy); free(dt);
+  return 0;
+}
+
+static int solve_method(const orc_problem *P, const orc_problem *P0, const double *D, const double *E,
+                        const orc_options *opt, const double *y0, const double *w0, const double *x0,
+                        double *y_out, double *z_out, double *w_out, double *x_out, orc_info *info) {
+  if (opt->method == 1 || opt->method == 2)
+    return solve_primal(P, P0, D, E, opt, y0, w0, x0, y_out, z_out, w_out, x_out, info);
+  return solve_core(P, P0, D, E, opt, y0, w0, x0, y_out, z_out, w_out, x_out, info);
+}
+
 int orc_solve(const orc_problem *P, const orc_options *opt,
               const double *y0, const double *w0, const double *x0,
               double *y_out, double *z_out, double *w_out, double *x_out, orc_info *info) {
   if (!opt->precondition || (P->qkind != ORC_Q_CSR && P->qkind != ORC_Q_ZERO) || P->l1_weight != 0.0)
-    return solve_core(P, NULL, NULL, NULL, opt, y0, w0, x0, y_out, z_out, w_out, x_out, info);
+    return solve_method(P, NULL, NULL, NULL, opt, y0, w0, x0, y_out, z_out, w_out, x_out, info);
   /* Section 4.1: solve the scaled problem, stop on the given one */
   const int n = P->n, m = P->m;
   const int nq = (P->qkind == ORC_Q_CSR) ? P->q_rowptr[n] : 0;
@@ -579,7 +824,7 @@ int orc_solve(const orc_problem *P, const orc_options *opt,
   if (y0) { ys = vnew(m); for (int i = 0; i < m; ++i) ys[i] = y0[i] / E[i]; }
   if (w0) { ws = vnew(n); for (int j = 0; j < n; ++j) ws[j] = w0[j] / D[j]; }
   if (x0) { xs = vnew(n); for (int j = 0; j < n; ++j) xs[j] = x0[j] / D[j]; }
-  int rc = solve_core(&S, P, D, E, opt, ys, ws, xs, y_out, z_out, w_out, x_out, info);
+  int rc = solve_method(&S, P, D, E, opt, ys, ws, xs, y_out, z_out, w_out, x_out, info);
   for (int i = 0; i < m; ++i) y_out[i] *= E[i];
   for (int j = 0; j < n; ++j) { z_out[j] /= D[j]; w_out[j] *= D[j]; x_out[j] *= D[j]; }
   free(D); free(E); free(qv); free(av); free(c); free(L); free(U); free(l); free(u);

@@ -16,7 +16,10 @@
  *     Algorithm 5 (SigmaUpdate, Section 3.3);
  *   - the merit R~ = ||u - ubar||_M with M the metric of Section 2.3
  *     ("eq:metric-M");
- *   - the stopping quantities eta_p, eta_d, eta_gap of Section 4.1.
+ *   - the stopping quantities eta_p, eta_d, eta_gap of Section 4.1;
+ *   - HPR applied to the primal reformulations "QP-primal-s" and
+ *     "QP-primal-sv" (Algorithms 6 and 7 of Appendix A), the baselines of
+ *     Table 1, with the restart rule carried over from HPR-QP.
  * Every product A x, A^T y, Q x is recomputed directly from the data each
  * time it is needed (no cached linear combinations).
  */
@@ -65,6 +68,9 @@ typedef struct {
                              solve the diagonally scaled problem, stop on the
                              residuals of the given one                               */
   int ruiz_iters;         /* Ruiz passes of the scaling (Section 4.1: 10)             */
+  int method;             /* 0: HPR-QP (Algorithm 4); 1, 2: HPR on the primal
+                             reformulation "QP-primal-s" (Algorithm 6) or
+                             "QP-primal-sv" (Algorithm 7) of Appendix A             */
 } orc_options;
 
 typedef struct {
@@ -117,7 +123,21 @@ double orc_prox(const orc_problem *P, int j, double sigma, double r);
 void orc_residuals(const orc_problem *P, const double *y, const double *z,
                    const double *x, double *out);
 
-/* Algorithm 4.  y0/w0/x0 may be NULL (origin).  Outputs ubar = (y, z, w, x). */
+/* One pass of Steps 1-3 of Algorithm 6 (variant 1) or 7 (variant 2) from the
+ * state (x, v, y, t) (v, t, vb, tb: variant 2 only, else unused).  Writes
+ * sbar, ybar (m), vbar, tbar, xbar and zbar (n), zbar the multiplier of the
+ * x-step (-zbar in the subdifferential of phi at xbar).                    */
+void orc_primal_step(const orc_problem *P, int variant, double sigma, double lamA, double lamQ,
+                     const double *x, const double *v, const double *y, const double *t,
+                     double *sb, double *yb, double *vb, double *tb, double *xb, double *zb);
+/* ||(dx, dv, dy, dt)||_M^2 for the metric of Algorithm 6/7 (dv, dt: variant 2). */
+double orc_primal_mnorm2(const orc_problem *P, int variant, double sigma, double lamA, double lamQ,
+                         const double *dx, const double *dv, const double *dy, const double *dt);
+
+/* Algorithm 4 (method 0), or Algorithm 6/7 (method 1/2: w0 is the start of
+ * v for method 2 and unused for method 1; the output w is xbar for method 1
+ * and vbar for method 2).  y0/w0/x0 may be NULL (origin).  Outputs ubar =
+ * (y, z, w, x). */
 int orc_solve(const orc_problem *P, const orc_options *opt,
               const double *y0, const double *w0, const double *x0,
               double *y, double *z, double *w, double *x, orc_info *info);

@@ -43,7 +43,7 @@ class _Options(C.Structure):
                 ("enable_restart", C.c_int), ("enable_sigma_update", C.c_int),
                 ("trace_iters", C.c_int), ("trace", _dp),
                 ("log_cap", C.c_int), ("check_log", _dp),
-                ("precondition", C.c_int), ("ruiz_iters", C.c_int)]
+                ("precondition", C.c_int), ("ruiz_iters", C.c_int), ("method", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -87,6 +87,11 @@ def _L():
         _lib.orc_sigma_argmin.argtypes = [C.c_double] * 4
         _lib.orc_sigma_argmin.restype = C.c_double
         _lib.orc_scaling.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int, _dp, _dp]
+        _lib.orc_primal_step.argtypes = [C.POINTER(_Problem), C.c_int, C.c_double, C.c_double, C.c_double,
+                                         _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        _lib.orc_primal_mnorm2.argtypes = [C.POINTER(_Problem), C.c_int, C.c_double, C.c_double, C.c_double,
+                                           _dp, _dp, _dp, _dp]
+        _lib.orc_primal_mnorm2.restype = C.c_double
     return _lib
 
 
@@ -163,7 +168,11 @@ class OracleResult:
 def solve(qp, tol=1e-8, max_iter=100_000, check_every=100, time_limit_s=0.0, sigma0=0.0,
           lambda_A=0.0, lambda_Q=0.0, alpha=(0.2, 0.8, 0.5), enable_restart=True,
           enable_sigma_update=True, trace_iters=0, log_cap=0, y0=None, w0=None, x0=None,
-          power_start_A=None, power_start_Q=None, precondition=False, ruiz_iters=10) -> OracleResult:
+          power_start_A=None, power_start_Q=None, precondition=False, ruiz_iters=10,
+          method=0) -> OracleResult:
+    """Algorithm 4 (method 0) or HPR on the primal reformulation of Algorithm 6
+    (method 1) / Algorithm 7 (method 2); for methods 1/2, w0 starts v (method 2)
+    and the returned w is xbar (method 1) or vbar (method 2)."""
     L = _L()
     M = _Marshal(qp)
     O = _Options()
@@ -174,7 +183,7 @@ def solve(qp, tol=1e-8, max_iter=100_000, check_every=100, time_limit_s=0.0, sig
     O.power_start_A, O.power_start_Q = _d(psA), _d(psQ)
     O.alpha1, O.alpha2, O.alpha3 = alpha
     O.enable_restart, O.enable_sigma_update = int(enable_restart), int(enable_sigma_update)
-    O.precondition, O.ruiz_iters = int(precondition), int(ruiz_iters)
+    O.precondition, O.ruiz_iters, O.method = int(precondition), int(ruiz_iters), int(method)
     trace = None
     if trace_iters > 0:
         trace = np.zeros((trace_iters, 2 * qp.m + 4 * qp.n))
@@ -283,3 +292,26 @@ def mnorm2(qp, sigma, lamA, lamQ, dy, dw, dx) -> float:
 
 def sigma_argmin(th1, th2, th3, lamQ) -> float:
     return _L().orc_sigma_argmin(th1, th2, th3, lamQ)
+
+
+def primal_step(qp, variant, sigma, lamA, lamQ, x, y, v=None, t=None) -> dict:
+    """Steps 1-3 of Algorithm 6 (variant 1) or 7 (variant 2) from (x, v, y, t)."""
+    M = _Marshal(qp)
+    n, m = qp.n, qp.m
+    f = lambda a, k: np.ascontiguousarray(np.zeros(max(k, 1)) if a is None else
+                                          (a if k else np.zeros(1)), dtype=np.float64)
+    xx, vv, yy, tt = f(x, n), f(v, n), f(y, m), f(t, n)
+    sb, yb = np.zeros(max(m, 1)), np.zeros(max(m, 1))
+    vb, tb, xb, zb = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    _L().orc_primal_step(C.byref(M.P), int(variant), sigma, lamA, lamQ, _d(xx), _d(vv), _d(yy), _d(tt),
+                         _d(sb), _d(yb), _d(vb), _d(tb), _d(xb), _d(zb))
+    return dict(s=sb[:m].copy(), y=yb[:m].copy(), v=vb, t=tb, x=xb, z=zb)
+
+
+def primal_mnorm2(qp, variant, sigma, lamA, lamQ, dx, dy, dv=None, dt=None) -> float:
+    M = _Marshal(qp)
+    n, m = qp.n, qp.m
+    f = lambda a, k: np.ascontiguousarray(np.zeros(max(k, 1)) if a is None else
+                                          (a if k else np.zeros(1)), dtype=np.float64)
+    a = [f(dx, n), f(dv, n), f(dy, m), f(dt, n)]
+    return _L().orc_primal_mnorm2(C.byref(M.P), int(variant), sigma, lamA, lamQ, *[_d(v) for v in a])

@@ -42,6 +42,45 @@ MUTANTS = {
                       "if (p == 0) { if (a > ny[i]) ny[i] = a; }"),
 }
 
+# mistakes in HPR on the primal reformulations (Appendix A), caught by its own pin file
+PRIMAL_MUTANTS = {
+    "p1_tau_without_lamQ": ("const double tau = lamQ + sigma * lamA;", "const double tau = sigma * lamA;"),
+    "p_no_extrapolation": ("e[i] = 2.0 * yb[i] - y[i];", "e[i] = yb[i];"),
+    "p_s_shift_sign": ("const double r = Ax[i] - y[i] / sigma;", "const double r = Ax[i] + y[i] / sigma;"),
+    "p2_v_prox_term": ("(sigma * x[j] - t[j] + lamQ * v[j] - Qin[j]) / (lamQ + sigma)",
+                       "(sigma * x[j] - t[j] - Qin[j]) / (lamQ + sigma)"),
+    "p2_t_sign": ("tb[j] = t[j] + sigma * (vb[j] - x[j]);", "tb[j] = t[j] - sigma * (vb[j] - x[j]);"),
+    "p2_kappa": ("const double kap = sigma * (1.0 + lamA);", "const double kap = sigma * lamA;"),
+    "p_metric_cross": ("double r = -2.0 * dot(Adx, dy, m) + dot(dy, dy, m) / sigma;",
+                       "double r = 2.0 * dot(Adx, dy, m) + dot(dy, dy, m) / sigma;"),
+    "p2_metric_dt_cross": ("- 2.0 * dot(dx, dt, n) + dot(dt, dt, n) / sigma", "+ dot(dt, dt, n) / sigma"),
+    "p2_halpern_v": ("v[j] = rho * va[j] + (1.0 - rho) * (2.0 * vb[j] - v[j]);",
+                     "v[j] = rho * va[j] + (1.0 - rho) * vb[j];"),
+    "p_sigma_inverted": ("double snew = sqrt(th2 / th1);", "double snew = sqrt(th1 / th2);"),
+    "p_zbar_sign": ("      zb[j] = tau * (xb[j] - r);", "      zb[j] = tau * (r - xb[j]);"),
+}
+
+
+def _run_mutant(old, new, pin_file, tmp_path, name):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique/found"
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=199309L", "-fPIC", "-shared",
+                           "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(msrc), "-lm"])
+    env = dict(os.environ, HPRQP_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", pin_file)],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pin suite"
+
+
+@pytest.mark.parametrize("name", sorted(PRIMAL_MUTANTS))
+def test_primal_pins_catch_mutant(name, tmp_path):
+    old, new = PRIMAL_MUTANTS[name]
+    _run_mutant(old, new, "test_oracle_primal.py", tmp_path, name)
+
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(name, tmp_path):

@@ -123,6 +123,21 @@ typedef struct {
                                  kernel gathering from an LDS copy of the input vector
                                  (matrices with at most 16384 columns, else 0); 1, 2, 4,
                                  ..., 256: that many lanes per row, for every matrix; -1  */
+  int32_t method;             /* 0: HPR-QP (Algorithm 4 on the restricted Wolfe dual).
+                                 1, 2: HPR applied to the primal reformulations of
+                                 Appendix A, the baselines of Table 1: 1 = Algorithm 6 on
+                                 "QP-primal-s" (A x = s; state x, y), 2 = Algorithm 7 on
+                                 "QP-primal-sv" (A x = s, x = v; state x, v, y, t).  Same
+                                 stopping test, check cadence and restart criteria; the
+                                 merit R~ uses the metric of the reformulation, sigma is
+                                 updated to the minimiser of the sigma-dependent part of
+                                 ||ubar - u^{r,0}||_M^2 (smoothed as in Algorithm 5), and
+                                 sigma0 = ||c||/||b|| (the reciprocal rule; an explicit
+                                 sigma0 is used as given).  w0 starts v (method 2; unused
+                                 by 1); t starts at 0.  Outputs: ybar, zbar (the x-step's
+                                 multiplier), w = xbar (1) or vbar (2), xbar.  Trace rows
+                                 hold [y, v, x, ybar, vbar, xbar] (method 1: x in the v
+                                 places).  Per-solve option; 0                               */
 } hprqp_options;
 
 typedef struct {
@@ -149,7 +164,7 @@ void hprqp_default_options(hprqp_options *opt);
  * an explicit CSR on the device (rows of A^T ordered by row of A, so every
  * product is deterministic), runs the power method when lambda_A/lambda_Q
  * are not given (Section 4.1), computes sigma0 and allocates the workspace
- * (about 30 n + 12 m doubles plus A^T).  The problem arrays are borrowed.
+ * (about 34 n + 15 m doubles plus A^T).  The problem arrays are borrowed.
  * Returns HPRQP_ERR_BOUNDS / HPRQP_ERR_SHAPE on invalid data. */
 hprqp_status hprqp_create(const hprqp_problem *prob, const hprqp_options *opt,
                           hipStream_t stream, hprqp_handle **out);
@@ -157,7 +172,9 @@ hprqp_status hprqp_create(const hprqp_problem *prob, const hprqp_options *opt,
 /* Runs Algorithm 4 from (y0, w0, x0) (each may be NULL: origin, Section 4.1)
  * and writes the last bar iterate ubar = (ybar, zbar, wbar, xbar), the output
  * of Algorithm 4: y (m), z (n), w (n; the unprojected shadow w_Q of
- * Proposition 2.4), x (n).  info may be NULL. */
+ * Proposition 2.4), x (n).  With options.method = 1 or 2 it runs Algorithm 6
+ * or 7 instead (see hprqp_options.method for the meaning of w0 and w).
+ * info may be NULL. */
 hprqp_status hprqp_solve(hprqp_handle *h, const double *y0, const double *w0, const double *x0,
                          double *y, double *z, double *w, double *x, hprqp_info *info);
 
@@ -189,7 +206,8 @@ hprqp_status hprqp_scaling(hprqp_handle *h, double *D, double *E);
 /* Kernel timing of the last hprqp_solve made with profile_kernels = 1:
  * avg_ms_host[i] = mean duration (ms) and launches_host[i] = number of timed
  * launches of product i, i = 0: Q xhat (with its epilogue), 1: A v, 2: A^T ybar,
- * 3: Q A^T(ybar - y) with the Halpern epilogue.  Also reports the
+ * 3: Q A^T(ybar - y) with the Halpern epilogue (methods 1, 2: 0 = Q x or Q v,
+ * 1 = A x, 2 = A^T(2 ybar - y), 3 unused).  Also reports the
  * lanes-per-row choice of A, A^T and Q (g_host[3], may be NULL). */
 hprqp_status hprqp_kernel_stats(hprqp_handle *h, double *avg_ms_host, int64_t *launches_host, int32_t *g_host);
 

@@ -13,6 +13,7 @@
 #include "hprqp.h"
 #include "common.hpp"
 #include "epilogues.hpp"
+#include "epilogues_primal.hpp"
 #include "qops.hpp"
 #include "spmv.hpp"
 #include "precond.hpp"
@@ -249,6 +250,7 @@ struct hprqp_handle {
   int* at_perm = nullptr;
   hprqp_options opt{};
   double lamA = 0, lamQ = 0, sigma0 = 1, binf = 0, cinf = 0;
+  double sigma0_primal = 1;  // sigma0 of HPR on the primal reformulations (methods 1, 2)
   double powA_est = 0, powQ_est = 0;
   int powA_it = 0, powQ_it = 0;
   double t_setup = 0, t_precond = 0;
@@ -261,6 +263,10 @@ struct hprqp_handle {
          *Qwa = nullptr, *xh = nullptr, *v = nullptr, *q1 = nullptr, *d = nullptr, *g = nullptr, *e = nullptr,
          *XB = nullptr, *ZB = nullptr, *wbar = nullptr, *qwbar = nullptr, *xbo = nullptr, *zbo = nullptr,
          *t1 = nullptr, *t2 = nullptr, *kronT = nullptr;
+  // HPR on the primal reformulations: e = 2 ybar - y, A x and dy at merit
+  // iterations (m each); t, its anchor and bar, dt (n each)
+  double *pe = nullptr, *pax = nullptr, *pdy = nullptr, *pt = nullptr, *pta = nullptr, *ptb = nullptr,
+         *pdt = nullptr;
   double *partials = nullptr, *scalars = nullptr, *hist = nullptr;
   int* counts = nullptr;
   int* dflags = nullptr;
@@ -271,6 +277,9 @@ struct hprqp_handle {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   int graph_T = 0;
+  hipGraphExec_t pgexec = nullptr;   // segment graph of the primal methods
+  hipGraph_t pgraph = nullptr;
+  int pgraph_T = 0, pgraph_method = 0;
   // kernel timing (profile_kernels): events around the four products of the
   // plain iterations 1..HQ_PROF_ITERS of a timed segment, accumulated over the
   // solve (the first and the check iteration carry extra reductions)
@@ -289,6 +298,8 @@ struct hprqp_handle {
   ~hprqp_handle() {
     if (gexec) hipGraphExecDestroy(gexec);
     if (graph) hipGraphDestroy(graph);
+    if (pgexec) hipGraphExecDestroy(pgexec);
+    if (pgraph) hipGraphDestroy(pgraph);
     for (void* p : owned) hipFree(p);
     if (hs) hipHostFree(hs);
     if (hp) hipHostFree(hp);
@@ -653,6 +664,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
   if (P->m > 0 && (!P->a_rowptr || !P->l || !P->u || (P->a_nnz > 0 && (!P->a_col || !P->a_val))))
     fail(HPRQP_ERR_ARG, "A, l, u are required when m > 0");
   if (opt->check_every <= 0 || opt->max_iter <= 0 || !(opt->tol >= 0.0)) fail(HPRQP_ERR_ARG, "bad options");
+  if (opt->method < 0 || opt->method > 2) fail(HPRQP_ERR_ARG, "method must be 0, 1 or 2");
   if (P->a_nnz < 0 || P->a_nnz >= (1ll << 31) || P->q_nnz < 0 || P->q_nnz >= (1ll << 31))
     fail(HPRQP_ERR_SHAPE, "nnz must fit int32");
   auto hp = new hprqp_handle();
@@ -713,10 +725,11 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
     k_zero_ints<<<1, 64, 0, st>>>(SL_TOTAL, h.counts);
     k_zero_ints<<<1, 64, 0, st>>>(1, h.dflags);
     double** nv[] = {&h.w, &h.wa, &h.x, &h.xa, &h.ATy, &h.ATya, &h.Qw, &h.Qwa, &h.xh, &h.v, &h.q1, &h.d, &h.g,
-                     &h.e, &h.XB, &h.ZB, &h.wbar, &h.qwbar, &h.xbo, &h.zbo, &h.t1, &h.t2};
+                     &h.e, &h.XB, &h.ZB, &h.wbar, &h.qwbar, &h.xbo, &h.zbo, &h.t1, &h.t2,
+                     &h.pt, &h.pta, &h.ptb, &h.pdt};
     for (double** p : nv) *p = h.dalloc<double>(n);
     if (h.qkind == HPRQP_Q_KRON) h.kronT = h.dalloc<double>(n);
-    double** mv[] = {&h.y, &h.ya, &h.ybar, &h.tm};
+    double** mv[] = {&h.y, &h.ya, &h.ybar, &h.tm, &h.pe, &h.pax, &h.pdy};
     for (double** p : mv) *p = h.dalloc<double>(std::max(m, 1));
     for (double** p : nv) k_fill<<<hq_grid(n, 256), 256, 0, st>>>(n, *p, 0.0);
     for (double** p : mv) k_fill<<<hq_grid(std::max(m, 1), 256), 256, 0, st>>>(std::max(m, 1), *p, 0.0);
@@ -868,9 +881,12 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       h.binf = m > 0 ? h.hs[1] : 0.0;
       h.cinf = h.hs[3];
     }
+    const bool norms_ok = nb >= 1e-16 && nb <= 1e16 && nc >= 1e-16 && nc <= 1e16;
     if (opt->sigma0 > 0) h.sigma0 = opt->sigma0;
-    else if (nb >= 1e-16 && nb <= 1e16 && nc >= 1e-16 && nc <= 1e16) h.sigma0 = nb / nc;
-    else h.sigma0 = 1.0;
+    else h.sigma0 = norms_ok ? nb / nc : 1.0;
+    // the primal methods' sigma multiplies the primal residual: the reciprocal rule
+    if (opt->sigma0 > 0) h.sigma0_primal = opt->sigma0;
+    else h.sigma0_primal = norms_ok ? nc / nb : 1.0;
     HQC(hipStreamSynchronize(st));
     h.t_setup = now_s() - t0;
     *out = hp;
@@ -1034,6 +1050,254 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
   }
 }
 
+// ---------------------------------------------------------------------------
+// HPR on the primal reformulations (Appendix A: Algorithm 6, method 1;
+// Algorithm 7, method 2), the baselines of Table 1.  Same check segments,
+// graphs, stopping test and restart criteria as HPR-QP; the merit uses the
+// metric of the reformulation and needs two extra products (A xbar and
+// Q xbar / Q vbar) at the first iteration of a segment and at its check.
+// ---------------------------------------------------------------------------
+void enqueue_primal_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
+  const int meth = h.opt.method;
+  const bool check = (j == Tseg - 1);
+  const int rgroup = check ? SL_RC : (j == 0 ? SL_RF : -1);
+  const bool want_r = rgroup >= 0;
+  const bool store_bar = want_r || check || trace;
+  int ps = -1;
+  if (prof && !trace && j >= 1 && j <= HQ_PROF_ITERS && j < Tseg - 1) ps = j - 1;
+  auto mark = [&](int kind, int edge) {
+    if (ps >= 0) HQC(hipEventRecord(h.pev[ps][kind][edge], h.st));
+  };
+  auto slots = [&](std::initializer_list<int> s) {
+    RedOut r = no_red(h);
+    int k = 0;
+    for (int v : s) r.slot[k++] = (int8_t)v;
+    r.active = 0;
+    for (int q = 0; q < k; ++q) r.active |= r.slot[q] >= 0;
+    return r;
+  };
+  auto at = [&](int off) { return want_r ? rgroup + off : -1; };
+  // Q x (Algorithm 6) or Q v with the v/t-step (Algorithm 7)
+  mark(0, 0);
+  if (meth == 1) {
+    q_apply(h, h.x, EpiStore{h.q1}, j, no_red(h));
+  } else {
+    EpiP2V ev{h.w, h.x, h.pta, h.pt, h.wbar, h.v, h.Qw, h.e, h.pdt, h.ptb, want_r, check};
+    q_apply(h, h.w, ev, j, slots({at(1), at(4), check ? SL_TH + 2 : -1}));
+  }
+  mark(0, 1);
+  // A x with the s/y-step
+  if (h.m > 0) {
+    mark(1, 0);
+    EpiPY ey{h.l, h.u, h.ya, h.y, h.ybar, h.pe, h.pax, h.pdy, want_r, check, store_bar};
+    launch_csr(h, h.A, h.x, ey, j, slots({at(3), check ? SL_TH + 1 : -1}));
+    mark(1, 1);
+  }
+  // A^T (2 ybar - y) with the x-step
+  mark(2, 0);
+  if (meth == 1) {
+    EpiP1X ex{h.q1, h.c, h.L, h.U, h.xa, h.x, h.XB, h.ZB, h.d, want_r, check, store_bar, h.l1};
+    RedOut rx = slots({at(0), check ? SL_TH : -1});
+    if (h.m > 0) launch_csr(h, h.AT, h.pe, ex, j, rx);
+    else launch_elem(h, h.n, nullptr, ex, j, rx);
+  } else {
+    EpiP2X ex{h.v, h.c, h.L, h.U, h.xa, h.wa, h.wbar, h.pdt, h.x, h.w, h.XB, h.ZB, h.d, want_r, check, store_bar,
+              h.l1};
+    RedOut rx = slots({at(0), at(5), check ? SL_TH : -1});
+    if (h.m > 0) launch_csr(h, h.AT, h.pe, ex, j, rx);
+    else launch_elem(h, h.n, nullptr, ex, j, rx);
+  }
+  mark(2, 1);
+  if (want_r) {
+    // <A dx, dy> and <dx, Q dx> (Algorithm 6) or <dv, Q dv> (Algorithm 7)
+    if (h.m > 0) launch_csr(h, h.A, h.XB, EpiMeritA{h.pax, h.pdy}, j, slots({rgroup + 2}));
+    if (meth == 1) q_apply(h, h.XB, EpiMeritQ{h.q1, h.d}, j, slots({rgroup + 1}));
+    else q_apply(h, h.wbar, EpiMeritQ{h.Qw, h.e}, j, slots({rgroup + 6}));
+  }
+  if (check) {
+    // stopping quantities at (ybar, zbar, xbar): A^T ybar, A xbar, Q xbar
+    if (h.m > 0) {
+      launch_csr(h, h.AT, h.ybar, EpiStore{h.g}, j, no_red(h));
+      launch_csr(h, h.A, h.XB, EpiResA{h.l, h.u, h.ybar, h.iEs}, j, red_seq(h, SL_RA, 4));
+    }
+    q_apply(h, h.XB, EpiResQ{h.XB, h.ZB, h.m > 0 ? h.g : nullptr, h.c, h.L, h.U, h.xbo, h.zbo, h.iDs, h.l1}, j,
+            red_seq(h, SL_RQ, 7));
+  }
+}
+
+void enqueue_primal_segment(hprqp_handle& h, int Tseg, bool prof) {
+  for (int j = 0; j < Tseg; ++j) enqueue_primal_iter(h, j, Tseg, false, prof);
+  final_reduce(h, 0, SL_ITER_END);
+  HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
+}
+
+// ||du||_M from the merit slots, metric of Algorithm 6 / 7
+double primal_mnorm(const hprqp_handle& h, const double* S, double sigma) {
+  double m2;
+  if (h.opt.method == 1)
+    m2 = (h.lamQ + sigma * h.lamA) * S[0] - S[1] - 2.0 * S[2] + S[3] / sigma;
+  else
+    m2 = sigma * (1.0 + h.lamA) * S[0] - 2.0 * S[2] - 2.0 * S[5] + (S[3] + S[4]) / sigma + h.lamQ * S[1] - S[6];
+  return std::sqrt(m2 > 0.0 ? m2 : 0.0);
+}
+
+// trace row [y, v, x, ybar, vbar, xbar] (Algorithm 6 has no v: x stands in)
+void primal_trace_row(hprqp_handle& h, double* row) {
+  const int n = h.n, m = h.m;
+  const bool two = h.opt.method == 2;
+  HQC(hipStreamSynchronize(h.st));
+  HQC(hipMemcpy(row, h.y, m * sizeof(double), hipMemcpyDeviceToHost)); row += m;
+  HQC(hipMemcpy(row, two ? h.w : h.x, n * sizeof(double), hipMemcpyDeviceToHost)); row += n;
+  HQC(hipMemcpy(row, h.x, n * sizeof(double), hipMemcpyDeviceToHost)); row += n;
+  HQC(hipMemcpy(row, h.ybar, m * sizeof(double), hipMemcpyDeviceToHost)); row += m;
+  HQC(hipMemcpy(row, two ? h.wbar : h.XB, n * sizeof(double), hipMemcpyDeviceToHost)); row += n;
+  HQC(hipMemcpy(row, h.XB, n * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+// anchor <- state
+void primal_reset_epoch(hprqp_handle& h) {
+  const long long n = h.n, m = h.m;
+  if (m > 0) k_copy<<<hq_grid(m, 256), 256, 0, h.st>>>(m, h.y, h.ya, nullptr);
+  k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.x, h.xa, nullptr);
+  if (h.opt.method == 2) {
+    k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.w, h.wa, nullptr);
+    k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.pt, h.pta, nullptr);
+  }
+}
+
+void solve_primal_impl(hprqp_handle& h, const double* y0, const double* w0, const double* x0, double* yo,
+                       double* zo, double* wo, double* xo, hprqp_info* info) {
+  const double tstart = now_s();
+  if (h.own_st) HQC(hipDeviceSynchronize());
+  for (int kind = 0; kind < 4; ++kind) { h.prof_ms[kind] = 0.0; h.prof_n[kind] = 0; }
+  const hprqp_options& o = h.opt;
+  const int n = h.n, m = h.m, meth = o.method;
+  const int T = o.check_every;
+  const bool tracing = o.trace_iters > 0 && o.trace_host;
+  if (!yo && m > 0) fail(HPRQP_ERR_ARG, "output y required");
+  if (!zo || !wo || !xo) fail(HPRQP_ERR_ARG, "outputs z, w, x required");
+  // state (x, v, y, t) from (x0, w0, y0, 0), scaled when preconditioned
+  if (m > 0) copy_or_zero(h, m, y0, h.y, h.pre ? h.iEs : nullptr);
+  copy_or_zero(h, n, x0, h.x, h.pre ? h.iDs : nullptr);
+  copy_or_zero(h, n, meth == 2 ? w0 : nullptr, h.w, h.pre ? h.iDs : nullptr);
+  copy_or_zero(h, n, nullptr, h.pt);
+  double sigma = h.sigma0_primal;
+  primal_reset_epoch(h);
+  long long k = 0, t = 0;
+  int r = 0, term = -1, nlog = 0;
+  double alpha3 = o.alpha3, R0ref = -1.0, Rr0 = -1.0, Rprev = -1.0, R = 0.0;
+  Resid res{};
+  const int rowlen = 2 * m + 4 * n;
+  long long seg = 0;
+  while (term < 0) {
+    const int Tseg = (int)std::min<long long>(T, o.max_iter - k);
+    const bool prof = o.profile_kernels && Tseg >= 4 && (seg++ % 4) == 1 && !(tracing && k < o.trace_iters);
+    write_params(h, sigma, t);
+    if (tracing && k < o.trace_iters) {
+      for (int j = 0; j < Tseg; ++j) {
+        enqueue_primal_iter(h, j, Tseg, true, false);
+        if (j < Tseg - 1 && k + j + 1 <= o.trace_iters) primal_trace_row(h, o.trace_host + (size_t)(k + j) * rowlen);
+      }
+      final_reduce(h, 0, SL_ITER_END);
+      HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
+    } else if (o.use_graph && Tseg == T && !prof) {
+      if (!h.pgexec || h.pgraph_T != T || h.pgraph_method != meth) {
+        if (h.pgexec) { hipGraphExecDestroy(h.pgexec); h.pgexec = nullptr; }
+        if (h.pgraph) { hipGraphDestroy(h.pgraph); h.pgraph = nullptr; }
+        HQC(hipStreamBeginCapture(h.st, hipStreamCaptureModeThreadLocal));
+        enqueue_primal_segment(h, T, false);
+        HQC(hipStreamEndCapture(h.st, &h.pgraph));
+        HQC(hipGraphInstantiate(&h.pgexec, h.pgraph, nullptr, nullptr, 0));
+        h.pgraph_T = T;
+        h.pgraph_method = meth;
+      }
+      HQC(hipGraphLaunch(h.pgexec, h.st));
+    } else {
+      enqueue_primal_segment(h, Tseg, prof);
+    }
+    HQC(hipStreamSynchronize(h.st));
+    if (prof) {
+      for (int ps = 0; ps < HQ_PROF_ITERS && ps + 1 < Tseg - 1; ++ps)
+        for (int kind = 0; kind < 3; ++kind) {
+          if (m == 0 && kind == 1) continue;
+          float ms = 0.f;
+          HQC(hipEventElapsedTime(&ms, h.pev[ps][kind][0], h.pev[ps][kind][1]));
+          h.prof_ms[kind] += ms;
+          h.prof_n[kind] += 1;
+        }
+    }
+    const double* S = h.hs;
+    if (t == 0) Rr0 = primal_mnorm(h, S + (Tseg == 1 ? SL_RC : SL_RF), sigma);
+    R = primal_mnorm(h, S + SL_RC, sigma);
+    res = residuals_from(h, S);
+    const double nDx = S[SL_TH], nDy = m > 0 ? S[SL_TH + 1] : 0.0, nDt = meth == 2 ? S[SL_TH + 2] : 0.0;
+    k += Tseg;
+    t += Tseg;
+    const long long t_check = t;
+    const double kkt = std::max(res.eta_p, std::max(res.eta_d, res.eta_gap));
+    const double sigma_used = sigma;
+    int restarted = 0;
+    bool do_restart = false;
+    if (std::isnan(kkt) || std::isnan(R)) term = HPRQP_NUMERICAL;
+    else if (kkt <= o.tol) term = HPRQP_SOLVED;
+    else if (k >= o.max_iter) term = HPRQP_MAX_ITER;
+    else if (o.time_limit_s > 0 && now_s() - tstart >= o.time_limit_s) term = HPRQP_TIME_LIMIT;
+    else if (o.enable_restart) {
+      const bool c1 = R <= o.alpha1 * Rr0;
+      const bool c2 = Rprev >= 0.0 && R <= o.alpha2 * Rr0 && R > Rprev;
+      const bool c3 = (double)t >= alpha3 * (double)k;
+      do_restart = c1 || c2 || c3;
+    }
+    Rprev = R;
+    if (term < 0 && do_restart) {
+      if (R0ref < 0.0) R0ref = R;
+      const double ratio = R / R0ref;
+      if (o.enable_sigma_update && !(meth == 1 && m == 0)) {
+        // minimiser of the sigma-dependent part of ||ubar - u_a||_M^2, smoothed as in Algorithm 5
+        const double th1 = std::max((meth == 1 ? h.lamA : 1.0 + h.lamA) * nDx, 1e-12);
+        const double th2 = std::max(nDy + nDt, 1e-12);
+        const double snew = std::sqrt(th2 / th1);
+        const double beta = std::exp(-ratio);
+        sigma = std::exp(beta * std::log(snew) + (1.0 - beta) * std::log(sigma));
+      }
+      if (ratio <= 0.1) alpha3 = 0.2;
+      // u^{r+1,0} = ubar
+      if (m > 0) k_copy<<<hq_grid(m, 256), 256, 0, h.st>>>(m, h.ybar, h.y, nullptr);
+      k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.XB, h.x, nullptr);
+      if (meth == 2) {
+        k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.wbar, h.w, nullptr);
+        k_copy<<<hq_grid(n, 256), 256, 0, h.st>>>(n, h.ptb, h.pt, nullptr);
+      }
+      primal_reset_epoch(h);
+      t = 0;
+      Rprev = -1.0;
+      r += 1;
+      restarted = 1;
+    }
+    if (tracing && k <= o.trace_iters) primal_trace_row(h, o.trace_host + (size_t)(k - 1) * rowlen);
+    if (o.check_log_host && nlog < o.log_cap) {
+      double* row = o.check_log_host + 10 * (size_t)nlog;
+      row[0] = (double)k; row[1] = (double)t_check;
+      row[2] = R; row[3] = res.eta_p; row[4] = res.eta_d; row[5] = res.eta_gap;
+      row[6] = sigma_used; row[7] = restarted; row[8] = sigma; row[9] = r;
+      ++nlog;
+    }
+  }
+  // output ubar of the last (check) iteration; w = xbar (Algorithm 6) or vbar (7)
+  if (m > 0) copy_or_zero(h, m, h.ybar, yo, h.pre ? h.Es : nullptr);
+  copy_or_zero(h, n, h.zbo, zo, h.pre ? h.iDs : nullptr);
+  copy_or_zero(h, n, meth == 2 ? h.wbar : h.xbo, wo, h.pre ? h.Ds : nullptr);
+  copy_or_zero(h, n, h.xbo, xo, h.pre ? h.Ds : nullptr);
+  HQC(hipStreamSynchronize(h.st));
+  if (info) {
+    info->term = term; info->iters = k; info->restarts = r; info->n_log = nlog;
+    info->sigma = sigma; info->sigma0 = h.sigma0_primal; info->lambda_A = h.lamA; info->lambda_Q = h.lamQ;
+    info->eta_p = res.eta_p; info->eta_d = res.eta_d; info->eta_gap = res.eta_gap;
+    info->pobj = res.pobj; info->dobj = res.dobj; info->R_last = R;
+    info->t_setup_s = h.t_setup; info->t_solve_s = now_s() - tstart; info->t_precond_s = h.t_precond;
+  }
+}
+
 void residuals_impl(hprqp_handle& h, const double* y, const double* z, const double* x, double* out) {
   if (!z || !x || (h.m > 0 && !y) || !out) fail(HPRQP_ERR_ARG, "NULL argument");
   write_params(h, h.sigma0, 0);
@@ -1116,7 +1380,9 @@ hprqp_status hprqp_create(const hprqp_problem* prob, const hprqp_options* opt, h
 
 hprqp_status hprqp_solve(hprqp_handle* h, const double* y0, const double* w0, const double* x0, double* y, double* z,
                          double* w, double* x, hprqp_info* info) {
-  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); hq::solve_impl(*h, y0, w0, x0, y, z, w, x, info));
+  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle");
+           if (h->opt.method == 0) hq::solve_impl(*h, y0, w0, x0, y, z, w, x, info);
+           else hq::solve_primal_impl(*h, y0, w0, x0, y, z, w, x, info));
 }
 
 hprqp_status hprqp_residuals(hprqp_handle* h, const double* y, const double* z, const double* x, double* out_host) {
@@ -1136,6 +1402,7 @@ hprqp_status hprqp_set_options(hprqp_handle* h, const hprqp_options* opt) {
   HQ_GUARD(
       if (!h || !opt) hq::fail(HPRQP_ERR_ARG, "NULL argument");
       if (opt->check_every <= 0 || opt->max_iter <= 0 || !(opt->tol >= 0.0)) hq::fail(HPRQP_ERR_ARG, "bad options");
+      if (opt->method < 0 || opt->method > 2) hq::fail(HPRQP_ERR_ARG, "method must be 0, 1 or 2");
       if (opt->profile_kernels && !h->pev[0][0][0])
         for (auto& a : h->pev)
           for (auto& b : a)
@@ -1148,6 +1415,9 @@ hprqp_status hprqp_set_options(hprqp_handle* h, const hprqp_options* opt) {
       if (h->gexec) { hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
       if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
       h->graph_T = 0;
+      if (h->pgexec) { hipGraphExecDestroy(h->pgexec); h->pgexec = nullptr; }
+      if (h->pgraph) { hipGraphDestroy(h->pgraph); h->pgraph = nullptr; }
+      h->pgraph_T = 0;
       h->opt = *opt;
       h->opt.lambda_A = la; h->opt.lambda_Q = lq; h->opt.sigma0 = s0;
       h->opt.power_start_A = pa; h->opt.power_start_Q = pq; h->opt.spmv_autotune = at;

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hprqp_oracle.c")
 
 MUTANTS = {
-    "halpern_sign": ("(2.0 * yb[i] - y[i])", "(2.0 * yb[i] + y[i])"),
+    "halpern_sign": ("const double rho = 1.0 / (double)(t + 2);\n      for (int i = 0; i < m; ++i) y[i] = rho * ya[i] + (1.0 - rho) * (2.0 * yb[i] - y[i]);",
+                     "const double rho = 1.0 / (double)(t + 2);\n      for (int i = 0; i < m; ++i) y[i] = rho * ya[i] + (1.0 - rho) * (2.0 * yb[i] + y[i]);"),
     "halpern_index": ("1.0 / (double)(t + 2)", "1.0 / (double)(t + 3)"),
     "w_half_coef": ("(sQ * w[j] + xh[j]) / (1.0 + sQ)", "(sQ * w[j] + xh[j]) / (1.0 + 2.0 * sQ)"),
     "ybar_sign": ("(clamp(ry[i], P->l[i], P->u[i]) - ry[i]) / (sigma * lamA)",
@@ -25,15 +26,16 @@ MUTANTS = {
     "theta1_cross": ("- 2.0 * dot(Qdw, ATdy, n);", "+ 2.0 * dot(Qdw, ATdy, n);"),
     "mnorm_sigma2": ("sigma * sigma * th[2] / (1.0 + sigma * lamQ)", "sigma * th[2] / (1.0 + sigma * lamQ)"),
     "dual_obj_sign": ("else sup += P->l[i] * y[i];", "else sup -= P->l[i] * y[i];"),
-    "beta_swap": ("exp(beta * log(snew) + (1.0 - beta) * log(sigma))",
-                  "exp((1.0 - beta) * log(snew) + beta * log(sigma))"),
+    "beta_swap": ("double beta = exp(-ratio);\n            sigma = exp(beta * log(snew) + (1.0 - beta) * log(sigma));\n          }\n          if (ratio <= 0.1) alpha3 = 0.2;\n          /* u^{r+1,0}",
+                  "double beta = exp(-ratio);\n            sigma = exp((1.0 - beta) * log(snew) + beta * log(sigma));\n          }\n          if (ratio <= 0.1) alpha3 = 0.2;\n          /* u^{r+1,0}"),
     "kron_transpose": ("acc += T[i + (size_t)s * b] * B[j + (size_t)p * b];",
                        "acc += T[i + (size_t)s * b] * B[b + (size_t)p * j];"),
     "power_no_norm": ("for (int i = 0; i < k; ++i) v[i] = w[i] / nw;", "for (int i = 0; i < k; ++i) v[i] = w[i] / (2.0 * nw);"),
     "precond_box_unscaled": ("L[j] = P->L[j] / D[j]; U[j] = P->U[j] / D[j];", "L[j] = P->L[j]; U[j] = P->U[j];"),
     "precond_y_unscale": ("for (int i = 0; i < m; ++i) y_out[i] *= E[i];", "for (int i = 0; i < m; ++i) y_out[i] /= E[i];"),
     "ruiz_no_sqrt": ("if (nrm[i] > 0.0) f[i] /= sqrt(nrm[i]);", "if (nrm[i] > 0.0) f[i] /= nrm[i];"),
-    "precond_stop_on_scaled": ("        if (D) {\n", "        if (0) {\n"),
+    "precond_stop_on_scaled": ("        if (D) {\n          for (int i = 0; i < m; ++i) dy[i] = E[i] * yb[i];\n          for (int j = 0; j < n; ++j) { dw[j]",
+                               "        if (0) {\n          for (int i = 0; i < m; ++i) dy[i] = E[i] * yb[i];\n          for (int j = 0; j < n; ++j) { dw[j]"),
     "soft_threshold_sign": ("(r > t) ? r - t :", "(r > t) ? r + t :"),
     "l1_missing_in_pobj": ("double pobj = 0.5 * xQx + cx + P->l1_weight * l1;", "double pobj = 0.5 * xQx + cx;"),
     "gram_abs_values": ("acc += P->gram_val[k] * x[P->gram_col[k]];", "acc += fabs(P->gram_val[k]) * x[P->gram_col[k]];"),

@@ -99,6 +99,22 @@ void orc_apply_Q(const orc_problem *P, const double *x, double *out) {
         for (int b = 0; b < p; ++b) acc += T[i + (size_t)s * b] * B[j + (size_t)p * b];
         out[i + (size_t)s * j] = acc;
       }
+    /* QAP relaxation (Section 4.5): Q = B (x) C - I (x) S - T (x) I, i.e.
+     * out -= vec(S X) + vec(X T^T) */
+    if (P->kron_S)
+      for (int j = 0; j < p; ++j)
+        for (int i = 0; i < s; ++i) {
+          double acc = 0.0;
+          for (int a = 0; a < s; ++a) acc += P->kron_S[i + (size_t)s * a] * x[a + (size_t)s * j];
+          out[i + (size_t)s * j] -= acc;
+        }
+    if (P->kron_T)
+      for (int j = 0; j < p; ++j)
+        for (int i = 0; i < s; ++i) {
+          double acc = 0.0;
+          for (int b = 0; b < p; ++b) acc += x[i + (size_t)s * b] * P->kron_T[j + (size_t)p * b];
+          out[i + (size_t)s * j] -= acc;
+        }
     free(T);
   } else if (P->qkind == ORC_Q_GRAM) {
     /* Q x = Ahat^T (Ahat x) */

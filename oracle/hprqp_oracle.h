@@ -46,6 +46,9 @@ typedef struct {
   double l1_weight;       /* lambda >= 0: phi(x) = lambda ||x||_1 + delta_[L,U](x)   */
   int gram_p; const int *gram_rowptr, *gram_col; const double *gram_val;
                           /* Q = Ahat^T Ahat, Ahat p x n CSR (matrix-free Q)          */
+  const double *kron_S, *kron_T;  /* Kronecker Q only, may be NULL: Q = B (x) C
+                          - I (x) S - T (x) I (the QAP relaxation of Section 4.5),
+                          S s x s, T p x p, column-major                             */
 } orc_problem;
 
 typedef struct {

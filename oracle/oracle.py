@@ -31,7 +31,8 @@ class _Problem(C.Structure):
                 ("a_rowptr", _ip), ("a_col", _ip), ("a_val", _dp),
                 ("l", _dp), ("u", _dp),
                 ("l1_weight", C.c_double),
-                ("gram_p", C.c_int), ("gram_rowptr", _ip), ("gram_col", _ip), ("gram_val", _dp)]
+                ("gram_p", C.c_int), ("gram_rowptr", _ip), ("gram_col", _ip), ("gram_val", _dp),
+                ("kron_S", _dp), ("kron_T", _dp)]
 
 
 class _Options(C.Structure):
@@ -122,6 +123,10 @@ class _Marshal:
             P.kron_p = qp.kron_B.shape[0]; P.kron_s = qp.kron_C.shape[0]
             P.kron_B = _d(k(np.asfortranarray(qp.kron_B, dtype=np.float64).ravel(order="F")))
             P.kron_C = _d(k(np.asfortranarray(qp.kron_C, dtype=np.float64).ravel(order="F")))
+            if getattr(qp, "kron_S", None) is not None:
+                P.kron_S = _d(k(np.asfortranarray(qp.kron_S, dtype=np.float64).ravel(order="F")))
+            if getattr(qp, "kron_T", None) is not None:
+                P.kron_T = _d(k(np.asfortranarray(qp.kron_T, dtype=np.float64).ravel(order="F")))
         if qp.qkind == "lowrank":
             P.lr_rank = qp.lr_F.shape[1]
             P.lr_d = _d(k(f64(qp.lr_d))); P.lr_F = _d(k(f64(qp.lr_F)))

@@ -21,6 +21,8 @@ Workloads (all seeded with ``numpy.random.default_rng``):
 * ``make_random_large`` OSQP-style "random" class at scale (n=1e6, m=5e5).
 * ``make_kron``          matrix-free Q = B (x) C with assignment constraints
                          (the QAP-relaxation structure of Section 4.5).
+* ``make_qap``           the synthetic QAP relaxation of Section 4.5, Q = 2(Bhat (x)
+                         Ahat - I (x) S - T (x) I), S and T from ``qap_st``.
 * ``make_portfolio``     portfolio-style QP, Q = F F^T + D, budget + sector rows.
 * ``make_portfolio_family`` a fixed portfolio instance plus per-sample
                          perturbations of c and of the sector bounds.
@@ -57,6 +59,8 @@ class QP:
     q_val: Optional[np.ndarray] = None
     kron_B: Optional[np.ndarray] = None   # p x p (Q = B (x) C)
     kron_C: Optional[np.ndarray] = None   # s x s
+    kron_S: Optional[np.ndarray] = None   # s x s (QAP relaxation: Q = B (x) C - I (x) S - T (x) I)
+    kron_T: Optional[np.ndarray] = None   # p x p
     lr_d: Optional[np.ndarray] = None     # n
     lr_F: Optional[np.ndarray] = None     # n x r, row-major
     gram_rowptr: Optional[np.ndarray] = None   # Ahat (p x n) CSR, Q = Ahat^T Ahat
@@ -86,7 +90,12 @@ class QP:
             return sp.csr_matrix((self.q_val, self.q_col, self.q_rowptr),
                                  shape=(self.n, self.n)).toarray()
         if self.qkind == "kron":
-            return np.kron(self.kron_B, self.kron_C)
+            Q = np.kron(self.kron_B, self.kron_C)
+            if self.kron_S is not None:
+                Q -= np.kron(np.eye(self.kron_B.shape[0]), self.kron_S)
+            if self.kron_T is not None:
+                Q -= np.kron(self.kron_T, np.eye(self.kron_C.shape[0]))
+            return Q
         if self.qkind == "lowrank":
             return np.diag(self.lr_d) + self.lr_F @ self.lr_F.T
         if self.qkind == "gram":
@@ -238,6 +247,56 @@ def make_kron(seed: int = 1002, d: int = 300) -> QP:
               kron_B=Bm, kron_C=Cm,
               meta=dict(workload="kron_assignment", seed=seed, d=d,
                         x_feasible=np.full(n, 1.0 / d)))
+
+
+def qap_st(Ahat: np.ndarray, Bhat: np.ndarray):
+    """The matrices S, T of the QAP relaxation of Section 4.5 (problem data).
+
+    Ahat = V_A diag(alpha) V_A^T with alpha descending, Bhat = V_B diag(beta)
+    V_B^T with beta ascending; (s, t) is an optimal solution of the LP
+    max { sum(s) + sum(t) : s_i + t_j <= alpha_i beta_j for all i, j }, and
+    S = V_A diag(s) V_A^T, T = V_B diag(t) V_B^T.  The LP is the dual of the
+    assignment problem with costs alpha_i beta_j, whose optimum pairs alpha_i
+    with beta_i (rearrangement inequality); one optimal (s, t) is the pair of
+    potentials  t_1 = 0,  t_{k+1} = t_k + alpha_k (beta_{k+1} - beta_k),
+    s_i = alpha_i beta_i - t_i  (feasible because alpha is descending and
+    beta ascending).  The LP has other optimal solutions; this one is fixed
+    here.  Returns (S, T, s, t, alpha, beta)."""
+    al, VA = np.linalg.eigh(0.5 * (Ahat + Ahat.T))
+    be, VB = np.linalg.eigh(0.5 * (Bhat + Bhat.T))
+    al, VA = al[::-1], VA[:, ::-1]              # descending
+    d = len(al)
+    t = np.zeros(d)
+    for k in range(d - 1):
+        t[k + 1] = t[k] + al[k] * (be[k + 1] - be[k])
+    s = al * be - t
+    S = (VA * s) @ VA.T
+    T = (VB * t) @ VB.T
+    return 0.5 * (S + S.T), 0.5 * (T + T.T), s, t, al, be
+
+
+def make_qap(seed: int = 1007, d: int = 256) -> QP:
+    """The synthetic QAP relaxation of Section 4.5: d points uniform in the
+    unit square, Ahat their Euclidean distance matrix, Bhat symmetric with
+    U[0,1) entries and zero diagonal; the CQP
+        min <vec X, Qhat vec X>  s.t.  X e = e, X^T e = e, vec X >= 0,
+        Qhat = Bhat (x) Ahat - I (x) S - T (x) I   (S, T from qap_st),
+    written as 1/2 <x, Q x> with Q = 2 Qhat (so the objective is the paper's)
+    and c = 0.  n = d^2, m = 2d."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random((d, 2))
+    Ah = np.sqrt(((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1))
+    Ub = np.triu(rng.random((d, d)), 1)
+    Bh = Ub + Ub.T
+    S, T, s, t, al, be = qap_st(Ah, Bh)
+    n = d * d
+    A = assignment_A(d)
+    ar, ac, av = _csr_arrays(A)
+    return QP(n=n, m=2 * d, qkind="kron", c=np.zeros(n), L=np.zeros(n), U=np.full(n, np.inf),
+              a_rowptr=ar, a_col=ac, a_val=av, l=np.ones(2 * d), u=np.ones(2 * d),
+              kron_B=2.0 * Bh, kron_C=Ah, kron_S=2.0 * S, kron_T=2.0 * T,
+              meta=dict(workload="qap_relaxation", seed=seed, d=d, Ahat=Ah, Bhat=Bh, s=s, t=t,
+                        alpha=al, beta=be))
 
 
 # ---------------------------------------------------------------------------

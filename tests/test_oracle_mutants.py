@@ -63,6 +63,22 @@ PRIMAL_MUTANTS = {
 }
 
 
+# mistakes in the QAP-relaxation operator (Section 4.5), caught by its pin file
+QAP_MUTANTS = {
+    "qap_S_sign": ("P->kron_S[i + (size_t)s * a] * x[a + (size_t)s * j];\n          out[i + (size_t)s * j] -= acc;",
+                   "P->kron_S[i + (size_t)s * a] * x[a + (size_t)s * j];\n          out[i + (size_t)s * j] += acc;"),
+    "qap_T_right_side": ("acc += x[i + (size_t)s * b] * P->kron_T[j + (size_t)p * b];",
+                         "acc += x[b + (size_t)s * j] * P->kron_T[i + (size_t)p * b];"),
+    "qap_S_dropped": ("    if (P->kron_S)\n", "    if (0)\n"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(QAP_MUTANTS))
+def test_qap_pins_catch_mutant(name, tmp_path):
+    old, new = QAP_MUTANTS[name]
+    _run_mutant(old, new, "test_qap.py", tmp_path, name)
+
+
 def _run_mutant(old, new, pin_file, tmp_path, name):
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation site for {name} not unique/found"

@@ -56,7 +56,7 @@ typedef enum {
 typedef enum {
   HPRQP_Q_ZERO = 0,           /* Q = 0 (the LP case of Remark 2.1)               */
   HPRQP_Q_CSR = 1,            /* explicit symmetric CSR, both triangles stored   */
-  HPRQP_Q_KRON = 2,           /* matrix-free Q = B (x) C (Section 4.5)           */
+  HPRQP_Q_KRON = 2,           /* matrix-free Q = B (x) C [- I(x)S - T(x)I] (4.5)  */
   HPRQP_Q_LOWRANK = 3,        /* Q = diag(d) + F F^T                              */
   HPRQP_Q_GRAM = 4            /* matrix-free Q = Ahat^T Ahat, Ahat sparse (Lasso) */
 } hprqp_qkind;
@@ -81,6 +81,12 @@ typedef struct {
   double l1_weight;           /* >= 0: weight of ||x||_1 in phi (Lasso, Section 4.4) */
   /* HPRQP_Q_GRAM: Q = Ahat^T Ahat applied as two products; Ahat gram_p x n CSR */
   int32_t gram_p; const int32_t *gram_rowptr, *gram_col; const double *gram_val; int64_t gram_nnz;
+  /* HPRQP_Q_KRON, optional (NULL: 0): Q = B (x) C - I (x) S - T (x) I, i.e.
+   * Q vec(X) = vec(C X B^T - S X - X T^T), the QAP-relaxation operator of
+   * Section 4.5 (C = Ahat, B = Bhat up to the factor 2 of 1/2<x,Qx>); S
+   * kron_s x kron_s and T kron_p x kron_p, dense column-major.  Q must stay
+   * PSD (the LP conditions on the eigenvalues of S, T of Section 4.5). */
+  const double *kron_S, *kron_T;
 } hprqp_problem;
 
 typedef struct {

@@ -25,7 +25,7 @@ class hprqp_problem(C.Structure):
                 ("l", _vp), ("u", _vp),
                 ("l1_weight", C.c_double),
                 ("gram_p", C.c_int32), ("gram_rowptr", _vp), ("gram_col", _vp), ("gram_val", _vp),
-                ("gram_nnz", C.c_int64)]
+                ("gram_nnz", C.c_int64), ("kron_S", _vp), ("kron_T", _vp)]
 
 
 class hprqp_options(C.Structure):

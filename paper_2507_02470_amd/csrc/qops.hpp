@@ -18,18 +18,38 @@ typedef double hq_dx4 __attribute__((ext_vector_type(4)));
 // supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register v of lane l
 // holds D[l/16 + 4v][l%16], v = 0..3.
 // ---------------------------------------------------------------------------
+//
+// EXTRA: up to two more terms sign_t * A_t op_t(B_t) (same M x N output, own
+// K_t, lda, ldb, transpose flag) are added to the same accumulator; their
+// k-steps follow those of the main term, and the waves split all of them.
+// Used for the QAP-relaxation operator C X B^T - X T^T - S X.
 #define HQ_KSPLIT 8
 #define HQ_KUNROLL 5
-template <bool TRANSB, class Epi>
+struct GemmTerms {
+  const double* A[2];
+  const double* B[2];
+  int lda[2], ldb[2], K[2], transb[2];
+  double sign[2];
+  int nt;   // extra terms used (0..2)
+};
+template <bool TRANSB, class Epi, bool EXTRA = false>
 __global__ __launch_bounds__(64 * HQ_KSPLIT) void k_dgemm16(int M, int N, int K, const double* __restrict__ A, int lda,
                                                             const double* __restrict__ B, int ldb, int ldo, Epi epi,
-                                                            const DevParams* __restrict__ prm, int jit, RedOut red) {
+                                                            const DevParams* __restrict__ prm, int jit, RedOut red,
+                                                            GemmTerms ex = GemmTerms{}) {
   constexpr int NR = Epi::NR;
   __shared__ double part[HQ_KSPLIT][16][17];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int tiles_m = (M + 15) >> 4, tiles_n = (N + 15) >> 4;
-  const int ksteps = (K + 3) >> 2;
+  const int ks_main = (K + 3) >> 2;
+  int ksteps = ks_main;
+  int ks_t1 = 0;   // first k-step of the second extra term
+  if constexpr (EXTRA) {
+    const int k0 = ex.nt > 0 ? (ex.K[0] + 3) >> 2 : 0, k1 = ex.nt > 1 ? (ex.K[1] + 3) >> 2 : 0;
+    ks_t1 = ks_main + k0;
+    ksteps = ks_t1 + k1;
+  }
   const int per = (ksteps + HQ_KSPLIT - 1) / HQ_KSPLIT;
   const int ks0 = wv * per;
   const int ks1 = (ks0 + per < ksteps) ? ks0 + per : ksteps;
@@ -51,14 +71,29 @@ __global__ __launch_bounds__(64 * HQ_KSPLIT) void k_dgemm16(int M, int N, int K,
 #pragma unroll
       for (int u = 0; u < HQ_KUNROLL; ++u) {
         const int ks = kc + u;
-        const int k = (ks << 2) + lk;
-        const bool kin = ks < ks1 && k < K;
-        const int kk = kin ? k : 0;
         const int ic = ia < M ? ia : M - 1, jc = jb < N ? jb : N - 1;
-        const double a = A[ic + (size_t)lda * kk];
-        const double b = TRANSB ? B[jc + (size_t)ldb * kk] : B[kk + (size_t)ldb * jc];
-        av[u] = (ia < M && kin) ? a : 0.0;
-        bv[u] = (jb < N && kin) ? b : 0.0;
+        if (!EXTRA || ks < ks_main) {
+          const int k = (ks << 2) + lk;
+          const bool kin = ks < ks1 && k < K;
+          const int kk = kin ? k : 0;
+          const double a = A[ic + (size_t)lda * kk];
+          const double b = TRANSB ? B[jc + (size_t)ldb * kk] : B[kk + (size_t)ldb * jc];
+          av[u] = (ia < M && kin) ? a : 0.0;
+          bv[u] = (jb < N && kin) ? b : 0.0;
+        } else if (ks >= ks1) {
+          av[u] = 0.0;
+          bv[u] = 0.0;
+        } else {
+          // extra term t (a wave-uniform choice; t = 1 only when two are given)
+          const int t = ks < ks_t1 ? 0 : 1;
+          const int k = ((ks - (t ? ks_t1 : ks_main)) << 2) + lk;
+          const bool kin = ks < ks1 && k < ex.K[t];
+          const int kk = kin ? k : 0;
+          const double a = ex.A[t][ic + (size_t)ex.lda[t] * kk];
+          const double b = ex.transb[t] ? ex.B[t][jc + (size_t)ex.ldb[t] * kk] : ex.B[t][kk + (size_t)ex.ldb[t] * jc];
+          av[u] = (ia < M && kin) ? a : 0.0;
+          bv[u] = (jb < N && kin) ? ex.sign[t] * b : 0.0;
+        }
       }
 #pragma unroll
       for (int u = 0; u < HQ_KUNROLL; ++u) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], d, 0, 0, 0);

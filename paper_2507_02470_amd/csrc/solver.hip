@@ -235,6 +235,7 @@ struct hprqp_handle {
   Mat A, AT, Q;
   int kp = 0, ks = 0;
   const double *kB = nullptr, *kC = nullptr;
+  const double *kS = nullptr, *kT = nullptr;   // QAP relaxation: Q = B (x) C - I (x) S - T (x) I
   int lr_r = 0;
   const double *lr_d = nullptr, *lr_F = nullptr;
   Mat G, GT;                 // Q = Ahat^T Ahat: Ahat (p x n) and its stored transpose
@@ -396,7 +397,22 @@ void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedO
       const int grid = std::min(tiles, HQ_GRID_CAP);
       k_dgemm16<false, EpiStore><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, s, h.kC, s, x, s, s, EpiStore{h.kronT},
                                                                     h.dprm, j, no_red(h));
-      k_dgemm16<true, Epi><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, p, h.kronT, s, h.kB, p, s, epi, h.dprm, j, red);
+      if (!h.kS && !h.kT) {
+        k_dgemm16<true, Epi><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, p, h.kronT, s, h.kB, p, s, epi, h.dprm, j, red);
+      } else {
+        // QAP relaxation: Y = T1 B^T - X T^T - S X in one accumulation
+        GemmTerms ex{};
+        if (h.kT) {
+          const int t = ex.nt++;
+          ex.A[t] = x; ex.lda[t] = s; ex.B[t] = h.kT; ex.ldb[t] = p; ex.K[t] = p; ex.transb[t] = 1; ex.sign[t] = -1.0;
+        }
+        if (h.kS) {
+          const int t = ex.nt++;
+          ex.A[t] = h.kS; ex.lda[t] = s; ex.B[t] = x; ex.ldb[t] = s; ex.K[t] = s; ex.transb[t] = 0; ex.sign[t] = -1.0;
+        }
+        k_dgemm16<true, Epi, true><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, p, h.kronT, s, h.kB, p, s, epi, h.dprm,
+                                                                      j, red, ex);
+      }
       break;
     }
     case HPRQP_Q_GRAM:
@@ -699,6 +715,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         if (!P->kron_B || !P->kron_C || P->kron_p <= 0 || P->kron_s <= 0) fail(HPRQP_ERR_ARG, "Kronecker factors required");
         if ((long long)P->kron_p * P->kron_s != n) fail(HPRQP_ERR_SHAPE, "n must equal kron_p * kron_s");
         h.kp = P->kron_p; h.ks = P->kron_s; h.kB = P->kron_B; h.kC = P->kron_C;
+        h.kS = P->kron_S; h.kT = P->kron_T;
         break;
       case HPRQP_Q_GRAM:
         if (P->gram_p <= 0 || !P->gram_rowptr || (P->gram_nnz > 0 && (!P->gram_col || !P->gram_val)))
@@ -744,6 +761,8 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
     if (h.qkind == HPRQP_Q_KRON) {
       k_validate_finite<<<64, 256, 0, st>>>((long long)h.kp * h.kp, h.kB, h.dflags);
       k_validate_finite<<<64, 256, 0, st>>>((long long)h.ks * h.ks, h.kC, h.dflags);
+      if (h.kS) k_validate_finite<<<64, 256, 0, st>>>((long long)h.ks * h.ks, h.kS, h.dflags);
+      if (h.kT) k_validate_finite<<<64, 256, 0, st>>>((long long)h.kp * h.kp, h.kT, h.dflags);
     }
     if (h.qkind == HPRQP_Q_LOWRANK) {
       k_validate_finite<<<64, 256, 0, st>>>(n, h.lr_d, h.dflags);

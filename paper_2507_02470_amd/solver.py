@@ -54,6 +54,10 @@ class DeviceProblem:
             t["kron_C"] = _dev(np.asarray(qp.kron_C).ravel(order="F"), f64, device)
             P.kron_p, P.kron_s = qp.kron_B.shape[0], qp.kron_C.shape[0]
             P.kron_B, P.kron_C = t["kron_B"].data_ptr(), t["kron_C"].data_ptr()
+            for nm in ("kron_S", "kron_T"):
+                if getattr(qp, nm, None) is not None:
+                    t[nm] = _dev(np.asarray(getattr(qp, nm)).ravel(order="F"), f64, device)
+                    setattr(P, nm, t[nm].data_ptr())
         elif qp.qkind == "lowrank":
             t["lr_d"] = _dev(qp.lr_d, f64, device)
             t["lr_F"] = _dev(qp.lr_F, f64, device)

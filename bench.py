@@ -61,7 +61,7 @@ def kernel_bytes(qp) -> dict:
 
 # sources of the single-instance solver's kernels and launches (the batched
 # solver and the MLP do not enter the dominant kernel)
-SOLVER_SOURCES = ("common.hpp", "spmv.hpp", "epilogues.hpp", "qops.hpp", "solver.hip")
+SOLVER_SOURCES = ("common.hpp", "spmv.hpp", "epilogues.hpp", "epilogues_primal.hpp", "qops.hpp", "solver.hip")
 
 
 def src_hash() -> str:
@@ -140,6 +140,53 @@ def extra_kron(steps, cpu):
                           sigma0=r.sigma0)
         out["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
     s.close()
+    return out
+
+
+def extra_qap(dims, steps, cpu, time_cap):
+    """The synthetic QAP relaxation of Section 4.5 (d points in the unit square,
+    Ahat their distance matrix, Bhat symmetric U[0,1) with zero diagonal),
+    Q = 2(Bhat (x) Ahat - I (x) S - T (x) I) applied matrix-free: per d the
+    iteration rate, the FP64-MFMA rate of the Q product (C X, then the
+    three-term C X B^T - X T^T - S X: 8 d^3 flop) and the solve to 1e-8
+    (power method included, capped at `time_cap` seconds)."""
+    import torch
+    import qpgen
+    from paper_2507_02470_amd.solver import DeviceProblem, Solver
+    out = {}
+    for d in dims:
+        qp = qpgen.make_qap(d=d)
+        s = Solver(DeviceProblem(qp), power_start_A=qpgen.power_start(qp.m),
+                   power_start_Q=qpgen.power_start(qp.n), check_every=T_CHECK, tol=0.0, max_iter=T_CHECK)
+        s.solve()
+        s.set_options(tol=0.0, max_iter=steps * T_CHECK, profile_kernels=1, time_limit_s=0.0)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ta
+        ks = s.kernel_stats()["avg_ms"]
+        q_flop = 8.0 * d ** 3
+        q_ms = 0.5 * (ks["q_xhat"] + ks["q_d_halpern"])
+        s.set_options(tol=1e-8, max_iter=50_000_000, profile_kernels=0, time_limit_s=time_cap)
+        rt = s.solve()
+        o = dict(n=qp.n, m=qp.m, iterations_per_s=round(r.iters / dt, 1),
+                 us_per_iteration=round(dt / r.iters * 1e6, 2),
+                 q_product=dict(flop=q_flop, avg_us=round(q_ms * 1e3, 2),
+                                tflops=round(q_flop / (q_ms * 1e-3) / 1e12, 2),
+                                fp64_mfma_util=round(q_flop / (q_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)),
+                 time_to_1e8=dict(term=rt.term, iterations=rt.iters, kkt=rt.kkt, restarts=rt.restarts,
+                                  time_s=round(rt.t_setup_s + rt.t_solve_s, 3), time_cap_s=time_cap,
+                                  relaxation_bound=rt.pobj + float(qp.meta["s"].sum() + qp.meta["t"].sum())))
+        if cpu and d <= 256:
+            import oracle
+            t0 = time.perf_counter()
+            ro = oracle.solve(qp, tol=0.0, max_iter=3, check_every=T_CHECK, lambda_A=r.lambda_A,
+                              lambda_Q=r.lambda_Q, sigma0=r.sigma0)
+            o["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
+        s.close()
+        out[f"d{d}"] = o
+        log(f"qap d={d}: {o}")
     return out
 
 
@@ -297,6 +344,57 @@ def extra_small(cpu):
     return out
 
 
+def extra_ablation(qp, dp, lamA, lamQ, steps, cpu, time_cap):
+    """HPR-QP against HPR on the primal reformulations (Appendix A: method 1,
+    Algorithm 6; method 2, Algorithm 7), the comparison of Table 1: full solves
+    of the small CCQP, and on the random QP the iteration rate and the solve to
+    1e-8 (capped at `time_cap` seconds per method)."""
+    import torch
+    import qpgen
+    from paper_2507_02470_amd.solver import DeviceProblem, Solver
+    small = qpgen.make_small_ccqp()
+    sdp = DeviceProblem(small)
+    out = {"small_ccqp": {}, "random_large": {}}
+    for meth in (0, 1, 2):
+        s = Solver(sdp, power_start_A=qpgen.power_start(small.m), power_start_Q=qpgen.power_start(small.n),
+                   tol=1e-8, max_iter=2_000_000, method=meth)
+        s.solve()
+        r = s.solve()
+        s.close()
+        out["small_ccqp"][f"method{meth}"] = dict(term=r.term, iterations=r.iters, restarts=r.restarts,
+                                                  time_s=round(r.t_setup_s + r.t_solve_s, 4), pobj=r.pobj)
+    for meth in (1, 2):
+        s = Solver(dp, lambda_A=lamA, lambda_Q=lamQ, check_every=T_CHECK, tol=0.0, max_iter=T_CHECK,
+                   spmv_autotune=1, method=meth)
+        s.solve()
+        s.set_options(tol=0.0, max_iter=steps * T_CHECK, profile_kernels=1, time_limit_s=0.0)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ta
+        ks = s.kernel_stats()["avg_ms"]
+        s.set_options(tol=1e-8, max_iter=50_000_000, profile_kernels=0, time_limit_s=time_cap)
+        rt = s.solve()
+        s.close()
+        out["random_large"][f"method{meth}"] = dict(
+            iterations_per_s=round(r.iters / dt, 1), us_per_iteration=round(dt / r.iters * 1e6, 2),
+            product_avg_us={"Q": round(ks["q_xhat"] * 1e3, 2), "A": round(ks["a_v"] * 1e3, 2),
+                            "AT": round(ks["at_ybar"] * 1e3, 2)},
+            to_1e8=dict(term=rt.term, iterations=rt.iters, kkt=rt.kkt, time_s=round(rt.t_solve_s, 3),
+                        time_cap_s=time_cap))
+    if cpu:
+        import oracle
+        for meth in (1, 2):
+            t0 = time.perf_counter()
+            ro = oracle.solve(small, tol=1e-8, max_iter=2_000_000, method=meth,
+                              power_start_A=qpgen.power_start(small.m), power_start_Q=qpgen.power_start(small.n))
+            out["small_ccqp"][f"method{meth}"]["cpu_oracle"] = dict(term=ro.term, iterations=ro.iters,
+                                                                    time_s=round(time.perf_counter() - t0, 3),
+                                                                    cores=1)
+    return out
+
+
 def extra_warm_cold(n_train, n_eval, epochs):
     """Learned warm start on the parametric portfolio family (n = 1000, m = 21)."""
     import numpy as np
@@ -361,6 +459,11 @@ def main():
     ap.add_argument("--train-samples", type=int, default=50_000)
     ap.add_argument("--eval-samples", type=int, default=4096)
     ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--qap-dims", type=int, nargs="*", default=[256, 512],
+                    help="sizes d of the synthetic QAP relaxations (n = d^2)")
+    ap.add_argument("--qap-time-cap", type=float, default=30.0, help="seconds per QAP solve to 1e-8")
+    ap.add_argument("--ablation-time-cap", type=float, default=15.0,
+                    help="seconds per primal method for its solve of the random QP to 1e-8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the HPR-QP path here is "
@@ -452,12 +555,17 @@ def main():
         extras = {}
         extras["small_ccqp"] = extra_small(not args.no_cpu_baseline)
         log(f"small: {extras['small_ccqp']}")
+        extras["primal_ablation"] = extra_ablation(qp, dp, r.lambda_A, r.lambda_Q, max(5, args.steps // 2),
+                                                   not args.no_cpu_baseline, args.ablation_time_cap)
+        log(f"ablation: {extras['primal_ablation']}")
         extras["precond"] = extra_precond(qp, dp, not args.no_cpu_baseline)
         log(f"precond: {extras['precond']}")
         extras["lasso"] = extra_lasso(max(5, args.steps // 2), not args.no_cpu_baseline)
         log(f"lasso: {extras['lasso']}")
         extras["kron"] = extra_kron(max(5, args.steps // 2), not args.no_cpu_baseline)
         log(f"kron: {extras['kron']}")
+        extras["qap_relaxation"] = extra_qap(args.qap_dims, max(3, args.steps // 4), not args.no_cpu_baseline,
+                                             args.qap_time_cap)
         extras["batch"] = extra_batch(args.batch_count, not args.no_cpu_baseline)
         log(f"batch: {extras['batch']}")
         extras["warm_vs_cold"] = extra_warm_cold(args.train_samples, args.eval_samples, args.epochs)

@@ -115,6 +115,180 @@ __global__ __launch_bounds__(64 * HQ_KSPLIT) void k_dgemm16(int M, int N, int K,
 }
 
 // ---------------------------------------------------------------------------
+// LDS-tiled FP64 MFMA GEMM for large Kronecker factors (d >~ 400), same
+// operation as k_dgemm16 with up to three terms:
+//   D (M x N) = sum_t sign_t A_t (M x K_t, col-major) op_t(B_t).
+// A block of 256 threads (4 waves, 2 x 2) owns a 64 x 64 output tile, each
+// wave a 32 x 32 part (2 x 2 MFMA 16 x 16 tiles, every operand fragment used
+// twice).  K runs in chunks of 16: the 64 x 16 slice of A and the 16 x 64 slice
+// of op(B) are loaded with coalesced global reads into registers while the
+// previous chunk is multiplied out of LDS (two LDS buffers, one barrier per
+// chunk).  The MFMA is fed op(B)^T as its A operand and A^T as its B operand,
+// so it produces D^T: lane l then holds rows l%16 of the tile for columns
+// l/16 + 4v, and the epilogue's vector accesses (index i + ldo j) are 16
+// consecutive rows per column.
+// Split-K (PART): the chunks of all terms are divided among `kgroups` groups
+// (grid = tiles x kgroups); group g writes its partial tile to
+// parts + g * M * N and k_gemm_sum adds the groups in order and runs the
+// epilogue.  Deterministic either way.
+// ---------------------------------------------------------------------------
+#define HQ_TB 64
+#define HQ_TKC 16
+#define HQ_TPITCH (HQ_TB + 2)
+struct GemmOps {
+  const double* A[3];
+  const double* B[3];
+  int lda[3], ldb[3], K[3], transb[3];
+  double sign[3];
+  int nt;
+};
+
+template <class Epi, bool PART>
+__global__ __launch_bounds__(256) void k_dgemm_tile(int M, int N, GemmOps op, int ldo, Epi epi,
+                                                    const DevParams* __restrict__ prm, int jit, RedOut red,
+                                                    int kgroups, double* __restrict__ parts) {
+  constexpr int NR = Epi::NR;
+  __shared__ double As[2][HQ_TKC][HQ_TPITCH];
+  __shared__ double Bs[2][HQ_TKC][HQ_TPITCH];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv & 1, wn = wv >> 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tiles_m = (M + HQ_TB - 1) / HQ_TB, tiles_n = (N + HQ_TB - 1) / HQ_TB;
+  const int tiles = tiles_m * tiles_n;
+  const int n0 = (op.K[0] + HQ_TKC - 1) / HQ_TKC;
+  const int n1 = op.nt > 1 ? (op.K[1] + HQ_TKC - 1) / HQ_TKC : 0;
+  const int n2 = op.nt > 2 ? (op.K[2] + HQ_TKC - 1) / HQ_TKC : 0;
+  const int total = n0 + n1 + n2;
+  const int per = (total + kgroups - 1) / kgroups;
+  Epi e = epi;
+  e.setup(prm, jit);
+  double acc[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int q = 0; q < (NR > 0 ? NR : 1); ++q) acc[q] = 0.0;
+  for (int w = blockIdx.x; w < tiles * kgroups; w += gridDim.x) {
+    const int tile = w % tiles, grp = w / tiles;
+    const int i0 = (tile % tiles_m) * HQ_TB, j0 = (tile / tiles_m) * HQ_TB;
+    const int c0 = grp * per, c1 = min(total, c0 + per);
+    double ra[4], rb[4];
+    // global -> registers for chunk c (term t, first k k0); out-of-range -> 0
+    auto load = [&](int c) {
+      int t = 0, cc = c;      // chunk c -> (term t, chunk cc of that term); wave-uniform
+      if (cc >= n0) { cc -= n0; t = 1; if (cc >= n1) { cc -= n1; t = 2; } }
+      const int k0 = cc * HQ_TKC, Kt = op.K[t];
+      const double* __restrict__ Ap = op.A[t];
+      const double* __restrict__ Bp = op.B[t];
+      const int lda = op.lda[t], ldb = op.ldb[t];
+      const double sg = op.sign[t];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = tid & 63, kk = (tid >> 6) + 4 * q;
+        const int gi = i0 + r, gk = k0 + kk;
+        const bool ok = gi < M && gk < Kt;
+        const double v = Ap[(size_t)(ok ? gi : 0) + (size_t)lda * (ok ? gk : 0)];
+        ra[q] = ok ? v : 0.0;
+      }
+      if (op.transb[t]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = tid & 63, kk = (tid >> 6) + 4 * q;
+          const int gj = j0 + c, gk = k0 + kk;
+          const bool ok = gj < N && gk < Kt;
+          const double v = Bp[(size_t)(ok ? gj : 0) + (size_t)ldb * (ok ? gk : 0)];
+          rb[q] = ok ? sg * v : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int kk = tid & 15, c = (tid >> 4) + 16 * q;
+          const int gj = j0 + c, gk = k0 + kk;
+          const bool ok = gj < N && gk < Kt;
+          const double v = Bp[(size_t)(ok ? gk : 0) + (size_t)ldb * (ok ? gj : 0)];
+          rb[q] = ok ? sg * v : 0.0;
+        }
+      }
+      return (int)op.transb[t];
+    };
+    auto store = [&](int buf, int tb) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[buf][(tid >> 6) + 4 * q][tid & 63] = ra[q];
+      if (tb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Bs[buf][(tid >> 6) + 4 * q][tid & 63] = rb[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Bs[buf][tid & 15][(tid >> 4) + 16 * q] = rb[q];
+      }
+    };
+    hq_dx4 d[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) d[a][b] = hq_dx4{0.0, 0.0, 0.0, 0.0};
+    int buf = 0;
+    if (c0 < c1) {
+      const int tb = load(c0);
+      store(0, tb);
+    }
+    __syncthreads();
+    for (int c = c0; c < c1; ++c) {
+      int tb = 0;
+      if (c + 1 < c1) tb = load(c + 1);
+#pragma unroll
+      for (int ks = 0; ks < HQ_TKC / 4; ++ks) {
+        const int kr = ks * 4 + lk;
+        double fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) fb[a] = As[buf][kr][wm * 32 + a * 16 + li];   // A^T: rows of D
+#pragma unroll
+        for (int b = 0; b < 2; ++b) fa[b] = Bs[buf][kr][wn * 32 + b * 16 + li];   // op(B)^T: columns
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) d[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[b], fb[a], d[a][b], 0, 0, 0);
+      }
+      if (c + 1 < c1) store(buf ^ 1, tb);
+      __syncthreads();
+      buf ^= 1;
+    }
+    // lane l holds D[i0 + wm*32 + a*16 + l%16][j0 + wn*32 + b*16 + l/16 + 4v]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = i0 + wm * 32 + a * 16 + li, gj = j0 + wn * 32 + b * 16 + lk + 4 * v;
+          if (gi < M && gj < N) {
+            if constexpr (PART) parts[(size_t)grp * M * N + gi + (size_t)M * gj] = d[a][b][v];
+            else e(gi + ldo * gj, d[a][b][v], acc);
+          }
+        }
+  }
+  if constexpr (!PART) {
+    if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
+  }
+}
+
+// out(i) = sum over the kgroups partial products in group order -> epilogue
+template <class Epi>
+__global__ __launch_bounds__(HQ_BLOCK) void k_gemm_sum(long long count, int kgroups, const double* __restrict__ parts,
+                                                       Epi epi, const DevParams* __restrict__ prm, int jit,
+                                                       RedOut red) {
+  constexpr int NR = Epi::NR;
+  Epi e = epi;
+  e.setup(prm, jit);
+  double acc[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int q = 0; q < (NR > 0 ? NR : 1); ++q) acc[q] = 0.0;
+  for (long long i = (long long)blockIdx.x * HQ_BLOCK + threadIdx.x; i < count; i += (long long)gridDim.x * HQ_BLOCK) {
+    double q = parts[i];
+    for (int g = 1; g < kgroups; ++g) q += parts[(size_t)g * count + i];
+    e((int)i, q, acc);
+  }
+  if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
+}
+
+// ---------------------------------------------------------------------------
 // Q = diag(d) + F F^T, F n x r row-major (r <= 16).
 // Stage 1: per-block partial sums of t = F^T x (slots red.slot[0..r-1]).
 // Stage 2 (after the final reduction): (Q x)_i = d_i x_i + sum_k F_ik t_k.

@@ -236,6 +236,10 @@ struct hprqp_handle {
   int kp = 0, ks = 0;
   const double *kB = nullptr, *kC = nullptr;
   const double *kS = nullptr, *kT = nullptr;   // QAP relaxation: Q = B (x) C - I (x) S - T (x) I
+  int kron_mode = 0;          // 0: k_dgemm16 (K split over waves), 1: LDS-tiled k_dgemm_tile
+  int kron_groups = 1;        // split-K groups of the tiled kernel
+  int kron_groups_max = 1;    // capacity of kparts (in n-vectors)
+  double* kparts = nullptr;
   int lr_r = 0;
   const double *lr_d = nullptr, *lr_F = nullptr;
   Mat G, GT;                 // Q = Ahat^T Ahat: Ahat (p x n) and its stored transpose
@@ -380,6 +384,45 @@ void final_reduce(hprqp_handle& h, int slot0, int nslot) {
   k_final_reduce<<<nslot, 256, 0, h.st>>>(h.partials, h.counts, slot0, kMaxMask, h.scalars);
 }
 
+// one term list through the tiled GEMM, split-K when h.kron_groups > 1
+template <class Epi>
+void launch_tile(hprqp_handle& h, int M, int N, const GemmOps& ops, const Epi& epi, int j, const RedOut& red) {
+  const int tiles = ((M + HQ_TB - 1) / HQ_TB) * ((N + HQ_TB - 1) / HQ_TB);
+  const int G = h.kron_groups;
+  if (G <= 1) {
+    k_dgemm_tile<Epi, false><<<std::min(tiles, HQ_GRID_CAP), 256, 0, h.st>>>(M, N, ops, M, epi, h.dprm, j, red, 1,
+                                                                          nullptr);
+  } else {
+    k_dgemm_tile<Epi, true><<<std::min(tiles * G, HQ_GRID_CAP), 256, 0, h.st>>>(M, N, ops, M, epi, h.dprm, j,
+                                                                             no_red(h), G, h.kparts);
+    const long long cnt = (long long)M * N;
+    k_gemm_sum<Epi><<<hq_grid(cnt, HQ_BLOCK), HQ_BLOCK, 0, h.st>>>(cnt, G, h.kparts, epi, h.dprm, j, red);
+  }
+}
+
+// Kronecker / QAP-relaxation Q through the tiled GEMM: T1 = C X, then
+// Y = T1 B^T (- X T^T - S X) with the epilogue
+template <class Epi>
+void kron_tiled(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedOut& red) {
+  const int s = h.ks, p = h.kp;
+  GemmOps g1{};
+  g1.nt = 1;
+  g1.A[0] = h.kC; g1.lda[0] = s; g1.B[0] = x; g1.ldb[0] = s; g1.K[0] = s; g1.transb[0] = 0; g1.sign[0] = 1.0;
+  launch_tile(h, s, p, g1, EpiStore{h.kronT}, j, no_red(h));
+  GemmOps g2{};
+  g2.nt = 1;
+  g2.A[0] = h.kronT; g2.lda[0] = s; g2.B[0] = h.kB; g2.ldb[0] = p; g2.K[0] = p; g2.transb[0] = 1; g2.sign[0] = 1.0;
+  if (h.kT) {
+    const int t = g2.nt++;
+    g2.A[t] = x; g2.lda[t] = s; g2.B[t] = h.kT; g2.ldb[t] = p; g2.K[t] = p; g2.transb[t] = 1; g2.sign[t] = -1.0;
+  }
+  if (h.kS) {
+    const int t = g2.nt++;
+    g2.A[t] = h.kS; g2.lda[t] = s; g2.B[t] = x; g2.ldb[t] = s; g2.K[t] = s; g2.transb[t] = 0; g2.sign[t] = -1.0;
+  }
+  launch_tile(h, s, p, g2, epi, j, red);
+}
+
 // out-of-place Q product with a fused epilogue: epi(i, (Q x)_i)
 template <class Epi>
 void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedOut& red) {
@@ -393,6 +436,10 @@ void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedO
     case HPRQP_Q_KRON: {
       // Q vec(X) = vec(C X B^T): T = C X, then Y = T B^T with the epilogue
       const int s = h.ks, p = h.kp;
+      if (h.kron_mode == 1) {
+        kron_tiled(h, x, epi, j, red);
+        break;
+      }
       const int tiles = ((s + 15) / 16) * ((p + 15) / 16);
       const int grid = std::min(tiles, HQ_GRID_CAP);
       k_dgemm16<false, EpiStore><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, s, h.kC, s, x, s, s, EpiStore{h.kronT},
@@ -658,6 +705,46 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   hipEventDestroy(e1);
 }
 
+// Kronecker Q: the K-split kernel for small factors (latency-bound, d ~ 300),
+// the LDS-tiled kernel above that, split-K while its 64 x 64 tiles are fewer
+// than the compute units
+void default_kron(hprqp_handle& h) {
+  const int tiles = ((h.ks + HQ_TB - 1) / HQ_TB) * ((h.kp + HQ_TB - 1) / HQ_TB);
+  if (std::max(h.ks, h.kp) <= 384) { h.kron_mode = 0; h.kron_groups = 1; return; }
+  h.kron_mode = 1;
+  int G = 1;
+  while (G < h.kron_groups_max && tiles * G < h.ncu) G *= 2;
+  h.kron_groups = G;
+}
+
+// time the Kronecker variants on a full Q product; keep the default unless
+// another is at least 5% faster
+void autotune_kron(hprqp_handle& h, const double* x, double* out) {
+  hipEvent_t e0, e1;
+  HQC(hipEventCreate(&e0));
+  HQC(hipEventCreate(&e1));
+  const int m0 = h.kron_mode, g0 = h.kron_groups;
+  float best = 1e30f, t_default = 1e30f;
+  int bm = m0, bg = g0;
+  for (int mode = 0; mode < 2; ++mode)
+    for (int G = 1; G <= (mode ? h.kron_groups_max : 1); G *= 2) {
+      h.kron_mode = mode; h.kron_groups = G;
+      q_apply(h, x, EpiStore{out}, 0, no_red(h));
+      HQC(hipEventRecord(e0, h.st));
+      for (int r = 0; r < 5; ++r) q_apply(h, x, EpiStore{out}, 0, no_red(h));
+      HQC(hipEventRecord(e1, h.st));
+      HQC(hipEventSynchronize(e1));
+      float ms = 0;
+      HQC(hipEventElapsedTime(&ms, e0, e1));
+      if (mode == m0 && G == g0) t_default = ms;
+      if (ms < best) { best = ms; bm = mode; bg = G; }
+    }
+  if (best < 0.95f * t_default) { h.kron_mode = bm; h.kron_groups = bg; }
+  else { h.kron_mode = m0; h.kron_groups = g0; }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+}
+
 // Lanes per row of the row-split kernel, or 0 for the CSR-stream kernel
 // (short rows: average up to 32 nonzeros and none longer than 4096).  The
 // variant gathering from an LDS copy of the vector is left to the autotuner:
@@ -745,7 +832,14 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
                      &h.e, &h.XB, &h.ZB, &h.wbar, &h.qwbar, &h.xbo, &h.zbo, &h.t1, &h.t2,
                      &h.pt, &h.pta, &h.ptb, &h.pdt};
     for (double** p : nv) *p = h.dalloc<double>(n);
-    if (h.qkind == HPRQP_Q_KRON) h.kronT = h.dalloc<double>(n);
+    if (h.qkind == HPRQP_Q_KRON) {
+      h.kronT = h.dalloc<double>(n);
+      // split-K workspace of the tiled GEMM while its tiles are fewer than 2 per CU
+      const int tiles = ((h.ks + HQ_TB - 1) / HQ_TB) * ((h.kp + HQ_TB - 1) / HQ_TB);
+      h.kron_groups_max = tiles < 2 * h.ncu ? 4 : 1;
+      if (h.kron_groups_max > 1) h.kparts = h.dalloc<double>((size_t)h.kron_groups_max * n);
+      default_kron(h);
+    }
     double** mv[] = {&h.y, &h.ya, &h.ybar, &h.tm, &h.pe, &h.pax, &h.pdy};
     for (double** p : mv) *p = h.dalloc<double>(std::max(m, 1));
     for (double** p : nv) k_fill<<<hq_grid(n, 256), 256, 0, st>>>(n, *p, 0.0);
@@ -856,10 +950,18 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         autotune_csr(h, h.AT, h.tm, h.t1);
       }
       if (h.qkind == HPRQP_Q_CSR) autotune_csr(h, h.Q, h.t1, h.t2);
+      if (h.qkind == HPRQP_Q_KRON && opt->kron_kernel < 0) autotune_kron(h, h.t1, h.t2);
       if (h.qkind == HPRQP_Q_GRAM) {
         autotune_csr(h, h.G, h.t1, h.gtmp);
         autotune_csr(h, h.GT, h.gtmp, h.t1);
       }
+    }
+    if (h.qkind == HPRQP_Q_KRON && opt->kron_kernel >= 0) {
+      const int kk = opt->kron_kernel;
+      if (kk != 0 && kk != 1 && kk != 2 && kk != 4) fail(HPRQP_ERR_ARG, "kron_kernel must be -1, 0, 1, 2 or 4");
+      if (kk > h.kron_groups_max) fail(HPRQP_ERR_ARG, "kron_kernel: split-K groups need fewer than 2 tiles per CU");
+      h.kron_mode = kk == 0 ? 0 : 1;
+      h.kron_groups = kk == 0 ? 1 : kk;
     }
     if (opt->spmv_lanes >= 0 || opt->spmv_lanes == -2) {
       const int g = opt->spmv_lanes == -2 ? HQ_G_XLDS : opt->spmv_lanes;
@@ -1390,6 +1492,8 @@ void hprqp_default_options(hprqp_options* o) {
   o->precondition = 0;
   o->ruiz_iters = 10;
   o->spmv_lanes = -1;
+  o->method = 0;
+  o->kron_kernel = -1;
 }
 
 hprqp_status hprqp_create(const hprqp_problem* prob, const hprqp_options* opt, hipStream_t stream,
@@ -1430,6 +1534,7 @@ hprqp_status hprqp_set_options(hprqp_handle* h, const hprqp_options* opt) {
       const double la = h->opt.lambda_A, lq = h->opt.lambda_Q, s0 = h->opt.sigma0;
       const double *pa = h->opt.power_start_A, *pq = h->opt.power_start_Q;
       const int at = h->opt.spmv_autotune, pc = h->opt.precondition, ri = h->opt.ruiz_iters;
+      const int kk = h->opt.kron_kernel;
       // the captured segment depends on the options (length, timing events): capture again
       if (h->gexec) { hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
       if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
@@ -1440,7 +1545,7 @@ hprqp_status hprqp_set_options(hprqp_handle* h, const hprqp_options* opt) {
       h->opt = *opt;
       h->opt.lambda_A = la; h->opt.lambda_Q = lq; h->opt.sigma0 = s0;
       h->opt.power_start_A = pa; h->opt.power_start_Q = pq; h->opt.spmv_autotune = at;
-      h->opt.precondition = pc; h->opt.ruiz_iters = ri);
+      h->opt.precondition = pc; h->opt.ruiz_iters = ri; h->opt.kron_kernel = kk);
 }
 
 hprqp_status hprqp_scaling(hprqp_handle* h, double* D, double* E) {

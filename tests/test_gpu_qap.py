@@ -45,17 +45,20 @@ def _max_rel(a, b):
     return np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("d", [5, 16, 21, 40])
-@pytest.mark.parametrize("terms", ["ST", "S", "T"])
-def test_qap_operator_matches_oracle(d, terms):
+@pytest.mark.parametrize("kernel", [0, 1, 2, 4])
+@pytest.mark.parametrize("d", [5, 16, 21, 40, 70, 129])
+@pytest.mark.parametrize("terms", ["ST", "S", "T", ""])
+def test_qap_operator_matches_oracle(d, terms, kernel):
+    """Both product kernels (K-split; LDS-tiled with 1, 2 or 4 split-K groups),
+    sizes below, at and across the 16- and 64-wide tiles."""
     DP, Solver = _S()
     qp = qpgen.make_qap(seed=100 + d, d=d)
     if "S" not in terms:
         qp.kron_S = None
     if "T" not in terms:
         qp.kron_T = None
-    print(f"qap operator d={d} terms={terms}", flush=True)
-    s = Solver(DP(qp), lambda_A=1.0, lambda_Q=1.0, tol=0.0, max_iter=1)
+    print(f"qap operator d={d} terms={terms} kernel={kernel}", flush=True)
+    s = Solver(DP(qp), lambda_A=1.0, lambda_Q=1.0, tol=0.0, max_iter=1, kron_kernel=kernel)
     rng = np.random.default_rng(d)
     for _ in range(3):
         x = rng.standard_normal(qp.n)
@@ -65,17 +68,17 @@ def test_qap_operator_matches_oracle(d, terms):
     s.close()
 
 
-@pytest.mark.parametrize("d,check_every", [(9, 7), (16, 10)])
-def test_qap_iterates_match_oracle(d, check_every):
+@pytest.mark.parametrize("d,check_every,kernel", [(9, 7, -1), (16, 10, -1), (16, 10, 1), (67, 10, 4)])
+def test_qap_iterates_match_oracle(d, check_every, kernel):
     DP, Solver = _S()
     qp = qpgen.make_qap(seed=200 + d, d=d)
     lamA, lamQ = _lams(qp)
     K = 50
-    print(f"qap iterates d={d} T={check_every}", flush=True)
+    print(f"qap iterates d={d} T={check_every} kernel={kernel}", flush=True)
     ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=check_every, lambda_A=lamA, lambda_Q=lamQ,
                       trace_iters=K, log_cap=K)
     s = Solver(DP(qp), lambda_A=lamA, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=check_every,
-               trace_iters=K, log_cap=K)
+               trace_iters=K, log_cap=K, kron_kernel=kernel)
     rg = s.solve()
     s.close()
     np.testing.assert_array_equal(rg.check_log[:, 7], ro.check_log[:, 7])
@@ -126,3 +129,36 @@ def test_qap_d256_power_method_and_first_segment():
         print(f"  {name}: {e:.2e}", flush=True)
         assert e <= 1e-10, (name, e)
     np.testing.assert_allclose(rg.check_log[:, 2:7], ro.check_log[:, 2:7], rtol=1e-9)
+
+
+@pytest.mark.parametrize("kernel", [1, 4])
+def test_plain_kronecker_through_the_tiled_kernel(kernel):
+    """Q = B (x) C without S, T (the d = 300 workload's operator) on the tiled
+    kernel: operator and the first 30 iterates against the oracle."""
+    DP, Solver = _S()
+    qp = qpgen.make_kron(seed=6, d=33)
+    A = qp.A_scipy().toarray()
+    lamA = 1.01 * np.linalg.eigvalsh(A @ A.T).max()
+    lamQ = 1.01 * np.linalg.eigvalsh(qp.kron_B).max() * np.linalg.eigvalsh(qp.kron_C).max()
+    K = 30
+    ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_A=lamA, lambda_Q=lamQ, trace_iters=K)
+    s = Solver(DP(qp), lambda_A=lamA, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K,
+               kron_kernel=kernel)
+    x = np.random.default_rng(2).standard_normal(qp.n)
+    q = s.apply("Q", x).cpu().numpy()
+    want = oracle.apply_Q(qp, x)
+    assert np.max(np.abs(q - want)) <= 1e-13 * np.max(np.abs(want))
+    rg = s.solve()
+    s.close()
+    to, tg = split_trace(ro.trace, qp.n, qp.m), split_trace(rg.trace, qp.n, qp.m)
+    for k in range(K):
+        for name in ("y", "w", "x", "ybar", "wbar", "xbar"):
+            assert _max_rel(tg[name][k], to[name][k]) <= 1e-10, (k, name)
+
+
+def test_invalid_kron_kernel_is_rejected():
+    from paper_2507_02470_amd._native import HPRQPError
+    DP, Solver = _S()
+    qp = qpgen.make_qap(seed=1, d=6)
+    with pytest.raises(HPRQPError):
+        Solver(DP(qp), lambda_A=1.0, lambda_Q=1.0, kron_kernel=3)

@@ -157,7 +157,8 @@ def extra_qap(dims, steps, cpu, time_cap):
     for d in dims:
         qp = qpgen.make_qap(d=d)
         s = Solver(DeviceProblem(qp), power_start_A=qpgen.power_start(qp.m),
-                   power_start_Q=qpgen.power_start(qp.n), check_every=T_CHECK, tol=0.0, max_iter=T_CHECK)
+                   power_start_Q=qpgen.power_start(qp.n), check_every=T_CHECK, tol=0.0, max_iter=T_CHECK,
+                   spmv_autotune=1)
         s.solve()
         s.set_options(tol=0.0, max_iter=steps * T_CHECK, profile_kernels=1, time_limit_s=0.0)
         torch.cuda.synchronize()

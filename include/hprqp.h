@@ -147,9 +147,9 @@ typedef struct {
   int32_t kron_kernel;        /* HPRQP_Q_KRON product kernel: -1 choose (the K-split kernel for
                                  factors up to 384, else the LDS-tiled one, timed against each
                                  other when spmv_autotune = 1); 0: K-split kernel (one 16 x 16
-                                 tile per block, K over 8 waves); 1, 2, 4: LDS-tiled kernel
-                                 (64 x 64 tiles) with that many split-K groups (2 and 4 only
-                                 while the tiles are fewer than 2 per compute unit); -1      */
+                                 tile per block, K over 8 waves); 1, 2, 4, 8: LDS-tiled kernel
+                                 (64 x 64 tiles) with that many split-K groups (2 to 8 only
+                                 while the tiles are fewer than 4 per compute unit); -1      */
 } hprqp_options;
 
 typedef struct {

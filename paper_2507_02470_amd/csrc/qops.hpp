@@ -169,7 +169,8 @@ __global__ __launch_bounds__(256) void k_dgemm_tile(int M, int N, GemmOps op, in
     const int tile = w % tiles, grp = w / tiles;
     const int i0 = (tile % tiles_m) * HQ_TB, j0 = (tile / tiles_m) * HQ_TB;
     const int c0 = grp * per, c1 = min(total, c0 + per);
-    double ra[4], rb[4];
+    constexpr int NQ = HQ_TKC / 4;      // loads per thread and operand per chunk
+    double ra[NQ], rb[NQ];
     // global -> registers for chunk c (term t, first k k0); out-of-range -> 0
     auto load = [&](int c) {
       int t = 0, cc = c;      // chunk c -> (term t, chunk cc of that term); wave-uniform
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(256) void k_dgemm_tile(int M, int N, GemmOps op, in
       const int lda = op.lda[t], ldb = op.ldb[t];
       const double sg = op.sign[t];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         const int r = tid & 63, kk = (tid >> 6) + 4 * q;
         const int gi = i0 + r, gk = k0 + kk;
         const bool ok = gi < M && gk < Kt;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(256) void k_dgemm_tile(int M, int N, GemmOps op, in
       }
       if (op.transb[t]) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
           const int c = tid & 63, kk = (tid >> 6) + 4 * q;
           const int gj = j0 + c, gk = k0 + kk;
           const bool ok = gj < N && gk < Kt;
@@ -198,8 +199,8 @@ __global__ __launch_bounds__(256) void k_dgemm_tile(int M, int N, GemmOps op, in
         }
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int kk = tid & 15, c = (tid >> 4) + 16 * q;
+        for (int q = 0; q < NQ; ++q) {
+          const int kk = tid % HQ_TKC, c = tid / HQ_TKC + (256 / HQ_TKC) * q;
           const int gj = j0 + c, gk = k0 + kk;
           const bool ok = gj < N && gk < Kt;
           const double v = Bp[(size_t)(ok ? gk : 0) + (size_t)ldb * (ok ? gj : 0)];
@@ -210,13 +211,13 @@ __global__ __launch_bounds__(256) void k_dgemm_tile(int M, int N, GemmOps op, in
     };
     auto store = [&](int buf, int tb) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) As[buf][(tid >> 6) + 4 * q][tid & 63] = ra[q];
+      for (int q = 0; q < NQ; ++q) As[buf][(tid >> 6) + 4 * q][tid & 63] = ra[q];
       if (tb) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Bs[buf][(tid >> 6) + 4 * q][tid & 63] = rb[q];
+        for (int q = 0; q < NQ; ++q) Bs[buf][(tid >> 6) + 4 * q][tid & 63] = rb[q];
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Bs[buf][tid & 15][(tid >> 4) + 16 * q] = rb[q];
+        for (int q = 0; q < NQ; ++q) Bs[buf][tid % HQ_TKC][tid / HQ_TKC + (256 / HQ_TKC) * q] = rb[q];
       }
     };
     hq_dx4 d[2][2];

@@ -706,14 +706,16 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
 }
 
 // Kronecker Q: the K-split kernel for small factors (latency-bound, d ~ 300),
-// the LDS-tiled kernel above that, split-K while its 64 x 64 tiles are fewer
-// than the compute units
+// the LDS-tiled kernel above that, with split-K groups until there are 4
+// blocks per compute unit (one 4-wave block per CU leaves the MFMA pipes
+// waiting on LDS and L2; measured: d = 1024, 236 us with 4 groups against
+// 484 us with 1)
 void default_kron(hprqp_handle& h) {
   const int tiles = ((h.ks + HQ_TB - 1) / HQ_TB) * ((h.kp + HQ_TB - 1) / HQ_TB);
   if (std::max(h.ks, h.kp) <= 384) { h.kron_mode = 0; h.kron_groups = 1; return; }
   h.kron_mode = 1;
   int G = 1;
-  while (G < h.kron_groups_max && tiles * G < h.ncu) G *= 2;
+  while (G < h.kron_groups_max && tiles * G < 4 * h.ncu) G *= 2;
   h.kron_groups = G;
 }
 
@@ -834,9 +836,9 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
     for (double** p : nv) *p = h.dalloc<double>(n);
     if (h.qkind == HPRQP_Q_KRON) {
       h.kronT = h.dalloc<double>(n);
-      // split-K workspace of the tiled GEMM while its tiles are fewer than 2 per CU
+      // split-K workspace of the tiled GEMM while its tiles are fewer than 4 per CU
       const int tiles = ((h.ks + HQ_TB - 1) / HQ_TB) * ((h.kp + HQ_TB - 1) / HQ_TB);
-      h.kron_groups_max = tiles < 2 * h.ncu ? 4 : 1;
+      h.kron_groups_max = tiles < 4 * h.ncu ? 8 : 1;
       if (h.kron_groups_max > 1) h.kparts = h.dalloc<double>((size_t)h.kron_groups_max * n);
       default_kron(h);
     }
@@ -958,8 +960,9 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
     }
     if (h.qkind == HPRQP_Q_KRON && opt->kron_kernel >= 0) {
       const int kk = opt->kron_kernel;
-      if (kk != 0 && kk != 1 && kk != 2 && kk != 4) fail(HPRQP_ERR_ARG, "kron_kernel must be -1, 0, 1, 2 or 4");
-      if (kk > h.kron_groups_max) fail(HPRQP_ERR_ARG, "kron_kernel: split-K groups need fewer than 2 tiles per CU");
+      if (kk != 0 && kk != 1 && kk != 2 && kk != 4 && kk != 8)
+        fail(HPRQP_ERR_ARG, "kron_kernel must be -1, 0, 1, 2, 4 or 8");
+      if (kk > h.kron_groups_max) fail(HPRQP_ERR_ARG, "kron_kernel: split-K groups need fewer than 4 tiles per CU");
       h.kron_mode = kk == 0 ? 0 : 1;
       h.kron_groups = kk == 0 ? 1 : kk;
     }

@@ -45,11 +45,11 @@ def _max_rel(a, b):
     return np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 4])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 4, 8])
 @pytest.mark.parametrize("d", [5, 16, 21, 40, 70, 129])
 @pytest.mark.parametrize("terms", ["ST", "S", "T", ""])
 def test_qap_operator_matches_oracle(d, terms, kernel):
-    """Both product kernels (K-split; LDS-tiled with 1, 2 or 4 split-K groups),
+    """Both product kernels (K-split; LDS-tiled with 1, 2, 4 or 8 split-K groups),
     sizes below, at and across the 16- and 64-wide tiles."""
     DP, Solver = _S()
     qp = qpgen.make_qap(seed=100 + d, d=d)

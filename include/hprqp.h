@@ -150,6 +150,12 @@ typedef struct {
                                  tile per block, K over 8 waves); 1, 2, 4, 8: LDS-tiled kernel
                                  (64 x 64 tiles) with that many split-K groups (2 to 8 only
                                  while the tiles are fewer than 4 per compute unit); -1      */
+  int32_t small_path;         /* method 0 with explicit (CSR) or zero Q: run each check segment
+                                 as one workgroup (the four products as phases separated by
+                                 barriers, same fused epilogues) instead of four launches per
+                                 iteration.  -1: when n <= 4096 and m <= 4096; 0: never; 1:
+                                 always (HPRQP_ERR_UNSUPPORTED for other Q kinds).  Segments
+                                 timed by profile_kernels use the four-launch path; -1       */
 } hprqp_options;
 
 typedef struct {

@@ -39,7 +39,8 @@ class hprqp_options(C.Structure):
                 ("trace_iters", C.c_int32), ("trace_host", C.POINTER(C.c_double)),
                 ("log_cap", C.c_int32), ("check_log_host", C.POINTER(C.c_double)),
                 ("profile_kernels", C.c_int32), ("precondition", C.c_int32), ("ruiz_iters", C.c_int32),
-                ("spmv_lanes", C.c_int32), ("method", C.c_int32), ("kron_kernel", C.c_int32)]
+                ("spmv_lanes", C.c_int32), ("method", C.c_int32), ("kron_kernel", C.c_int32),
+                ("small_path", C.c_int32)]
 
 
 class hprqp_info(C.Structure):

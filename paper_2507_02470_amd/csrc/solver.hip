@@ -76,6 +76,9 @@ static constexpr unsigned long long kMaxMask =
     (1ull << (SL_RA + 0)) | (1ull << (SL_RA + 1)) | (1ull << (SL_RQ + 0)) | (1ull << (SL_RQ + 1)) |
     (1ull << (SL_RQ + 2)) | (1ull << (SL_NRM + 1)) | (1ull << (SL_NRM + 3));
 
+#include "small.hpp"   // uses the reduction slots above
+
+
 __global__ __launch_bounds__(256) void k_final_reduce(const double* __restrict__ partials, const int* __restrict__ counts,
                                                       int slot0, unsigned long long maxmask, double* __restrict__ out) {
   const int slot = slot0 + blockIdx.x;
@@ -236,6 +239,7 @@ struct hprqp_handle {
   int kp = 0, ks = 0;
   const double *kB = nullptr, *kC = nullptr;
   const double *kS = nullptr, *kT = nullptr;   // QAP relaxation: Q = B (x) C - I (x) S - T (x) I
+  int small_G = 0;            // > 0: segments run as one workgroup (k_small_segment<small_G>)
   int kron_mode = 0;          // 0: k_dgemm16 (K split over waves), 1: LDS-tiled k_dgemm_tile
   int kron_groups = 1;        // split-K groups of the tiled kernel
   int kron_groups_max = 1;    // capacity of kparts (in n-vectors)
@@ -548,7 +552,35 @@ void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
     q_apply(h, h.e, EpiTheta3{h.e}, j, red_seq(h, SL_TH + 4, 1));
 }
 
+// the whole segment in one workgroup (small explicit-Q problems)
+void enqueue_small_segment(hprqp_handle& h, int Tseg) {
+  SmallArgs a{};
+  a.A = SmallMat{h.m, h.A.rp, h.A.ci, h.A.v};
+  a.AT = SmallMat{h.n, h.AT.rp, h.AT.ci, h.AT.v};
+  a.Q = h.qkind == HPRQP_Q_CSR ? SmallMat{h.n, h.Q.rp, h.Q.ci, h.Q.v} : SmallMat{h.n, nullptr, nullptr, nullptr};
+  a.n = h.n; a.m = h.m;
+  a.l = h.l; a.u = h.u; a.c = h.c; a.L = h.L; a.U = h.U; a.iEs = h.iEs; a.iDs = h.iDs;
+  a.y = h.y; a.ya = h.ya; a.ybar = h.ybar; a.w = h.w; a.wa = h.wa; a.x = h.x; a.xa = h.xa;
+  a.ATy = h.ATy; a.ATya = h.ATya; a.Qw = h.Qw; a.Qwa = h.Qwa; a.xh = h.xh; a.v = h.v; a.q1 = h.q1;
+  a.d = h.d; a.g = h.g; a.e = h.e; a.XB = h.XB; a.ZB = h.ZB; a.wbar = h.wbar; a.qwbar = h.qwbar;
+  a.xbo = h.xbo; a.zbo = h.zbo; a.l1 = h.l1;
+  a.partials = h.partials; a.counts = h.counts; a.prm = h.dprm;
+  switch (h.small_G) {
+    case 1: k_small_segment<1><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
+    case 2: k_small_segment<2><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
+    case 4: k_small_segment<4><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
+    case 8: k_small_segment<8><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
+    default: k_small_segment<16><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
+  }
+  final_reduce(h, 0, SL_ITER_END);
+  HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
+}
+
 void enqueue_segment(hprqp_handle& h, int Tseg, bool prof) {
+  if (h.small_G > 0 && !prof) {
+    enqueue_small_segment(h, Tseg);
+    return;
+  }
   for (int j = 0; j < Tseg; ++j) enqueue_iter(h, j, Tseg, false, prof);
   final_reduce(h, 0, SL_ITER_END);
   HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
@@ -956,6 +988,19 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       if (h.qkind == HPRQP_Q_GRAM) {
         autotune_csr(h, h.G, h.t1, h.gtmp);
         autotune_csr(h, h.GT, h.gtmp, h.t1);
+      }
+    }
+    // one-workgroup segments for small explicit-Q problems (a launch per product
+    // would cost more than the product)
+    {
+      const bool ok = (h.qkind == HPRQP_Q_CSR || h.qkind == HPRQP_Q_ZERO);
+      if (opt->small_path < -1 || opt->small_path > 1) fail(HPRQP_ERR_ARG, "small_path must be -1, 0 or 1");
+      if (opt->small_path == 1 && !ok) fail(HPRQP_ERR_UNSUPPORTED, "small_path needs an explicit or zero Q");
+      const bool on = ok && (opt->small_path == 1 || (opt->small_path == -1 && n <= 4096 && m <= 4096));
+      if (on) {
+        int G = 1;
+        while (G < 16 && (long long)std::max(n, m) * G * 2 <= HQ_SMALL_BS) G *= 2;
+        h.small_G = G;
       }
     }
     if (h.qkind == HPRQP_Q_KRON && opt->kron_kernel >= 0) {
@@ -1497,6 +1542,7 @@ void hprqp_default_options(hprqp_options* o) {
   o->spmv_lanes = -1;
   o->method = 0;
   o->kron_kernel = -1;
+  o->small_path = -1;
 }
 
 hprqp_status hprqp_create(const hprqp_problem* prob, const hprqp_options* opt, hipStream_t stream,
@@ -1537,7 +1583,7 @@ hprqp_status hprqp_set_options(hprqp_handle* h, const hprqp_options* opt) {
       const double la = h->opt.lambda_A, lq = h->opt.lambda_Q, s0 = h->opt.sigma0;
       const double *pa = h->opt.power_start_A, *pq = h->opt.power_start_Q;
       const int at = h->opt.spmv_autotune, pc = h->opt.precondition, ri = h->opt.ruiz_iters;
-      const int kk = h->opt.kron_kernel;
+      const int kk = h->opt.kron_kernel, sp = h->opt.small_path;
       // the captured segment depends on the options (length, timing events): capture again
       if (h->gexec) { hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
       if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
@@ -1548,7 +1594,7 @@ hprqp_status hprqp_set_options(hprqp_handle* h, const hprqp_options* opt) {
       h->opt = *opt;
       h->opt.lambda_A = la; h->opt.lambda_Q = lq; h->opt.sigma0 = s0;
       h->opt.power_start_A = pa; h->opt.power_start_Q = pq; h->opt.spmv_autotune = at;
-      h->opt.precondition = pc; h->opt.ruiz_iters = ri; h->opt.kron_kernel = kk);
+      h->opt.precondition = pc; h->opt.ruiz_iters = ri; h->opt.kron_kernel = kk; h->opt.small_path = sp);
 }
 
 hprqp_status hprqp_scaling(hprqp_handle* h, double* D, double* E) {

@@ -39,7 +39,7 @@ def test_default_options_without_gpu():
     assert (o.alpha1, o.alpha2, o.alpha3) == (0.2, 0.8, 0.5)
     assert o.enable_restart == 1 and o.enable_sigma_update == 1
     assert o.precondition == 0 and o.ruiz_iters == 10 and o.spmv_lanes == -1 and o.method == 0
-    assert o.kron_kernel == -1
+    assert o.kron_kernel == -1 and o.small_path == -1
 
 
 def _struct_fields(header, name):

@@ -7,15 +7,18 @@
 // 1024-thread workgroup separated by barriers: each phase runs the same
 // fused epilogue as the multi-block kernels (so the arithmetic is that of
 // the four-launch path), rows are taken by groups of G lanes (butterfly sum
-// in a fixed order), the vectors stay in global memory (they fit the CU's
-// caches), and the reductions of a phase go through the block reduction
-// into the same slots, with one partial per slot.  Explicit Q (CSR) or
-// Q = 0 only.
+// in a fixed order), and the reductions of a phase go through the block
+// reduction into the same slots, with one partial per slot.  When the
+// matrices and every vector of the iteration fit (dynamic LDS, up to
+// HQ_SMALL_LDS bytes), they are copied into LDS at the start of the segment
+// and the written vectors back at its end, so every gather is an LDS access;
+// otherwise they stay in global memory.  Explicit Q (CSR) or Q = 0 only.
 #pragma once
 #include "common.hpp"
 #include "epilogues.hpp"
 
 #define HQ_SMALL_BS 1024
+#define HQ_SMALL_LDS (150 * 1024)
 
 struct SmallMat {
   int rows;
@@ -24,16 +27,30 @@ struct SmallMat {
   const double* v;
 };
 
+// vectors of the iteration, by index
+enum : int {
+  SV_L, SV_U, SV_C, SV_LB, SV_UB, SV_IE, SV_ID,                 // read only
+  SV_YA, SV_WA, SV_XA, SV_ATYA, SV_QWA,                          // read only during a segment
+  SV_Y, SV_YBAR, SV_W, SV_X, SV_ATY, SV_QW, SV_XH, SV_V, SV_Q1, SV_D, SV_G, SV_E, SV_XB, SV_ZB, SV_WBAR,
+  SV_QWBAR, SV_XBO, SV_ZBO,                                      // written
+  SV_COUNT,
+  SV_FIRST_WRITTEN = SV_Y
+};
+
 struct SmallArgs {
   SmallMat A, AT, Q;
   int n, m;
-  const double *l, *u, *c, *L, *U, *iEs, *iDs;
-  double *y, *ya, *ybar, *w, *wa, *x, *xa, *ATy, *ATya, *Qw, *Qwa, *xh, *v, *q1, *d, *g, *e, *XB, *ZB, *wbar,
-      *qwbar, *xbo, *zbo;
+  double* vec[SV_COUNT];      // global arrays (nullptr: absent)
+  int vlen[SV_COUNT];
   double l1;
   double* partials;
   int* counts;
   const DevParams* prm;
+  // LDS staging (lds_bytes = 0: none): byte offsets of the vectors and of the
+  // matrices' row pointers, columns and values
+  int lds_bytes;
+  int voff[SV_COUNT];
+  int moff[3][3];             // [A, AT, Q][rp, ci, v]
 };
 
 // q_i = (M x)_i for every row, then epi(i, q_i); block reduction of the
@@ -73,44 +90,90 @@ __device__ __forceinline__ RedOut small_red(const SmallArgs& a, int s0, int s1 =
   return r;
 }
 
+template <class T>
+__device__ __forceinline__ void small_copy(T* __restrict__ dst, const T* __restrict__ src, int count) {
+  for (int i = threadIdx.x; i < count; i += HQ_SMALL_BS) dst[i] = src[i];
+}
+
 template <int G>
 __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int Tseg) {
+  extern __shared__ __align__(16) unsigned char small_lds[];
+  // the arrays the phases use: LDS copies when staged, else the global ones
+  double* V[SV_COUNT];
+  SmallMat mats[3] = {a.A, a.AT, a.Q};
+  // (loops over the arrays are unrolled so that V and mats stay in registers)
+#pragma unroll
+  for (int s = 0; s < SV_COUNT; ++s) V[s] = a.vec[s];
+  if (a.lds_bytes > 0) {
+#pragma unroll
+    for (int s = 0; s < SV_COUNT; ++s)
+      if (a.vec[s]) {
+        double* p = (double*)(small_lds + a.voff[s]);
+        small_copy(p, a.vec[s], a.vlen[s]);
+        V[s] = p;
+      }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (mats[q].rp) {
+        SmallMat& M = mats[q];
+        int* rp = (int*)(small_lds + a.moff[q][0]);
+        int* ci = (int*)(small_lds + a.moff[q][1]);
+        double* v = (double*)(small_lds + a.moff[q][2]);
+        small_copy(rp, M.rp, M.rows + 1);
+        __syncthreads();   // the row pointers give the number of nonzeros
+        const int nnz = rp[M.rows];
+        small_copy(ci, M.ci, nnz);
+        small_copy(v, M.v, nnz);
+        M.rp = rp; M.ci = ci; M.v = v;
+      }
+    __syncthreads();
+  }
+  // the segment's scalars (sigma, lambda's, t0) are read by every phase: keep a copy in LDS
+  __shared__ DevParams sprm;
+  if (threadIdx.x == 0) sprm = *a.prm;
+  __syncthreads();
+  const DevParams* prm = &sprm;
+  const SmallMat& A = mats[0];
+  const SmallMat& AT = mats[1];
+  const SmallMat& Q = mats[2];
   const RedOut none = small_red(a, -1);
-  SmallMat zero_n{a.n, nullptr, nullptr, nullptr};
+  const SmallMat zero_n{a.n, nullptr, nullptr, nullptr};
   for (int j = 0; j < Tseg; ++j) {
     const bool check = (j == Tseg - 1);
     const int rgroup = check ? SL_RC : (j == 0 ? SL_RF : -1);
     const bool want_r = rgroup >= 0;
     const bool xb_next = j >= Tseg - 2;
     // a3: q1 = Q xhat, v
-    small_phase<G>(a.Q, a.xh, EpiQ1{a.xh, a.Qw, a.v, a.q1, 0.0}, a.prm, j, none);
+    small_phase<G>(Q, V[SV_XH], EpiQ1{V[SV_XH], V[SV_QW], V[SV_V], V[SV_Q1], 0.0}, prm, j, none);
     if (a.m > 0) {
       // a4: A v, ybar, y+
-      small_phase<G>(a.A, a.v, EpiY{a.l, a.u, a.ya, a.y, a.ybar, want_r, check, 0.0, 0.0}, a.prm, j,
-                     small_red(a, want_r ? rgroup : -1, check ? SL_TH : -1));
+      small_phase<G>(A, V[SV_V], EpiY{V[SV_L], V[SV_U], V[SV_YA], V[SV_Y], V[SV_YBAR], want_r, check, 0.0, 0.0},
+                     prm, j, small_red(a, want_r ? rgroup : -1, check ? SL_TH : -1));
       // a5: A^T ybar, d, A^T y+
-      small_phase<G>(a.AT, a.ybar, EpiAT{a.ATy, a.ATya, a.d, a.g, a.e, check, 0.0}, a.prm, j, none);
+      small_phase<G>(AT, V[SV_YBAR], EpiAT{V[SV_ATY], V[SV_ATYA], V[SV_D], V[SV_G], V[SV_E], check, 0.0}, prm, j,
+                     none);
     }
     if (check) {
       if (a.m > 0) {
         RedOut r = none;
         for (int s = 0; s < 4; ++s) r.slot[s] = (int8_t)(SL_RA + s);
         r.active = 1;
-        small_phase<G>(a.A, a.XB, EpiResA{a.l, a.u, a.ybar, a.iEs}, a.prm, j, r);
+        small_phase<G>(A, V[SV_XB], EpiResA{V[SV_L], V[SV_U], V[SV_YBAR], V[SV_IE]}, prm, j, r);
       }
       RedOut r = none;
       for (int s = 0; s < 7; ++s) r.slot[s] = (int8_t)(SL_RQ + s);
       r.active = 1;
-      small_phase<G>(a.Q, a.XB,
-                     EpiResQ{a.XB, a.ZB, a.m > 0 ? a.g : nullptr, a.c, a.L, a.U, a.xbo, a.zbo, a.iDs, a.l1}, a.prm, j,
-                     r);
+      small_phase<G>(Q, V[SV_XB],
+                     EpiResQ{V[SV_XB], V[SV_ZB], a.m > 0 ? V[SV_G] : nullptr, V[SV_C], V[SV_LB], V[SV_UB], V[SV_XBO],
+                             V[SV_ZBO], V[SV_ID], a.l1},
+                     prm, j, r);
     }
     // a6: Q d, wbar, Halpern, next z/x step
     EpiQ2 e6;
-    e6.xh = a.xh; e6.w = a.w; e6.Qw = a.Qw; e6.XB = a.XB; e6.ZB = a.ZB;
-    e6.q1 = a.q1; e6.d = a.d; e6.wa = a.wa; e6.Qwa = a.Qwa; e6.xa = a.xa; e6.ATy = a.ATy;
-    e6.c = a.c; e6.L = a.L; e6.U = a.U; e6.e = a.e;
-    e6.wbar = a.wbar; e6.qwbar = a.qwbar; e6.x = a.x; e6.xbar_out = a.xbo;
+    e6.xh = V[SV_XH]; e6.w = V[SV_W]; e6.Qw = V[SV_QW]; e6.XB = V[SV_XB]; e6.ZB = V[SV_ZB];
+    e6.q1 = V[SV_Q1]; e6.d = V[SV_D]; e6.wa = V[SV_WA]; e6.Qwa = V[SV_QWA]; e6.xa = V[SV_XA]; e6.ATy = V[SV_ATY];
+    e6.c = V[SV_C]; e6.L = V[SV_LB]; e6.U = V[SV_UB]; e6.e = V[SV_E];
+    e6.wbar = V[SV_WBAR]; e6.qwbar = V[SV_QWBAR]; e6.x = V[SV_X]; e6.xbar_out = V[SV_XBO];
     e6.want_r = want_r; e6.check = check; e6.xb_next = xb_next; e6.trace = 0;
     e6.l1 = a.l1;
     RedOut r6 = none;
@@ -119,8 +182,12 @@ __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int 
     if (check)
       for (int s = 0; s < 3; ++s) r6.slot[6 + s] = (int8_t)(SL_TH + 1 + s);
     r6.active = want_r || check;
-    small_phase<G>(a.m > 0 ? a.Q : zero_n, a.d, e6, a.prm, j, r6);
-    if (check && a.m > 0 && a.Q.rp)
-      small_phase<G>(a.Q, a.e, EpiTheta3{a.e}, a.prm, j, small_red(a, SL_TH + 4));
+    small_phase<G>(a.m > 0 ? Q : zero_n, V[SV_D], e6, prm, j, r6);
+    if (check && a.m > 0 && Q.rp) small_phase<G>(Q, V[SV_E], EpiTheta3{V[SV_E]}, prm, j, small_red(a, SL_TH + 4));
+  }
+  if (a.lds_bytes > 0) {
+#pragma unroll
+    for (int s = SV_FIRST_WRITTEN; s < SV_COUNT; ++s)
+      if (a.vec[s]) small_copy(a.vec[s], V[s], a.vlen[s]);
   }
 }

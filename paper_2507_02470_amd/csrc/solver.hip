@@ -553,24 +553,61 @@ void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
 }
 
 // the whole segment in one workgroup (small explicit-Q problems)
-void enqueue_small_segment(hprqp_handle& h, int Tseg) {
+SmallArgs small_args(hprqp_handle& h) {
   SmallArgs a{};
   a.A = SmallMat{h.m, h.A.rp, h.A.ci, h.A.v};
   a.AT = SmallMat{h.n, h.AT.rp, h.AT.ci, h.AT.v};
   a.Q = h.qkind == HPRQP_Q_CSR ? SmallMat{h.n, h.Q.rp, h.Q.ci, h.Q.v} : SmallMat{h.n, nullptr, nullptr, nullptr};
+  if (h.m == 0) { a.A = SmallMat{0, nullptr, nullptr, nullptr}; a.AT = SmallMat{h.n, nullptr, nullptr, nullptr}; }
   a.n = h.n; a.m = h.m;
-  a.l = h.l; a.u = h.u; a.c = h.c; a.L = h.L; a.U = h.U; a.iEs = h.iEs; a.iDs = h.iDs;
-  a.y = h.y; a.ya = h.ya; a.ybar = h.ybar; a.w = h.w; a.wa = h.wa; a.x = h.x; a.xa = h.xa;
-  a.ATy = h.ATy; a.ATya = h.ATya; a.Qw = h.Qw; a.Qwa = h.Qwa; a.xh = h.xh; a.v = h.v; a.q1 = h.q1;
-  a.d = h.d; a.g = h.g; a.e = h.e; a.XB = h.XB; a.ZB = h.ZB; a.wbar = h.wbar; a.qwbar = h.qwbar;
-  a.xbo = h.xbo; a.zbo = h.zbo; a.l1 = h.l1;
+  const int n = h.n, m = h.m;
+  auto set = [&](int s, const double* p, int len) { a.vec[s] = const_cast<double*>(p); a.vlen[s] = p ? len : 0; };
+  set(SV_L, h.l, m); set(SV_U, h.u, m); set(SV_C, h.c, n); set(SV_LB, h.L, n); set(SV_UB, h.U, n);
+  set(SV_IE, h.iEs, m); set(SV_ID, h.iDs, n);
+  set(SV_YA, h.ya, m); set(SV_WA, h.wa, n); set(SV_XA, h.xa, n); set(SV_ATYA, h.ATya, n); set(SV_QWA, h.Qwa, n);
+  set(SV_Y, h.y, m); set(SV_YBAR, h.ybar, m); set(SV_W, h.w, n); set(SV_X, h.x, n); set(SV_ATY, h.ATy, n);
+  set(SV_QW, h.Qw, n); set(SV_XH, h.xh, n); set(SV_V, h.v, n); set(SV_Q1, h.q1, n); set(SV_D, h.d, n);
+  set(SV_G, h.g, n); set(SV_E, h.e, n); set(SV_XB, h.XB, n); set(SV_ZB, h.ZB, n); set(SV_WBAR, h.wbar, n);
+  set(SV_QWBAR, h.qwbar, n); set(SV_XBO, h.xbo, n); set(SV_ZBO, h.zbo, n);
+  a.l1 = h.l1;
   a.partials = h.partials; a.counts = h.counts; a.prm = h.dprm;
+  // LDS layout: every vector, then row pointers, columns and values of A, A^T, Q
+  long long off = 0;
+  auto take = [&](long long bytes) { const long long o = off; off += (bytes + 15) / 16 * 16; return (int)o; };
+  for (int s = 0; s < SV_COUNT; ++s) a.voff[s] = a.vec[s] ? take(8ll * a.vlen[s]) : 0;
+  const Mat* ms[3] = {&h.A, &h.AT, &h.Q};
+  const SmallMat sm[3] = {a.A, a.AT, a.Q};
+  for (int q = 0; q < 3; ++q) {
+    if (!sm[q].rp) { a.moff[q][0] = a.moff[q][1] = a.moff[q][2] = 0; continue; }
+    a.moff[q][0] = take(4ll * (sm[q].rows + 1));
+    a.moff[q][1] = take(4ll * ms[q]->nnz);
+    a.moff[q][2] = take(8ll * ms[q]->nnz);
+  }
+  a.lds_bytes = off <= HQ_SMALL_LDS ? (int)off : 0;
+  return a;
+}
+
+template <int G>
+void launch_small(hprqp_handle& h, const SmallArgs& a, int Tseg) {
+  k_small_segment<G><<<1, HQ_SMALL_BS, a.lds_bytes, h.st>>>(a, Tseg);
+}
+
+// dynamic LDS above 64 KB must be enabled per kernel (at create, outside any capture)
+void small_attrs() {
+  const void* ks[] = {(const void*)k_small_segment<1>, (const void*)k_small_segment<2>,
+                      (const void*)k_small_segment<4>, (const void*)k_small_segment<8>,
+                      (const void*)k_small_segment<16>};
+  for (const void* k : ks) HQC(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, HQ_SMALL_LDS));
+}
+
+void enqueue_small_segment(hprqp_handle& h, int Tseg) {
+  const SmallArgs a = small_args(h);
   switch (h.small_G) {
-    case 1: k_small_segment<1><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
-    case 2: k_small_segment<2><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
-    case 4: k_small_segment<4><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
-    case 8: k_small_segment<8><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
-    default: k_small_segment<16><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg); break;
+    case 1: launch_small<1>(h, a, Tseg); break;
+    case 2: launch_small<2>(h, a, Tseg); break;
+    case 4: launch_small<4>(h, a, Tseg); break;
+    case 8: launch_small<8>(h, a, Tseg); break;
+    default: launch_small<16>(h, a, Tseg); break;
   }
   final_reduce(h, 0, SL_ITER_END);
   HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
@@ -996,11 +1033,13 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       const bool ok = (h.qkind == HPRQP_Q_CSR || h.qkind == HPRQP_Q_ZERO);
       if (opt->small_path < -1 || opt->small_path > 1) fail(HPRQP_ERR_ARG, "small_path must be -1, 0 or 1");
       if (opt->small_path == 1 && !ok) fail(HPRQP_ERR_UNSUPPORTED, "small_path needs an explicit or zero Q");
-      const bool on = ok && (opt->small_path == 1 || (opt->small_path == -1 && n <= 4096 && m <= 4096));
+      // automatic: when the matrices and the vectors fit the workgroup's LDS
+      const bool on = ok && (opt->small_path == 1 || (opt->small_path == -1 && small_args(h).lds_bytes > 0));
       if (on) {
         int G = 1;
         while (G < 16 && (long long)std::max(n, m) * G * 2 <= HQ_SMALL_BS) G *= 2;
         h.small_G = G;
+        small_attrs();
       }
     }
     if (h.qkind == HPRQP_Q_KRON && opt->kron_kernel >= 0) {

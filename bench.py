@@ -61,7 +61,8 @@ def kernel_bytes(qp) -> dict:
 
 # sources of the single-instance solver's kernels and launches (the batched
 # solver and the MLP do not enter the dominant kernel)
-SOLVER_SOURCES = ("common.hpp", "spmv.hpp", "epilogues.hpp", "epilogues_primal.hpp", "qops.hpp", "solver.hip")
+SOLVER_SOURCES = ("common.hpp", "spmv.hpp", "epilogues.hpp", "epilogues_primal.hpp", "qops.hpp", "small.hpp",
+                  "solver.hip")
 
 
 def src_hash() -> str:
@@ -87,9 +88,14 @@ def read_traffic(kernel: str, workload: str):
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(qp, lam_A, lam_Q, sigma0, iters):
-    """The oracle as it stands, single thread, on the first `iters` iterations."""
+def cpu_baseline(qp, lam_A, lam_Q, sigma0, iters, budget_s=20.0):
+    """The oracle as it stands, single thread, on the first `iters` iterations
+    (fewer when two iterations show that `iters` would exceed `budget_s`)."""
     import oracle
+    t0 = time.perf_counter()
+    oracle.solve(qp, tol=0.0, max_iter=2, check_every=T_CHECK, lambda_A=lam_A, lambda_Q=lam_Q, sigma0=sigma0)
+    per_it = (time.perf_counter() - t0) / 2
+    iters = int(max(2, min(iters, budget_s / max(per_it, 1e-9))))
     t0 = time.perf_counter()
     r = oracle.solve(qp, tol=0.0, max_iter=iters, check_every=T_CHECK, lambda_A=lam_A, lambda_Q=lam_Q,
                      sigma0=sigma0)
@@ -447,7 +453,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="random_large", choices=["random_large", "small_ccqp", "kron"])
+    ap.add_argument("--workload", default="random_large",
+                    choices=["random_large", "small_ccqp", "kron", "qap", "batch"])
+    ap.add_argument("--qap-d", type=int, default=512, help="d of --workload qap (n = d^2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tol-solve", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
@@ -483,6 +491,18 @@ def main():
     elif args.workload == "kron":
         qp = qpgen.make_kron()
         wl = dict(workload="kron_assignment", n=qp.n, m=qp.m, d=300, seed=1002)
+    elif args.workload == "qap":
+        qp = qpgen.make_qap(d=args.qap_d)
+        wl = dict(workload="qap_relaxation", n=qp.n, m=qp.m, d=args.qap_d, seed=1007)
+    elif args.workload == "batch":
+        # the batched solver alone (what the batch leg of the extras reports)
+        b = extra_batch(args.batch_count, not args.no_cpu_baseline)
+        print(json.dumps(dict(metric="instances/s (batched HPR-QP to 1e-8)", value=b["instances_per_s"],
+                              unit="instances/s", n_gpus=1, higher_is_better=True, dtype="f64",
+                              data="synthetic (seeded portfolio generator)", config=dict(workload="portfolio_batch",
+                              instances=args.batch_count), roofline=b["roofline"], cpu_baseline=b.get("cpu_oracle"),
+                              detail=b)))
+        return
     else:
         qp = qpgen.make_small_ccqp()
         wl = dict(workload="small_ccqp", n=qp.n, m=qp.m, seed=1000)
@@ -514,6 +534,17 @@ def main():
     # roofline of the dominant kernel (largest share of timed kernel time)
     by = kernel_bytes(qp) if qp.qkind == "csr" else None
     roofline = None
+    if qp.qkind == "kron":
+        # Kronecker / QAP-relaxation Q product on FP64 MFMA: 2 d^3 flop per GEMM term
+        # (C X, then C X B^T and, for the QAP relaxation, X T^T and S X)
+        d = qp.kron_C.shape[0]
+        flop = (8.0 if qp.kron_S is not None else 4.0) * d ** 3
+        dom = max(("q_xhat", "q_d_halpern"), key=lambda k: ks["avg_ms"][k])
+        avg_s = ks["avg_ms"][dom] * 1e-3
+        roofline = dict(bound="mfma", kernel=dom, achieved=round(flop / avg_s / 1e12, 3), peak=FP64_PEAK_TFLOPS,
+                        unit="TFLOP/s", frac=round(flop / avg_s / 1e12 / FP64_PEAK_TFLOPS, 4), traffic=None,
+                        flop_per_launch=flop, avg_launch_us=round(avg_s * 1e6, 2),
+                        launches_timed=ks["launches"][dom])
     if by is not None:
         dom = max(ks["avg_ms"], key=lambda k: ks["avg_ms"][k])
         avg_s = ks["avg_ms"][dom] * 1e-3

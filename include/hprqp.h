@@ -127,8 +127,12 @@ typedef struct {
   int32_t spmv_lanes;         /* -1: SpMV kernel per matrix from its row lengths (and the
                                  autotuner); 0: the CSR-stream kernel; -2: the CSR-stream
                                  kernel gathering from an LDS copy of the input vector
-                                 (matrices with at most 16384 columns, else 0); 1, 2, 4,
-                                 ..., 256: that many lanes per row, for every matrix; -1  */
+                                 (matrices with at most 14336 columns, else 0); -3: the
+                                 panel-ordered product (columns cut into 4 panels walked in
+                                 the same order by a persistent grid; an extra copy of the
+                                 matrix; rows of at most 4096 nonzeros, else the default);
+                                 1, 2, 4, ..., 256: that many lanes per row, for every
+                                 matrix; -1                                               */
   int32_t method;             /* 0: HPR-QP (Algorithm 4 on the restricted Wolfe dual).
                                  1, 2: HPR applied to the primal reformulations of
                                  Appendix A, the baselines of Table 1: 1 = Algorithm 6 on

@@ -17,6 +17,7 @@
 #include "qops.hpp"
 #include "spmv.hpp"
 #include "precond.hpp"
+#include "panel.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -226,6 +227,8 @@ struct Mat {
   long long nnz = 0;
   int G = 4;
   int maxlen = -1;    // longest row (-1: not measured)
+  PanelMat pm;        // panel-ordered copy (pm.pp == nullptr: not built)
+  int G_np = 0;       // kernel used in place of the panel-ordered one under a heavy epilogue
 };
 
 #define HQ_PROF_ITERS 64
@@ -340,6 +343,8 @@ inline RedOut red_seq(hprqp_handle& h, int slot0, int nr) {
 // Lanes-per-row code of the stream kernel that gathers from an LDS copy of the
 // input vector (matrices with at most HQ_XLDS_MAX columns).
 #define HQ_G_XLDS (-1)
+// Lanes-per-row code of the panel-ordered product (Mat::pm built).
+#define HQ_G_PANEL (-3)
 
 template <class Epi>
 void launch_csr_xlds(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
@@ -362,6 +367,11 @@ void launch_csr_xlds(hprqp_handle& h, const Mat& M, const double* x, const Epi& 
 template <class Epi>
 void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
   if (M.G == HQ_G_XLDS) { launch_csr_xlds(h, M, x, epi, j, red); return; }
+  if (M.G == HQ_G_PANEL) {
+    const int nblk = (M.rows + HQ_BLOCK - 1) / HQ_BLOCK;
+    k_csr_panel<Epi><<<(nblk + HQ_PANEL_BPB - 1) / HQ_PANEL_BPB, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red);
+    return;
+  }
   // stream kernel: HQ_BLOCK rows per block; row-split kernel: HQ_BLOCK / G rows per block
   const int grid = M.G == 0 ? hq_grid(M.rows, HQ_BLOCK) : hq_grid(M.rows, HQ_BLOCK / M.G);
   hipStream_t st = h.st;
@@ -427,15 +437,23 @@ void kron_tiled(hprqp_handle& h, const double* x, const Epi& epi, int j, const R
   launch_tile(h, s, p, g2, epi, j, red);
 }
 
-// out-of-place Q product with a fused epilogue: epi(i, (Q x)_i)
+// out-of-place Q product with a fused epilogue: epi(i, (Q x)_i).  heavy: the
+// epilogue streams many vectors; the panel-ordered product, whose epilogues all
+// run at the end of the launch, then gives way to the best other kernel
 template <class Epi>
-void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedOut& red) {
+void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedOut& red, bool heavy = false) {
   switch (h.qkind) {
     case HPRQP_Q_ZERO:
       launch_elem(h, h.n, nullptr, epi, j, red);
       break;
     case HPRQP_Q_CSR:
-      launch_csr(h, h.Q, x, epi, j, red);
+      if (heavy && h.Q.G == HQ_G_PANEL) {
+        Mat M = h.Q;
+        M.G = h.Q.G_np;
+        launch_csr(h, M, x, epi, j, red);
+      } else {
+        launch_csr(h, h.Q, x, epi, j, red);
+      }
       break;
     case HPRQP_Q_KRON: {
       // Q vec(X) = vec(C X B^T): T = C X, then Y = T B^T with the epilogue
@@ -545,7 +563,7 @@ void enqueue_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof) {
     for (int s = 0; s < 3; ++s) r6.slot[6 + s] = (int8_t)(SL_TH + 1 + s);
   r6.active = want_r || check;
   mark(3, 0);
-  if (h.m > 0) q_apply(h, h.d, e6, j, r6);
+  if (h.m > 0) q_apply(h, h.d, e6, j, r6, true);
   else launch_elem(h, h.n, nullptr, e6, j, r6);  // Q A^T(ybar - y) = 0 without constraints
   mark(3, 1);
   if (check && h.m > 0 && h.qkind != HPRQP_Q_ZERO)
@@ -743,21 +761,56 @@ double power_method(hprqp_handle& h, int which, const double* start, int maxit, 
   return lam;
 }
 
+// Panel-ordered copy of M (panel.hpp); false when a chunk would need more than
+// 16-bit local offsets or the matrix is too small to gain from it
+bool build_panel(hprqp_handle& h, Mat& M, bool any_size = false) {
+  if (M.pm.pp) return true;
+  if (M.rows == 0 || M.nnz == 0 || M.cols < HQ_PANELS) return false;
+  if (!any_size && M.cols < 262144) return false;   // a vector of 2 MB or less stays in the L2 anyway
+  const int nblk = (M.rows + HQ_BLOCK - 1) / HQ_BLOCK;
+  const long long nch = (long long)nblk * HQ_PANELS;
+  int *cnt = nullptr, *size = nullptr;
+  HQC(hipMalloc(&cnt, sizeof(int) * (size_t)M.rows * HQ_PANELS));
+  HQC(hipMalloc(&size, sizeof(int) * (size_t)nch));
+  unsigned short* lrp = h.dalloc<unsigned short>((size_t)nch * (HQ_BLOCK + 1));
+  k_panel_count<<<hq_grid(M.rows, 256), 256, 0, h.st>>>(M.rows, M.cols, M.rp, M.ci, cnt);
+  k_panel_offsets<<<hq_grid(nch, 256), 256, 0, h.st>>>(M.rows, cnt, lrp, size);
+  std::vector<int> hs((size_t)nch), hp((size_t)nch + 1, 0);
+  HQC(hipMemcpyAsync(hs.data(), size, sizeof(int) * (size_t)nch, hipMemcpyDeviceToHost, h.st));
+  HQC(hipStreamSynchronize(h.st));
+  hipFree(cnt);
+  hipFree(size);
+  for (long long c = 0; c < nch; ++c) {
+    if (hs[c] > 65535) return false;   // local offsets are 16-bit
+    hp[c + 1] = hp[c] + hs[c];
+  }
+  if (hp[nch] != M.nnz) fail(HPRQP_ERR_HIP, "panel layout: nonzero count mismatch");
+  int* pp = h.dalloc<int>((size_t)nch + 1);
+  int* pci = h.dalloc<int>((size_t)M.nnz);
+  double* pv = h.dalloc<double>((size_t)M.nnz);
+  HQC(hipMemcpyAsync(pp, hp.data(), sizeof(int) * ((size_t)nch + 1), hipMemcpyHostToDevice, h.st));
+  k_panel_scatter<<<hq_grid(M.rows, 256), 256, 0, h.st>>>(M.rows, M.cols, M.rp, M.ci, M.v, pp, lrp, pci, pv);
+  HQC(hipStreamSynchronize(h.st));
+  M.pm = PanelMat{M.rows, M.cols, pp, lrp, pci, pv};
+  return true;
+}
+
 void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   if (M.rows == 0 || M.nnz == 0) return;
-  const int Gs[] = {0, HQ_G_XLDS, 2, 4, 8, 16, 32, 64, 128, 256};
+  const int Gs[] = {0, HQ_G_XLDS, HQ_G_PANEL, 2, 4, 8, 16, 32, 64, 128, 256};
   hipEvent_t e0, e1;
   HQC(hipEventCreate(&e0));
   HQC(hipEventCreate(&e1));
   // the default choice is kept unless another is at least 5% faster, so that
   // near-ties do not flip between runs
   const int G0 = M.G;
-  float best = 1e30f, t_default = 1e30f;
-  int bestG = G0;
+  float best = 1e30f, t_default = 1e30f, best_np = 1e30f;
+  int bestG = G0, bestG_np = G0;
   for (int G : Gs) {
     // the CSR-stream kernels add a row serially: not candidates for very long rows
     if ((G == 0 || G == HQ_G_XLDS) && M.maxlen > 4096 && G0 != 0) continue;
     if (G == HQ_G_XLDS && M.cols > HQ_XLDS_MAX) continue;
+    if (G == HQ_G_PANEL && (M.maxlen > 4096 || !build_panel(h, M))) continue;
     M.G = G;
     launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
     HQC(hipEventRecord(e0, h.st));
@@ -768,8 +821,10 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
     HQC(hipEventElapsedTime(&ms, e0, e1));
     if (G == G0) t_default = ms;
     if (ms < best) { best = ms; bestG = G; }
+    if (G != HQ_G_PANEL && ms < best_np) { best_np = ms; bestG_np = G; }
   }
   M.G = best < 0.95f * t_default ? bestG : G0;
+  M.G_np = best_np < 0.95f * t_default ? bestG_np : G0;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
 }
@@ -1007,6 +1062,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       HQC(hipMemcpyAsync(&mx, h.dflags, sizeof(int), hipMemcpyDeviceToHost, st));
       HQC(hipStreamSynchronize(st));
       M.G = default_G(M.nnz, M.rows, mx, M.cols);
+      M.G_np = M.G;
       M.maxlen = mx;
     };
     if (m > 0) { pick(h.A); pick(h.AT); }
@@ -1050,12 +1106,20 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       h.kron_mode = kk == 0 ? 0 : 1;
       h.kron_groups = kk == 0 ? 1 : kk;
     }
-    if (opt->spmv_lanes >= 0 || opt->spmv_lanes == -2) {
+    if (opt->spmv_lanes == -3) {
+      // panel-ordered products wherever the layout applies, else the default kernel
+      for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT})
+        if (M->rows > 0 && M->maxlen <= 4096 && build_panel(h, *M, true)) { M->G_np = M->G; M->G = HQ_G_PANEL; }
+    } else if (opt->spmv_lanes >= 0 || opt->spmv_lanes == -2) {
       const int g = opt->spmv_lanes == -2 ? HQ_G_XLDS : opt->spmv_lanes;
       if (g != HQ_G_XLDS && (g > HQ_BLOCK || (g & (g - 1)) != 0))
-        fail(HPRQP_ERR_ARG, "spmv_lanes must be -2, -1, 0 or a power of 2 <= 256");
-      for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT})
+        fail(HPRQP_ERR_ARG, "spmv_lanes must be -3, -2, -1, 0 or a power of 2 <= 256");
+      for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT}) {
         M->G = (g == HQ_G_XLDS && M->cols > HQ_XLDS_MAX) ? 0 : g;   // the LDS copy needs a small vector
+        M->G_np = M->G;
+      }
+    } else if (opt->spmv_lanes != -1) {
+      fail(HPRQP_ERR_ARG, "spmv_lanes must be -3, -2, -1, 0 or a power of 2 <= 256");
     }
     if (opt->lambda_A > 0) h.lamA = opt->lambda_A;
     else if (m > 0) {

@@ -55,7 +55,7 @@ def test_operators_csr_kron_lowrank():
         print("operators:", qp.meta.get("workload"), qp.n, qp.m, flush=True)
         x = rng.standard_normal(qp.n); y = rng.standard_normal(qp.m)
         dp = DP(qp)
-        for lanes in (-1, 0, -2):    # default choice, CSR-stream, CSR-stream gathering from LDS
+        for lanes in (-1, 0, -2, -3):    # default, CSR-stream, gathering from LDS, panel-ordered
             s = Solver(dp, lambda_A=1.0, lambda_Q=1.0, spmv_lanes=lanes)
             Qd = qp.Q_dense() if qp.n <= 4000 else None
             ref_q = Qd @ x
@@ -87,7 +87,7 @@ def test_operators_large_csr_all_lane_groups():
     assert _max_rel(s.apply("Q", x).cpu().numpy(), ref) < 1e-13
     s.close()
     dp = DP(qp)
-    for g in (0, 1, 2, 4, 8, 16, 32, 64, 128, 256):
+    for g in (-3, 0, 1, 2, 4, 8, 16, 32, 64, 128, 256):
         s = Solver(dp, lambda_Q=1.0, spmv_lanes=g)
         assert _max_rel(s.apply("Q", x).cpu().numpy(), ref) < 1e-13, g
         s.close()
@@ -103,13 +103,34 @@ def test_long_rows_and_every_kernel_in_the_iteration():
     ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_Q=lamQ, trace_iters=K)
     to = split_trace(ro.trace, qp.n, qp.m)
     dp = DP(qp)
-    for g in (-2, 0, 1, 8, 64, 128, 256):
+    for g in (-3, -2, 0, 1, 8, 64, 128, 256):
         s = Solver(dp, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K, spmv_lanes=g)
         rg = s.solve()
         s.close()
         tg = split_trace(rg.trace, qp.n, qp.m)
         for name in ("w", "x", "wbar", "xbar"):
             assert _max_rel(tg[name][K - 1], to[name][K - 1]) <= 1e-10, (g, name)
+
+
+def test_panel_ordered_products_in_the_iteration():
+    """All three CSR matrices (A, A^T, Q) in the panel-ordered layout: the
+    traced iterates of 50 iterations with restarts against the oracle."""
+    DP, Solver = _S()
+    qp = qpgen.make_small_ccqp(seed=13, n=3000, m=1700, nb=400, density=0.003)
+    lamA = 1.01 * oracle.power(qp, "A", qpgen.power_start(qp.m), maxit=5000, tol=1e-12)[0]
+    lamQ = 1.01 * oracle.power(qp, "Q", qpgen.power_start(qp.n), maxit=5000, tol=1e-12)[0]
+    K = 50
+    ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_A=lamA, lambda_Q=lamQ, trace_iters=K,
+                      log_cap=K)
+    s = Solver(DP(qp), lambda_A=lamA, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K,
+               log_cap=K, spmv_lanes=-3)
+    rg = s.solve()
+    s.close()
+    np.testing.assert_array_equal(rg.check_log[:, 7], ro.check_log[:, 7])
+    to, tg = split_trace(ro.trace, qp.n, qp.m), split_trace(rg.trace, qp.n, qp.m)
+    for k in range(K):
+        for name in ("y", "w", "x", "ybar", "wbar", "xbar"):
+            assert _max_rel(tg[name][k], to[name][k]) <= 1e-10, (k, name)
 
 
 def test_power_method_matches_oracle():

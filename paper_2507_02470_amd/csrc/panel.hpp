@@ -17,7 +17,6 @@
 #include "common.hpp"
 
 #define HQ_PANELS 4
-#define HQ_PANEL_BPB 2
 
 struct PanelMat {
   int rows = 0, cols = 0;
@@ -87,27 +86,11 @@ __global__ void k_panel_scatter(int rows, int cols, const int* __restrict__ rp, 
   }
 }
 
-// values only (the structure is unchanged): the panel copy of new values
-__global__ void k_panel_values(int rows, int cols, const int* __restrict__ rp, const int* __restrict__ ci,
-                               const double* __restrict__ v, const int* __restrict__ pp,
-                               const unsigned short* __restrict__ lrp, double* __restrict__ pv) {
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
-    const int rb = r / HQ_BLOCK, lr = r % HQ_BLOCK;
-    int p_prev = -1, dst = 0;
-    for (int k = rp[r]; k < rp[r + 1]; ++k) {
-      const int p = hq_panel_of(ci[k], cols);
-      if (p != p_prev) {
-        const int ch = rb * HQ_PANELS + p;
-        dst = pp[ch] + lrp[(size_t)ch * (HQ_BLOCK + 1) + lr];
-        p_prev = p;
-      }
-      pv[dst++] = v[k];
-    }
-  }
-}
-
-// the product with a fused epilogue; grid = ceil(row blocks / BPB)
-template <class Epi>
+// the product with a fused epilogue; each workgroup owns BPB consecutive row
+// blocks, grid = ceil(row blocks / BPB) (chosen so that the whole grid is
+// resident at once: a late workgroup would gather from a panel the others
+// have left)
+template <class Epi, int BPB>
 __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double* __restrict__ xin, Epi epi,
                                                         const DevParams* __restrict__ prm, int j, RedOut red) {
   constexpr int NR = Epi::NR;
@@ -119,13 +102,13 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
   for (int s = 0; s < (NR > 0 ? NR : 1); ++s) acc[s] = 0.0;
   const int nblk = (M.rows + HQ_BLOCK - 1) / HQ_BLOCK;
   const int t = threadIdx.x;
-  double sum[HQ_PANEL_BPB];
+  double sum[BPB];
 #pragma unroll
-  for (int q = 0; q < HQ_PANEL_BPB; ++q) sum[q] = 0.0;
-  const int rb0 = blockIdx.x * HQ_PANEL_BPB;
+  for (int q = 0; q < BPB; ++q) sum[q] = 0.0;
+  const int rb0 = blockIdx.x * BPB;
   for (int p = 0; p < HQ_PANELS; ++p) {
 #pragma unroll
-    for (int q = 0; q < HQ_PANEL_BPB; ++q) {
+    for (int q = 0; q < BPB; ++q) {
       const int rb = rb0 + q;
       if (rb < nblk) {
         const int ch = rb * HQ_PANELS + p;
@@ -146,7 +129,7 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
     }
   }
 #pragma unroll
-  for (int q = 0; q < HQ_PANEL_BPB; ++q) {
+  for (int q = 0; q < BPB; ++q) {
     const int rb = rb0 + q;
     if (rb < nblk && t < min(HQ_BLOCK, M.rows - rb * HQ_BLOCK)) e(rb * HQ_BLOCK + t, sum[q], acc);
   }

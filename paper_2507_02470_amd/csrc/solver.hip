@@ -368,8 +368,21 @@ template <class Epi>
 void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
   if (M.G == HQ_G_XLDS) { launch_csr_xlds(h, M, x, epi, j, red); return; }
   if (M.G == HQ_G_PANEL) {
+    // row blocks per workgroup: the fewest for which the whole grid is resident
+    static int per_cu = 0;   // resident workgroups per CU of this epilogue's kernel
+    if (!per_cu) {
+      HQC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_csr_panel<Epi, 2>, HQ_BLOCK, 0));
+      per_cu = std::max(per_cu, 1);
+    }
     const int nblk = (M.rows + HQ_BLOCK - 1) / HQ_BLOCK;
-    k_csr_panel<Epi><<<(nblk + HQ_PANEL_BPB - 1) / HQ_PANEL_BPB, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red);
+    const long long resident = (long long)h.ncu * per_cu;
+    const int bpb = (int)std::min<long long>(4, std::max<long long>(1, (nblk + resident - 1) / resident));
+    switch (bpb) {
+      case 1: k_csr_panel<Epi, 1><<<nblk, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+      case 2: k_csr_panel<Epi, 2><<<(nblk + 1) / 2, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+      case 3: k_csr_panel<Epi, 3><<<(nblk + 2) / 3, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+      default: k_csr_panel<Epi, 4><<<(nblk + 3) / 4, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+    }
     return;
   }
   // stream kernel: HQ_BLOCK rows per block; row-split kernel: HQ_BLOCK / G rows per block
@@ -871,6 +884,37 @@ void autotune_kron(hprqp_handle& h, const double* x, double* out) {
   hipEventDestroy(e1);
 }
 
+// The Q d product carries the heaviest epilogue (11 vectors read, 3 written),
+// which the panel-ordered kernel runs only after its last panel: time that
+// product both ways (on the workspace as it is; every solve resets the state)
+// and keep the panel-ordered kernel for it only if it is at least 5% faster.
+void autotune_heavy_q(hprqp_handle& h) {
+  if (h.Q.G != HQ_G_PANEL || h.m == 0) return;
+  EpiQ2 e6{};
+  e6.xh = h.xh; e6.w = h.w; e6.Qw = h.Qw; e6.XB = h.XB; e6.ZB = h.ZB;
+  e6.q1 = h.q1; e6.d = h.d; e6.wa = h.wa; e6.Qwa = h.Qwa; e6.xa = h.xa; e6.ATy = h.ATy;
+  e6.c = h.c; e6.L = h.L; e6.U = h.U; e6.e = h.e;
+  e6.wbar = h.wbar; e6.qwbar = h.qwbar; e6.x = h.x; e6.xbar_out = h.xbo;
+  e6.l1 = h.l1;
+  hipEvent_t e0, e1;
+  HQC(hipEventCreate(&e0));
+  HQC(hipEventCreate(&e1));
+  const int g_np = h.Q.G_np;
+  float t[2] = {0.f, 0.f};
+  for (int v = 0; v < 2; ++v) {
+    h.Q.G_np = v ? HQ_G_PANEL : g_np;
+    q_apply(h, h.d, e6, 0, no_red(h), true);
+    HQC(hipEventRecord(e0, h.st));
+    for (int r = 0; r < 5; ++r) q_apply(h, h.d, e6, 0, no_red(h), true);
+    HQC(hipEventRecord(e1, h.st));
+    HQC(hipEventSynchronize(e1));
+    HQC(hipEventElapsedTime(&t[v], e0, e1));
+  }
+  h.Q.G_np = t[1] < 0.95f * t[0] ? HQ_G_PANEL : g_np;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+}
+
 // Lanes per row of the row-split kernel, or 0 for the CSR-stream kernel
 // (short rows: average up to 32 nonzeros and none longer than 4096).  The
 // variant gathering from an LDS copy of the vector is left to the autotuner:
@@ -1078,6 +1122,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       }
       if (h.qkind == HPRQP_Q_CSR) autotune_csr(h, h.Q, h.t1, h.t2);
       if (h.qkind == HPRQP_Q_KRON && opt->kron_kernel < 0) autotune_kron(h, h.t1, h.t2);
+      if (h.qkind == HPRQP_Q_CSR) autotune_heavy_q(h);
       if (h.qkind == HPRQP_Q_GRAM) {
         autotune_csr(h, h.G, h.t1, h.gtmp);
         autotune_csr(h, h.GT, h.gtmp, h.t1);

@@ -824,6 +824,9 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
     if ((G == 0 || G == HQ_G_XLDS) && M.maxlen > 4096 && G0 != 0) continue;
     if (G == HQ_G_XLDS && M.cols > HQ_XLDS_MAX) continue;
     if (G == HQ_G_PANEL && (M.maxlen > 4096 || !build_panel(h, M))) continue;
+    // row-split groups much wider than the rows only idle their lanes: skip them
+    if (G > 1 && M.maxlen >= 0 && M.maxlen <= 4096 && (double)G > 4.0 * ((double)M.nnz / M.rows) && G > 8)
+      continue;
     M.G = G;
     launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
     HQC(hipEventRecord(e0, h.st));

@@ -112,6 +112,22 @@ def test_long_rows_and_every_kernel_in_the_iteration():
             assert _max_rel(tg[name][K - 1], to[name][K - 1]) <= 1e-10, (g, name)
 
 
+def test_panel_layout_falls_back_when_a_chunk_is_too_large():
+    """A dense 2048 x 2048 Q puts 131,072 nonzeros in each (row block, panel)
+    chunk, beyond the layout's 16-bit offsets: spmv_lanes = -3 must keep the
+    default kernel for it and still give the right products."""
+    DP, Solver = _S()
+    rng = np.random.default_rng(3)
+    n = 2048
+    G = rng.standard_normal((n, 64))
+    Qd = G @ G.T / 64
+    qp = qpgen.from_dense(Qd, rng.standard_normal(n), -np.ones(n), np.ones(n), np.zeros((0, n)), [], [])
+    x = rng.standard_normal(n)
+    s = Solver(DP(qp), lambda_Q=1.0, spmv_lanes=-3)
+    assert _max_rel(s.apply("Q", x).cpu().numpy(), Qd @ x) < 1e-13
+    s.close()
+
+
 def test_panel_ordered_products_in_the_iteration():
     """All three CSR matrices (A, A^T, Q) in the panel-ordered layout: the
     traced iterates of 50 iterations with restarts against the oracle."""

@@ -2,11 +2,16 @@
 // 2507.02470) in one persistent kernel on one MI355X.
 //
 // One 512-thread workgroup owns one instance at a time; instances are pulled
-// from a work queue ordered by size (largest first).  The iterate, the
-// per-iteration vectors and the low-rank factor F of Q = diag(d) + F F^T
-// live in registers (HB_EPT variables per thread, so n <= 512 * HB_EPT; F
-// padded to rank 10 or 16 by template); the Halpern anchors and vectors of
-// length m (<= 64) live in LDS.  The whole method runs on the
+// from a work queue ordered by size (largest first).  Thread t owns entries
+// t + 512 e, e < HB_EPT (so n <= 512 * HB_EPT): the per-iteration vectors of
+// its entries are in registers, and so are its rows of the low-rank factor F
+// of Q = diag(d) + F F^T at rank <= 10 (at rank 16 they are read from memory
+// at each product); the iterate, its images Q w and A^T y, the Halpern
+// anchors and the vectors of length m (<= 64) are in LDS.  The iteration
+// is bound by the latency of its dependent steps (a block-wide reduction
+// per Q product, the A and A^T products through LDS), not by bandwidth, so
+// the loads of each step are issued together and kept to global (not
+// generic) addresses.  The whole method runs on the
 // device in FP64: power method for lambda_A and lambda_Q, the sigma0 rule,
 // the iteration, the merit R~, the stopping test, the restart criteria of
 // Section 3.2 and the golden-section sigma update of Algorithm 5 (thread 0,
@@ -32,6 +37,7 @@ extern thread_local std::string g_err;
 #define HB_MMAX 64
 #define HB_RMAX 16
 #define HB_APIECE 256                                  // nonzeros of A per wave work item
+#define HB_ATSTEP 3                                    // nonzeros per entry and step of the A^T product
 #define HB_PMAX (HB_MMAX + HB_MMAX * HB_NMAX / HB_APIECE)  // pieces of A at most
 
 struct BInst {
@@ -82,6 +88,7 @@ struct BShared {
   double part[HB_PMAX];
   short prow[HB_PMAX];
   int pstart[HB_MMAX + 1];
+  int arp[HB_MMAX + 1];              // row pointers of A
   int np;
   double ctrl[8];
   int inst;
@@ -148,21 +155,76 @@ __device__ __forceinline__ void bred(BShared& S, int& par, double (&v)[K], unsig
 // ---------------------------------------------------------------------------
 // the per-instance operator pieces
 // ---------------------------------------------------------------------------
+// Load of element i of an instance array.  The arrays are in global memory
+// but their pointers are read from memory, so plain indexing would give
+// generic (flat) loads, which every wait for an LDS access also waits for.
+template <class T>
+__device__ __forceinline__ T gld(const T* p, long long i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+__device__ __forceinline__ double2 gld(const double2* p, long long i) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = ((const __attribute__((address_space(1))) v2*)p)[i];
+  return double2{v.x, v.y};
+}
+
 template <int RM>
 struct Elem {
   int n, m, r;
   const double* FT;       // F with rows padded to RM: F(i, k) = FT[i RM + k], zero for k >= r
   const double *c, *L, *U, *dg;
-  __device__ bool valid(int e) const { return (int)threadIdx.x + e * HB_BS < n; }
-  __device__ int idx(int e) const { return threadIdx.x + e * HB_BS; }
+  int tid;                // threadIdx.x, refreshed through an empty asm statement every iteration
+  __device__ bool valid(int e) const { return tid + e * HB_BS < n; }
+  __device__ int idx(int e) const { return tid + e * HB_BS; }
+  // Addresses derived from the thread index are then recomputed in every
+  // iteration instead of being hoisted out of the solve loop, where they
+  // would outnumber the registers and be spilled.
+  __device__ void refresh() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    tid = t;
+  }
 };
 
-// q = Q p = diag(d) p + F (F^T p).  F is read from the library's copy with
+// The rows of F that a thread owns, read from the library's copy of F with
 // rows padded to RM entries (16-byte loads at fixed offsets from one address
-// per entry; L2-resident while the instance is solved).
-template <int RM>
-__device__ __forceinline__ void q_apply(BShared& S, int& par, const Elem<RM>& E, const double (&p)[HB_EPT],
-                                        double (&q)[HB_EPT]) {
+// per entry).  REG: loaded once into registers, so that the products of the
+// iteration read only diag(d) from memory (rank 10; at rank 16 the copy would
+// take too many registers).  Otherwise read at every product.
+template <int RM, bool REG>
+struct QRows {
+  double f[REG ? HB_EPT : 1][REG ? RM : 2];
+  // (the base address passes through an empty asm statement so that the
+  // compiler cannot move the loads above the point of the call, which would
+  // keep the copy live across a check)
+  __device__ void load(const Elem<RM>& E) {
+    if constexpr (REG) {
+      const double* FT = E.FT;
+      asm volatile("" : "+s"(FT));
+#pragma unroll
+      for (int e = 0; e < HB_EPT; ++e) {
+        const bool ok = E.valid(e);
+        const double2* fr = reinterpret_cast<const double2*>(FT + (size_t)(ok ? E.idx(e) : 0) * RM);
+#pragma unroll
+        for (int k = 0; k < RM / 2; ++k) {
+          const double2 v = ok ? gld(fr, k) : double2{0.0, 0.0};
+          f[e][2 * k] = v.x;
+          f[e][2 * k + 1] = v.y;
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ double2 row2(const Elem<RM>& E, int e, int k) const {
+    if constexpr (REG) return double2{f[e][2 * k], f[e][2 * k + 1]};
+    else return gld(reinterpret_cast<const double2*>(E.FT + (size_t)E.idx(e) * RM), k);
+  }
+  __device__ __forceinline__ double diag(const Elem<RM>& E, int e) const { return gld(E.dg, E.idx(e)); }
+};
+
+// q = Q p = diag(d) p + F (F^T p)
+template <int RM, bool REG>
+__device__ __forceinline__ void q_apply(BShared& S, int& par, const Elem<RM>& E, const QRows<RM, REG>& Fq,
+                                        const double (&p)[HB_EPT], double (&q)[HB_EPT]) {
   static_assert(RM % 2 == 0, "rows are read in pairs");
   double t[RM];
 #pragma unroll
@@ -170,24 +232,25 @@ __device__ __forceinline__ void q_apply(BShared& S, int& par, const Elem<RM>& E,
 #pragma unroll
   for (int e = 0; e < HB_EPT; ++e)
     if (E.valid(e)) {
-      const double2* f = reinterpret_cast<const double2*>(E.FT + (size_t)E.idx(e) * RM);
 #pragma unroll
       for (int k = 0; k < RM / 2; ++k) {
-        const double2 v = f[k];
+        const double2 v = Fq.row2(E, e, k);
         t[2 * k] += v.x * p[e];
         t[2 * k + 1] += v.y * p[e];
       }
     }
+  double dg[HB_EPT];   // loaded before the reduction's barrier, used after it
+#pragma unroll
+  for (int e = 0; e < HB_EPT; ++e) dg[e] = E.valid(e) ? Fq.diag(E, e) : 0.0;
   bred<RM>(S, par, t, 0u);
 #pragma unroll
   for (int e = 0; e < HB_EPT; ++e) {
     double s = 0.0;
     if (E.valid(e)) {
-      s = E.dg[E.idx(e)] * p[e];
-      const double2* f = reinterpret_cast<const double2*>(E.FT + (size_t)E.idx(e) * RM);
+      s = dg[e] * p[e];
 #pragma unroll
       for (int k = 0; k < RM / 2; ++k) {
-        const double2 v = f[k];
+        const double2 v = Fq.row2(E, e, k);
         s += v.x * t[2 * k];
         s += v.y * t[2 * k + 1];
       }
@@ -201,10 +264,12 @@ __device__ void a_pieces(BShared& S, const BInst& I) {
   int q = 0;
   for (int r = 0; r < I.m; ++r) {
     S.pstart[r] = q;
+    S.arp[r] = I.arp[r];
     const int len = I.arp[r + 1] - I.arp[r];
     for (int c = 0; c * HB_APIECE < len; ++c) S.prow[q++] = (short)r;
   }
   S.pstart[I.m] = q;
+  S.arp[I.m] = I.m > 0 ? I.arp[I.m] : 0;
   S.np = q;
 }
 
@@ -217,44 +282,79 @@ __device__ __forceinline__ void a_apply(BShared& S, const Elem<RM>& E, const BIn
   for (int e = 0; e < HB_EPT; ++e)
     if (E.valid(e)) S.vm[E.idx(e)] = p[e];
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q = wv; q < S.np; q += HB_WAVES) {
-    const int row = S.prow[q];
-    const int b = I.arp[row] + (q - S.pstart[row]) * HB_APIECE;
-    const int e = min(I.arp[row + 1], b + HB_APIECE);
-    double s = 0.0;
+  // a wave takes pieces q0 and q0 + HB_WAVES together (loads of both in
+  // flight); each piece's sum is formed as for one piece at a time
+  const int lane = E.tid & 63, wv = E.tid >> 6;
+  constexpr int U = HB_APIECE / 64;
+  for (int q0 = wv; q0 < S.np; q0 += 2 * HB_WAVES) {
+    double av[2][U];
+    int ac[2][U];
 #pragma unroll
-    for (int u = 0; u < HB_APIECE / 64; ++u) {
-      const int k = b + lane + 64 * u;
-      if (k < e) s += I.aval[k] * S.vm[I.aci[k]];
+    for (int h = 0; h < 2; ++h) {
+      const int q = q0 + h * HB_WAVES;
+      int b = 0, e = 0;
+      if (q < S.np) {
+        const int row = S.prow[q];
+        b = S.arp[row] + (q - S.pstart[row]) * HB_APIECE;
+        e = min(S.arp[row + 1], b + HB_APIECE);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = b + lane + 64 * u;
+        av[h][u] = k < e ? gld(I.aval, k) : 0.0;
+        ac[h][u] = k < e ? gld(I.aci, k) : -1;
+      }
     }
-    s = wave_sum(s);
-    if (lane == 0) S.part[q] = s;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ac[h][u] >= 0) s += av[h][u] * S.vm[ac[h][u]];
+      s = wave_sum(s);
+      const int q = q0 + h * HB_WAVES;
+      if (lane == 0 && q < S.np) S.part[q] = s;
+    }
   }
   __syncthreads();
-  if ((int)threadIdx.x < E.m) {
+  if (E.tid < E.m) {
     double s = 0.0;
-    for (int q = S.pstart[threadIdx.x]; q < S.pstart[threadIdx.x + 1]; ++q) s += S.part[q];
-    S.ry[threadIdx.x] = s;
+    for (int q = S.pstart[E.tid]; q < S.pstart[E.tid + 1]; ++q) s += S.part[q];
+    S.ry[E.tid] = s;
   }
 }
 
 // g = A^T yv (yv in LDS, length m); tb/te: the entries' ranges in A^T,
-// loaded once per instance.  Two entries per step keep two loads in flight.
+// loaded once per instance.  The thread's entries advance together,
+// HB_ATSTEP nonzeros per step, so that their loads are in flight at the same
+// time (each entry's sum still runs over its nonzeros in order).
 template <int RM>
 __device__ __forceinline__ void at_apply(const Elem<RM>& E, const BInst& I, const int (&tb)[HB_EPT],
                                          const int (&te)[HB_EPT], const double* yv, double (&g)[HB_EPT]) {
+  int len = 0;
 #pragma unroll
   for (int e = 0; e < HB_EPT; ++e) {
-    double s = 0.0;
-    for (int k = tb[e]; k < te[e]; k += 2) {
-      const bool two = k + 1 < te[e];
-      const double v0 = I.tval[k], v1 = two ? I.tval[k + 1] : 0.0;
-      const int c0 = I.tci[k], c1 = two ? I.tci[k + 1] : c0;
-      s += v0 * yv[c0];
-      if (two) s += v1 * yv[c1];
-    }
-    g[e] = s;
+    g[e] = 0.0;
+    len = max(len, te[e] - tb[e]);
+  }
+  constexpr int J = HB_ATSTEP;
+  for (int j = 0; j < len; j += J) {
+    double v[HB_EPT][J];
+    int c[HB_EPT][J];
+#pragma unroll
+    for (int e = 0; e < HB_EPT; ++e)
+#pragma unroll
+      for (int u = 0; u < J; ++u) {
+        const int k = tb[e] + j + u;
+        const bool ok = k < te[e];
+        v[e][u] = ok ? gld(I.tval, k) : 0.0;
+        c[e][u] = ok ? gld(I.tci, k) : -1;
+      }
+#pragma unroll
+    for (int e = 0; e < HB_EPT; ++e)
+#pragma unroll
+      for (int u = 0; u < J; ++u)
+        if (c[e][u] >= 0) g[e] += v[e][u] * yv[c[e][u]];
   }
 }
 
@@ -353,15 +453,17 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
     Elem<RM> E;
     E.n = I.n; E.m = I.m; E.r = I.r; E.FT = I.FT;
     E.c = I.c; E.L = I.L; E.U = I.U; E.dg = I.dg;
+    E.refresh();
     const int n = I.n, m = I.m;
     if (tid < m) { S.l[tid] = I.l[tid]; S.u[tid] = I.u[tid]; }
     if (tid == 0) a_pieces(S, I);
+    QRows<RM, false> Fg;   // F from memory: power method and checks (rare)
     int tb[HB_EPT], te[HB_EPT];   // A^T ranges of the thread's entries (empty when invalid)
 #pragma unroll
     for (int e = 0; e < HB_EPT; ++e) {
       const int i = E.idx(e);
-      tb[e] = i < n ? I.trp[i] : 0;
-      te[e] = i < n ? I.trp[i + 1] : 0;
+      tb[e] = i < n ? gld(I.trp, i) : 0;
+      te[e] = i < n ? gld(I.trp, i + 1) : 0;
     }
     __syncthreads();
 
@@ -374,7 +476,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
       for (int e = 0; e < HB_EPT; ++e) pv[e] = E.valid(e) ? s0 : 0.0;
       double lam = 0.0, lam_old = 0.0;
       for (int it = 1; it <= 5000; ++it) {
-        q_apply(S, par, E, pv, qv);
+        q_apply(S, par, E, Fg, pv, qv);
         double rr[2] = {0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) { rr[0] += pv[e] * qv[e]; rr[1] += qv[e] * qv[e]; }
@@ -446,12 +548,18 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
     if (tid < m) S.y[tid] = y0 ? y0[I.off_m + tid] : 0.0;
     __syncthreads();
 
+    // F in registers for the iteration; not live across a check, which reads
+    // F from memory and loads this copy again when it is done
+    QRows<RM, (RM <= 10)> Fq;
+    Fq.load(E);
     long long k = 0, t = 0;
     int r = 0, term = -1;
     double alpha3 = o.alpha3, R0ref = -1.0, Rr0 = -1.0, Rprev = -1.0, R = 0.0;
     double eta_p = 0, eta_d = 0, eta_gap = 0, pobj = 0, dobj = 0;
     bool new_epoch = true;
     while (term < 0) {
+      E.refresh();
+      const int tid = E.tid;
       if (new_epoch) {
         // anchor u^{r,0} = u; exact A^T y and Q w.  Each thread keeps the
         // anchors of its own variables in LDS (no other thread reads them).
@@ -461,7 +569,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) w[e] = S.ws[E.idx(e)];
         at_apply(E, I, tb, te, S.y, ATy);
-        q_apply(S, par, E, w, Qw);
+        q_apply(S, par, E, Fq, w, Qw);
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) {
           const int i = E.idx(e);
@@ -482,13 +590,13 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
         const int i = E.idx(e);
         const bool ok = E.valid(e);
         const double xe = S.xs[i];
-        const double rz = xe + sigma * (-S.Qws[i] + S.ATys[i] - (ok ? E.c[i] : 0.0));
-        xb[e] = ok ? clampd(rz, E.L[i], E.U[i]) : 0.0;
+        const double rz = xe + sigma * (-S.Qws[i] + S.ATys[i] - (ok ? gld(E.c, i) : 0.0));
+        xb[e] = ok ? clampd(rz, gld(E.L, i), gld(E.U, i)) : 0.0;
         xh[e] = ok ? 2.0 * xb[e] - xe : 0.0;
       }
       // Q xhat, v = xhat + kappa (Qw - Q xhat)
       double q1[HB_EPT];
-      q_apply(S, par, E, xh, q1);
+      q_apply(S, par, E, Fq, xh, q1);
       // y step ("update-y") and its Halpern update
       double dy2 = 0.0, th_y = 0.0;
       if (m > 0) {
@@ -513,7 +621,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
 #pragma unroll
       for (int e = 0; e < HB_EPT; ++e) d[e] = m > 0 ? g[e] - S.ATys[E.idx(e)] : 0.0;
       double q2[HB_EPT];
-      q_apply(S, par, E, d, q2);
+      q_apply(S, par, E, Fq, d, q2);
       // wbar ("update-w") and Q wbar
       double wb[HB_EPT], Qwb[HB_EPT];
 #pragma unroll
@@ -568,7 +676,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
         double ev[HB_EPT], Qe[HB_EPT];
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) ev[e] = (m > 0 && E.valid(e)) ? Hg[E.idx(e)] - S.ATya[E.idx(e)] : 0.0;
-        q_apply(S, par, E, ev, Qe);
+        q_apply(S, par, E, Fg, ev, Qe);
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) {
           if (!E.valid(e)) continue;
@@ -586,7 +694,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
         double xbv[HB_EPT], Qx[HB_EPT];
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) xbv[e] = Hx[E.idx(e)];
-        q_apply(S, par, E, xbv, Qx);
+        q_apply(S, par, E, Fg, xbv, Qx);
         if (m > 0) a_apply(S, E, I, xbv);           // S.ry = A xbar
         // res: 0 max|Ax-PiK|, 1 max|Ax|, 2 sum(l y+ + u y-), 3 #inf, 4 max|dual|, 5 max|g|, 6 max|Qx|,
         //      7 <x,Qx>, 8 <c,x>, 9 sum(L z+ + U z-) (+ #inf folded into 3)
@@ -601,7 +709,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
         for (int e = 0; e < HB_EPT; ++e) {
           if (!E.valid(e)) continue;
           const int i = E.idx(e);
-          const double ce = E.c[i], Le = E.L[i], Ue = E.U[i], ge = Hg[i];
+          const double ce = gld(E.c, i), Le = gld(E.L, i), Ue = gld(E.U, i), ge = Hg[i];
           const double rz = S.xs[i] + sigma * (-S.Qws[i] + S.ATys[i] - ce);
           const double zbe = (xbv[e] - rz) / sigma;
           Hz[i] = zbe;
@@ -661,6 +769,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
         if (tid < m) S.y[tid] = S.yn[tid];
         __syncthreads();
       }
+      Fq.load(E);
     }
     if (tid < m) yo[I.off_m + tid] = S.yb[tid];
     if (tid == 0) {

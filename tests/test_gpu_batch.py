@@ -60,6 +60,45 @@ def test_batch_iterates_match_oracle_after_50():
             assert e <= 1e-10, (i, q.n, name, e)
 
 
+def _no_rows(q):
+    """The same QP without the constraints l <= Ax <= u (m = 0)."""
+    q.m = 0
+    q.a_rowptr = np.zeros(1, dtype=np.int32)
+    q.a_col = np.zeros(0, dtype=np.int32)
+    q.a_val = np.zeros(0)
+    q.l = np.zeros(0)
+    q.u = np.zeros(0)
+    return q
+
+
+@pytest.mark.parametrize("ranks", [(10, 3, 10), (16, 3, 10, 16)])
+def test_batch_ranks_and_instances_without_rows(ranks):
+    """Instances of rank below the kernel's (F padded with zero columns), the
+    rank-16 kernel (F read from memory at every product) and instances with
+    m = 0 in the same batch: iterates after 60 iterations against the oracle."""
+    BS = _B()
+    ns = [700, 64, 1537, 2000]
+    qps = [qpgen.make_portfolio(40_000 + i, n=ns[i], rank=r) for i, r in enumerate(ranks)]
+    qps.append(_no_rows(qpgen.make_portfolio(40_100, n=513, rank=ranks[0])))
+    qps.append(_no_rows(qpgen.make_portfolio(40_101, n=2048, rank=ranks[-1])))
+    print("batch ranks:", [q.lr_F.shape[1] for q in qps], "m:", [q.m for q in qps], flush=True)
+    b = BS(qps, tol=0.0, max_iter=60, check_every=20)
+    r = b.solve()
+    b.close()
+    for i, q in enumerate(qps):
+        o = oracle.solve(q, tol=0.0, max_iter=60, check_every=20)
+        f = r.infos[i]
+        assert f["iters"] == o.iters == 60
+        assert f["restarts"] == o.restarts, (i, f["restarts"], o.restarts)
+        assert f["lambda_Q"] == pytest.approx(o.lambda_Q, rel=1e-12)
+        pairs = [("z", r.z[i], o.z), ("w", r.w[i], o.w), ("x", r.x[i], o.x)]
+        if q.m:
+            pairs.append(("y", r.y[i], o.y))
+        for name, g, ref in pairs:
+            e = _rel(g, ref)
+            assert e <= 1e-10, (i, q.n, q.m, name, e)
+
+
 def test_batch_full_solves_match_oracle():
     BS = _B()
     qps = [qpgen.make_portfolio(30_000 + i) for i in range(12)]

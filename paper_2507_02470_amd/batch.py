@@ -36,6 +36,15 @@ class BatchResult:
         return np.array([f["iters"] for f in self.infos])
 
 
+def _problem_dtype():
+    """numpy view of hprqp_problem (pointers as uint64)."""
+    S = N.hprqp_problem
+    kinds = {C.c_int32: np.int32, C.c_int64: np.int64, C.c_double: np.float64}
+    return np.dtype(dict(names=[f for f, _ in S._fields_],
+                         formats=[kinds.get(ct, np.uint64) for _, ct in S._fields_],
+                         offsets=[getattr(S, f).offset for f, _ in S._fields_], itemsize=C.sizeof(S)))
+
+
 class BatchSolver:
     """Solve many QPs with Q = diag(d) + F F^T in one persistent kernel.
 
@@ -46,6 +55,7 @@ class BatchSolver:
         self.lib = N.load()
         f64, i32 = torch.float64, torch.int32
         self.count = len(instances)
+        self.shared = shared
         dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)
         if shared is not None:
             base = shared
@@ -62,17 +72,18 @@ class BatchSolver:
                           aval=dev(base.a_val if len(base.a_val) else np.zeros(1), f64))
             P = (N.hprqp_problem * self.count)()
             t = self.t
-            for i in range(self.count):
-                p = P[i]
-                p.n, p.m, p.qkind = base.n, base.m, 3
-                p.lr_rank = base.lr_F.shape[1]
-                p.lr_d, p.lr_F = t["d"].data_ptr(), t["F"].data_ptr()
-                p.c = t["c"].data_ptr() + 8 * i * base.n
-                p.L, p.U = t["L"].data_ptr(), t["U"].data_ptr()
-                p.a_rowptr, p.a_col, p.a_val = t["arp"].data_ptr(), t["aci"].data_ptr(), t["aval"].data_ptr()
-                p.a_nnz = int(base.a_rowptr[-1])
-                p.l = t["l"].data_ptr() + 8 * i * base.m
-                p.u = t["u"].data_ptr() + 8 * i * base.m
+            # every instance's descriptor at once, through a structured view of the array
+            a = np.frombuffer((C.c_char * C.sizeof(P)).from_buffer(P), dtype=_problem_dtype())
+            i = np.arange(self.count, dtype=np.uint64)
+            a["n"], a["m"], a["qkind"] = base.n, base.m, 3
+            a["lr_rank"] = base.lr_F.shape[1]
+            a["lr_d"], a["lr_F"] = t["d"].data_ptr(), t["F"].data_ptr()
+            a["c"] = np.uint64(t["c"].data_ptr()) + np.uint64(8 * base.n) * i
+            a["L"], a["U"] = t["L"].data_ptr(), t["U"].data_ptr()
+            a["a_rowptr"], a["a_col"], a["a_val"] = t["arp"].data_ptr(), t["aci"].data_ptr(), t["aval"].data_ptr()
+            a["a_nnz"] = int(base.a_rowptr[-1])
+            a["l"] = np.uint64(t["l"].data_ptr()) + np.uint64(8 * base.m) * i
+            a["u"] = np.uint64(t["u"].data_ptr()) + np.uint64(8 * base.m) * i
         else:
             qps = instances
             ns = [q.n for q in qps]
@@ -115,6 +126,16 @@ class BatchSolver:
         N.check(self.lib.hprqp_batch_create(self.count, P, C.byref(self.opts), C.c_void_p(self.stream.cuda_stream),
                                             C.byref(h)))
         self.h = h
+
+    def shared_features(self) -> torch.Tensor:
+        """[c; u] of every instance of a shared-structure batch as a (count,
+        n + m) float32 device tensor, from the copies already on the device."""
+        if self.shared is None:
+            raise ValueError("shared_features needs a batch built with `shared`")
+        n, m = self.shared.n, self.shared.m
+        c = self.t["c"].view(self.count, n)
+        parts = [c, self.t["u"][:self.count * m].view(self.count, m)] if m else [c]
+        return torch.cat(parts, dim=1).to(torch.float32)
 
     def close(self):
         if getattr(self, "h", None):

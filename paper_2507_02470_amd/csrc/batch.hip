@@ -21,6 +21,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -851,10 +853,11 @@ __global__ void k_batch_transpose(const BInst* __restrict__ insts, const int* __
 
 // F of every instance with rows padded to the kernel's rank RM:
 // FT[i RM + k] = F(i, k) for k < r, 0 for r <= k < RM
-__global__ void k_batch_ft(const BInst* __restrict__ insts, int count, int RM, double* __restrict__ ft_all,
-                           const long long* __restrict__ ft_off) {
-  const int ii = blockIdx.x;
-  if (ii >= count) return;
+// (one block per distinct copy: rep lists one instance of each)
+__global__ void k_batch_ft(const BInst* __restrict__ insts, const int* __restrict__ rep, int nrep, int RM,
+                           double* __restrict__ ft_all, const long long* __restrict__ ft_off) {
+  if ((int)blockIdx.x >= nrep) return;
+  const int ii = rep[blockIdx.x];
   const BInst I = insts[ii];
   double* ft = ft_all + ft_off[ii];
   const long long tot = (long long)RM * I.n;
@@ -884,6 +887,7 @@ struct hprqp_batch {
   int* d_rep = nullptr;
   double* ft = nullptr;        // F of every instance, rows padded to rank_max
   long long* d_ftoff = nullptr;
+  int* d_ftrep = nullptr;      // one instance per distinct F
   double* hbuf = nullptr;      // per-block check buffers
   long long total_n = 0, total_m = 0;
   int grid = 0;
@@ -891,7 +895,7 @@ struct hprqp_batch {
   double last_kernel_s = 0.0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ~hprqp_batch() {
-    void* ps[] = {d_insts, d_order, d_queue, d_flags, d_infos, trp, tci, tval, d_toff, d_rep, ft, d_ftoff, hbuf};
+    void* ps[] = {d_insts, d_order, d_queue, d_flags, d_infos, trp, tci, tval, d_toff, d_rep, ft, d_ftoff, d_ftrep, hbuf};
     for (void* p : ps)
       if (p) hipFree(p);
     if (e0) hipEventDestroy(e0);
@@ -935,6 +939,7 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     // unique A matrices (instances may share one) -> one A^T each
     std::vector<int> rep_of(count);
     std::vector<int> reps;
+    std::map<std::tuple<const void*, const void*, const void*, int, int>, int> rep_index;
     std::vector<long long> toff;
     long long tn = 0, tz = 0;
     for (int i = 0; i < count; ++i) {
@@ -956,13 +961,12 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
       I.annz = P.m > 0 ? P.a_nnz : 0;
       if (P.a_nnz < 0 || P.a_nnz > (1ll << 30)) bfail(HPRQP_ERR_SHAPE, "bad a_nnz in instance " + std::to_string(i));
       b->total_n += P.n; b->total_m += P.m;
-      int found = -1;
-      for (size_t q = 0; q < reps.size() && found < 0; ++q) {
-        const hprqp_problem& R = probs[reps[q]];
-        if (R.a_rowptr == P.a_rowptr && R.a_col == P.a_col && R.a_val == P.a_val && R.n == P.n && R.m == P.m) found = (int)q;
-      }
+      const auto akey = std::make_tuple((const void*)P.a_rowptr, (const void*)P.a_col, (const void*)P.a_val, P.n, P.m);
+      const auto it = rep_index.find(akey);
+      int found = it == rep_index.end() ? -1 : it->second;
       if (found < 0) {
         found = (int)reps.size();
+        rep_index.emplace(akey, found);
         reps.push_back(i);
         toff.push_back(tn);
         toff.push_back(tz);
@@ -984,9 +988,20 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     int maxr = 0;
     for (int i = 0; i < count; ++i) maxr = std::max(maxr, hi[i].r);
     b->rank_max = maxr <= 10 ? 10 : 16;
+    // (one padded copy per distinct F: instances that share F share the copy)
     std::vector<long long> ftoff(count);
+    std::map<std::tuple<const double*, int, int>, long long> ft_index;
+    std::vector<int> ft_rep;
     long long tf = 0;
-    for (int i = 0; i < count; ++i) { ftoff[i] = tf; tf += (long long)b->rank_max * hi[i].n; }
+    for (int i = 0; i < count; ++i) {
+      const auto key = std::make_tuple(hi[i].F, hi[i].n, hi[i].r);
+      const auto it = ft_index.find(key);
+      if (it != ft_index.end()) { ftoff[i] = it->second; continue; }
+      ftoff[i] = tf;
+      ft_index.emplace(key, tf);
+      ft_rep.push_back(i);
+      tf += (long long)b->rank_max * hi[i].n;
+    }
     HBC(hipMalloc(&b->ft, std::max<long long>(tf, 1) * sizeof(double)));
     HBC(hipMalloc(&b->d_ftoff, count * sizeof(long long)));
     HBC(hipMemcpyAsync(b->d_ftoff, ftoff.data(), count * sizeof(long long), hipMemcpyHostToDevice, st));
@@ -1009,7 +1024,10 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     HBC(hipMemcpyAsync(b->d_toff, toff.data(), toff.size() * sizeof(long long), hipMemcpyHostToDevice, st));
     k_batch_transpose<<<(int)reps.size(), 256, 0, st>>>(b->d_insts, b->d_rep, (int)reps.size(), b->trp, b->tci,
                                                          b->tval, b->d_toff);
-    k_batch_ft<<<count, 256, 0, st>>>(b->d_insts, count, b->rank_max, b->ft, b->d_ftoff);
+    HBC(hipMalloc(&b->d_ftrep, ft_rep.size() * sizeof(int)));
+    HBC(hipMemcpyAsync(b->d_ftrep, ft_rep.data(), ft_rep.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    k_batch_ft<<<(int)ft_rep.size(), 256, 0, st>>>(b->d_insts, b->d_ftrep, (int)ft_rep.size(), b->rank_max, b->ft,
+                                                   b->d_ftoff);
     // largest instances first
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;

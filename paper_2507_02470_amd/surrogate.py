@@ -237,21 +237,24 @@ class WarmStartSurrogate:
 
 def warm_vs_cold(sur: WarmStartSurrogate, samples, tol=1e-8, max_iter=200_000):
     """Solve `samples` cold and warm-started (with fallback); returns a dict of
-    per-sample iterations, wall times and the fallback count."""
+    per-sample iterations, wall times and the fallback count.  Both timings
+    include staging the samples on the device; the warm one also the network
+    (its input [c; u] taken from the staged copies)."""
     base = sur.base
     n, m = base.n, base.m
-    X = np.stack([family_features(c, u) for (c, l, u) in samples])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc = solve_family(base, samples, tol=tol, max_iter=max_iter)
     torch.cuda.synchronize()
     t_cold = time.perf_counter() - t0
     t0 = time.perf_counter()
-    y0, w0, x0, bad = sur.starts(X)
+    bs = BatchSolver(samples, shared=base, tol=tol, max_iter=max_iter)
+    y0, w0, x0, bad = sur.starts(bs.shared_features())
     badm = bad.bool()
     if badm.any():
         y0[badm] = 0; w0[badm] = 0; x0[badm] = 0
-    rw = solve_family(base, samples, tol=tol, max_iter=max_iter, starts=(y0, w0, x0))
+    rw = bs.solve(y0=y0.reshape(-1), w0=w0.reshape(-1), x0=x0.reshape(-1), split=False)
+    bs.close()
     it_w = np.array([f["iters"] for f in rw.infos])
     failed = [i for i, f in enumerate(rw.infos) if f["term"] != "solved"]
     fallback = sorted(set(failed) | set(np.nonzero(badm.cpu().numpy())[0].tolist()))

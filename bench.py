@@ -429,6 +429,7 @@ def extra_warm_cold(n_train, n_eval, epochs):
     Xe = np.stack([family_features(c, u) for (c, l, u) in held[:512]])
     sur.net.forward(Xe)
     ms, fl = sur.net.gemm_stats()
+    sur.starts(Xe)   # first use of the warm-start kernels outside the timed comparison
     res = warm_vs_cold(sur, held)
     ic, iw = res["iters_cold"], res["iters_warm"]
     return dict(workload="portfolio_family", n=base.n, m=base.m, train_samples=n_train, eval_samples=n_eval,
@@ -467,7 +468,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--train-samples", type=int, default=50_000)
     ap.add_argument("--eval-samples", type=int, default=4096)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--qap-dims", type=int, nargs="*", default=[256, 512],
                     help="sizes d of the synthetic QAP relaxations (n = d^2)")
     ap.add_argument("--qap-time-cap", type=float, default=30.0, help="seconds per QAP solve to 1e-8")

@@ -1,9 +1,12 @@
 // batch.hip -- many independent HPR-QPs (Algorithm 4 + Algorithm 5 of arXiv
-// 2507.02470) in one persistent kernel on one MI355X.
+// 2507.02470) in persistent kernels on one MI355X.
 //
-// One 512-thread workgroup owns one instance at a time; instances are pulled
-// from a work queue ordered by size (largest first).  Thread t owns entries
-// t + 512 e, e < HB_EPT (so n <= 512 * HB_EPT): the per-iteration vectors of
+// One workgroup owns one instance at a time; instances are pulled from a
+// work queue ordered by size (largest first).  Instances with n <= 1024 run
+// on a 256-thread kernel whose LDS lets two workgroups share a CU, the
+// others on a 512-thread kernel (one per CU), both at once on two streams.
+// Thread t of a BS-thread workgroup owns entries t + BS e, e < HB_EPT (so
+// n <= BS * HB_EPT): the per-iteration vectors of
 // its entries are in registers, and so are its rows of the low-rank factor F
 // of Q = diag(d) + F F^T at rank <= 10 (at rank 16 they are read from memory
 // at each product); the iterate, its images Q w and A^T y, the Halpern
@@ -23,6 +26,7 @@
 #include <chrono>
 #include <map>
 #include <tuple>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -33,14 +37,27 @@ extern thread_local std::string g_err;
 }
 
 #define HB_BS 512
-#define HB_WAVES (HB_BS / 64)
 #define HB_EPT 4
-#define HB_NMAX (HB_BS * HB_EPT)
+#define HB_NMAX (HB_BS * HB_EPT)                      // largest n (the 512-thread kernel)
+#define HB_NMAX_SMALL 1024                             // largest n of the 256-thread kernel
 #define HB_MMAX 64
 #define HB_RMAX 16
 #define HB_APIECE 256                                  // nonzeros of A per wave work item
 #define HB_ATSTEP 3                                    // nonzeros per entry and step of the A^T product
-#define HB_PMAX (HB_MMAX + HB_MMAX * HB_NMAX / HB_APIECE)  // pieces of A at most
+
+// Per-block sizes of the two kernels: 512 threads for n <= 2048 (one block
+// per CU, the LDS holds 156 KB), 256 threads for n <= 1024 (two per CU, so
+// that one block's waits are covered by the other's work).  Entry i of a
+// vector belongs to thread i mod BS, so NMAX = BS * HB_EPT: the slots of
+// every thread's HB_EPT entries exist, also beyond n.
+template <int BS>
+struct BCfg {
+  static constexpr int WAVES = BS / 64;
+  static constexpr int NMAX = BS * HB_EPT;
+  // pieces of A at most: a row has at most n nonzeros (checked at create)
+  static constexpr int PMAX = HB_MMAX * ((NMAX + HB_APIECE - 1) / HB_APIECE);
+  static_assert(NMAX == (BS == HB_BS ? HB_NMAX : HB_NMAX_SMALL), "class sizes");
+};
 
 struct BInst {
   int n, m, r;
@@ -75,20 +92,24 @@ struct BInfo {
 // ---------------------------------------------------------------------------
 #define HB_RED 16   // most values reduced at once
 
+template <int BS>
 struct BShared {
-  alignas(16) double red[2][HB_RED][HB_WAVES];   // wave partials, two buffers used in turn
-  double vm[HB_NMAX];                // a length-n vector shared by the block (A v, A xbar)
+  static constexpr int NMAX = BCfg<BS>::NMAX, PMAX = BCfg<BS>::PMAX;
+  alignas(16) double red[2][HB_RED][BCfg<BS>::WAVES];   // wave partials, two buffers used in turn
+  double vm[NMAX];                   // a length-n vector shared by the block (A v, A xbar)
   // Halpern anchors u^{r,0} and their images (read once per iteration)
-  double xa[HB_NMAX], wa[HB_NMAX], Qwa[HB_NMAX], ATya[HB_NMAX];
+  double xa[NMAX], wa[NMAX], Qwa[NMAX], ATya[NMAX];
   // iterate u^{r,t} = (x, w) with the images Q w and A^T y kept by linearity
-  double xs[HB_NMAX], ws[HB_NMAX], Qws[HB_NMAX], ATys[HB_NMAX];
-  double y[HB_MMAX], ya[HB_MMAX], yb[HB_MMAX], l[HB_MMAX], u[HB_MMAX], ry[HB_MMAX];
-  double yn[HB_MMAX];                // y^{t+1} (Halpern) until the check is done
-  double pw[HB_MMAX];                // power method vector (length m)
+  double xs[NMAX], ws[NMAX], Qws[NMAX], ATys[NMAX];
+  double y[HB_MMAX], ya[HB_MMAX], yb[HB_MMAX], l[HB_MMAX], u[HB_MMAX];
+  union {
+    double yn[HB_MMAX];              // y^{t+1} (Halpern) until the check is done
+    double pw[HB_MMAX];              // power method vector (length m), before the iterations
+  };
   // A products: row r of A is cut into pieces of HB_APIECE nonzeros; piece
   // q belongs to row prow[q] and pieces pstart[r] .. pstart[r+1]-1 to row r
-  double part[HB_PMAX];
-  short prow[HB_PMAX];
+  double part[PMAX];
+  unsigned char prow[PMAX];          // (m <= 64)
   int pstart[HB_MMAX + 1];
   int arp[HB_MMAX + 1];              // row pointers of A
   int np;
@@ -124,13 +145,14 @@ __device__ __forceinline__ double wave_reduce63(double v) {
 // Block-wide reduction of K values (sum, or max where bit s of maxmask is
 // set; maxima only of non-negative values) with one barrier: DPP wave
 // reductions, lane 63 of each wave stores its partials, then every wave
-// combines the partials of value s on lanes 8s..8s+7 with a fixed butterfly
-// and broadcasts the result.  Fixed order, deterministic.  The two partial
+// combines the W wave partials of value s on lanes Ws..Ws+W-1 with a fixed
+// butterfly and broadcasts the result.  Fixed order, deterministic.  The two partial
 // buffers alternate between calls, so a buffer is rewritten only after every
 // thread has passed the barrier of the call in between.
-template <int K>
-__device__ __forceinline__ void bred(BShared& S, int& par, double (&v)[K], unsigned maxmask) {
-  static_assert(K <= HB_RED && HB_WAVES == 8, "reduction layout");
+template <int K, int BS>
+__device__ __forceinline__ void bred(BShared<BS>& S, int& par, double (&v)[K], unsigned maxmask) {
+  constexpr int W = BCfg<BS>::WAVES;   // partials per value
+  static_assert(K <= HB_RED && (W == 4 || W == 8), "reduction layout");
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int s = 0; s < K; ++s) {
@@ -138,18 +160,19 @@ __device__ __forceinline__ void bred(BShared& S, int& par, double (&v)[K], unsig
     if (lane == 63) S.red[par][s][wv] = x;
   }
   __syncthreads();
+  constexpr int VP = 64 / W;   // values combined per pass
 #pragma unroll
-  for (int s0 = 0; s0 < K; s0 += 8) {
-    const int s = s0 + (lane >> 3), w = lane & 7;
+  for (int s0 = 0; s0 < K; s0 += VP) {
+    const int s = s0 + lane / W, w = lane % W;
     const bool mx = (maxmask >> s) & 1u;
     double x = s < K ? S.red[par][s][w] : 0.0;
 #pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
+    for (int off = 1; off < W; off <<= 1) {
       const double y = __shfl_xor(x, off);
       x = mx ? fmax(x, y) : x + y;
     }
 #pragma unroll
-    for (int q = s0; q < K && q < s0 + 8; ++q) v[q] = __shfl(x, (q - s0) * 8);
+    for (int q = s0; q < K && q < s0 + VP; ++q) v[q] = __shfl(x, (q - s0) * W);
   }
   par ^= 1;
 }
@@ -170,14 +193,14 @@ __device__ __forceinline__ double2 gld(const double2* p, long long i) {
   return double2{v.x, v.y};
 }
 
-template <int RM>
+template <int RM, int BS>
 struct Elem {
   int n, m, r;
   const double* FT;       // F with rows padded to RM: F(i, k) = FT[i RM + k], zero for k >= r
   const double *c, *L, *U, *dg;
   int tid;                // threadIdx.x, refreshed through an empty asm statement every iteration
-  __device__ bool valid(int e) const { return tid + e * HB_BS < n; }
-  __device__ int idx(int e) const { return tid + e * HB_BS; }
+  __device__ bool valid(int e) const { return tid + e * BS < n; }
+  __device__ int idx(int e) const { return tid + e * BS; }
   // Addresses derived from the thread index are then recomputed in every
   // iteration instead of being hoisted out of the solve loop, where they
   // would outnumber the registers and be spilled.
@@ -199,7 +222,8 @@ struct QRows {
   // (the base address passes through an empty asm statement so that the
   // compiler cannot move the loads above the point of the call, which would
   // keep the copy live across a check)
-  __device__ void load(const Elem<RM>& E) {
+  template <int BS>
+  __device__ void load(const Elem<RM, BS>& E) {
     if constexpr (REG) {
       const double* FT = E.FT;
       asm volatile("" : "+s"(FT));
@@ -216,16 +240,18 @@ struct QRows {
       }
     }
   }
-  __device__ __forceinline__ double2 row2(const Elem<RM>& E, int e, int k) const {
+  template <int BS>
+  __device__ __forceinline__ double2 row2(const Elem<RM, BS>& E, int e, int k) const {
     if constexpr (REG) return double2{f[e][2 * k], f[e][2 * k + 1]};
     else return gld(reinterpret_cast<const double2*>(E.FT + (size_t)E.idx(e) * RM), k);
   }
-  __device__ __forceinline__ double diag(const Elem<RM>& E, int e) const { return gld(E.dg, E.idx(e)); }
+  template <int BS>
+  __device__ __forceinline__ double diag(const Elem<RM, BS>& E, int e) const { return gld(E.dg, E.idx(e)); }
 };
 
 // q = Q p = diag(d) p + F (F^T p)
-template <int RM, bool REG>
-__device__ __forceinline__ void q_apply(BShared& S, int& par, const Elem<RM>& E, const QRows<RM, REG>& Fq,
+template <int RM, bool REG, int BS>
+__device__ __forceinline__ void q_apply(BShared<BS>& S, int& par, const Elem<RM, BS>& E, const QRows<RM, REG>& Fq,
                                         const double (&p)[HB_EPT], double (&q)[HB_EPT]) {
   static_assert(RM % 2 == 0, "rows are read in pairs");
   double t[RM];
@@ -262,38 +288,41 @@ __device__ __forceinline__ void q_apply(BShared& S, int& par, const Elem<RM>& E,
 }
 
 // Pieces of the rows of A for a_apply (thread 0, once per instance).
-__device__ void a_pieces(BShared& S, const BInst& I) {
+template <int BS>
+__device__ void a_pieces(BShared<BS>& S, const BInst& I) {
   int q = 0;
   for (int r = 0; r < I.m; ++r) {
     S.pstart[r] = q;
     S.arp[r] = I.arp[r];
     const int len = I.arp[r + 1] - I.arp[r];
-    for (int c = 0; c * HB_APIECE < len; ++c) S.prow[q++] = (short)r;
+    for (int c = 0; c * HB_APIECE < len; ++c) S.prow[q++] = (unsigned char)r;
   }
   S.pstart[I.m] = q;
   S.arp[I.m] = I.m > 0 ? I.arp[I.m] : 0;
   S.np = q;
 }
 
-// S.ry[row] = (A p)_row, p staged through S.vm.  The waves share the pieces
-// of all rows (a dense row does not serialise on one wave); thread row < m
-// then adds its row's pieces in order and is the only reader of S.ry[row].
-template <int RM>
-__device__ __forceinline__ void a_apply(BShared& S, const Elem<RM>& E, const BInst& I, const double (&p)[HB_EPT]) {
+// (A p)_row for thread row < m (0 for the other threads), p staged through
+// S.vm.  The waves share the pieces of all rows (a dense row does not
+// serialise on one wave); thread row < m then adds its row's pieces in order.
+template <int RM, int BS>
+__device__ __forceinline__ double a_apply(BShared<BS>& S, const Elem<RM, BS>& E, const BInst& I,
+                                          const double (&p)[HB_EPT]) {
+  constexpr int WAVES = BCfg<BS>::WAVES;
 #pragma unroll
   for (int e = 0; e < HB_EPT; ++e)
     if (E.valid(e)) S.vm[E.idx(e)] = p[e];
   __syncthreads();
-  // a wave takes pieces q0 and q0 + HB_WAVES together (loads of both in
+  // a wave takes pieces q0 and q0 + WAVES together (loads of both in
   // flight); each piece's sum is formed as for one piece at a time
   const int lane = E.tid & 63, wv = E.tid >> 6;
   constexpr int U = HB_APIECE / 64;
-  for (int q0 = wv; q0 < S.np; q0 += 2 * HB_WAVES) {
+  for (int q0 = wv; q0 < S.np; q0 += 2 * WAVES) {
     double av[2][U];
     int ac[2][U];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int q = q0 + h * HB_WAVES;
+      const int q = q0 + h * WAVES;
       int b = 0, e = 0;
       if (q < S.np) {
         const int row = S.prow[q];
@@ -314,24 +343,23 @@ __device__ __forceinline__ void a_apply(BShared& S, const Elem<RM>& E, const BIn
       for (int u = 0; u < U; ++u)
         if (ac[h][u] >= 0) s += av[h][u] * S.vm[ac[h][u]];
       s = wave_sum(s);
-      const int q = q0 + h * HB_WAVES;
+      const int q = q0 + h * WAVES;
       if (lane == 0 && q < S.np) S.part[q] = s;
     }
   }
   __syncthreads();
-  if (E.tid < E.m) {
-    double s = 0.0;
+  double s = 0.0;
+  if (E.tid < E.m)
     for (int q = S.pstart[E.tid]; q < S.pstart[E.tid + 1]; ++q) s += S.part[q];
-    S.ry[E.tid] = s;
-  }
+  return s;
 }
 
 // g = A^T yv (yv in LDS, length m); tb/te: the entries' ranges in A^T,
 // loaded once per instance.  The thread's entries advance together,
 // HB_ATSTEP nonzeros per step, so that their loads are in flight at the same
 // time (each entry's sum still runs over its nonzeros in order).
-template <int RM>
-__device__ __forceinline__ void at_apply(const Elem<RM>& E, const BInst& I, const int (&tb)[HB_EPT],
+template <int RM, int BS>
+__device__ __forceinline__ void at_apply(const Elem<RM, BS>& E, const BInst& I, const int (&tb)[HB_EPT],
                                          const int (&te)[HB_EPT], const double* yv, double (&g)[HB_EPT]) {
   int len = 0;
 #pragma unroll
@@ -379,7 +407,8 @@ __device__ double golden_sigma_dev(double th1, double th2, double th3, double la
 
 // Halpern step for entry i: u^{r,t+1} = rho u^{r,0} + (1 - rho)(2 ubar - u),
 // with Q w and A^T y carried along by linearity
-__device__ __forceinline__ void halpern(BShared& S, int i, double rho, bool has_rows, double xb, double wb,
+template <int BS>
+__device__ __forceinline__ void halpern(BShared<BS>& S, int i, double rho, bool has_rows, double xb, double wb,
                                         double Qwb, double g) {
   const double xn = rho * S.xa[i] + (1.0 - rho) * (2.0 * xb - S.xs[i]);
   const double wn = rho * S.wa[i] + (1.0 - rho) * (2.0 * wb - S.ws[i]);
@@ -392,7 +421,8 @@ __device__ __forceinline__ void halpern(BShared& S, int i, double rho, bool has_
 // Algorithm 5 at a check; thread 0 only, results in S.ctrl.  Kept out of
 // line: it runs once per check and its golden section needs registers the
 // iteration does not.
-__device__ __noinline__ void check_decision(BShared& S, const BOpts& o, double eta_p, double eta_d, double eta_gap,
+template <int BS>
+__device__ __noinline__ void check_decision(BShared<BS>& S, const BOpts& o, double eta_p, double eta_d, double eta_gap,
                                             double R, double Rr0, double Rprev, long long t, long long k, double lamA,
                                             double lamQ, double thy, double thw, double thq, double th2, double th3,
                                             double sigma, double alpha3, double R0ref) {
@@ -427,23 +457,24 @@ __device__ __noinline__ void check_decision(BShared& S, const BOpts& o, double e
 // ---------------------------------------------------------------------------
 // persistent kernel (RM: largest rank of F handled, F rows padded with zeros)
 // ---------------------------------------------------------------------------
-template <int RM>
-__global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__ insts, const int* __restrict__ order,
+template <int RM, int BS>
+__global__ __launch_bounds__(BS, 2) void k_batch_solve(const BInst* __restrict__ insts, const int* __restrict__ order,
                                                       int count, int* __restrict__ queue, BOpts o,
                                                       const double* __restrict__ y0, const double* __restrict__ w0,
                                                       const double* __restrict__ x0, double* __restrict__ yo,
                                                       double* __restrict__ zo, double* __restrict__ wo,
                                                       double* __restrict__ xo, BInfo* __restrict__ infos,
                                                       double* __restrict__ hbuf) {
-  __shared__ BShared S;
+  constexpr int NM = BCfg<BS>::NMAX;
+  __shared__ BShared<BS> S;
   const int tid = threadIdx.x;
   int par = 0;
   // the block's check buffer: xbar, wbar, Q wbar, A^T ybar, zbar (entries owned per thread)
-  double* const Hx = hbuf + (size_t)blockIdx.x * 5 * HB_NMAX;
-  double* const Hw = Hx + HB_NMAX;
-  double* const HQw = Hx + 2 * HB_NMAX;
-  double* const Hg = Hx + 3 * HB_NMAX;
-  double* const Hz = Hx + 4 * HB_NMAX;   // reduction buffer in turn (uniform over the block)
+  double* const Hx = hbuf + (size_t)blockIdx.x * 5 * NM;
+  double* const Hw = Hx + NM;
+  double* const HQw = Hx + 2 * NM;
+  double* const Hg = Hx + 3 * NM;
+  double* const Hz = Hx + 4 * NM;
   for (;;) {
     if (tid == 0) S.inst = atomicAdd(queue, 1);
     __syncthreads();
@@ -452,7 +483,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
     if (qi >= count) break;                        // every wave leaves together
     const int ii = order[qi];
     const BInst I = insts[ii];
-    Elem<RM> E;
+    Elem<RM, BS> E;
     E.n = I.n; E.m = I.m; E.r = I.r; E.FT = I.FT;
     E.c = I.c; E.L = I.L; E.U = I.U; E.dg = I.dg;
     E.refresh();
@@ -501,15 +532,15 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
       double lam = 0.0, lam_old = 0.0;
       for (int it = 1; it <= 5000; ++it) {
         at_apply(E, I, tb, te, S.pw, pv);          // u = A^T v
-        a_apply(S, E, I, pv);                      // w = A u  -> S.ry
+        const double au = a_apply(S, E, I, pv);    // w = A u (row tid)
         double rr[2] = {0.0, 0.0};
-        if (tid < m) { rr[0] = S.pw[tid] * S.ry[tid]; rr[1] = S.ry[tid] * S.ry[tid]; }
+        if (tid < m) { rr[0] = S.pw[tid] * au; rr[1] = au * au; }
         bred<2>(S, par, rr, 0u);
         lam = rr[0];
         if (rr[1] == 0.0) break;
         if (it > 1 && fabs(lam - lam_old) <= 1e-6 * fabs(lam)) break;
         lam_old = lam;
-        if (tid < m) S.pw[tid] = S.ry[tid] / sqrt(rr[1]);
+        if (tid < m) S.pw[tid] = au / sqrt(rr[1]);
         __syncthreads();
       }
       lamA = 1.01 * lam;
@@ -538,7 +569,7 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
     const double sigma_init = sigma;
 
     // ---- state: origin or warm start ----
-    // the iterate lives in LDS; thread t owns entries t + 512 e (no other
+    // the iterate lives in LDS; thread t owns entries t + BS e (no other
     // thread reads them), so updates need no barrier
 #pragma unroll
     for (int e = 0; e < HB_EPT; ++e) {
@@ -605,10 +636,10 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
         double v[HB_EPT];
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) v[e] = E.valid(e) ? xh[e] + kappa * (S.Qws[E.idx(e)] - q1[e]) : 0.0;
-        a_apply(S, E, I, v);
+        const double av = a_apply(S, E, I, v);
         if (tid < m) {
           const double yi = S.y[tid], yai = S.ya[tid];
-          const double rr = S.ry[tid] - sA * yi;
+          const double rr = av - sA * yi;
           const double ybv = (clampd(rr, S.l[tid], S.u[tid]) - rr) / sA;
           S.yb[tid] = ybv;
           dy2 = (yi - ybv) * (yi - ybv);
@@ -697,11 +728,11 @@ __global__ __launch_bounds__(HB_BS) void k_batch_solve(const BInst* __restrict__
 #pragma unroll
         for (int e = 0; e < HB_EPT; ++e) xbv[e] = Hx[E.idx(e)];
         q_apply(S, par, E, Fg, xbv, Qx);
-        if (m > 0) a_apply(S, E, I, xbv);           // S.ry = A xbar
+        const double ax = m > 0 ? a_apply(S, E, I, xbv) : 0.0;   // (A xbar)_tid
         // res: 0 max|Ax-PiK|, 1 max|Ax|, 2 sum(l y+ + u y-), 3 #inf, 4 max|dual|, 5 max|g|, 6 max|Qx|,
         //      7 <x,Qx>, 8 <c,x>, 9 sum(L z+ + U z-) (+ #inf folded into 3)
         if (tid < m) {
-          const double ax = S.ry[tid], li = S.l[tid], ui = S.u[tid], yv = S.yb[tid];
+          const double li = S.l[tid], ui = S.u[tid], yv = S.yb[tid];
           res[0] = fabs(ax - clampd(ax, li, ui));
           res[1] = fabs(ax);
           if (yv > 0.0) { if (isinf(li)) res[3] += 1.0; else res[2] += li * yv; }
@@ -806,7 +837,8 @@ __global__ void k_batch_validate(const BInst* __restrict__ insts, int count, int
   for (int i = threadIdx.x; i < I.m; i += blockDim.x) {
     if (!(I.l[i] <= I.u[i]) || I.l[i] == INFINITY || I.u[i] == -INFINITY) f |= 1;
     const int b = I.arp[i], e = I.arp[i + 1];
-    if ((i == 0 && b != 0) || b < 0 || e < b || (long long)e > I.annz || (i == I.m - 1 && e != I.annz)) f |= 2;
+    if ((i == 0 && b != 0) || b < 0 || e < b || (long long)e > I.annz || (i == I.m - 1 && e != I.annz) || e - b > I.n)
+      f |= 2;
   }
   if (f) atomicOr(&sflag, f);
   __syncthreads();
@@ -867,7 +899,9 @@ __global__ void k_batch_ft(const BInst* __restrict__ insts, const int* __restric
   }
 }
 
-__global__ void k_zero_int1(int* p) { *p = 0; }
+__global__ void k_zero_ints(int* p, int k) {
+  if ((int)threadIdx.x < k) p[threadIdx.x] = 0;
+}
 
 // ---------------------------------------------------------------------------
 // host side
@@ -888,18 +922,29 @@ struct hprqp_batch {
   double* ft = nullptr;        // F of every instance, rows padded to rank_max
   long long* d_ftoff = nullptr;
   int* d_ftrep = nullptr;      // one instance per distinct F
-  double* hbuf = nullptr;      // per-block check buffers
+  // instances with n > HB_NMAX_SMALL (d_order[0, nbig)) run on the 512-thread
+  // kernel, the others (d_order[nbig, count)) on the 256-thread kernel, on a
+  // second stream at the same time; d_queue holds one counter per kernel
+  int nbig = 0, nsmall = 0;
+  int grid_big = 0, grid_small = 0;
+  double* hbuf = nullptr;      // per-block check buffers of the 512-thread kernel
+  double* hbuf_small = nullptr;
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   long long total_n = 0, total_m = 0;
-  int grid = 0;
   int rank_max = 0;       // 10 or 16: the kernel instantiation used
   double last_kernel_s = 0.0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ~hprqp_batch() {
-    void* ps[] = {d_insts, d_order, d_queue, d_flags, d_infos, trp, tci, tval, d_toff, d_rep, ft, d_ftoff, d_ftrep, hbuf};
+    void* ps[] = {d_insts, d_order, d_queue, d_flags,   d_infos, trp,     tci,     tval,
+                  d_toff,  d_rep,   ft,      d_ftoff,   d_ftrep, hbuf,    hbuf_small};
     for (void* p : ps)
       if (p) hipFree(p);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
+    if (ev_fork) hipEventDestroy(ev_fork);
+    if (ev_join) hipEventDestroy(ev_join);
+    if (st2) hipStreamDestroy(st2);
     if (own_st) hipStreamDestroy(own_st);
   }
 };
@@ -1034,15 +1079,36 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return hi[a].n > hi[c].n; });
     HBC(hipMalloc(&b->d_order, count * sizeof(int)));
     HBC(hipMemcpyAsync(b->d_order, order.data(), count * sizeof(int), hipMemcpyHostToDevice, st));
-    HBC(hipMalloc(&b->d_queue, sizeof(int)));
+    HBC(hipMalloc(&b->d_queue, 2 * sizeof(int)));
     HBC(hipMalloc(&b->d_infos, count * sizeof(BInfo)));
-    int dev = 0, ncu = 0, per_cu = 0;
+    b->nbig = 0;
+    while (b->nbig < count && hi[order[b->nbig]].n > HB_NMAX_SMALL) ++b->nbig;
+    b->nsmall = count - b->nbig;
+    int dev = 0, ncu = 0;
     HBC(hipGetDevice(&dev));
     HBC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    if (b->rank_max == 10) HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_solve<10>, HB_BS, 0));
-    else HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_solve<16>, HB_BS, 0));
-    b->grid = std::max(1, std::min(count, ncu * std::max(per_cu, 1)));
-    HBC(hipMalloc(&b->hbuf, (size_t)b->grid * 5 * HB_NMAX * sizeof(double)));
+    const auto resident = [&](const void* kern, int bs) {
+      int per_cu = 0;
+      HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, bs, 0));
+      return ncu * std::max(per_cu, 1);
+    };
+    if (b->nbig > 0) {
+      const int r = b->rank_max == 10 ? resident((const void*)k_batch_solve<10, HB_BS>, HB_BS)
+                                      : resident((const void*)k_batch_solve<16, HB_BS>, HB_BS);
+      b->grid_big = std::max(1, std::min(b->nbig, r));
+      HBC(hipMalloc(&b->hbuf, (size_t)b->grid_big * 5 * HB_NMAX * sizeof(double)));
+    }
+    if (b->nsmall > 0) {
+      const int r = b->rank_max == 10 ? resident((const void*)k_batch_solve<10, HB_BS / 2>, HB_BS / 2)
+                                      : resident((const void*)k_batch_solve<16, HB_BS / 2>, HB_BS / 2);
+      b->grid_small = std::max(1, std::min(b->nsmall, r));
+      HBC(hipMalloc(&b->hbuf_small, (size_t)b->grid_small * 5 * HB_NMAX_SMALL * sizeof(double)));
+    }
+    if (b->nbig > 0 && b->nsmall > 0) {
+      HBC(hipStreamCreateWithFlags(&b->st2, hipStreamNonBlocking));
+      HBC(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+      HBC(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    }
     HBC(hipEventCreate(&b->e0));
     HBC(hipEventCreate(&b->e1));
     HBC(hipStreamSynchronize(st));
@@ -1057,15 +1123,34 @@ void solve_batch_impl(hprqp_batch* b, const double* y0, const double* w0, const 
                       double* w, double* x, hprqp_info* infos) {
   if (!b || !z || !w || !x || (b->total_m > 0 && !y)) bfail(HPRQP_ERR_ARG, "NULL argument");
   if (b->own_st) HBC(hipDeviceSynchronize());
-  k_zero_int1<<<1, 1, 0, b->st>>>(b->d_queue);
+  k_zero_ints<<<1, 64, 0, b->st>>>(b->d_queue, 2);
   HBC(hipEventRecord(b->e0, b->st));
-  if (b->rank_max == 10)
-    k_batch_solve<10><<<b->grid, HB_BS, 0, b->st>>>(b->d_insts, b->d_order, b->count, b->d_queue, b->o, y0, w0, x0,
-                                                    y, z, w, x, b->d_infos, b->hbuf);
-  else
-    k_batch_solve<16><<<b->grid, HB_BS, 0, b->st>>>(b->d_insts, b->d_order, b->count, b->d_queue, b->o, y0, w0, x0,
-                                                    y, z, w, x, b->d_infos, b->hbuf);
-  HBC(hipGetLastError());
+  // one launch per class; the 256-thread kernel on the second stream when both run
+  const auto launch = [&](auto bs_tag, hipStream_t s, int grid, int first, int cnt, int* queue, double* hbuf) {
+    constexpr int BS = decltype(bs_tag)::value;
+    if (b->rank_max == 10)
+      k_batch_solve<10, BS><<<grid, BS, 0, s>>>(b->d_insts, b->d_order + first, cnt, queue, b->o, y0, w0, x0, y, z, w,
+                                                x, b->d_infos, hbuf);
+    else
+      k_batch_solve<16, BS><<<grid, BS, 0, s>>>(b->d_insts, b->d_order + first, cnt, queue, b->o, y0, w0, x0, y, z, w,
+                                                x, b->d_infos, hbuf);
+    HBC(hipGetLastError());
+  };
+  hipStream_t s_small = b->st;
+  if (b->st2) {
+    HBC(hipEventRecord(b->ev_fork, b->st));
+    HBC(hipStreamWaitEvent(b->st2, b->ev_fork, 0));
+    s_small = b->st2;
+  }
+  if (b->nbig > 0)
+    launch(std::integral_constant<int, HB_BS>{}, b->st, b->grid_big, 0, b->nbig, b->d_queue, b->hbuf);
+  if (b->nsmall > 0)
+    launch(std::integral_constant<int, HB_BS / 2>{}, s_small, b->grid_small, b->nbig, b->nsmall, b->d_queue + 1,
+           b->hbuf_small);
+  if (b->st2) {
+    HBC(hipEventRecord(b->ev_join, b->st2));
+    HBC(hipStreamWaitEvent(b->st, b->ev_join, 0));
+  }
   HBC(hipEventRecord(b->e1, b->st));
   std::vector<BInfo> hi(b->count);
   HBC(hipMemcpyAsync(hi.data(), b->d_infos, b->count * sizeof(BInfo), hipMemcpyDeviceToHost, b->st));

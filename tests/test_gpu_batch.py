@@ -34,7 +34,8 @@ def _rel(a, b):
     return np.max(np.abs(a - b), initial=0.0) / max(1.0, np.max(np.abs(b), initial=0.0))
 
 
-SIZES = [50, 63, 64, 65, 511, 512, 513, 1000, 1537, 2000, 2048]
+# (n <= 1024 runs on the 256-thread kernel, larger n on the 512-thread one)
+SIZES = [50, 63, 64, 65, 511, 512, 513, 1000, 1024, 1025, 1537, 2000, 2048]
 
 
 def _insts(seed0=20_000):

@@ -236,11 +236,14 @@ hprqp_status hprqp_kernel_stats(hprqp_handle *h, double *avg_ms_host, int64_t *l
 void hprqp_destroy(hprqp_handle *h);
 
 /* ---------------------------------------------------------------------
- * Batched solve: many independent QPs (sizes may differ) solved by one
- * persistent kernel, one workgroup per instance at a time, with the whole
+ * Batched solve: many independent QPs (sizes may differ) solved by
+ * persistent kernels, one workgroup per instance at a time, with the whole
  * of Algorithm 4 + 5 (restart, sigma update, termination) on the device.
- * Supported: qkind HPRQP_Q_LOWRANK with lr_rank <= 16 and n <= 2048,
- * m <= 64 per instance (no preconditioning: Q is matrix-free).
+ * Instances with n <= 1024 run on a second kernel (two workgroups per
+ * compute unit) on a stream of the library's, joined to `stream` before
+ * the solve returns.  Supported: qkind HPRQP_Q_LOWRANK with lr_rank <= 16
+ * and n <= 2048, m <= 64 per instance, at most n nonzeros in a row of A
+ * (no preconditioning: Q is matrix-free).
  * --------------------------------------------------------------------- */
 
 /* probs: host array of `count` problems whose arrays are device pointers;
@@ -258,7 +261,8 @@ hprqp_status hprqp_batch_create(int32_t count, const hprqp_problem *probs,
 hprqp_status hprqp_solve_batch(hprqp_batch *b, const double *y0, const double *w0, const double *x0,
                                double *y, double *z, double *w, double *x, hprqp_info *infos_host);
 
-/* Elapsed time of the last hprqp_solve_batch kernel (HIP events), seconds. */
+/* Elapsed time of the last hprqp_solve_batch kernels (HIP events on `stream`
+ * around both), seconds. */
 double hprqp_batch_last_kernel_s(hprqp_batch *b);
 
 void hprqp_batch_destroy(hprqp_batch *b);

@@ -10,9 +10,13 @@
 // in a fixed order), and the reductions of a phase go through the block
 // reduction into the same slots, with one partial per slot.  When the
 // matrices and every vector of the iteration fit (dynamic LDS, up to
-// HQ_SMALL_LDS bytes), they are copied into LDS at the start of the segment
-// and the written vectors back at its end, so every gather is an LDS access;
-// otherwise they stay in global memory.  Explicit Q (CSR) or Q = 0 only.
+// HQ_SMALL_LDS bytes; STAGED), they are copied into LDS at the start of the
+// segment and the written vectors back at its end, so every gather is an LDS
+// access; otherwise they stay in global memory.  The staged kernel derives
+// every pointer from the LDS base only (never a global fallback), so the
+// compiler addresses them as LDS (ds_read/ds_write) instead of generic flat
+// accesses, which go through the vector-memory path and are counted by both
+// wait counters.  Explicit Q (CSR) or Q = 0 only.
 #pragma once
 #include "common.hpp"
 #include "epilogues.hpp"
@@ -95,7 +99,7 @@ __device__ __forceinline__ void small_copy(T* __restrict__ dst, const T* __restr
   for (int i = threadIdx.x; i < count; i += HQ_SMALL_BS) dst[i] = src[i];
 }
 
-template <int G>
+template <int G, bool STAGED>
 __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int Tseg) {
   extern __shared__ __align__(16) unsigned char small_lds[];
   // the arrays the phases use: LDS copies when staged, else the global ones
@@ -103,8 +107,8 @@ __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int 
   SmallMat mats[3] = {a.A, a.AT, a.Q};
   // (loops over the arrays are unrolled so that V and mats stay in registers)
 #pragma unroll
-  for (int s = 0; s < SV_COUNT; ++s) V[s] = a.vec[s];
-  if (a.lds_bytes > 0) {
+  for (int s = 0; s < SV_COUNT; ++s) V[s] = STAGED ? nullptr : a.vec[s];
+  if (STAGED) {
 #pragma unroll
     for (int s = 0; s < SV_COUNT; ++s)
       if (a.vec[s]) {
@@ -113,19 +117,22 @@ __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int 
         V[s] = p;
       }
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-      if (mats[q].rp) {
-        SmallMat& M = mats[q];
+    for (int q = 0; q < 3; ++q) {
+      SmallMat& M = mats[q];
+      const SmallMat Mg = M;   // the arrays in global memory (rp == nullptr: the zero matrix)
+      M.rp = nullptr; M.ci = nullptr; M.v = nullptr;
+      if (Mg.rp) {
         int* rp = (int*)(small_lds + a.moff[q][0]);
         int* ci = (int*)(small_lds + a.moff[q][1]);
         double* v = (double*)(small_lds + a.moff[q][2]);
-        small_copy(rp, M.rp, M.rows + 1);
+        small_copy(rp, Mg.rp, Mg.rows + 1);
         __syncthreads();   // the row pointers give the number of nonzeros
-        const int nnz = rp[M.rows];
-        small_copy(ci, M.ci, nnz);
-        small_copy(v, M.v, nnz);
+        const int nnz = rp[Mg.rows];
+        small_copy(ci, Mg.ci, nnz);
+        small_copy(v, Mg.v, nnz);
         M.rp = rp; M.ci = ci; M.v = v;
       }
+    }
     __syncthreads();
   }
   // the segment's scalars (sigma, lambda's, t0) are read by every phase: keep a copy in LDS
@@ -185,7 +192,7 @@ __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int 
     small_phase<G>(a.m > 0 ? Q : zero_n, V[SV_D], e6, prm, j, r6);
     if (check && a.m > 0 && Q.rp) small_phase<G>(Q, V[SV_E], EpiTheta3{V[SV_E]}, prm, j, small_red(a, SL_TH + 4));
   }
-  if (a.lds_bytes > 0) {
+  if (STAGED) {
 #pragma unroll
     for (int s = SV_FIRST_WRITTEN; s < SV_COUNT; ++s)
       if (a.vec[s]) small_copy(a.vec[s], V[s], a.vlen[s]);

@@ -620,14 +620,15 @@ SmallArgs small_args(hprqp_handle& h) {
 
 template <int G>
 void launch_small(hprqp_handle& h, const SmallArgs& a, int Tseg) {
-  k_small_segment<G><<<1, HQ_SMALL_BS, a.lds_bytes, h.st>>>(a, Tseg);
+  if (a.lds_bytes > 0) k_small_segment<G, true><<<1, HQ_SMALL_BS, a.lds_bytes, h.st>>>(a, Tseg);
+  else k_small_segment<G, false><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg);
 }
 
 // dynamic LDS above 64 KB must be enabled per kernel (at create, outside any capture)
 void small_attrs() {
-  const void* ks[] = {(const void*)k_small_segment<1>, (const void*)k_small_segment<2>,
-                      (const void*)k_small_segment<4>, (const void*)k_small_segment<8>,
-                      (const void*)k_small_segment<16>};
+  const void* ks[] = {(const void*)k_small_segment<1, true>, (const void*)k_small_segment<2, true>,
+                      (const void*)k_small_segment<4, true>, (const void*)k_small_segment<8, true>,
+                      (const void*)k_small_segment<16, true>};
   for (const void* k : ks) HQC(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, HQ_SMALL_LDS));
 }
 

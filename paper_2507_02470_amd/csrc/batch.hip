@@ -128,6 +128,14 @@ __device__ __forceinline__ double dpp_mov(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Value of lane l of a wave, in scalar registers (l wave-uniform).
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Wave reduction with DPP (fixed pattern: quad swaps, row shifts by 4 and 8,
 // row broadcasts 15 and 31); the result is exact in lane 63 only.
 template <bool MX>
@@ -146,7 +154,7 @@ __device__ __forceinline__ double wave_reduce63(double v) {
 // set; maxima only of non-negative values) with one barrier: DPP wave
 // reductions, lane 63 of each wave stores its partials, then every wave
 // combines the W wave partials of value s on lanes Ws..Ws+W-1 with a fixed
-// butterfly and broadcasts the result.  Fixed order, deterministic.  The two partial
+// butterfly and reads the result from lane Ws into scalar registers.  Fixed order, deterministic.  The two partial
 // buffers alternate between calls, so a buffer is rewritten only after every
 // thread has passed the barrier of the call in between.
 template <int K, int BS>
@@ -168,11 +176,13 @@ __device__ __forceinline__ void bred(BShared<BS>& S, int& par, double (&v)[K], u
     double x = s < K ? S.red[par][s][w] : 0.0;
 #pragma unroll
     for (int off = 1; off < W; off <<= 1) {
-      const double y = __shfl_xor(x, off);
+      // partner lane l ^ off: DPP quad permutations for 1 and 2, a shuffle for 4
+      const double y = off == 1 ? dpp_mov<0xb1>(x) : off == 2 ? dpp_mov<0x4e>(x) : __shfl_xor(x, off);
       x = mx ? fmax(x, y) : x + y;
     }
+    // every lane of group q holds value q: broadcast it from the group's first lane
 #pragma unroll
-    for (int q = s0; q < K && q < s0 + VP; ++q) v[q] = __shfl(x, (q - s0) * W);
+    for (int q = s0; q < K && q < s0 + VP; ++q) v[q] = readlane_d(x, (q - s0) * W);
   }
   par ^= 1;
 }
@@ -342,9 +352,9 @@ __device__ __forceinline__ double a_apply(BShared<BS>& S, const Elem<RM, BS>& E,
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (ac[h][u] >= 0) s += av[h][u] * S.vm[ac[h][u]];
-      s = wave_sum(s);
+      s = wave_reduce63<false>(s);   // exact in lane 63
       const int q = q0 + h * WAVES;
-      if (lane == 0 && q < S.np) S.part[q] = s;
+      if (lane == 63 && q < S.np) S.part[q] = s;
     }
   }
   __syncthreads();

@@ -39,16 +39,47 @@ struct RedOut {
   int active;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+// Value of lane l ^ OFF.  Within a quad (OFF = 1, 2) a DPP quad permutation,
+// otherwise a cross-lane shuffle (which goes through the LDS unit).  Every
+// lane of the quad must be active (the callers use it outside divergent code,
+// or within groups of lanes that are active together).
+template <int OFF>
+__device__ __forceinline__ double lane_xor(double x) {
+  if constexpr (OFF == 1 || OFF == 2) {
+    constexpr int ctrl = OFF == 1 ? 0xb1 : 0x4e;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  } else {
+    return __shfl_xor(x, OFF);
+  }
+}
+
+// Butterfly sum (or max) over groups of G lanes (offsets G/2, ..., 1); every
+// lane of a group ends with the group's result.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G > 32) v += lane_xor<32>(v);
+  if constexpr (G > 16) v += lane_xor<16>(v);
+  if constexpr (G > 8) v += lane_xor<8>(v);
+  if constexpr (G > 4) v += lane_xor<4>(v);
+  if constexpr (G > 2) v += lane_xor<2>(v);
+  if constexpr (G > 1) v += lane_xor<1>(v);
   return v;
 }
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+  if constexpr (G > 32) v = fmax(v, lane_xor<32>(v));
+  if constexpr (G > 16) v = fmax(v, lane_xor<16>(v));
+  if constexpr (G > 8) v = fmax(v, lane_xor<8>(v));
+  if constexpr (G > 4) v = fmax(v, lane_xor<4>(v));
+  if constexpr (G > 2) v = fmax(v, lane_xor<2>(v));
+  if constexpr (G > 1) v = fmax(v, lane_xor<1>(v));
   return v;
 }
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
+__device__ __forceinline__ double wave_max(double v) { return group_max<64>(v); }
 
 // Fixed-order block reduction of NR accumulators (sum, or max where bit s of
 // MAXMASK is set) and store of one partial per block.  Deterministic.

@@ -57,29 +57,6 @@ struct SmallArgs {
   int moff[3][3];             // [A, AT, Q][rp, ci, v]
 };
 
-// Sum over the G lanes of a row group (butterfly, offsets G/2, ..., 1): the
-// exchanges within a quad are DPP moves, the others cross-lane shuffles.
-template <int OFF>
-__device__ __forceinline__ double small_xor(double x) {
-  if constexpr (OFF == 1 || OFF == 2) {
-    constexpr int ctrl = OFF == 1 ? 0xb1 : 0x4e;   // quad_perm [1,0,3,2] / [2,3,0,1]
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), ctrl, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-  } else {
-    return __shfl_xor(x, OFF);
-  }
-}
-template <int G>
-__device__ __forceinline__ double small_group_sum(double s) {
-  if constexpr (G > 8) s += small_xor<8>(s);
-  if constexpr (G > 4) s += small_xor<4>(s);
-  if constexpr (G > 2) s += small_xor<2>(s);
-  if constexpr (G > 1) s += small_xor<1>(s);
-  return s;
-}
-
 // q_i = (M x)_i for every row, then epi(i, q_i); block reduction of the
 // epilogue's accumulators; a barrier makes the epilogue's stores visible to
 // the next phase
@@ -99,7 +76,7 @@ __device__ __forceinline__ void small_phase(const SmallMat& M, const double* __r
 #pragma unroll 4
       for (int k = b + gl; k < en; k += G) sum += M.v[k] * x[M.ci[k]];
     }
-    sum = small_group_sum<G>(sum);
+    sum = group_sum<G>(sum);   // (a group's lanes share a row: active together)
     if (gl == 0) e(row, sum, acc);
   }
   if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);

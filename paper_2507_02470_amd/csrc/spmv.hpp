@@ -47,8 +47,7 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr(int nrows, const int* __restri
       }
       __syncthreads();   // wpart is rewritten by the next pass
     } else if constexpr (G > 1) {
-#pragma unroll
-      for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      sum = group_sum<G>(sum);
     }
     if (row < nrows && gl == 0) e((int)row, sum, acc);
   }

@@ -20,6 +20,7 @@
 #pragma once
 #include "common.hpp"
 #include "epilogues.hpp"
+#include "epilogues_primal.hpp"
 
 #define HQ_SMALL_BS 1024
 #define HQ_SMALL_LDS (150 * 1024)
@@ -34,9 +35,10 @@ struct SmallMat {
 // vectors of the iteration, by index
 enum : int {
   SV_L, SV_U, SV_C, SV_LB, SV_UB, SV_IE, SV_ID,                 // read only
-  SV_YA, SV_WA, SV_XA, SV_ATYA, SV_QWA,                          // read only during a segment
+  SV_YA, SV_WA, SV_XA, SV_ATYA, SV_QWA, SV_PTA,                  // read only during a segment
   SV_Y, SV_YBAR, SV_W, SV_X, SV_ATY, SV_QW, SV_XH, SV_V, SV_Q1, SV_D, SV_G, SV_E, SV_XB, SV_ZB, SV_WBAR,
   SV_QWBAR, SV_XBO, SV_ZBO,                                      // written
+  SV_PE, SV_PAX, SV_PDY, SV_PT, SV_PTB, SV_PDT,                  // written (primal methods only)
   SV_COUNT,
   SV_FIRST_WRITTEN = SV_Y
 };
@@ -98,20 +100,19 @@ __device__ __forceinline__ void small_copy(T* __restrict__ dst, const T* __restr
   for (int i = threadIdx.x; i < count; i += HQ_SMALL_BS) dst[i] = src[i];
 }
 
-template <int G, bool STAGED>
-__global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int Tseg) {
-  extern __shared__ __align__(16) unsigned char small_lds[];
-  // the arrays the phases use: LDS copies when staged, else the global ones
-  double* V[SV_COUNT];
-  SmallMat mats[3] = {a.A, a.AT, a.Q};
-  // (loops over the arrays are unrolled so that V and mats stay in registers)
+// The arrays the phases use: LDS copies when staged (copied in here), else
+// the global ones.  (Loops over the arrays are unrolled so that V and mats
+// stay in registers.)
+template <bool STAGED>
+__device__ __forceinline__ void small_stage_in(const SmallArgs& a, unsigned char* lds, double* (&V)[SV_COUNT],
+                                               SmallMat (&mats)[3]) {
 #pragma unroll
   for (int s = 0; s < SV_COUNT; ++s) V[s] = STAGED ? nullptr : a.vec[s];
   if (STAGED) {
 #pragma unroll
     for (int s = 0; s < SV_COUNT; ++s)
       if (a.vec[s]) {
-        double* p = (double*)(small_lds + a.voff[s]);
+        double* p = (double*)(lds + a.voff[s]);
         small_copy(p, a.vec[s], a.vlen[s]);
         V[s] = p;
       }
@@ -121,9 +122,9 @@ __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int 
       const SmallMat Mg = M;   // the arrays in global memory (rp == nullptr: the zero matrix)
       M.rp = nullptr; M.ci = nullptr; M.v = nullptr;
       if (Mg.rp) {
-        int* rp = (int*)(small_lds + a.moff[q][0]);
-        int* ci = (int*)(small_lds + a.moff[q][1]);
-        double* v = (double*)(small_lds + a.moff[q][2]);
+        int* rp = (int*)(lds + a.moff[q][0]);
+        int* ci = (int*)(lds + a.moff[q][1]);
+        double* v = (double*)(lds + a.moff[q][2]);
         small_copy(rp, Mg.rp, Mg.rows + 1);
         __syncthreads();   // the row pointers give the number of nonzeros
         const int nnz = rp[Mg.rows];
@@ -134,6 +135,24 @@ __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int 
     }
     __syncthreads();
   }
+}
+
+// the written vectors back to global memory at the end of a staged segment
+template <bool STAGED>
+__device__ __forceinline__ void small_stage_out(const SmallArgs& a, double* const (&V)[SV_COUNT]) {
+  if (STAGED) {
+#pragma unroll
+    for (int s = SV_FIRST_WRITTEN; s < SV_COUNT; ++s)
+      if (a.vec[s]) small_copy(a.vec[s], V[s], a.vlen[s]);
+  }
+}
+
+template <int G, bool STAGED>
+__global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int Tseg) {
+  extern __shared__ __align__(16) unsigned char small_lds[];
+  double* V[SV_COUNT];
+  SmallMat mats[3] = {a.A, a.AT, a.Q};
+  small_stage_in<STAGED>(a, small_lds, V, mats);
   // the segment's scalars (sigma, lambda's, t0) are read by every phase: keep a copy in LDS
   __shared__ DevParams sprm;
   if (threadIdx.x == 0) sprm = *a.prm;
@@ -188,12 +207,90 @@ __global__ __launch_bounds__(HQ_SMALL_BS) void k_small_segment(SmallArgs a, int 
     if (check)
       for (int s = 0; s < 3; ++s) r6.slot[6 + s] = (int8_t)(SL_TH + 1 + s);
     r6.active = want_r || check;
-    small_phase<G>(a.m > 0 ? Q : zero_n, V[SV_D], e6, prm, j, r6);
+    const SmallMat Qd{a.n, a.m > 0 ? Q.rp : nullptr, a.m > 0 ? Q.ci : nullptr, a.m > 0 ? Q.v : nullptr};
+    small_phase<G>(Qd, V[SV_D], e6, prm, j, r6);
     if (check && a.m > 0 && Q.rp) small_phase<G>(Q, V[SV_E], EpiTheta3{V[SV_E]}, prm, j, small_red(a, SL_TH + 4));
   }
-  if (STAGED) {
-#pragma unroll
-    for (int s = SV_FIRST_WRITTEN; s < SV_COUNT; ++s)
-      if (a.vec[s]) small_copy(a.vec[s], V[s], a.vlen[s]);
+  small_stage_out<STAGED>(a, V);
+}
+
+// HPR on the primal reformulations (Algorithms 6 and 7 of the appendix,
+// meth = 1, 2): the products of an iteration as phases, in the order and with
+// the epilogues of the multi-launch path.
+template <int G, bool STAGED>
+__global__ __launch_bounds__(HQ_SMALL_BS) void k_small_primal(SmallArgs a, int Tseg, int meth) {
+  extern __shared__ __align__(16) unsigned char small_lds[];
+  double* V[SV_COUNT];
+  SmallMat mats[3] = {a.A, a.AT, a.Q};
+  small_stage_in<STAGED>(a, small_lds, V, mats);
+  __shared__ DevParams sprm;
+  if (threadIdx.x == 0) sprm = *a.prm;
+  __syncthreads();
+  const DevParams* prm = &sprm;
+  const SmallMat& A = mats[0];
+  const SmallMat& AT = mats[1];
+  const SmallMat& Q = mats[2];
+  const RedOut none = small_red(a, -1);
+  const SmallMat zero_n{a.n, nullptr, nullptr, nullptr};
+  const bool rows = a.m > 0;
+  for (int j = 0; j < Tseg; ++j) {
+    const bool check = (j == Tseg - 1);
+    const int rgroup = check ? SL_RC : (j == 0 ? SL_RF : -1);
+    const bool want_r = rgroup >= 0;
+    const int store_bar = want_r || check;
+    const auto at = [&](int off) { return want_r ? rgroup + off : -1; };
+    // Q x (Algorithm 6) or Q v with the v/t-step (Algorithm 7)
+    if (meth == 1) {
+      small_phase<G>(Q, V[SV_X], EpiStore{V[SV_Q1]}, prm, j, none);
+    } else {
+      small_phase<G>(Q, V[SV_W],
+                     EpiP2V{V[SV_W], V[SV_X], V[SV_PTA], V[SV_PT], V[SV_WBAR], V[SV_V], V[SV_QW], V[SV_E], V[SV_PDT],
+                            V[SV_PTB], want_r, check},
+                     prm, j, small_red(a, at(1), at(4), check ? SL_TH + 2 : -1));
+    }
+    // A x with the s/y-step
+    if (rows)
+      small_phase<G>(A, V[SV_X],
+                     EpiPY{V[SV_L], V[SV_U], V[SV_YA], V[SV_Y], V[SV_YBAR], V[SV_PE], V[SV_PAX], V[SV_PDY], want_r,
+                           check, store_bar},
+                     prm, j, small_red(a, at(3), check ? SL_TH + 1 : -1));
+    // A^T (2 ybar - y) with the x-step
+    // (a value, not a reference to one of two locals: that would keep both in scratch)
+    const SmallMat ATx{a.n, rows ? AT.rp : nullptr, rows ? AT.ci : nullptr, rows ? AT.v : nullptr};
+    if (meth == 1) {
+      small_phase<G>(ATx, V[SV_PE],
+                     EpiP1X{V[SV_Q1], V[SV_C], V[SV_LB], V[SV_UB], V[SV_XA], V[SV_X], V[SV_XB], V[SV_ZB], V[SV_D],
+                            want_r, check, store_bar, a.l1},
+                     prm, j, small_red(a, at(0), check ? SL_TH : -1));
+    } else {
+      small_phase<G>(ATx, V[SV_PE],
+                     EpiP2X{V[SV_V], V[SV_C], V[SV_LB], V[SV_UB], V[SV_XA], V[SV_WA], V[SV_WBAR], V[SV_PDT], V[SV_X],
+                            V[SV_W], V[SV_XB], V[SV_ZB], V[SV_D], want_r, check, store_bar, a.l1},
+                     prm, j, small_red(a, at(0), at(5), check ? SL_TH : -1));
+    }
+    if (want_r) {
+      // <A dx, dy> and <dx, Q dx> (Algorithm 6) or <dv, Q dv> (Algorithm 7)
+      if (rows) small_phase<G>(A, V[SV_XB], EpiMeritA{V[SV_PAX], V[SV_PDY]}, prm, j, small_red(a, rgroup + 2));
+      if (meth == 1) small_phase<G>(Q, V[SV_XB], EpiMeritQ{V[SV_Q1], V[SV_D]}, prm, j, small_red(a, rgroup + 1));
+      else small_phase<G>(Q, V[SV_WBAR], EpiMeritQ{V[SV_QW], V[SV_E]}, prm, j, small_red(a, rgroup + 6));
+    }
+    if (check) {
+      // stopping quantities at (ybar, zbar, xbar): A^T ybar, A xbar, Q xbar
+      if (rows) {
+        small_phase<G>(AT, V[SV_YBAR], EpiStore{V[SV_G]}, prm, j, none);
+        RedOut r = none;
+        for (int s = 0; s < 4; ++s) r.slot[s] = (int8_t)(SL_RA + s);
+        r.active = 1;
+        small_phase<G>(A, V[SV_XB], EpiResA{V[SV_L], V[SV_U], V[SV_YBAR], V[SV_IE]}, prm, j, r);
+      }
+      RedOut r = none;
+      for (int s = 0; s < 7; ++s) r.slot[s] = (int8_t)(SL_RQ + s);
+      r.active = 1;
+      small_phase<G>(Q, V[SV_XB],
+                     EpiResQ{V[SV_XB], V[SV_ZB], rows ? V[SV_G] : nullptr, V[SV_C], V[SV_LB], V[SV_UB], V[SV_XBO],
+                             V[SV_ZBO], V[SV_ID], a.l1},
+                     prm, j, r);
+    }
   }
+  small_stage_out<STAGED>(a, V);
 }

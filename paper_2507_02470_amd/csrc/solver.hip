@@ -600,6 +600,10 @@ SmallArgs small_args(hprqp_handle& h) {
   set(SV_QW, h.Qw, n); set(SV_XH, h.xh, n); set(SV_V, h.v, n); set(SV_Q1, h.q1, n); set(SV_D, h.d, n);
   set(SV_G, h.g, n); set(SV_E, h.e, n); set(SV_XB, h.XB, n); set(SV_ZB, h.ZB, n); set(SV_WBAR, h.wbar, n);
   set(SV_QWBAR, h.qwbar, n); set(SV_XBO, h.xbo, n); set(SV_ZBO, h.zbo, n);
+  if (h.opt.method != 0) {   // the primal methods' own vectors
+    set(SV_PTA, h.pta, n); set(SV_PT, h.pt, n); set(SV_PTB, h.ptb, n); set(SV_PDT, h.pdt, n);
+    set(SV_PE, h.pe, m); set(SV_PAX, h.pax, m); set(SV_PDY, h.pdy, m);
+  }
   a.l1 = h.l1;
   a.partials = h.partials; a.counts = h.counts; a.prm = h.dprm;
   // LDS layout: every vector, then row pointers, columns and values of A, A^T, Q
@@ -620,15 +624,23 @@ SmallArgs small_args(hprqp_handle& h) {
 
 template <int G>
 void launch_small(hprqp_handle& h, const SmallArgs& a, int Tseg) {
-  if (a.lds_bytes > 0) k_small_segment<G, true><<<1, HQ_SMALL_BS, a.lds_bytes, h.st>>>(a, Tseg);
-  else k_small_segment<G, false><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg);
+  const int meth = h.opt.method;
+  if (meth == 0) {
+    if (a.lds_bytes > 0) k_small_segment<G, true><<<1, HQ_SMALL_BS, a.lds_bytes, h.st>>>(a, Tseg);
+    else k_small_segment<G, false><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg);
+  } else {
+    if (a.lds_bytes > 0) k_small_primal<G, true><<<1, HQ_SMALL_BS, a.lds_bytes, h.st>>>(a, Tseg, meth);
+    else k_small_primal<G, false><<<1, HQ_SMALL_BS, 0, h.st>>>(a, Tseg, meth);
+  }
 }
 
 // dynamic LDS above 64 KB must be enabled per kernel (at create, outside any capture)
 void small_attrs() {
   const void* ks[] = {(const void*)k_small_segment<1, true>, (const void*)k_small_segment<2, true>,
-                      (const void*)k_small_segment<4, true>, (const void*)k_small_segment<8, true>,
-                      (const void*)k_small_segment<16, true>};
+                      (const void*)k_small_segment<4, true>,  (const void*)k_small_segment<8, true>,
+                      (const void*)k_small_segment<16, true>, (const void*)k_small_primal<1, true>,
+                      (const void*)k_small_primal<2, true>,   (const void*)k_small_primal<4, true>,
+                      (const void*)k_small_primal<8, true>,   (const void*)k_small_primal<16, true>};
   for (const void* k : ks) HQC(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, HQ_SMALL_LDS));
 }
 
@@ -1459,6 +1471,10 @@ void enqueue_primal_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof
 }
 
 void enqueue_primal_segment(hprqp_handle& h, int Tseg, bool prof) {
+  if (h.small_G > 0 && !prof) {
+    enqueue_small_segment(h, Tseg);   // the primal kernel: launch_small dispatches on the method
+    return;
+  }
   for (int j = 0; j < Tseg; ++j) enqueue_primal_iter(h, j, Tseg, false, prof);
   final_reduce(h, 0, SL_ITER_END);
   HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));

@@ -85,6 +85,36 @@ def test_small_path_segments_match_oracle(name, make, T, K):
             assert e <= 1e-10, (nm, e)
 
 
+@pytest.mark.parametrize("method", [1, 2])
+@pytest.mark.parametrize("name,make,T,K", [
+    ("small_ccqp", lambda: qpgen.make_small_ccqp(), 100, 400),
+    ("tiny_m0", lambda: qpgen.make_tiny(4, n=6, m=0), 10, 120),
+    ("tiny_l1", lambda: _l1(qpgen.make_tiny(6, n=7, m=3, n_eq=1), 0.3), 10, 120),
+])
+def test_small_path_primal_methods_match_oracle(method, name, make, T, K):
+    """HPR on the primal reformulations (Algorithms 6 and 7) in one workgroup per
+    segment: outputs after whole segments and the check log against the oracle."""
+    DP, Solver = _S()
+    qp = make()
+    lamA, lamQ = _lams(qp)
+    print(f"small path primal {name}: method={method} T={T} K={K}", flush=True)
+    ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=T, lambda_A=lamA, lambda_Q=lamQ, log_cap=K,
+                      method=method)
+    s = Solver(DP(qp), lambda_A=lamA, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=T, log_cap=K,
+               small_path=1, method=method)
+    rg = s.solve()
+    s.close()
+    assert rg.iters == ro.iters == K
+    np.testing.assert_array_equal(rg.check_log[:, [0, 1, 7]], ro.check_log[:, [0, 1, 7]])
+    np.testing.assert_allclose(rg.check_log[:, 2:7], ro.check_log[:, 2:7], rtol=1e-7, atol=1e-13)
+    for nm in ("y", "z", "w", "x"):
+        a = getattr(rg, nm).cpu().numpy()
+        if a.size:
+            e = _max_rel(a, getattr(ro, nm))
+            print(f"  {nm}: {e:.2e}", flush=True)
+            assert e <= 1e-10, (nm, e)
+
+
 @pytest.mark.parametrize("precondition", [False, True])
 def test_small_path_full_solve(precondition):
     DP, Solver = _S()

@@ -99,7 +99,11 @@ __device__ __forceinline__ void block_reduce_store(const double* acc, const RedO
       double v = sh[0][s];
       const bool mx = (MAXMASK >> s) & 1u;
       for (int w = 1; w < (int)(blockDim.x / HQ_WAVE); ++w) v = mx ? fmax(v, sh[w][s]) : v + sh[w][s];
-      const int slot = red.slot[s];
+      // (slot of value s by compares, not by indexing red.slot with a thread
+      // index, which would keep the struct in scratch when it is a local)
+      int slot = -1;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) slot = s == q ? red.slot[q] : slot;
       if (slot >= 0) {
         red.partials[(size_t)slot * HQ_PCAP + blockIdx.x] = v;
         if (blockIdx.x == 0) red.counts[slot] = gridDim.x;

@@ -243,6 +243,7 @@ struct hprqp_handle {
   const double *kB = nullptr, *kC = nullptr;
   const double *kS = nullptr, *kT = nullptr;   // QAP relaxation: Q = B (x) C - I (x) S - T (x) I
   int small_G = 0;            // > 0: segments run as one workgroup (k_small_segment<small_G>)
+  bool small_forced = false;  // small_path = 1: also when the data does not fit the LDS
   int kron_mode = 0;          // 0: k_dgemm16 (K split over waves), 1: LDS-tiled k_dgemm_tile
   int kron_groups = 1;        // split-K groups of the tiled kernel
   int kron_groups_max = 1;    // capacity of kparts (in n-vectors)
@@ -657,8 +658,12 @@ void enqueue_small_segment(hprqp_handle& h, int Tseg) {
   HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
 }
 
+// one workgroup per segment: chosen at create, and used while the data of
+// the current method fits the LDS (a method switched to later may need more)
+bool use_small(hprqp_handle& h) { return h.small_G > 0 && (h.small_forced || small_args(h).lds_bytes > 0); }
+
 void enqueue_segment(hprqp_handle& h, int Tseg, bool prof) {
-  if (h.small_G > 0 && !prof) {
+  if (!prof && use_small(h)) {
     enqueue_small_segment(h, Tseg);
     return;
   }
@@ -1168,6 +1173,7 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         int G = 1;
         while (G < 16 && (long long)std::max(n, m) * G * 2 <= HQ_SMALL_BS) G *= 2;
         h.small_G = G;
+        h.small_forced = opt->small_path == 1;
         small_attrs();
       }
     }
@@ -1471,7 +1477,7 @@ void enqueue_primal_iter(hprqp_handle& h, int j, int Tseg, bool trace, bool prof
 }
 
 void enqueue_primal_segment(hprqp_handle& h, int Tseg, bool prof) {
-  if (h.small_G > 0 && !prof) {
+  if (!prof && use_small(h)) {
     enqueue_small_segment(h, Tseg);   // the primal kernel: launch_small dispatches on the method
     return;
   }

@@ -83,7 +83,7 @@ __device__ __forceinline__ double wave_max(double v) { return group_max<64>(v); 
 
 // Fixed-order block reduction of NR accumulators (sum, or max where bit s of
 // MAXMASK is set) and store of one partial per block.  Deterministic.
-template <int NR, unsigned MAXMASK>
+template <int NR, unsigned MAXMASK, bool LOCAL = false>
 __device__ __forceinline__ void block_reduce_store(const double* acc, const RedOut& red) {
   if constexpr (NR > 0) {
     __shared__ double sh[16][NR > 0 ? NR : 1];   // up to 1024-thread blocks
@@ -99,11 +99,18 @@ __device__ __forceinline__ void block_reduce_store(const double* acc, const RedO
       double v = sh[0][s];
       const bool mx = (MAXMASK >> s) & 1u;
       for (int w = 1; w < (int)(blockDim.x / HQ_WAVE); ++w) v = mx ? fmax(v, sh[w][s]) : v + sh[w][s];
-      // (slot of value s by compares, not by indexing red.slot with a thread
-      // index, which would keep the struct in scratch when it is a local)
-      int slot = -1;
+      // LOCAL: red is a local of the kernel (the one-workgroup segments); its
+      // slot is then picked by compares, since indexing it with the thread
+      // index would keep the struct in scratch.  A kernel argument is indexed
+      // directly (the compares would cost the multi-block kernels SGPRs).
+      int slot;
+      if constexpr (LOCAL) {
+        slot = -1;
 #pragma unroll
-      for (int q = 0; q < NR; ++q) slot = s == q ? red.slot[q] : slot;
+        for (int q = 0; q < NR; ++q) slot = s == q ? red.slot[q] : slot;
+      } else {
+        slot = red.slot[s];
+      }
       if (slot >= 0) {
         red.partials[(size_t)slot * HQ_PCAP + blockIdx.x] = v;
         if (blockIdx.x == 0) red.counts[slot] = gridDim.x;

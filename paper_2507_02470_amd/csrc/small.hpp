@@ -81,7 +81,7 @@ __device__ __forceinline__ void small_phase(const SmallMat& M, const double* __r
     sum = group_sum<G>(sum);   // (a group's lanes share a row: active together)
     if (gl == 0) e(row, sum, acc);
   }
-  if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
+  if (red.active) block_reduce_store<NR, Epi::MAXMASK, true>(acc, red);
   __syncthreads();
 }
 

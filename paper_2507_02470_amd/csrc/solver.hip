@@ -369,15 +369,22 @@ template <class Epi>
 void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
   if (M.G == HQ_G_XLDS) { launch_csr_xlds(h, M, x, epi, j, red); return; }
   if (M.G == HQ_G_PANEL) {
-    // row blocks per workgroup: the fewest for which the whole grid is resident
-    static int per_cu = 0;   // resident workgroups per CU of this epilogue's kernel
-    if (!per_cu) {
-      HQC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_csr_panel<Epi, 2>, HQ_BLOCK, 0));
-      per_cu = std::max(per_cu, 1);
+    // row blocks per workgroup: the fewest for which the whole grid is
+    // resident, by the occupancy of the instantiation that would run (the
+    // four differ in registers, so one count does not hold for the others)
+    static int per_cu[5] = {0, 0, 0, 0, 0};   // resident workgroups per CU, by row blocks per workgroup
+    if (!per_cu[1]) {
+      const void* ks[5] = {nullptr, (const void*)k_csr_panel<Epi, 1>, (const void*)k_csr_panel<Epi, 2>,
+                           (const void*)k_csr_panel<Epi, 3>, (const void*)k_csr_panel<Epi, 4>};
+      for (int b = 1; b <= 4; ++b) {
+        HQC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[b], ks[b], HQ_BLOCK, 0));
+        per_cu[b] = std::max(per_cu[b], 1);
+      }
     }
     const int nblk = (M.rows + HQ_BLOCK - 1) / HQ_BLOCK;
-    const long long resident = (long long)h.ncu * per_cu;
-    const int bpb = (int)std::min<long long>(4, std::max<long long>(1, (nblk + resident - 1) / resident));
+    int bpb = 4;
+    for (int b = 1; b <= 4; ++b)
+      if ((long long)(nblk + b - 1) / b <= (long long)h.ncu * per_cu[b]) { bpb = b; break; }
     switch (bpb) {
       case 1: k_csr_panel<Epi, 1><<<nblk, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
       case 2: k_csr_panel<Epi, 2><<<(nblk + 1) / 2, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;

@@ -94,6 +94,7 @@ struct EpiQ2 {
   double l1;                      // lambda of phi (0: the box projection)
   double sigma, sQ, kappa, rho;
   static constexpr int NR = 9;
+  static constexpr bool PANEL_PREFETCH = true;   // panel-ordered product: prefetch the next chunk
   static constexpr unsigned MAXMASK = 0u;
   __device__ void setup(const DevParams* p, int j) {
     IterScalars s; s.load(p, j);

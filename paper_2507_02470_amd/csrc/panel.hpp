@@ -14,6 +14,7 @@
 // order (deterministic; the order of the additions differs from the plain
 // kernel only in that a row's panels are added one after the other).
 #pragma once
+#include <type_traits>
 #include "common.hpp"
 
 #define HQ_PANELS 4
@@ -86,6 +87,46 @@ __global__ void k_panel_scatter(int rows, int cols, const int* __restrict__ rp, 
   }
 }
 
+// Optional prefetch: the next chunk's loads are issued before the current
+// chunk's products and sums, so that their latency overlaps the gathers and
+// the LDS phase.  Chosen per epilogue (an epilogue type that declares
+// PANEL_PREFETCH = true): measured on a random QP with n = 1e6 and 5e6
+// nonzeros per matrix, it takes the product with the Halpern epilogue from
+// 62.5 to 59.6 us, but slows the plain products down (A v 46 -> 52 us, the
+// power method's Q product 41 -> 43 us), whose resident workgroups already
+// hide that latency and whose early loads then only compete with the gathers.
+template <class E, class = void> struct panel_prefetch : std::false_type {};
+template <class E>
+struct panel_prefetch<E, std::void_t<decltype(E::PANEL_PREFETCH)>> : std::bool_constant<E::PANEL_PREFETCH> {};
+
+#define HQ_PANEL_PF 4                               // prefetched elements per thread
+#define HQ_PANEL_PASS (HQ_PANEL_PF * HQ_BLOCK)      // elements per LDS pass
+
+struct PanelChunk {
+  int kb = 0, ke = 0, myb = 0, mye = 0;
+  int ci[HQ_PANEL_PF];
+  double v[HQ_PANEL_PF];
+};
+
+__device__ __forceinline__ void panel_fetch(const PanelMat& M, int rb, int p, int t, PanelChunk& c) {
+  const int ch = rb * HQ_PANELS + p;
+  c.kb = M.pp[ch];
+  c.ke = M.pp[ch + 1];
+  const int nr = min(HQ_BLOCK, M.rows - rb * HQ_BLOCK);
+  c.myb = t < nr ? c.kb + M.lrp[(size_t)ch * (HQ_BLOCK + 1) + t] : 0;
+  c.mye = t < nr ? c.kb + M.lrp[(size_t)ch * (HQ_BLOCK + 1) + t + 1] : 0;
+#pragma unroll
+  for (int i = 0; i < HQ_PANEL_PF; ++i) {
+    const int k = c.kb + t + i * HQ_BLOCK;
+    c.ci[i] = 0;
+    c.v[i] = 0.0;
+    if (k < c.ke) {
+      c.ci[i] = ld_stream(M.ci + k);
+      c.v[i] = ld_stream(M.v + k);
+    }
+  }
+}
+
 // the product with a fused epilogue; each workgroup owns BPB consecutive row
 // blocks, grid = ceil(row blocks / BPB) (chosen so that the whole grid is
 // resident at once: a late workgroup would gather from a panel the others
@@ -94,7 +135,8 @@ template <class Epi, int BPB>
 __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double* __restrict__ xin, Epi epi,
                                                         const DevParams* __restrict__ prm, int j, RedOut red) {
   constexpr int NR = Epi::NR;
-  __shared__ double prod[HQ_STREAM_CHUNK];
+  constexpr bool PF = panel_prefetch<Epi>::value;
+  __shared__ double prod[PF ? HQ_PANEL_PASS : HQ_STREAM_CHUNK];
   Epi e = epi;
   e.setup(prm, j);
   double acc[NR > 0 ? NR : 1];
@@ -106,24 +148,67 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
 #pragma unroll
   for (int q = 0; q < BPB; ++q) sum[q] = 0.0;
   const int rb0 = blockIdx.x * BPB;
-  for (int p = 0; p < HQ_PANELS; ++p) {
+  if constexpr (PF) {
+    const int nq = min(BPB, nblk - rb0);   // >= 1: grid = ceil(nblk / BPB)
+    // chunks in the order (panel, row block); cur holds the loads of the next one
+    PanelChunk cur;
+    panel_fetch(M, rb0, 0, t, cur);
+    for (int p = 0; p < HQ_PANELS; ++p) {
 #pragma unroll
-    for (int q = 0; q < BPB; ++q) {
-      const int rb = rb0 + q;
-      if (rb < nblk) {
-        const int ch = rb * HQ_PANELS + p;
-        const int kb = M.pp[ch], ke = M.pp[ch + 1];
-        const int nr = min(HQ_BLOCK, M.rows - rb * HQ_BLOCK);
-        const int myb = t < nr ? kb + M.lrp[(size_t)ch * (HQ_BLOCK + 1) + t] : 0;
-        const int mye = t < nr ? kb + M.lrp[(size_t)ch * (HQ_BLOCK + 1) + t + 1] : 0;
-        for (int c0 = kb; c0 < ke; c0 += HQ_STREAM_CHUNK) {
-          const int c1 = min(ke, c0 + HQ_STREAM_CHUNK);
+      for (int q = 0; q < BPB; ++q) {
+        if (q < nq) {
+          double xv[HQ_PANEL_PF];
+#pragma unroll
+          for (int i = 0; i < HQ_PANEL_PF; ++i)
+            xv[i] = cur.kb + t + i * HQ_BLOCK < cur.ke ? xin[cur.ci[i]] : 0.0;
+          const int kb = cur.kb, ke = cur.ke, myb = cur.myb, mye = cur.mye;
+          double pv[HQ_PANEL_PF];
+#pragma unroll
+          for (int i = 0; i < HQ_PANEL_PF; ++i) pv[i] = cur.v[i];
+          const bool last_q = q + 1 == nq;
+          if (!last_q || p + 1 < HQ_PANELS) panel_fetch(M, rb0 + (last_q ? 0 : q + 1), last_q ? p + 1 : p, t, cur);
+#pragma unroll
+          for (int i = 0; i < HQ_PANEL_PF; ++i)
+            if (kb + t + i * HQ_BLOCK < ke) prod[t + i * HQ_BLOCK] = pv[i] * xv[i];
+          __syncthreads();
+          {
+            const int hi = min(mye, kb + HQ_PANEL_PASS);
+            for (int k = myb; k < hi; ++k) sum[q] += prod[k - kb];
+          }
+          __syncthreads();
+          // chunks longer than one pass: the rest without prefetch
+          for (int c0 = kb + HQ_PANEL_PASS; c0 < ke; c0 += HQ_PANEL_PASS) {
+            const int c1 = min(ke, c0 + HQ_PANEL_PASS);
 #pragma unroll 4
-          for (int k = c0 + t; k < c1; k += HQ_BLOCK) prod[k - c0] = ld_stream(M.v + k) * xin[ld_stream(M.ci + k)];
-          __syncthreads();
-          const int lo = max(myb, c0), hi = min(mye, c1);
-          for (int k = lo; k < hi; ++k) sum[q] += prod[k - c0];
-          __syncthreads();
+            for (int k = c0 + t; k < c1; k += HQ_BLOCK) prod[k - c0] = ld_stream(M.v + k) * xin[ld_stream(M.ci + k)];
+            __syncthreads();
+            const int lo = max(myb, c0), hi = min(mye, c1);
+            for (int k = lo; k < hi; ++k) sum[q] += prod[k - c0];
+            __syncthreads();
+          }
+        }
+      }
+    }
+  } else {
+    for (int p = 0; p < HQ_PANELS; ++p) {
+#pragma unroll
+      for (int q = 0; q < BPB; ++q) {
+        const int rb = rb0 + q;
+        if (rb < nblk) {
+          const int ch = rb * HQ_PANELS + p;
+          const int kb = M.pp[ch], ke = M.pp[ch + 1];
+          const int nr = min(HQ_BLOCK, M.rows - rb * HQ_BLOCK);
+          const int myb = t < nr ? kb + M.lrp[(size_t)ch * (HQ_BLOCK + 1) + t] : 0;
+          const int mye = t < nr ? kb + M.lrp[(size_t)ch * (HQ_BLOCK + 1) + t + 1] : 0;
+          for (int c0 = kb; c0 < ke; c0 += HQ_STREAM_CHUNK) {
+            const int c1 = min(ke, c0 + HQ_STREAM_CHUNK);
+#pragma unroll 4
+            for (int k = c0 + t; k < c1; k += HQ_BLOCK) prod[k - c0] = ld_stream(M.v + k) * xin[ld_stream(M.ci + k)];
+            __syncthreads();
+            const int lo = max(myb, c0), hi = min(mye, c1);
+            for (int k = lo; k < hi; ++k) sum[q] += prod[k - c0];
+            __syncthreads();
+          }
         }
       }
     }

@@ -128,11 +128,15 @@ def test_panel_layout_falls_back_when_a_chunk_is_too_large():
     s.close()
 
 
-def test_panel_ordered_products_in_the_iteration():
+@pytest.mark.parametrize("density", [0.003, 0.01])
+def test_panel_ordered_products_in_the_iteration(density):
     """All three CSR matrices (A, A^T, Q) in the panel-ordered layout: the
-    traced iterates of 50 iterations with restarts against the oracle."""
+    traced iterates of 50 iterations with restarts against the oracle.  At
+    density 0.01 the rows of Q hold ~120 nonzeros, so each (row block, panel)
+    chunk takes several LDS passes (the prefetching Q d product's tail loop)."""
     DP, Solver = _S()
-    qp = qpgen.make_small_ccqp(seed=13, n=3000, m=1700, nb=400, density=0.003)
+    qp = qpgen.make_small_ccqp(seed=13, n=3000, m=1700, nb=400, density=density)
+    print(f"panel iteration: density={density} nnz_Q={len(qp.q_col)}", flush=True)
     lamA = 1.01 * oracle.power(qp, "A", qpgen.power_start(qp.m), maxit=5000, tol=1e-12)[0]
     lamQ = 1.01 * oracle.power(qp, "Q", qpgen.power_start(qp.n), maxit=5000, tol=1e-12)[0]
     K = 50

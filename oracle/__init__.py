@@ -12,5 +12,5 @@ shares no code with it.
 """
 from .oracle import (  # noqa: F401
     build_oracle, solve, residuals, apply_Q, apply_A, apply_AT, power, sigma0,
-    thetas, mnorm2, sigma_argmin, scaling, primal_step, primal_mnorm2, OracleResult, TERM_NAMES,
+    thetas, mnorm2, sigma_argmin, restart_test, alpha3_next, scaling, primal_step, primal_mnorm2, OracleResult, TERM_NAMES,
 )

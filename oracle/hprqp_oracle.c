@@ -263,6 +263,32 @@ double orc_sigma_argmin(double th1, double th2, double th3, double lamQ) {
   return exp(0.5 * (a + b));
 }
 
+/* Restart test of Section 3.2, taken at a check.  R is the merit R~ of the
+ * iteration just completed, Rr0 that of the epoch's first iteration (the
+ * reference R~_{r,0}), Rprev that of the previous check of the same epoch
+ * (negative: this is the epoch's first check, and the comparison of the second
+ * criterion has nothing to compare with); t and k are the iterations done in
+ * the epoch and in total.  Returns a bit mask of the criteria that hold:
+ *   1  sufficient decay, "eq:restart_1":          R <= alpha1 Rr0
+ *   2  insufficient local progress, "eq:restart_2": R <= alpha2 Rr0 and R > Rprev
+ *   4  excessively long inner loop, "eq:restart_3": t >= alpha3 k
+ * Any nonzero mask ends the epoch.                                         */
+int orc_restart_test(double R, double Rr0, double Rprev, int64_t t, int64_t k,
+                     double alpha1, double alpha2, double alpha3) {
+  int mask = 0;
+  if (R <= alpha1 * Rr0) mask |= 1;
+  if (Rprev >= 0.0 && R <= alpha2 * Rr0 && R > Rprev) mask |= 2;
+  if ((double)t >= alpha3 * (double)k) mask |= 4;
+  return mask;
+}
+
+/* alpha_3 for the epochs after a restart (Section 4.1, parameter setting):
+ * tightened to 0.2 once the ratio R~_{r,tau_r-1}/R~_{0,tau_0-1} of the
+ * restart is at most 0.1, and kept there.                                  */
+double orc_alpha3_next(double alpha3, double ratio) {
+  return (ratio <= 0.1) ? 0.2 : alpha3;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Diagonal preconditioning (Section 4.1, "Preconditioning")               */
 /* ------------------------------------------------------------------------ */
@@ -516,12 +542,8 @@ static int solve_core(const orc_problem *P, const orc_problem *P0, const double 
         else if (kkt <= opt->tol) term = ORC_SOLVED;
         else if (k >= opt->max_iter) term = ORC_MAX_ITER;
         else if (opt->time_limit_s > 0.0 && now_s() - t_start >= opt->time_limit_s) term = ORC_TIME_LIMIT;
-        else if (opt->enable_restart) {
-          int c1 = R <= opt->alpha1 * Rr0;
-          int c2 = (Rprev >= 0.0) && (R <= opt->alpha2 * Rr0) && (R > Rprev);
-          int c3 = (double)t >= alpha3 * (double)k;
-          do_restart = c1 || c2 || c3;
-        }
+        else if (opt->enable_restart)
+          do_restart = orc_restart_test(R, Rr0, Rprev, t, k, opt->alpha1, opt->alpha2, alpha3) != 0;
         Rprev = R;
         if (term < 0 && do_restart) {
           if (R0ref < 0.0) R0ref = R;
@@ -539,7 +561,7 @@ static int solve_core(const orc_problem *P, const orc_problem *P0, const double 
             double beta = exp(-ratio);
             sigma = exp(beta * log(snew) + (1.0 - beta) * log(sigma));
           }
-          if (ratio <= 0.1) alpha3 = 0.2;
+          alpha3 = orc_alpha3_next(alpha3, ratio);
           /* u^{r+1,0} = ubar^{r,tau_r} */
           memcpy(y, yb, sizeof(double) * m); memcpy(w, wb, sizeof(double) * n); memcpy(x, xb, sizeof(double) * n);
           r += 1;
@@ -747,12 +769,8 @@ static int solve_primal(const orc_problem *P, const orc_problem *P0, const doubl
         else if (kkt <= opt->tol) term = ORC_SOLVED;
         else if (k >= opt->max_iter) term = ORC_MAX_ITER;
         else if (opt->time_limit_s > 0.0 && now_s() - t_start >= opt->time_limit_s) term = ORC_TIME_LIMIT;
-        else if (opt->enable_restart) {
-          int c1 = R <= opt->alpha1 * Rr0;
-          int c2 = (Rprev >= 0.0) && (R <= opt->alpha2 * Rr0) && (R > Rprev);
-          int c3 = (double)it >= alpha3 * (double)k;
-          do_restart = c1 || c2 || c3;
-        }
+        else if (opt->enable_restart)
+          do_restart = orc_restart_test(R, Rr0, Rprev, it, k, opt->alpha1, opt->alpha2, alpha3) != 0;
         Rprev = R;
         if (term < 0 && do_restart) {
           if (R0ref < 0.0) R0ref = R;
@@ -771,7 +789,7 @@ static int solve_primal(const orc_problem *P, const orc_problem *P0, const doubl
             double beta = exp(-ratio);
             sigma = exp(beta * log(snew) + (1.0 - beta) * log(sigma));
           }
-          if (ratio <= 0.1) alpha3 = 0.2;
+          alpha3 = orc_alpha3_next(alpha3, ratio);
           memcpy(x, xb, sizeof(double) * n); memcpy(y, yb, sizeof(double) * m);
           if (var == 2) { memcpy(v, vb, sizeof(double) * n); memcpy(t, tb, sizeof(double) * n); }
           r += 1;

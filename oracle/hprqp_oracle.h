@@ -106,6 +106,16 @@ double orc_mnorm2(const orc_problem *P, double sigma, double lamA, double lamQ,
                   const double *dy, const double *dw, const double *dx);
 /* Algorithm 5 without the smoothing: argmin of f(sigma) by golden section. */
 double orc_sigma_argmin(double th1, double th2, double th3, double lamQ);
+/* Restart test of Section 3.2 at a check ("eq:restart_1".."eq:restart_3"):
+ * bit 1, 2, 4 set for the criterion that holds (0: no restart).  R: merit of
+ * the iteration just completed; Rr0: merit of the epoch's first iteration;
+ * Rprev: merit at the epoch's previous check, negative if there is none;
+ * t, k: iterations done in the epoch and in total.                          */
+int orc_restart_test(double R, double Rr0, double Rprev, int64_t t, int64_t k,
+                     double alpha1, double alpha2, double alpha3);
+/* alpha_3 after a restart with ratio R~_{r,tau_r-1}/R~_{0,tau_0-1} (Section
+ * 4.1): 0.2 when ratio <= 0.1, else unchanged.                             */
+double orc_alpha3_next(double alpha3, double ratio);
 
 /* Diagonal preconditioning (Section 4.1, "Preconditioning"): scale factors
  * D (n, variables) and E (m, rows of A) of the symmetric scaling of

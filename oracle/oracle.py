@@ -87,6 +87,11 @@ def _L():
         _lib.orc_mnorm2.restype = C.c_double
         _lib.orc_sigma_argmin.argtypes = [C.c_double] * 4
         _lib.orc_sigma_argmin.restype = C.c_double
+        _lib.orc_restart_test.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int64,
+                                          C.c_double, C.c_double, C.c_double]
+        _lib.orc_restart_test.restype = C.c_int
+        _lib.orc_alpha3_next.argtypes = [C.c_double, C.c_double]
+        _lib.orc_alpha3_next.restype = C.c_double
         _lib.orc_scaling.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int, _dp, _dp]
         _lib.orc_primal_step.argtypes = [C.POINTER(_Problem), C.c_int, C.c_double, C.c_double, C.c_double,
                                          _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -297,6 +302,22 @@ def mnorm2(qp, sigma, lamA, lamQ, dy, dw, dx) -> float:
 
 def sigma_argmin(th1, th2, th3, lamQ) -> float:
     return _L().orc_sigma_argmin(th1, th2, th3, lamQ)
+
+
+RESTART_DECAY, RESTART_STALL, RESTART_LONG = 1, 2, 4
+
+
+def restart_test(R, Rr0, Rprev, t, k, alpha1=0.2, alpha2=0.8, alpha3=0.5) -> int:
+    """Bit mask of the restart criteria of Section 3.2 that hold at a check
+    (1: "eq:restart_1", 2: "eq:restart_2", 4: "eq:restart_3"); Rprev < 0 means
+    the epoch has no earlier check."""
+    return int(_L().orc_restart_test(float(R), float(Rr0), float(Rprev), int(t), int(k),
+                                     float(alpha1), float(alpha2), float(alpha3)))
+
+
+def alpha3_next(alpha3, ratio) -> float:
+    """alpha_3 after a restart whose ratio R~_{r,tau_r-1}/R~_{0,tau_0-1} is `ratio` (Section 4.1)."""
+    return float(_L().orc_alpha3_next(float(alpha3), float(ratio)))
 
 
 def primal_step(qp, variant, sigma, lamA, lamQ, x, y, v=None, t=None) -> dict:

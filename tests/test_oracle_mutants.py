@@ -26,8 +26,8 @@ MUTANTS = {
     "theta1_cross": ("- 2.0 * dot(Qdw, ATdy, n);", "+ 2.0 * dot(Qdw, ATdy, n);"),
     "mnorm_sigma2": ("sigma * sigma * th[2] / (1.0 + sigma * lamQ)", "sigma * th[2] / (1.0 + sigma * lamQ)"),
     "dual_obj_sign": ("else sup += P->l[i] * y[i];", "else sup -= P->l[i] * y[i];"),
-    "beta_swap": ("double beta = exp(-ratio);\n            sigma = exp(beta * log(snew) + (1.0 - beta) * log(sigma));\n          }\n          if (ratio <= 0.1) alpha3 = 0.2;\n          /* u^{r+1,0}",
-                  "double beta = exp(-ratio);\n            sigma = exp((1.0 - beta) * log(snew) + beta * log(sigma));\n          }\n          if (ratio <= 0.1) alpha3 = 0.2;\n          /* u^{r+1,0}"),
+    "beta_swap": ("double beta = exp(-ratio);\n            sigma = exp(beta * log(snew) + (1.0 - beta) * log(sigma));\n          }\n          alpha3 = orc_alpha3_next(alpha3, ratio);\n          /* u^{r+1,0}",
+                  "double beta = exp(-ratio);\n            sigma = exp((1.0 - beta) * log(snew) + beta * log(sigma));\n          }\n          alpha3 = orc_alpha3_next(alpha3, ratio);\n          /* u^{r+1,0}"),
     "kron_transpose": ("acc += T[i + (size_t)s * b] * B[j + (size_t)p * b];",
                        "acc += T[i + (size_t)s * b] * B[b + (size_t)p * j];"),
     "power_no_norm": ("for (int i = 0; i < k; ++i) v[i] = w[i] / nw;", "for (int i = 0; i < k; ++i) v[i] = w[i] / (2.0 * nw);"),
@@ -42,6 +42,35 @@ MUTANTS = {
     "conj_ignores_lambda": ("(isinf(L) && z > lam + slack)", "(isinf(L) && z > slack)"),
     "ruiz_col_part": ("if (p == 0) { if (a > ny[i]) ny[i] = a; if (a > na[j]) na[j] = a; }",
                       "if (p == 0) { if (a > ny[i]) ny[i] = a; }"),
+}
+
+# mistakes in the restart rule of Section 3.2, the alpha3 tightening of Section 4.1
+# and the bookkeeping that feeds them, each caught by the dedicated restart pins
+# alone (hand-worked cases and the replay of a traced solve)
+RESTART_MUTANTS = {
+    "restart_c1_strict": ("if (R <= alpha1 * Rr0) mask |= 1;", "if (R < alpha1 * Rr0) mask |= 1;"),
+    "restart_c1_uses_alpha2": ("if (R <= alpha1 * Rr0) mask |= 1;", "if (R <= alpha2 * Rr0) mask |= 1;"),
+    "restart_c2_strict": ("R <= alpha2 * Rr0 && R > Rprev", "R < alpha2 * Rr0 && R > Rprev"),
+    "restart_c2_uses_alpha1": ("R <= alpha2 * Rr0 && R > Rprev", "R <= alpha1 * Rr0 && R > Rprev"),
+    "restart_c2_ge": ("R <= alpha2 * Rr0 && R > Rprev", "R <= alpha2 * Rr0 && R >= Rprev"),
+    "restart_c2_direction": ("R <= alpha2 * Rr0 && R > Rprev", "R <= alpha2 * Rr0 && R < Rprev"),
+    "restart_c2_first_check": ("if (Rprev >= 0.0 && R <= alpha2", "if (R <= alpha2"),
+    "restart_c3_strict": ("if ((double)t >= alpha3 * (double)k) mask |= 4;",
+                          "if ((double)t > alpha3 * (double)k) mask |= 4;"),
+    "alpha3_threshold_zero": ("return (ratio <= 0.1) ? 0.2 : alpha3;", "return (ratio <= 0.0) ? 0.2 : alpha3;"),
+    "alpha3_strict": ("return (ratio <= 0.1) ? 0.2 : alpha3;", "return (ratio < 0.1) ? 0.2 : alpha3;"),
+    "alpha3_value": ("return (ratio <= 0.1) ? 0.2 : alpha3;", "return (ratio <= 0.1) ? 0.1 : alpha3;"),
+    "alpha3_not_kept": ("return (ratio <= 0.1) ? 0.2 : alpha3;", "return (ratio <= 0.1) ? 0.2 : 0.5;"),
+    "restart_prev_updated_first": ("        int do_restart = 0;\n        if (!(kkt == kkt) || !(R == R)) term = ORC_NUMERICAL;        /* NaN guard */",
+                                   "        int do_restart = 0; Rprev = R;\n        if (!(kkt == kkt) || !(R == R)) term = ORC_NUMERICAL;        /* NaN guard */"),
+    "restart_ref_every_check": ("      t += 1; k += 1;\n      if (t == 1) Rr0 = R;",
+                                "      t += 1; k += 1;\n      if (t == 1 || is_check) Rr0 = R;"),
+    "restart_ref_first_check": ("      t += 1; k += 1;\n      if (t == 1) Rr0 = R;",
+                                "      t += 1; k += 1;\n      if (Rr0 < 0.0 && is_check) Rr0 = R;"),
+    "restart_global_t": ("do_restart = orc_restart_test(R, Rr0, Rprev, t, k,",
+                         "do_restart = orc_restart_test(R, Rr0, Rprev, k, k,"),
+    "restart_beta_ref_each_restart": ("          if (R0ref < 0.0) R0ref = R;\n          double ratio = R / R0ref;\n          if (opt->enable_sigma_update) {",
+                                      "          R0ref = R;\n          double ratio = R / R0ref;\n          if (opt->enable_sigma_update) {"),
 }
 
 # mistakes in HPR on the primal reformulations (Appendix A), caught by its own pin file
@@ -79,7 +108,13 @@ def test_qap_pins_catch_mutant(name, tmp_path):
     _run_mutant(old, new, "test_qap.py", tmp_path, name)
 
 
-def _run_mutant(old, new, pin_file, tmp_path, name):
+@pytest.mark.parametrize("name", sorted(RESTART_MUTANTS))
+def test_restart_pins_catch_mutant(name, tmp_path):
+    old, new = RESTART_MUTANTS[name]
+    _run_mutant(old, new, "test_oracle_pins.py", tmp_path, name, select="restart or alpha3")
+
+
+def _run_mutant(old, new, pin_file, tmp_path, name, select=None):
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation site for {name} not unique/found"
     msrc = tmp_path / "mutant.c"
@@ -89,9 +124,11 @@ def _run_mutant(old, new, pin_file, tmp_path, name):
                            "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(msrc), "-lm"])
     env = dict(os.environ, HPRQP_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", pin_file)],
+                        os.path.join(ROOT, "tests", pin_file)] + (["-k", select] if select else []),
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pin suite"
+    if select:      # a pin failed, rather than no test being selected
+        assert " failed" in r.stdout.strip().splitlines()[-1], r.stdout[-2000:]
 
 
 @pytest.mark.parametrize("name", sorted(PRIMAL_MUTANTS))

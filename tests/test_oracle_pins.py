@@ -193,6 +193,7 @@ def test_lp_reduction_matches_highs():
     r = _solve(qp, tol=1e-10)
     ref = so.linprog(c, A_ub=A[4:], b_ub=u[4:], A_eq=A[:4], b_eq=b[:4], bounds=list(zip(L, U)), method="highs")
     assert ref.status == 0
+    assert r.term == "solved"
     assert r.pobj == pytest.approx(ref.fun, rel=1e-7, abs=1e-8)
 
 
@@ -282,6 +283,128 @@ def test_restart_schedule_with_criterion_three():
     log = r.check_log
     assert log[0, 0] == 100 and log[0, 7] == 1.0
     assert np.all(np.isfinite(log[:, 8])) and np.all(log[:, 8] > 0)
+
+
+# ---------------------------------------------------------------------------
+# Restart rule (Section 3.2, "eq:restart_1".."eq:restart_3") and the alpha_3
+# tightening (Section 4.1, parameter setting): hand-worked cases with the
+# paper's alpha = (0.2, 0.8, 0.5)
+# ---------------------------------------------------------------------------
+A1, A2, A3 = 0.2, 0.8, 0.5
+DECAY, STALL, LONG = oracle.oracle.RESTART_DECAY, oracle.oracle.RESTART_STALL, oracle.oracle.RESTART_LONG
+
+
+def _rt(R, Rr0, Rprev, t, k, a3=A3):
+    return oracle.restart_test(R, Rr0, Rprev, t, k, A1, A2, a3)
+
+
+def test_restart_sufficient_decay_alone_and_at_equality():
+    # "eq:restart_1": R~_{r,t+1} <= alpha1 R~_{r,0}.  R = 0.19 < 0.2; the epoch's
+    # first check (Rprev < 0), t = 10 < 0.5 * 100
+    assert _rt(0.19, 1.0, -1.0, 10, 100) == DECAY
+    # equality: 0.2 * 1.25 rounds to exactly 0.25, so R = 0.25 satisfies "<="
+    assert 0.2 * 1.25 == 0.25
+    assert _rt(0.25, 1.25, 0.3, 10, 100) == DECAY
+    # just missing: one ulp above; R < Rprev keeps criterion 2 out
+    assert _rt(np.nextafter(0.25, 1.0), 1.25, 0.3, 10, 100) == 0
+
+
+def test_restart_insufficient_local_progress():
+    # "eq:restart_2": R~_{r,t+1} <= alpha2 R~_{r,0} and R~_{r,t+1} > R~_{r,t}
+    assert _rt(0.5, 1.0, 0.4, 10, 100) == STALL               # decayed to 0.5 but went up
+    assert _rt(0.5, 1.0, 0.6, 10, 100) == 0                   # still going down
+    assert _rt(0.5, 1.0, 0.5, 10, 100) == 0                   # equal is not an increase
+    assert _rt(np.nextafter(0.5, 1.0), 1.0, 0.5, 10, 100) == STALL
+    # first part at equality: 0.8 * 1.25 rounds to exactly 1.0
+    assert 0.8 * 1.25 == 1.0
+    assert _rt(1.0, 1.25, 0.9, 10, 100) == STALL
+    assert _rt(np.nextafter(1.0, 2.0), 1.25, 0.9, 10, 100) == 0
+    # an increase above alpha2 R~_{r,0} is not enough
+    assert _rt(0.9, 1.0, 0.85, 10, 100) == 0
+    # the epoch's first check has no R~_{r,t} to compare with: never criterion 2
+    assert _rt(0.5, 1.0, -1.0, 10, 100) == 0
+    # at or below alpha1 both hold
+    assert _rt(0.1, 1.0, 0.05, 10, 100) == DECAY | STALL
+
+
+def test_restart_long_inner_loop():
+    # "eq:restart_3": t >= alpha3 k (t and k counted after the iteration)
+    assert _rt(0.9, 1.0, 0.95, 50, 100) == LONG               # equality
+    assert _rt(0.9, 1.0, 0.95, 49, 100) == 0
+    assert _rt(0.9, 1.0, 0.95, 100, 100) == LONG              # epoch 0: t = k always holds
+    # after the tightening: 0.2 * 100 rounds to exactly 20
+    assert 0.2 * 100 == 20.0
+    assert _rt(0.9, 1.0, 0.95, 20, 100, a3=0.2) == LONG
+    assert _rt(0.9, 1.0, 0.95, 19, 100, a3=0.2) == 0
+    assert _rt(0.9, 1.0, 0.95, 49, 100, a3=0.2) == LONG
+    # all three at once
+    assert _rt(0.1, 1.0, 0.05, 60, 100) == DECAY | STALL | LONG
+
+
+def test_alpha3_tightening():
+    # Section 4.1: alpha3 becomes 0.2 when R~_{r,tau_r-1}/R~_{0,tau_0-1} <= 0.1
+    assert oracle.alpha3_next(0.5, 0.1) == 0.2
+    assert oracle.alpha3_next(0.5, 0.05) == 0.2
+    assert oracle.alpha3_next(0.5, np.nextafter(0.1, 1.0)) == 0.5
+    assert oracle.alpha3_next(0.5, 0.5) == 0.5
+    # once tightened it stays (reading: the tightening is permanent)
+    assert oracle.alpha3_next(0.2, 0.9) == 0.2
+
+
+def _replay_restarts(qp, check_every, K):
+    """Run the oracle with a trace and a check log, recompute R~ of every
+    iteration from the traced iterates with the metric M (pinned against the
+    dense metric above), and replay every check's decision with the pinned
+    restart test: R~_{r,0} from the epoch's first iteration, the previous check
+    of the same epoch, t counted from the last restart, R~_{0,tau_0-1} from the
+    first restart and alpha3 through its tightening rule."""
+    r = oracle.solve(qp, tol=1e-8, max_iter=K, check_every=check_every, log_cap=K, trace_iters=K,
+                     power_start_A=qpgen.power_start(qp.m), power_start_Q=qpgen.power_start(qp.n))
+    log = r.check_log
+    tr = split_trace(r.trace, qp.n, qp.m)
+    nit = int(log[-1, 0])
+    assert nit <= K
+    sig = np.zeros(nit + 1)
+    prev = 0
+    for row in log:                      # sigma is constant between checks
+        sig[prev + 1:int(row[0]) + 1] = row[6]
+        prev = int(row[0])
+    Rk = np.zeros(nit + 1)
+    for k in range(1, nit + 1):
+        if k == 1:
+            y0, w0, x0 = np.zeros(qp.m), np.zeros(qp.n), np.zeros(qp.n)
+        else:
+            y0, w0, x0 = tr["y"][k - 2], tr["w"][k - 2], tr["x"][k - 2]
+        m2 = oracle.mnorm2(qp, sig[k], r.lambda_A, r.lambda_Q, y0 - tr["ybar"][k - 1],
+                           w0 - tr["wbar"][k - 1], x0 - tr["xbar"][k - 1])
+        Rk[k] = np.sqrt(max(m2, 0.0))
+    kstart, Rprev, a3, R0ref, fired, tightened = 0, -1.0, A3, None, 0, False
+    for i, row in enumerate(log):
+        k, t, R, restarted = int(row[0]), int(row[1]), row[2], int(row[7])
+        assert k % check_every == 0 and t == k - kstart and R == Rk[k]
+        mask = _rt(R, Rk[kstart + 1], Rprev, t, k, a3)
+        last = i == len(log) - 1
+        if not (last and r.term == "solved"):
+            assert bool(mask) == bool(restarted), (k, mask, restarted)
+        Rprev = R
+        if restarted:
+            fired |= mask
+            if R0ref is None:
+                R0ref = R
+            a3n = oracle.alpha3_next(a3, R / R0ref)
+            tightened |= a3n != a3
+            a3, Rprev, kstart = a3n, -1.0, k
+            assert int(row[9]) == int(log[i - 1, 9] if i else 0) + 1
+    return r, fired, tightened
+
+
+def test_restart_decisions_replayed_from_trace():
+    # every check of a full solve of the small CCQP, with every criterion and
+    # the alpha3 tightening exercised along the way
+    qp = qpgen.make_small_ccqp()
+    r, fired, tightened = _replay_restarts(qp, 3, 2000)
+    assert r.term == "solved" and r.restarts >= 10
+    assert fired == DECAY | STALL | LONG and tightened
 
 
 def test_small_ccqp_solution_certificate():

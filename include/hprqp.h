@@ -19,6 +19,10 @@
  *    for the lifetime of the handle.  Outputs are caller-allocated.
  *  - Indices are int32, values double.  CSR arrays: rowptr has rows+1
  *    entries starting at 0 and non-decreasing; columns lie in [0, cols).
+ *    The columns of a row may come in any order and may repeat: every
+ *    product adds a row's entries in an order fixed by the data (results
+ *    are deterministic and differ from those of a sorted copy by rounding
+ *    only).
  *  - Infinite bounds are IEEE +-INFINITY; l_i == u_i marks an equality row.
  *  - All GPU work is enqueued on the stream given at creation; entry points
  *    return after the results they report are complete.

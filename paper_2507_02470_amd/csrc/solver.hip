@@ -341,6 +341,15 @@ inline RedOut red_seq(hprqp_handle& h, int slot0, int nr) {
   return r;
 }
 
+// A reducing launch stores one partial per workgroup into each of its slots,
+// which hold HQ_PCAP partials: every launcher checks its grid against that
+// (a larger grid would spill into the next slot).
+inline void check_red_grid(long long grid, const RedOut& red) {
+  if (red.active && grid > HQ_PCAP)
+    fail(HPRQP_ERR_UNSUPPORTED, "reducing launch of " + std::to_string(grid) + " workgroups exceeds the " +
+                                    std::to_string(HQ_PCAP) + " partials of a reduction slot");
+}
+
 // Lanes-per-row code of the stream kernel that gathers from an LDS copy of the
 // input vector (matrices with at most HQ_XLDS_MAX columns).
 #define HQ_G_XLDS (-1)
@@ -362,6 +371,7 @@ void launch_csr_xlds(hprqp_handle& h, const Mat& M, const double* x, const Epi& 
   const int per_cu = std::max(1, (int)((160 * 1024) / per_block));
   const int nblk = (M.rows + BS - 1) / BS;
   const int grid = std::max(1, std::min(nblk, std::min(h.ncu * per_cu, HQ_GRID_CAP)));
+  check_red_grid(grid, red);
   k_csr_stream<Epi, true, BS><<<grid, BS, lds, h.st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red, M.cols);
 }
 
@@ -381,20 +391,19 @@ void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, 
         per_cu[b] = std::max(per_cu[b], 1);
       }
     }
-    const int nblk = (M.rows + HQ_BLOCK - 1) / HQ_BLOCK;
-    int bpb = 4;
-    for (int b = 1; b <= 4; ++b)
-      if ((long long)(nblk + b - 1) / b <= (long long)h.ncu * per_cu[b]) { bpb = b; break; }
-    switch (bpb) {
-      case 1: k_csr_panel<Epi, 1><<<nblk, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
-      case 2: k_csr_panel<Epi, 2><<<(nblk + 1) / 2, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
-      case 3: k_csr_panel<Epi, 3><<<(nblk + 2) / 3, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
-      default: k_csr_panel<Epi, 4><<<(nblk + 3) / 4, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+    const PanelShape sh = panel_launch_shape(M.rows, h.ncu, per_cu);
+    check_red_grid(sh.grid, red);
+    switch (sh.bpb) {
+      case 1: k_csr_panel<Epi, 1><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+      case 2: k_csr_panel<Epi, 2><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+      case 3: k_csr_panel<Epi, 3><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+      default: k_csr_panel<Epi, 4><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
     }
     return;
   }
   // stream kernel: HQ_BLOCK rows per block; row-split kernel: HQ_BLOCK / G rows per block
   const int grid = M.G == 0 ? hq_grid(M.rows, HQ_BLOCK) : hq_grid(M.rows, HQ_BLOCK / M.G);
+  check_red_grid(grid, red);
   hipStream_t st = h.st;
   switch (M.G) {
     case 0: k_csr_stream<Epi><<<grid, HQ_BLOCK, 0, st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red); break;
@@ -412,6 +421,7 @@ void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, 
 
 template <class Epi>
 void launch_elem(hprqp_handle& h, int n, const double* q, const Epi& epi, int j, const RedOut& red) {
+  check_red_grid(hq_grid(n, HQ_BLOCK), red);
   k_elem<Epi><<<hq_grid(n, HQ_BLOCK), HQ_BLOCK, 0, h.st>>>(n, q, epi, h.dprm, j, red);
 }
 
@@ -425,12 +435,14 @@ void launch_tile(hprqp_handle& h, int M, int N, const GemmOps& ops, const Epi& e
   const int tiles = ((M + HQ_TB - 1) / HQ_TB) * ((N + HQ_TB - 1) / HQ_TB);
   const int G = h.kron_groups;
   if (G <= 1) {
+    check_red_grid(std::min(tiles, HQ_GRID_CAP), red);
     k_dgemm_tile<Epi, false><<<std::min(tiles, HQ_GRID_CAP), 256, 0, h.st>>>(M, N, ops, M, epi, h.dprm, j, red, 1,
                                                                           nullptr);
   } else {
     k_dgemm_tile<Epi, true><<<std::min(tiles * G, HQ_GRID_CAP), 256, 0, h.st>>>(M, N, ops, M, epi, h.dprm, j,
                                                                              no_red(h), G, h.kparts);
     const long long cnt = (long long)M * N;
+    check_red_grid(hq_grid(cnt, HQ_BLOCK), red);
     k_gemm_sum<Epi><<<hq_grid(cnt, HQ_BLOCK), HQ_BLOCK, 0, h.st>>>(cnt, G, h.kparts, epi, h.dprm, j, red);
   }
 }
@@ -485,6 +497,7 @@ void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedO
       }
       const int tiles = ((s + 15) / 16) * ((p + 15) / 16);
       const int grid = std::min(tiles, HQ_GRID_CAP);
+      check_red_grid(grid, red);
       k_dgemm16<false, EpiStore><<<grid, 64 * HQ_KSPLIT, 0, h.st>>>(s, p, s, h.kC, s, x, s, s, EpiStore{h.kronT},
                                                                     h.dprm, j, no_red(h));
       if (!h.kS && !h.kT) {
@@ -515,6 +528,8 @@ void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedO
       RedOut lr = no_red(h);
       for (int k = 0; k < h.lr_r; ++k) lr.slot[k] = (int8_t)(SL_LR + k);
       lr.active = 1;
+      check_red_grid(grid, lr);
+      check_red_grid(grid, red);
       k_lr_partial<<<grid, HQ_BLOCK, 0, h.st>>>(h.n, h.lr_r, h.lr_F, x, lr);
       final_reduce(h, SL_LR, h.lr_r);
       k_lr_apply<Epi><<<grid, HQ_BLOCK, 0, h.st>>>(h.n, h.lr_r, h.lr_d, h.lr_F, x, h.scalars + SL_LR, epi, h.dprm, j,

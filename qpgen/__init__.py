@@ -214,6 +214,24 @@ def make_random_large(seed: int = 1001, n: int = 1_000_000, m: int = 500_000,
               meta=dict(workload="random_large", seed=seed, x_feasible=x0))
 
 
+def shuffle_row_entries(qp: QP, seed: int) -> QP:
+    """A copy of `qp` whose CSR rows (A, and Q when explicit) list their
+    entries in a random order: the same matrices, unsorted column indices."""
+    rng = np.random.default_rng(seed)
+    out = qp.copy()
+
+    def shuffle(rp, col, val):
+        rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+        order = np.lexsort((rng.random(len(col)), rows))
+        return np.ascontiguousarray(col[order]), np.ascontiguousarray(val[order])
+
+    out.a_col, out.a_val = shuffle(qp.a_rowptr, qp.a_col, qp.a_val)
+    if qp.qkind == "csr":
+        out.q_col, out.q_val = shuffle(qp.q_rowptr, qp.q_col, qp.q_val)
+    out.meta = dict(qp.meta, shuffled_columns=seed)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Matrix-free Kronecker Q = B (x) C with assignment constraints
 # ---------------------------------------------------------------------------

@@ -177,6 +177,10 @@ typedef struct {
   double R_last;              /* merit R~ at the last check                        */
   double t_setup_s, t_solve_s;  /* seconds: create (incl. power method), solve    */
   double t_precond_s;         /* seconds of create spent on the preconditioning   */
+  double qwx_gap;             /* ||Q(w - x)||_inf at the returned point (w the shadow
+                                 w_Q of Proposition 2.4; 0 up to rounding at a
+                                 solution, where w - x lies in ker Q): a diagnostic,
+                                 not part of the stopping test (which uses Q x)      */
 } hprqp_info;
 
 typedef struct hprqp_handle hprqp_handle;
@@ -210,10 +214,14 @@ hprqp_status hprqp_solve(hprqp_handle *h, const double *y0, const double *w0, co
  * (lambda_A, lambda_Q, sigma0, power-method start, SpMV tuning) are kept. */
 hprqp_status hprqp_set_options(hprqp_handle *h, const hprqp_options *opt);
 
-/* Stopping quantities of Section 4.1 at the point (y, z, x):
- * out_host[0..4] = eta_p, eta_d, eta_gap, primal objective, dual objective. */
-hprqp_status hprqp_residuals(hprqp_handle *h, const double *y, const double *z, const double *x,
-                             double *out_host);
+/* Stopping quantities of Section 4.1 at the point (y, z, x), taken with Q x
+ * as in the paper's eta_d and gap, in the given problem's variables (also
+ * when the handle is preconditioned).  Writes eta_p, eta_d, eta_gap, pobj,
+ * dobj and qwx_gap = ||Q(w - x)||_inf of *info_host (host struct; the other
+ * fields are zeroed); w is the shadow iterate w_Q of Proposition 2.4 and may
+ * be NULL (qwx_gap is then NaN).  y (m), z, w, x (n) are device arrays. */
+hprqp_status hprqp_residuals(hprqp_handle *h, const double *y, const double *z, const double *w,
+                             const double *x, hprqp_info *info_host);
 
 /* Applies one operator of the handle: op 0: out = Q in (n -> n), op 1:
  * out = A in (n -> m), op 2: out = A^T in (m -> n, using the stored A^T). */
@@ -251,17 +259,23 @@ void hprqp_destroy(hprqp_handle *h);
  * --------------------------------------------------------------------- */
 
 /* probs: host array of `count` problems whose arrays are device pointers;
- * instances may share arrays (e.g. one Q and A with per-instance c, l, u).
- * The options apply to every instance (power method per instance when
- * lambda_A/lambda_Q <= 0, from an all-ones start).  Instances are scheduled
- * largest first. */
+ * instances may share arrays (e.g. one Q and A with per-instance c, l, u:
+ * shared arrays are detected by address, so an A is transposed once and an F
+ * padded once however many instances use it).  The library concatenates the
+ * instances itself; the per-instance offsets of the vectors are those of
+ * hprqp_solve_batch.  The options apply to every instance (power method per
+ * instance when lambda_A/lambda_Q <= 0, from an all-ones start); time_limit_s
+ * counts from the start of hprqp_solve_batch, and an instance still running
+ * then stops at its next check with HPRQP_TIME_LIMIT (0: no limit).
+ * Instances are scheduled largest first. */
 hprqp_status hprqp_batch_create(int32_t count, const hprqp_problem *probs,
                                 const hprqp_options *opt, hipStream_t stream, hprqp_batch **out);
 
 /* Solves every instance.  Vectors are concatenated in instance order:
  * y0/y use offsets sum_{j<i} m_j, w0/x0/z/w/x use offsets sum_{j<i} n_j.
  * y0, w0, x0 may each be NULL (origin for every instance).  infos_host:
- * host array of `count` hprqp_info (may be NULL). */
+ * host array of `count` hprqp_info (may be NULL); qwx_gap of each is taken
+ * at the instance's returned point after the solve kernels. */
 hprqp_status hprqp_solve_batch(hprqp_batch *b, const double *y0, const double *w0, const double *x0,
                                double *y, double *z, double *w, double *x, hprqp_info *infos_host);
 

@@ -49,7 +49,7 @@ class hprqp_info(C.Structure):
                 ("lambda_Q", C.c_double), ("eta_p", C.c_double), ("eta_d", C.c_double),
                 ("eta_gap", C.c_double), ("pobj", C.c_double), ("dobj", C.c_double),
                 ("R_last", C.c_double), ("t_setup_s", C.c_double), ("t_solve_s", C.c_double),
-                ("t_precond_s", C.c_double)]
+                ("t_precond_s", C.c_double), ("qwx_gap", C.c_double)]
 
 
 EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_apply",
@@ -71,7 +71,7 @@ def load():
     lib.hprqp_default_options.restype = None
     lib.hprqp_create.argtypes = [C.POINTER(hprqp_problem), C.POINTER(hprqp_options), _vp, C.POINTER(_vp)]
     lib.hprqp_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(hprqp_info)]
-    lib.hprqp_residuals.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(C.c_double)]
+    lib.hprqp_residuals.argtypes = [_vp, _vp, _vp, _vp, _vp, C.POINTER(hprqp_info)]
     lib.hprqp_apply.argtypes = [_vp, C.c_int32, _vp, _vp]
     lib.hprqp_power_info.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int32)]

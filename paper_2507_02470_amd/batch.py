@@ -160,7 +160,7 @@ class BatchSolver:
         ks = self.lib.hprqp_batch_last_kernel_s(self.h)
         inf = [dict(term=N.TERM[f.term], iters=int(f.iters), restarts=int(f.restarts), sigma=f.sigma,
                     sigma0=f.sigma0, lambda_A=f.lambda_A, lambda_Q=f.lambda_Q, eta_p=f.eta_p, eta_d=f.eta_d,
-                    eta_gap=f.eta_gap, pobj=f.pobj, dobj=f.dobj, R_last=f.R_last,
+                    eta_gap=f.eta_gap, pobj=f.pobj, dobj=f.dobj, R_last=f.R_last, qwx_gap=f.qwx_gap,
                     kkt=max(f.eta_p, f.eta_d, f.eta_gap)) for f in infos]
         if not split:
             return BatchResult(y=y[:self.total_m], z=z, w=w, x=x, infos=inf, kernel_s=ks)

@@ -79,6 +79,10 @@ struct BOpts {
   double sigma0, lamA, lamQ;
   double alpha1, alpha2, alpha3;
   int enable_restart, enable_sigma_update;
+  // time limit: wall-clock ticks (wall_clock64) since *t0, the stamp taken
+  // on the stream just before the solve kernels; 0: none
+  long long time_ticks;
+  const long long* t0;
 };
 
 struct BInfo {
@@ -441,6 +445,7 @@ __device__ __noinline__ void check_decision(BShared<BS>& S, const BOpts& o, doub
   if (isnan(kkt) || isnan(R)) tm = HPRQP_NUMERICAL;
   else if (kkt <= o.tol) tm = HPRQP_SOLVED;
   else if (k >= o.max_iter) tm = HPRQP_MAX_ITER;
+  else if (o.time_ticks > 0 && (long long)(wall_clock64() - *o.t0) >= o.time_ticks) tm = HPRQP_TIME_LIMIT;
   else if (o.enable_restart) {
     const bool c1 = R <= o.alpha1 * Rr0;                              // eq:restart_1
     const bool c2 = Rprev >= 0.0 && R <= o.alpha2 * Rr0 && R > Rprev; // eq:restart_2
@@ -913,6 +918,65 @@ __global__ void k_zero_ints(int* p, int k) {
   if ((int)threadIdx.x < k) p[threadIdx.x] = 0;
 }
 
+// the time-limit stamp of a solve
+__global__ void k_stamp(long long* t0) {
+  if (threadIdx.x == 0) *t0 = (long long)wall_clock64();
+}
+
+// ||Q(w - x)||_inf of every instance at its returned point, Q = diag(d) + F F^T
+// (the diagnostic of the shadow w_Q of Proposition 2.4): one workgroup per
+// instance, t = F^T (w - x) and the maximum by fixed-order reductions
+#define HB_QWX_BS 256
+__global__ __launch_bounds__(HB_QWX_BS) void k_batch_qwx(const BInst* __restrict__ insts, int count,
+                                                          const double* __restrict__ w, const double* __restrict__ x,
+                                                          double* __restrict__ out) {
+  constexpr int NW = HB_QWX_BS / 64;
+  __shared__ double part[16][NW];
+  __shared__ double t[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int ii = blockIdx.x; ii < count; ii += gridDim.x) {
+    const BInst I = insts[ii];
+    const double* wi = w + I.off_n;
+    const double* xi = x + I.off_n;
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    for (int i = threadIdx.x; i < I.n; i += HB_QWX_BS) {
+      const double d = wi[i] - xi[i];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < I.r) acc[k] += I.F[(size_t)i * I.r + k] * d;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double v = wave_sum(acc[k]);
+      if (lane == 0) part[k][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      double v = 0.0;
+      for (int q = 0; q < NW; ++q) v += part[threadIdx.x][q];
+      t[threadIdx.x] = v;
+    }
+    __syncthreads();
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < I.n; i += HB_QWX_BS) {
+      double q = I.dg[i] * (wi[i] - xi[i]);
+      for (int k = 0; k < I.r; ++k) q += I.F[(size_t)i * I.r + k] * t[k];
+      mx = fmax(mx, fabs(q));
+    }
+    mx = wave_max(mx);
+    if (lane == 0) part[0][wv] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = part[0][0];
+      for (int q = 1; q < NW; ++q) v = fmax(v, part[0][q]);
+      out[ii] = v;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -925,6 +989,8 @@ struct hprqp_batch {
   int* d_queue = nullptr;
   int* d_flags = nullptr;
   BInfo* d_infos = nullptr;
+  double* d_qwx = nullptr;     // ||Q(w - x)||_inf per instance
+  long long* d_t0 = nullptr;   // time-limit stamp
   int *trp = nullptr, *tci = nullptr;
   double* tval = nullptr;
   long long* d_toff = nullptr;
@@ -947,7 +1013,7 @@ struct hprqp_batch {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ~hprqp_batch() {
     void* ps[] = {d_insts, d_order, d_queue, d_flags,   d_infos, trp,     tci,     tval,
-                  d_toff,  d_rep,   ft,      d_ftoff,   d_ftrep, hbuf,    hbuf_small};
+                  d_toff,  d_rep,   ft,      d_ftoff,   d_ftrep, hbuf,    hbuf_small, d_qwx, d_t0};
     for (void* p : ps)
       if (p) hipFree(p);
     if (e0) hipEventDestroy(e0);
@@ -990,6 +1056,15 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     b->o.sigma0 = opt->sigma0; b->o.lamA = opt->lambda_A; b->o.lamQ = opt->lambda_Q;
     b->o.alpha1 = opt->alpha1; b->o.alpha2 = opt->alpha2; b->o.alpha3 = opt->alpha3;
     b->o.enable_restart = opt->enable_restart; b->o.enable_sigma_update = opt->enable_sigma_update;
+    if (!(opt->time_limit_s >= 0.0)) bfail(HPRQP_ERR_ARG, "time_limit_s must be >= 0");
+    if (opt->time_limit_s > 0.0) {
+      int dev = 0, khz = 0;
+      HBC(hipGetDevice(&dev));
+      HBC(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+      if (khz <= 0) bfail(HPRQP_ERR_HIP, "device reports no wall-clock rate");
+      const double ticks = std::ceil(opt->time_limit_s * 1e3 * (double)khz);
+      b->o.time_ticks = ticks >= 9e18 ? (long long)9e18 : std::max(1ll, (long long)ticks);
+    }
     std::vector<BInst> hi(count);
     // unique A matrices (instances may share one) -> one A^T each
     std::vector<int> rep_of(count);
@@ -1121,6 +1196,9 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     }
     HBC(hipEventCreate(&b->e0));
     HBC(hipEventCreate(&b->e1));
+    HBC(hipMalloc(&b->d_qwx, count * sizeof(double)));
+    HBC(hipMalloc(&b->d_t0, sizeof(long long)));
+    b->o.t0 = b->d_t0;
     HBC(hipStreamSynchronize(st));
     *out = b;
   } catch (...) {
@@ -1135,6 +1213,7 @@ void solve_batch_impl(hprqp_batch* b, const double* y0, const double* w0, const 
   if (b->own_st) HBC(hipDeviceSynchronize());
   k_zero_ints<<<1, 64, 0, b->st>>>(b->d_queue, 2);
   HBC(hipEventRecord(b->e0, b->st));
+  k_stamp<<<1, 64, 0, b->st>>>(b->d_t0);
   // one launch per class; the 256-thread kernel on the second stream when both run
   const auto launch = [&](auto bs_tag, hipStream_t s, int grid, int first, int cnt, int* queue, double* hbuf) {
     constexpr int BS = decltype(bs_tag)::value;
@@ -1162,8 +1241,12 @@ void solve_batch_impl(hprqp_batch* b, const double* y0, const double* w0, const 
     HBC(hipStreamWaitEvent(b->st, b->ev_join, 0));
   }
   HBC(hipEventRecord(b->e1, b->st));
+  k_batch_qwx<<<std::min(b->count, 4096), HB_QWX_BS, 0, b->st>>>(b->d_insts, b->count, w, x, b->d_qwx);
+  HBC(hipGetLastError());
   std::vector<BInfo> hi(b->count);
+  std::vector<double> hq(b->count);
   HBC(hipMemcpyAsync(hi.data(), b->d_infos, b->count * sizeof(BInfo), hipMemcpyDeviceToHost, b->st));
+  HBC(hipMemcpyAsync(hq.data(), b->d_qwx, b->count * sizeof(double), hipMemcpyDeviceToHost, b->st));
   HBC(hipStreamSynchronize(b->st));
   float ms = 0.f;
   HBC(hipEventElapsedTime(&ms, b->e0, b->e1));
@@ -1176,6 +1259,7 @@ void solve_batch_impl(hprqp_batch* b, const double* y0, const double* w0, const 
       f.sigma = hi[i].sigma; f.sigma0 = hi[i].sigma0; f.lambda_A = hi[i].lamA; f.lambda_Q = hi[i].lamQ;
       f.eta_p = hi[i].eta_p; f.eta_d = hi[i].eta_d; f.eta_gap = hi[i].eta_gap;
       f.pobj = hi[i].pobj; f.dobj = hi[i].dobj; f.R_last = hi[i].R_last;
+      f.qwx_gap = hq[i];
     }
 }
 }  // namespace

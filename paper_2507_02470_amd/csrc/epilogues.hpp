@@ -199,6 +199,18 @@ struct EpiResQ {
   }
 };
 
+// acc[0] = max |q_i| s_i (s NULL: 1): the inf-norm of a product, optionally
+// rescaled row by row
+struct EpiMaxAbs {
+  const double* s;
+  static constexpr int NR = 1;
+  static constexpr unsigned MAXMASK = 0x1u;
+  __device__ void setup(const DevParams*, int) {}
+  __device__ __forceinline__ void operator()(int i, double q, double* acc) const {
+    acc[0] = fmax(acc[0], fabs(q) * (s ? s[i] : 1.0));
+  }
+};
+
 // theta~_3 = <e, Q e>, e = A^T (ybar - y_a)
 struct EpiTheta3 {
   const double* e;

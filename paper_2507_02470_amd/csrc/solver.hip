@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -71,11 +72,12 @@ enum : int {
   SL_POW = 30,  // power method: 2 slots
   SL_NRM = 32,  // norms of b and c: 4 slots
   SL_LR = 36,   // F^T x of the low-rank Q: 16 slots
-  SL_TOTAL = 52
+  SL_QWX = 52,  // ||Q(w - x)||_inf at the returned point: 1 slot
+  SL_TOTAL = 53
 };
 static constexpr unsigned long long kMaxMask =
     (1ull << (SL_RA + 0)) | (1ull << (SL_RA + 1)) | (1ull << (SL_RQ + 0)) | (1ull << (SL_RQ + 1)) |
-    (1ull << (SL_RQ + 2)) | (1ull << (SL_NRM + 1)) | (1ull << (SL_NRM + 3));
+    (1ull << (SL_RQ + 2)) | (1ull << (SL_NRM + 1)) | (1ull << (SL_NRM + 3)) | (1ull << SL_QWX);
 
 #include "small.hpp"   // uses the reduction slots above
 
@@ -107,6 +109,12 @@ __global__ void k_zero_ints(int n, int* p) {
 __global__ void k_fill(long long n, double* p, double v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
+}
+// o = (a - b) f (f NULL: 1)
+__global__ void k_diff(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                       const double* __restrict__ f, double* __restrict__ o) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    o[i] = f ? (a[i] - b[i]) * f[i] : a[i] - b[i];
 }
 __global__ void k_mul(long long n, const double* __restrict__ s, const double* __restrict__ f, double* __restrict__ o) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -539,6 +547,19 @@ void q_apply(hprqp_handle& h, const double* x, const Epi& epi, int j, const RedO
     default:
       fail(HPRQP_ERR_UNSUPPORTED, "unknown qkind");
   }
+}
+
+// ||Q(w - x)||_inf of the problem as given, for (w, x) in the variables the
+// method runs on (the scaled ones when preconditioned: Q D (w~ - x~) =
+// D^-1 Q~ (w~ - x~)).  At a solution the shadow w_Q and x differ by an
+// element of ker Q (Proposition 2.4), so this is 0 up to rounding there.
+double qwx_norm(hprqp_handle& h, const double* wv, const double* xv) {
+  k_diff<<<hq_grid(h.n, 256), 256, 0, h.st>>>(h.n, wv, xv, nullptr, h.t1);
+  q_apply(h, h.t1, EpiMaxAbs{h.pre ? h.iDs : nullptr}, 0, red_seq(h, SL_QWX, 1));
+  final_reduce(h, SL_QWX, 1);
+  HQC(hipMemcpyAsync(h.hs + SL_QWX, h.scalars + SL_QWX, sizeof(double), hipMemcpyDeviceToHost, h.st));
+  HQC(hipStreamSynchronize(h.st));
+  return h.hs[SL_QWX];
 }
 
 void write_params(hprqp_handle& h, double sigma, long long t0) {
@@ -1415,11 +1436,13 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
   copy_or_zero(h, n, h.xbo, xo, h.pre ? h.Ds : nullptr);
   HQC(hipStreamSynchronize(h.st));
   if (info) {
+    const double tsolve = now_s() - tstart;
     info->term = term; info->iters = k; info->restarts = r; info->n_log = nlog;
     info->sigma = sigma; info->sigma0 = h.sigma0; info->lambda_A = h.lamA; info->lambda_Q = h.lamQ;
     info->eta_p = res.eta_p; info->eta_d = res.eta_d; info->eta_gap = res.eta_gap;
     info->pobj = res.pobj; info->dobj = res.dobj; info->R_last = R;
-    info->t_setup_s = h.t_setup; info->t_solve_s = now_s() - tstart; info->t_precond_s = h.t_precond;
+    info->t_setup_s = h.t_setup; info->t_solve_s = tsolve; info->t_precond_s = h.t_precond;
+    info->qwx_gap = qwx_norm(h, h.wbar, h.xbo);   // diagnostic of the shadow w_Q, after the timed solve
   }
 }
 
@@ -1672,11 +1695,15 @@ void solve_primal_impl(hprqp_handle& h, const double* y0, const double* w0, cons
     info->eta_p = res.eta_p; info->eta_d = res.eta_d; info->eta_gap = res.eta_gap;
     info->pobj = res.pobj; info->dobj = res.dobj; info->R_last = R;
     info->t_setup_s = h.t_setup; info->t_solve_s = now_s() - tstart; info->t_precond_s = h.t_precond;
+    // w = xbar (Algorithm 6: 0) or vbar (Algorithm 7)
+    info->qwx_gap = qwx_norm(h, meth == 2 ? h.wbar : h.xbo, h.xbo);
   }
 }
 
-void residuals_impl(hprqp_handle& h, const double* y, const double* z, const double* x, double* out) {
-  if (!z || !x || (h.m > 0 && !y) || !out) fail(HPRQP_ERR_ARG, "NULL argument");
+void residuals_impl(hprqp_handle& h, const double* y, const double* z, const double* w, const double* x,
+                    hprqp_info* info) {
+  if (!z || !x || (h.m > 0 && !y) || !info) fail(HPRQP_ERR_ARG, "NULL argument");
+  const double* const x_given = x;   // x below becomes the scaled copy when preconditioned
   write_params(h, h.sigma0, 0);
   k_zero_ints<<<1, 64, 0, h.st>>>(SL_ITER_END, h.counts);
   if (h.pre) {
@@ -1697,7 +1724,18 @@ void residuals_impl(hprqp_handle& h, const double* y, const double* z, const dou
   HQC(hipMemcpyAsync(h.hs, h.scalars, SL_ITER_END * sizeof(double), hipMemcpyDeviceToHost, h.st));
   HQC(hipStreamSynchronize(h.st));
   const Resid r = residuals_from(h, h.hs);
-  out[0] = r.eta_p; out[1] = r.eta_d; out[2] = r.eta_gap; out[3] = r.pobj; out[4] = r.dobj;
+  std::memset(info, 0, sizeof(*info));
+  info->eta_p = r.eta_p; info->eta_d = r.eta_d; info->eta_gap = r.eta_gap; info->pobj = r.pobj; info->dobj = r.dobj;
+  info->qwx_gap = std::numeric_limits<double>::quiet_NaN();
+  if (w) {
+    // Q (w - x) of the given problem: with preconditioning, (w - x)/D in the scaled variables
+    k_diff<<<hq_grid(h.n, 256), 256, 0, h.st>>>(h.n, w, x_given, h.pre ? h.iDs : nullptr, h.t2);
+    q_apply(h, h.t2, EpiMaxAbs{h.pre ? h.iDs : nullptr}, 0, red_seq(h, SL_QWX, 1));
+    final_reduce(h, SL_QWX, 1);
+    HQC(hipMemcpyAsync(h.hs + SL_QWX, h.scalars + SL_QWX, sizeof(double), hipMemcpyDeviceToHost, h.st));
+    HQC(hipStreamSynchronize(h.st));
+    info->qwx_gap = h.hs[SL_QWX];
+  }
 }
 
 void apply_impl(hprqp_handle& h, int op, const double* in, double* out) {
@@ -1765,8 +1803,9 @@ hprqp_status hprqp_solve(hprqp_handle* h, const double* y0, const double* w0, co
            else hq::solve_primal_impl(*h, y0, w0, x0, y, z, w, x, info));
 }
 
-hprqp_status hprqp_residuals(hprqp_handle* h, const double* y, const double* z, const double* x, double* out_host) {
-  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); hq::residuals_impl(*h, y, z, x, out_host));
+hprqp_status hprqp_residuals(hprqp_handle* h, const double* y, const double* z, const double* w, const double* x,
+                             hprqp_info* info_host) {
+  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); hq::residuals_impl(*h, y, z, w, x, info_host));
 }
 
 hprqp_status hprqp_apply(hprqp_handle* h, int32_t op, const double* in, double* out) {

@@ -111,6 +111,7 @@ class Result:
     t_setup_s: float
     t_solve_s: float
     t_precond_s: float = 0.0
+    qwx_gap: float = float("nan")
     trace: np.ndarray | None = None
     check_log: np.ndarray | None = None
 
@@ -185,17 +186,19 @@ class Solver:
                       lambda_A=info.lambda_A, lambda_Q=info.lambda_Q, eta_p=info.eta_p, eta_d=info.eta_d,
                       eta_gap=info.eta_gap, pobj=info.pobj, dobj=info.dobj, R_last=info.R_last,
                       t_setup_s=info.t_setup_s, t_solve_s=info.t_solve_s, t_precond_s=info.t_precond_s,
+                      qwx_gap=info.qwx_gap,
                       trace=None if self.trace is None else self.trace.copy(),
                       check_log=None if self.log is None else self.log[:info.n_log].copy())
 
-    def residuals(self, y, z, x) -> dict:
+    def residuals(self, y, z, x, w=None) -> dict:
         f64 = dict(dtype=torch.float64, device=self.device)
         yy = torch.as_tensor(y if self.dp.m else np.zeros(1), **f64).contiguous()
         zz = torch.as_tensor(z, **f64).contiguous(); xx = torch.as_tensor(x, **f64).contiguous()
-        out = (C.c_double * 5)()
-        N.check(self.lib.hprqp_residuals(self.h, _ptr(yy), _ptr(zz), _ptr(xx), out))
-        return dict(eta_p=out[0], eta_d=out[1], eta_gap=out[2], pobj=out[3], dobj=out[4],
-                    kkt=max(out[0], out[1], out[2]))
+        ww = None if w is None else torch.as_tensor(w, **f64).contiguous()
+        info = N.hprqp_info()
+        N.check(self.lib.hprqp_residuals(self.h, _ptr(yy), _ptr(zz), _ptr(ww), _ptr(xx), C.byref(info)))
+        return dict(eta_p=info.eta_p, eta_d=info.eta_d, eta_gap=info.eta_gap, pobj=info.pobj, dobj=info.dobj,
+                    kkt=max(info.eta_p, info.eta_d, info.eta_gap), qwx_gap=info.qwx_gap)
 
     def apply(self, op: str, v) -> torch.Tensor:
         code = {"Q": 0, "A": 1, "AT": 2}[op]

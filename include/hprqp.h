@@ -223,6 +223,27 @@ hprqp_status hprqp_set_options(hprqp_handle *h, const hprqp_options *opt);
 hprqp_status hprqp_residuals(hprqp_handle *h, const double *y, const double *z, const double *w,
                              const double *x, hprqp_info *info_host);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc, code that must not grow the device heap):
+ * the same quantities as hprqp_residuals -- eta_p, eta_d, eta_gap, pobj, dobj
+ * and qwx_gap = ||Q(w - x)||_inf (w may be NULL: NaN) of the problem as given
+ * -- without a handle and without allocating.  The problem is validated as
+ * at hprqp_create (HPRQP_ERR_BOUNDS / HPRQP_ERR_SHAPE); A^T y is formed by
+ * FP64 atomic additions (no stored transpose), so the last bits of eta_d and
+ * the dual objective can differ between calls.  Workspace: a 32 MiB device
+ * array of the library, one per GPU, held until the process ends; a problem
+ * needing more than 8 (n [m > 0] + n [w given] + n [Kronecker Q] + (gram_p + n)
+ * [Gram Q]) bytes beyond its 1.7 MiB of fixed parts is rejected with
+ * HPRQP_ERR_UNSUPPORTED (n = 1e6 with m > 0 and w fits).  Calls on one GPU
+ * share that array and are serialised within the process; calls from two
+ * processes on one GPU use separate copies.  The work runs on `stream` and
+ * the call returns after it (it synchronises the stream, so it cannot be
+ * captured into a graph).  y (m), z, w, x (n) are device arrays; info_host is
+ * a host struct whose other fields are zeroed. */
+hprqp_status hprqp_residuals_noalloc(const hprqp_problem *prob, const double *y, const double *z,
+                                     const double *w, const double *x, hprqp_info *info_host,
+                                     hipStream_t stream);
+
 /* Applies one operator of the handle: op 0: out = Q in (n -> n), op 1:
  * out = A in (n -> m), op 2: out = A^T in (m -> n, using the stored A^T). */
 hprqp_status hprqp_apply(hprqp_handle *h, int32_t op, const double *in, double *out);

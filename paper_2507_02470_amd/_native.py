@@ -52,7 +52,8 @@ class hprqp_info(C.Structure):
                 ("t_precond_s", C.c_double), ("qwx_gap", C.c_double)]
 
 
-EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_apply",
+EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_residuals_noalloc",
+           "hprqp_apply",
            "hprqp_power_info", "hprqp_scaling", "hprqp_kernel_stats", "hprqp_set_options", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
            "hprqp_batch_last_kernel_s", "hprqp_batch_destroy", "hprqp_last_error")
 
@@ -72,6 +73,7 @@ def load():
     lib.hprqp_create.argtypes = [C.POINTER(hprqp_problem), C.POINTER(hprqp_options), _vp, C.POINTER(_vp)]
     lib.hprqp_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(hprqp_info)]
     lib.hprqp_residuals.argtypes = [_vp, _vp, _vp, _vp, _vp, C.POINTER(hprqp_info)]
+    lib.hprqp_residuals_noalloc.argtypes = [C.POINTER(hprqp_problem), _vp, _vp, _vp, _vp, C.POINTER(hprqp_info), _vp]
     lib.hprqp_apply.argtypes = [_vp, C.c_int32, _vp, _vp]
     lib.hprqp_power_info.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int32)]
@@ -92,7 +94,8 @@ def load():
         lib.hprqp_batch_last_kernel_s.restype = C.c_double
         lib.hprqp_batch_destroy.argtypes = [_vp]
         lib.hprqp_batch_destroy.restype = None
-    for name in ("hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_apply", "hprqp_power_info",
+    for name in ("hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_residuals_noalloc", "hprqp_apply",
+                 "hprqp_power_info",
                  "hprqp_kernel_stats",
                  "hprqp_batch_create", "hprqp_solve_batch"):
         if hasattr(lib, name):

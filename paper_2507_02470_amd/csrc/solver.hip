@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1754,6 +1755,210 @@ void apply_impl(hprqp_handle& h, int op, const double* in, double* out) {
 }  // namespace hq
 
 // ---------------------------------------------------------------------------
+// Stopping quantities with no handle and no allocation (hprqp_residuals_noalloc)
+// ---------------------------------------------------------------------------
+// Workspace: one file-scope device array, which every GPU the library runs on
+// holds until the process ends.  Host code never uses its name as an address:
+// the device address comes from hipGetSymbolAddress, once per device.
+#define HQ_NOALLOC_BYTES (32ll << 20)
+static __device__ __align__(256) double scratch[HQ_NOALLOC_BYTES / sizeof(double)];
+
+// g += A^T y without a stored transpose: one nonzero per thread (its row
+// found by bisection of rowptr), added with FP64 atomics, so the order of the
+// additions, and the rounding of g, can differ between calls
+__global__ void k_csr_t_scatter(int rows, long long nnz, const int* __restrict__ rp, const int* __restrict__ ci,
+                                const double* __restrict__ v, const double* __restrict__ y, double* __restrict__ g) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (long long)gridDim.x * blockDim.x) {
+    int lo = 0, hi = rows - 1;   // the last row r with rp[r] <= k: the row holding k
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rp[mid] <= k) lo = mid;
+      else hi = mid - 1;
+    }
+    const double p = v[k] * y[lo];
+    if (p != 0.0) atomicAdd(g + ci[k], p);
+  }
+}
+
+namespace hq {
+
+#define HQ_NOALLOC_MAXDEV 64
+std::mutex g_noalloc_mu[HQ_NOALLOC_MAXDEV];        // one call at a time per device
+double* g_noalloc_ptr[HQ_NOALLOC_MAXDEV] = {};     // device address of `scratch`, per device
+
+// Fixed part of the workspace, in doubles: block partials, scalars, counters
+// and flags, the parameter block; the vectors follow.
+constexpr long long kNaPartials = (long long)SL_TOTAL * HQ_PCAP;
+constexpr long long kNaScalars = kNaPartials;            // 64 doubles
+constexpr long long kNaInts = kNaScalars + 64;           // 64 ints (32 doubles): counts, then flags
+constexpr long long kNaParams = kNaInts + 32;            // DevParams (32 doubles reserved)
+constexpr long long kNaVectors = kNaParams + 32;
+constexpr long long kNaCapacity = HQ_NOALLOC_BYTES / (long long)sizeof(double);
+static_assert(SL_TOTAL <= 60, "counts and flags share 64 ints");
+static_assert(sizeof(DevParams) <= 32 * sizeof(double), "parameter block");
+
+// Q v through the epilogue; the Gram Q = Ahat^T (Ahat v) takes Ahat v into
+// tp (p) and scatters Ahat^T of it into tq (n), then runs the epilogue on tq
+template <class Epi>
+void noalloc_q(hprqp_handle& h, const double* v, const Epi& epi, const RedOut& red, double* tp, double* tq) {
+  if (h.qkind != HPRQP_Q_GRAM) {
+    q_apply(h, v, epi, 0, red);
+    return;
+  }
+  launch_csr(h, h.G, v, EpiStore{tp}, 0, no_red(h));
+  k_fill<<<hq_grid(h.n, 256), 256, 0, h.st>>>(h.n, tq, 0.0);
+  if (h.G.nnz > 0)
+    k_csr_t_scatter<<<hq_grid(h.G.nnz, 256), 256, 0, h.st>>>(h.G.rows, h.G.nnz, h.G.rp, h.G.ci, h.G.v, tp, tq);
+  launch_elem(h, h.n, tq, epi, 0, red);
+}
+
+void residuals_noalloc_impl(const hprqp_problem* P, const double* y, const double* z, const double* w,
+                            const double* x, hprqp_info* info, hipStream_t st) {
+  if (!P || !info || !z || !x) fail(HPRQP_ERR_ARG, "NULL argument");
+  if (P->n <= 0 || P->m < 0) fail(HPRQP_ERR_SHAPE, "n must be > 0 and m >= 0");
+  if (!P->c || !P->L || !P->U) fail(HPRQP_ERR_ARG, "c, L, U are required");
+  if (P->m > 0 && (!y || !P->a_rowptr || !P->l || !P->u || (P->a_nnz > 0 && (!P->a_col || !P->a_val))))
+    fail(HPRQP_ERR_ARG, "y, A, l, u are required when m > 0");
+  if (P->a_nnz < 0 || P->a_nnz >= (1ll << 31) || P->q_nnz < 0 || P->q_nnz >= (1ll << 31))
+    fail(HPRQP_ERR_SHAPE, "nnz must fit int32");
+  if (!(P->l1_weight >= 0.0) || std::isinf(P->l1_weight)) fail(HPRQP_ERR_ARG, "l1_weight must be finite and >= 0");
+  const int n = P->n, m = P->m;
+  // the workspace this call needs: A^T y (n), the Kronecker or Gram
+  // intermediates, w - x (n)
+  long long need = (m > 0 ? n : 0) + (w ? n : 0);
+  switch (P->qkind) {
+    case HPRQP_Q_ZERO: break;
+    case HPRQP_Q_CSR:
+      if (!P->q_rowptr || (P->q_nnz > 0 && (!P->q_col || !P->q_val))) fail(HPRQP_ERR_ARG, "Q CSR arrays required");
+      break;
+    case HPRQP_Q_KRON:
+      if (!P->kron_B || !P->kron_C || P->kron_p <= 0 || P->kron_s <= 0) fail(HPRQP_ERR_ARG, "Kronecker factors required");
+      if ((long long)P->kron_p * P->kron_s != n) fail(HPRQP_ERR_SHAPE, "n must equal kron_p * kron_s");
+      need += n;
+      break;
+    case HPRQP_Q_GRAM:
+      if (P->gram_p <= 0 || !P->gram_rowptr || (P->gram_nnz > 0 && (!P->gram_col || !P->gram_val)))
+        fail(HPRQP_ERR_ARG, "Gram factor Ahat (gram_p > 0, CSR arrays) required");
+      if (P->gram_nnz < 0 || P->gram_nnz >= (1ll << 31)) fail(HPRQP_ERR_SHAPE, "gram_nnz must fit int32");
+      need += (long long)P->gram_p + n;
+      break;
+    case HPRQP_Q_LOWRANK:
+      if (!P->lr_d || (P->lr_rank > 0 && !P->lr_F)) fail(HPRQP_ERR_ARG, "low-rank arrays required");
+      if (P->lr_rank < 0 || P->lr_rank > 16) fail(HPRQP_ERR_UNSUPPORTED, "lr_rank must be in [0, 16]");
+      break;
+    default: fail(HPRQP_ERR_ARG, "unknown qkind");
+  }
+  if (need > kNaCapacity - kNaVectors)
+    fail(HPRQP_ERR_UNSUPPORTED, "problem needs " + std::to_string(need * 8) + " bytes of workspace; the allocation-free "
+                                "residuals hold " + std::to_string((kNaCapacity - kNaVectors) * 8));
+  int dev = 0;
+  HQC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= HQ_NOALLOC_MAXDEV) fail(HPRQP_ERR_UNSUPPORTED, "device index beyond the workspace table");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu[dev]);
+  if (!g_noalloc_ptr[dev]) {
+    void* addr = nullptr;
+    HQC(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+    g_noalloc_ptr[dev] = (double*)addr;
+  }
+  double* const ws = g_noalloc_ptr[dev];
+
+  // a handle on the stack whose workspace pointers point into `scratch`
+  // (it owns nothing: its destructor frees nothing)
+  hprqp_handle h;
+  h.dev = dev;
+  HQC(hipDeviceGetAttribute(&h.ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  h.st = st;
+  h.n = n; h.m = m; h.qkind = P->qkind; h.l1 = P->l1_weight;
+  h.c = P->c; h.L = P->L; h.U = P->U; h.l = P->l; h.u = P->u;
+  h.partials = ws;
+  h.scalars = ws + kNaScalars;
+  h.counts = (int*)(ws + kNaInts);
+  int* flags = h.counts + 60;                  // [0] validation, [1..3] longest row of A, Q, Ahat
+  h.dprm = (DevParams*)(ws + kNaParams);
+  double* vec = ws + kNaVectors;
+  double* g = nullptr;
+  if (m > 0) { g = vec; vec += n; }
+  double* d = nullptr;
+  if (w) { d = vec; vec += n; }
+  double *tp = nullptr, *tq = nullptr;
+  if (P->qkind == HPRQP_Q_KRON) { h.kronT = vec; vec += n; }
+  if (P->qkind == HPRQP_Q_GRAM) { tp = vec; vec += P->gram_p; tq = vec; vec += n; }
+  k_zero_ints<<<1, 64, 0, st>>>(64, h.counts);    // counts of every slot and the flags start at 0
+  k_fill<<<1, 64, 0, st>>>(32, ws + kNaParams, 0.0);
+  // validation (as at create) and the longest row of each CSR matrix
+  k_validate_vec<<<hq_grid(n, 256), 256, 0, st>>>(n, P->L, P->U, P->c, flags);
+  if (m > 0) {
+    k_validate_vec<<<hq_grid(m, 256), 256, 0, st>>>(m, P->l, P->u, nullptr, flags);
+    k_validate_csr<<<hq_grid(m, 256), 256, 0, st>>>(m, n, P->a_nnz, P->a_rowptr, P->a_col, P->a_val, flags);
+    k_max_row_len<<<hq_grid(m, 256), 256, 0, st>>>(m, P->a_rowptr, flags + 1);
+  }
+  switch (P->qkind) {
+    case HPRQP_Q_CSR:
+      k_validate_csr<<<hq_grid(n, 256), 256, 0, st>>>(n, n, P->q_nnz, P->q_rowptr, P->q_col, P->q_val, flags);
+      k_max_row_len<<<hq_grid(n, 256), 256, 0, st>>>(n, P->q_rowptr, flags + 2);
+      break;
+    case HPRQP_Q_KRON:
+      k_validate_finite<<<64, 256, 0, st>>>((long long)P->kron_p * P->kron_p, P->kron_B, flags);
+      k_validate_finite<<<64, 256, 0, st>>>((long long)P->kron_s * P->kron_s, P->kron_C, flags);
+      if (P->kron_S) k_validate_finite<<<64, 256, 0, st>>>((long long)P->kron_s * P->kron_s, P->kron_S, flags);
+      if (P->kron_T) k_validate_finite<<<64, 256, 0, st>>>((long long)P->kron_p * P->kron_p, P->kron_T, flags);
+      break;
+    case HPRQP_Q_LOWRANK:
+      k_validate_finite<<<64, 256, 0, st>>>(n, P->lr_d, flags);
+      if (P->lr_rank > 0) k_validate_finite<<<256, 256, 0, st>>>((long long)n * P->lr_rank, P->lr_F, flags);
+      break;
+    case HPRQP_Q_GRAM:
+      k_validate_csr<<<hq_grid(P->gram_p, 256), 256, 0, st>>>(P->gram_p, n, P->gram_nnz, P->gram_rowptr, P->gram_col,
+                                                              P->gram_val, flags);
+      k_max_row_len<<<hq_grid(P->gram_p, 256), 256, 0, st>>>(P->gram_p, P->gram_rowptr, flags + 3);
+      break;
+    default: break;
+  }
+  int hf[4] = {0, 0, 0, 0};
+  HQC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+  HQC(hipStreamSynchronize(st));
+  if (hf[0] & 2) fail(HPRQP_ERR_SHAPE, "CSR structure invalid (rowptr not monotone / not ending at nnz, or column out of range)");
+  if (hf[0] & 1) fail(HPRQP_ERR_BOUNDS, "invalid bounds (l > u, L > U, NaN, wrong-sided infinity) or non-finite data");
+  if (m > 0) h.A = Mat{m, n, P->a_rowptr, P->a_col, P->a_val, P->a_nnz, default_G(P->a_nnz, m, hf[1], n)};
+  if (P->qkind == HPRQP_Q_CSR) h.Q = Mat{n, n, P->q_rowptr, P->q_col, P->q_val, P->q_nnz, default_G(P->q_nnz, n, hf[2], n)};
+  if (P->qkind == HPRQP_Q_KRON) {
+    h.kp = P->kron_p; h.ks = P->kron_s; h.kB = P->kron_B; h.kC = P->kron_C; h.kS = P->kron_S; h.kT = P->kron_T;
+    h.kron_mode = 0;
+  }
+  if (P->qkind == HPRQP_Q_LOWRANK) { h.lr_r = P->lr_rank; h.lr_d = P->lr_d; h.lr_F = P->lr_F; }
+  if (P->qkind == HPRQP_Q_GRAM)
+    h.G = Mat{P->gram_p, n, P->gram_rowptr, P->gram_col, P->gram_val, P->gram_nnz,
+              default_G(P->gram_nnz, P->gram_p, hf[3], n)};
+  // norms of b and c (denominators of eta_p, eta_d)
+  if (m > 0) launch_elem(h, m, nullptr, EpiNormB{P->l, P->u}, 0, red_seq(h, SL_NRM, 2));
+  launch_elem(h, n, nullptr, EpiNormC{P->c}, 0, red_seq(h, SL_NRM + 2, 2));
+  // A^T y, then A x with the primal part, Q x with the dual part
+  if (m > 0) {
+    k_fill<<<hq_grid(n, 256), 256, 0, st>>>(n, g, 0.0);
+    if (P->a_nnz > 0)
+      k_csr_t_scatter<<<hq_grid(P->a_nnz, 256), 256, 0, st>>>(m, P->a_nnz, P->a_rowptr, P->a_col, P->a_val, y, g);
+    launch_csr(h, h.A, x, EpiResA{P->l, P->u, y, nullptr}, 0, red_seq(h, SL_RA, 4));
+  }
+  noalloc_q(h, x, EpiResQ{x, z, g, P->c, P->L, P->U, nullptr, nullptr, nullptr, h.l1}, red_seq(h, SL_RQ, 7), tp, tq);
+  if (w) {
+    k_diff<<<hq_grid(n, 256), 256, 0, st>>>(n, w, x, nullptr, d);
+    noalloc_q(h, d, EpiMaxAbs{nullptr}, red_seq(h, SL_QWX, 1), tp, tq);
+  }
+  final_reduce(h, 0, SL_TOTAL);
+  double hs[64];
+  HQC(hipMemcpyAsync(hs, h.scalars, SL_TOTAL * sizeof(double), hipMemcpyDeviceToHost, st));
+  HQC(hipStreamSynchronize(st));
+  h.binf = m > 0 ? hs[SL_NRM + 1] : 0.0;
+  h.cinf = hs[SL_NRM + 3];
+  const Resid r = residuals_from(h, hs);
+  std::memset(info, 0, sizeof(*info));
+  info->eta_p = r.eta_p; info->eta_d = r.eta_d; info->eta_gap = r.eta_gap; info->pobj = r.pobj; info->dobj = r.dobj;
+  info->qwx_gap = w ? hs[SL_QWX] : std::numeric_limits<double>::quiet_NaN();
+}
+
+}  // namespace hq
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 #define HQ_GUARD(...)                                    \
@@ -1806,6 +2011,11 @@ hprqp_status hprqp_solve(hprqp_handle* h, const double* y0, const double* w0, co
 hprqp_status hprqp_residuals(hprqp_handle* h, const double* y, const double* z, const double* w, const double* x,
                              hprqp_info* info_host) {
   HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle"); hq::residuals_impl(*h, y, z, w, x, info_host));
+}
+
+hprqp_status hprqp_residuals_noalloc(const hprqp_problem* prob, const double* y, const double* z, const double* w,
+                                     const double* x, hprqp_info* info_host, hipStream_t stream) {
+  HQ_GUARD(hq::residuals_noalloc_impl(prob, y, z, w, x, info_host, stream));
 }
 
 hprqp_status hprqp_apply(hprqp_handle* h, int32_t op, const double* in, double* out) {

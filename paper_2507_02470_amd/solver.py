@@ -79,6 +79,24 @@ class DeviceProblem:
         self.P = P
 
 
+def residuals_noalloc(dprob: DeviceProblem, y, z, x, w=None) -> dict:
+    """hprqp_residuals_noalloc: the stopping quantities of Section 4.1 (and
+    ||Q(w - x)||_inf) of the problem at (y, z, x) with no handle, computed in
+    the library's static workspace; the work runs on torch's current stream."""
+    lib = N.load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    f64 = dict(dtype=torch.float64, device=dev)
+    yy = torch.as_tensor(y if dprob.m else np.zeros(1), **f64).contiguous()
+    zz = torch.as_tensor(z, **f64).contiguous(); xx = torch.as_tensor(x, **f64).contiguous()
+    ww = None if w is None else torch.as_tensor(w, **f64).contiguous()
+    info = N.hprqp_info()
+    st = torch.cuda.current_stream(dev)
+    N.check(lib.hprqp_residuals_noalloc(C.byref(dprob.P), _ptr(yy), _ptr(zz), _ptr(ww), _ptr(xx), C.byref(info),
+                                        C.c_void_p(st.cuda_stream)))
+    return dict(eta_p=info.eta_p, eta_d=info.eta_d, eta_gap=info.eta_gap, pobj=info.pobj, dobj=info.dobj,
+                kkt=max(info.eta_p, info.eta_d, info.eta_gap), qwx_gap=info.qwx_gap)
+
+
 def default_options(**kw) -> N.hprqp_options:
     o = N.hprqp_options()
     N.load().hprqp_default_options(C.byref(o))

@@ -281,13 +281,27 @@ def extra_batch(count, cpu):
     import qpgen
     from paper_2507_02470_amd.batch import BatchSolver
     qps = qpgen.make_portfolio_batch(count)
-    b = BatchSolver(qps, tol=1e-8, max_iter=200_000)
-    b.solve(split=False)
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    r = b.solve(split=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - ta
+
+    def timed(**opts):
+        tc = time.perf_counter()
+        b = BatchSolver(qps, tol=1e-8, max_iter=200_000, **opts)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - tc
+        b.solve(split=False)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = b.solve(split=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ta
+        sh = b.shapes()
+        b.close()
+        return r, dt, tc, sh
+
+    # default shapes, then the shapes the autotuner picks at create (reported)
+    r0, dt0, tc0, sh0 = timed()
+    r, dt, tc, sh = timed(spmv_autotune=1)
+    log(f"batch: default shapes {sh0['threads']} kernel {r0.kernel_s:.4f} s; tuned {sh['threads']} "
+        f"kernel {r.kernel_s:.4f} s (create {tc:.3f} s incl. tuning)")
     it = r.iters
     terms = [f["term"] for f in r.infos]
     # FP64 vector work per iteration of an instance (n variables, rank r, nnz(A)):
@@ -304,8 +318,13 @@ def extra_batch(count, cpu):
                max_kkt=float(max(f["kkt"] for f in r.infos)),
                roofline=dict(bound="alu", achieved=round(achieved, 3), peak=FP64_VECTOR_PEAK_TFLOPS,
                              unit="TFLOP/s", frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                             flop_per_batch=flops))
-    b.close()
+                             flop_per_batch=flops),
+               shapes=dict(class_max_n=sh["class_max_n"], instances=sh["instances"], threads=sh["threads"],
+                           tuned_us_per_instance_iteration={f"n<={c},{t}thr": round(v, 4)
+                                                            for (c, t), v in sh["timed_us"].items()},
+                           create_s_with_tuning=round(tc, 3)),
+               default_shapes=dict(threads=sh0["threads"], kernel_s=round(r0.kernel_s, 4), wall_s=round(dt0, 4),
+                                   iterations_mean=round(float(r0.iters.mean()), 1)))
     if cpu:
         import oracle
         sample = sorted(range(count), key=lambda i: qps[i].n)[::max(1, count // 64)][:64]

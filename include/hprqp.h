@@ -164,6 +164,10 @@ typedef struct {
                                  iteration.  -1: when n <= 4096 and m <= 4096; 0: never; 1:
                                  always (HPRQP_ERR_UNSUPPORTED for other Q kinds).  Segments
                                  timed by profile_kernels use the four-launch path; -1       */
+  int32_t batch_threads;      /* batched solve: 0: threads per workgroup of each size class by
+                                 default or by the autotuner (spmv_autotune = 1); 64, 128, 256
+                                 or 512: that many for every class it can hold (n <= 4 x
+                                 threads), the default for the others; 0                    */
 } hprqp_options;
 
 typedef struct {
@@ -272,9 +276,10 @@ void hprqp_destroy(hprqp_handle *h);
  * Batched solve: many independent QPs (sizes may differ) solved by
  * persistent kernels, one workgroup per instance at a time, with the whole
  * of Algorithm 4 + 5 (restart, sigma update, termination) on the device.
- * Instances with n <= 1024 run on a second kernel (two workgroups per
- * compute unit) on a stream of the library's, joined to `stream` before
- * the solve returns.  Supported: qkind HPRQP_Q_LOWRANK with lr_rank <= 16
+ * The instances are cut into size classes, each run on a kernel of a block
+ * size of its own (hprqp_batch_shapes); the kernels run at once, all but
+ * one on streams of the library's, joined to `stream` before the solve
+ * returns.  Supported: qkind HPRQP_Q_LOWRANK with lr_rank <= 16
  * and n <= 2048, m <= 64 per instance, at most n nonzeros in a row of A
  * (no preconditioning: Q is matrix-free).
  * --------------------------------------------------------------------- */
@@ -300,8 +305,23 @@ hprqp_status hprqp_batch_create(int32_t count, const hprqp_problem *probs,
 hprqp_status hprqp_solve_batch(hprqp_batch *b, const double *y0, const double *w0, const double *x0,
                                double *y, double *z, double *w, double *x, hprqp_info *infos_host);
 
+/* Shapes of the batched solver: the instances are cut into 4 size classes
+ * (n <= 256, 512, 1024, 2048) and each class runs on a persistent kernel of
+ * 64, 128, 256 or 512 threads per workgroup (a thread holds up to 4 entries,
+ * so a class needs 4 x threads >= its largest n).  By default 256 threads up
+ * to n = 1024 and 512 above; with spmv_autotune = 1 at hprqp_batch_create,
+ * every fitting block size is timed on a sample of the class (100 iterations
+ * per instance, up to 8 instances per compute unit) and the fastest is kept
+ * unless the default is within 5% of it.  Host outputs (each may be NULL):
+ * class_count_host[4] instances per class, class_threads_host[4] the chosen
+ * threads per workgroup, class_us_host[4 * 4] the measured kernel time per
+ * instance-iteration in microseconds of class c with 64 << j threads at
+ * [4 c + j] (0 where not timed). */
+hprqp_status hprqp_batch_shapes(hprqp_batch *b, int32_t *class_count_host, int32_t *class_threads_host,
+                                double *class_us_host);
+
 /* Elapsed time of the last hprqp_solve_batch kernels (HIP events on `stream`
- * around both), seconds. */
+ * around them), seconds. */
 double hprqp_batch_last_kernel_s(hprqp_batch *b);
 
 void hprqp_batch_destroy(hprqp_batch *b);

@@ -40,7 +40,7 @@ class hprqp_options(C.Structure):
                 ("log_cap", C.c_int32), ("check_log_host", C.POINTER(C.c_double)),
                 ("profile_kernels", C.c_int32), ("precondition", C.c_int32), ("ruiz_iters", C.c_int32),
                 ("spmv_lanes", C.c_int32), ("method", C.c_int32), ("kron_kernel", C.c_int32),
-                ("small_path", C.c_int32)]
+                ("small_path", C.c_int32), ("batch_threads", C.c_int32)]
 
 
 class hprqp_info(C.Structure):
@@ -55,7 +55,7 @@ class hprqp_info(C.Structure):
 EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_residuals_noalloc",
            "hprqp_apply",
            "hprqp_power_info", "hprqp_scaling", "hprqp_kernel_stats", "hprqp_set_options", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
-           "hprqp_batch_last_kernel_s", "hprqp_batch_destroy", "hprqp_last_error")
+           "hprqp_batch_last_kernel_s", "hprqp_batch_shapes", "hprqp_batch_destroy", "hprqp_last_error")
 
 _lib = None
 
@@ -92,6 +92,8 @@ def load():
         lib.hprqp_solve_batch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(hprqp_info)]
         lib.hprqp_batch_last_kernel_s.argtypes = [_vp]
         lib.hprqp_batch_last_kernel_s.restype = C.c_double
+        lib.hprqp_batch_shapes.argtypes = [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        lib.hprqp_batch_shapes.restype = C.c_int
         lib.hprqp_batch_destroy.argtypes = [_vp]
         lib.hprqp_batch_destroy.restype = None
     for name in ("hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_residuals_noalloc", "hprqp_apply",

@@ -137,6 +137,15 @@ class BatchSolver:
         parts = [c, self.t["u"][:self.count * m].view(self.count, m)] if m else [c]
         return torch.cat(parts, dim=1).to(torch.float32)
 
+    def shapes(self) -> dict:
+        """Size classes (n <= 256, 512, 1024, 2048) of the batch: instances,
+        threads per workgroup of each, and the autotuner's measured kernel
+        time per instance-iteration (us) of every block size it timed."""
+        cnt = (C.c_int32 * 4)(); thr = (C.c_int32 * 4)(); us = (C.c_double * 16)()
+        N.check(self.lib.hprqp_batch_shapes(self.h, cnt, thr, us))
+        return dict(class_max_n=[256, 512, 1024, 2048], instances=list(cnt), threads=list(thr),
+                    timed_us={(256 << c, 64 << j): us[4 * c + j] for c in range(4) for j in range(4) if us[4 * c + j] > 0})
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.hprqp_batch_destroy(self.h)

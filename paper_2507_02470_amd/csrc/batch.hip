@@ -2,9 +2,13 @@
 // 2507.02470) in persistent kernels on one MI355X.
 //
 // One workgroup owns one instance at a time; instances are pulled from a
-// work queue ordered by size (largest first).  Instances with n <= 1024 run
-// on a 256-thread kernel whose LDS lets two workgroups share a CU, the
-// others on a 512-thread kernel (one per CU), both at once on two streams.
+// work queue ordered by size (largest first).  The instances are cut into
+// size classes (n <= 256, 512, 1024, 2048) and each class runs on a kernel of
+// 64, 128, 256 or 512 threads per workgroup (at most 4 entries per thread):
+// by default 256 threads up to n = 1024 (two workgroups per CU) and 512 above
+// (one per CU); with autotuning, create times every block size that can hold
+// a class on a sample of the class's instances and keeps the fastest.  The
+// kernels of the block sizes in use run at once on their own streams.
 // Thread t of a BS-thread workgroup owns entries t + BS e, e < HB_EPT (so
 // n <= BS * HB_EPT): the per-iteration vectors of
 // its entries are in registers, and so are its rows of the low-rank factor F
@@ -39,24 +43,29 @@ extern thread_local std::string g_err;
 #define HB_BS 512
 #define HB_EPT 4
 #define HB_NMAX (HB_BS * HB_EPT)                      // largest n (the 512-thread kernel)
-#define HB_NMAX_SMALL 1024                             // largest n of the 256-thread kernel
+#define HB_NCLASS 4                                    // size classes: n <= 256, 512, 1024, 2048
 #define HB_MMAX 64
 #define HB_RMAX 16
 #define HB_APIECE 256                                  // nonzeros of A per wave work item
 #define HB_ATSTEP 3                                    // nonzeros per entry and step of the A^T product
 
-// Per-block sizes of the two kernels: 512 threads for n <= 2048 (one block
-// per CU, the LDS holds 156 KB), 256 threads for n <= 1024 (two per CU, so
-// that one block's waits are covered by the other's work).  Entry i of a
-// vector belongs to thread i mod BS, so NMAX = BS * HB_EPT: the slots of
-// every thread's HB_EPT entries exist, also beyond n.
+// Per-block sizes of the kernels: BS = 64, 128, 256 or 512 threads for
+// n <= 4 BS (512 threads: one block per CU, the LDS holds 156 KB; 256: two per
+// CU, so that one block's waits are covered by the other's work; smaller
+// blocks let more instances share a CU).  Entry i of a vector belongs to
+// thread i mod BS, so NMAX = BS * HB_EPT: the slots of every thread's HB_EPT
+// entries exist, also beyond n.
 template <int BS>
 struct BCfg {
+  static_assert(BS == 64 || BS == 128 || BS == 256 || BS == 512, "block sizes");
   static constexpr int WAVES = BS / 64;
   static constexpr int NMAX = BS * HB_EPT;
   // pieces of A at most: a row has at most n nonzeros (checked at create)
   static constexpr int PMAX = HB_MMAX * ((NMAX + HB_APIECE - 1) / HB_APIECE);
-  static_assert(NMAX == (BS == HB_BS ? HB_NMAX : HB_NMAX_SMALL), "class sizes");
+  // launch bound: the compiler counts a block's waves per SIMD, so 2 blocks
+  // mean 2 waves per SIMD (about 256 VGPRs) at every block size; more small
+  // blocks still share a CU when the registers and LDS allow
+  static constexpr int MIN_BLOCKS = 2;
 };
 
 struct BInst {
@@ -164,7 +173,7 @@ __device__ __forceinline__ double wave_reduce63(double v) {
 template <int K, int BS>
 __device__ __forceinline__ void bred(BShared<BS>& S, int& par, double (&v)[K], unsigned maxmask) {
   constexpr int W = BCfg<BS>::WAVES;   // partials per value
-  static_assert(K <= HB_RED && (W == 4 || W == 8), "reduction layout");
+  static_assert(K <= HB_RED && (W == 1 || W == 2 || W == 4 || W == 8), "reduction layout");
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int s = 0; s < K; ++s) {
@@ -473,7 +482,7 @@ __device__ __noinline__ void check_decision(BShared<BS>& S, const BOpts& o, doub
 // persistent kernel (RM: largest rank of F handled, F rows padded with zeros)
 // ---------------------------------------------------------------------------
 template <int RM, int BS>
-__global__ __launch_bounds__(BS, 2) void k_batch_solve(const BInst* __restrict__ insts, const int* __restrict__ order,
+__global__ __launch_bounds__(BS, BCfg<BS>::MIN_BLOCKS) void k_batch_solve(const BInst* __restrict__ insts, const int* __restrict__ order,
                                                       int count, int* __restrict__ queue, BOpts o,
                                                       const double* __restrict__ y0, const double* __restrict__ w0,
                                                       const double* __restrict__ x0, double* __restrict__ yo,
@@ -998,29 +1007,41 @@ struct hprqp_batch {
   double* ft = nullptr;        // F of every instance, rows padded to rank_max
   long long* d_ftoff = nullptr;
   int* d_ftrep = nullptr;      // one instance per distinct F
-  // instances with n > HB_NMAX_SMALL (d_order[0, nbig)) run on the 512-thread
-  // kernel, the others (d_order[nbig, count)) on the 256-thread kernel, on a
-  // second stream at the same time; d_queue holds one counter per kernel
-  int nbig = 0, nsmall = 0;
-  int grid_big = 0, grid_small = 0;
-  double* hbuf = nullptr;      // per-block check buffers of the 512-thread kernel
-  double* hbuf_small = nullptr;
-  hipStream_t st2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // one persistent kernel per block size in use: kernel k takes the
+  // instances d_order[first, first + cnt) (largest first) with kern[k].bs
+  // threads per workgroup, on its own stream (kernel 0 on the batch stream);
+  // d_queue holds one counter per kernel
+  struct Kern {
+    int bs = 0, first = 0, cnt = 0, grid = 0;
+    double* hbuf = nullptr;    // per-block check buffers
+    hipStream_t st = nullptr;  // created by the library for kernels 1..
+    hipEvent_t ev_join = nullptr;
+  } kern[HB_NCLASS];
+  int nkern = 0;
+  hipEvent_t ev_fork = nullptr;
+  // size classes n <= 256 << c: instances, block size, and (autotuned) the
+  // mean kernel time per instance-iteration of each candidate block size
+  int class_cnt[HB_NCLASS] = {0, 0, 0, 0};
+  int class_bs[HB_NCLASS] = {0, 0, 0, 0};
+  double class_us[HB_NCLASS][HB_NCLASS] = {};   // [class][log2(bs / 64)], 0: not timed
+  int tuned = 0;
   long long total_n = 0, total_m = 0;
   int rank_max = 0;       // 10 or 16: the kernel instantiation used
   double last_kernel_s = 0.0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ~hprqp_batch() {
     void* ps[] = {d_insts, d_order, d_queue, d_flags,   d_infos, trp,     tci,     tval,
-                  d_toff,  d_rep,   ft,      d_ftoff,   d_ftrep, hbuf,    hbuf_small, d_qwx, d_t0};
+                  d_toff,  d_rep,   ft,      d_ftoff,   d_ftrep, d_qwx,   d_t0};
     for (void* p : ps)
       if (p) hipFree(p);
+    for (auto& k : kern) {
+      if (k.hbuf) hipFree(k.hbuf);
+      if (k.ev_join) hipEventDestroy(k.ev_join);
+      if (k.st) hipStreamDestroy(k.st);
+    }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     if (ev_fork) hipEventDestroy(ev_fork);
-    if (ev_join) hipEventDestroy(ev_join);
-    if (st2) hipStreamDestroy(st2);
     if (own_st) hipStreamDestroy(own_st);
   }
 };
@@ -1038,6 +1059,134 @@ void bcheck(hipError_t e, const char* what) {
   }
 }
 #define HBC(x) bcheck((x), #x)
+
+// Launch of the persistent solve kernel with bs threads per workgroup.
+void batch_launch(int bs, int rank, hipStream_t s, int grid, const BInst* insts, const int* order, int cnt, int* queue,
+                  const BOpts& o, const double* y0, const double* w0, const double* x0, double* y, double* z,
+                  double* w, double* x, BInfo* infos, double* hbuf) {
+#define HB_LAUNCH(RM, BS)                                                                                        \
+  k_batch_solve<RM, BS><<<grid, BS, 0, s>>>(insts, order, cnt, queue, o, y0, w0, x0, y, z, w, x, infos, hbuf)
+  if (rank == 10) {
+    switch (bs) {
+      case 64: HB_LAUNCH(10, 64); break;
+      case 128: HB_LAUNCH(10, 128); break;
+      case 256: HB_LAUNCH(10, 256); break;
+      default: HB_LAUNCH(10, 512); break;
+    }
+  } else {
+    switch (bs) {
+      case 64: HB_LAUNCH(16, 64); break;
+      case 128: HB_LAUNCH(16, 128); break;
+      case 256: HB_LAUNCH(16, 256); break;
+      default: HB_LAUNCH(16, 512); break;
+    }
+  }
+#undef HB_LAUNCH
+  HBC(hipGetLastError());
+}
+
+// Workgroups of the solve kernel with bs threads resident on the device at once.
+int batch_resident(int bs, int rank, int ncu) {
+  const void* k = nullptr;
+  if (rank == 10)
+    k = bs == 64 ? (const void*)k_batch_solve<10, 64> : bs == 128 ? (const void*)k_batch_solve<10, 128>
+        : bs == 256 ? (const void*)k_batch_solve<10, 256> : (const void*)k_batch_solve<10, 512>;
+  else
+    k = bs == 64 ? (const void*)k_batch_solve<16, 64> : bs == 128 ? (const void*)k_batch_solve<16, 128>
+        : bs == 256 ? (const void*)k_batch_solve<16, 256> : (const void*)k_batch_solve<16, 512>;
+  int per_cu = 0;
+  HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, bs, 0));
+  return ncu * std::max(per_cu, 1);
+}
+
+// The batched solver's shape autotuner.  For every size class with at least
+// 8 instances, each block size that can hold the class (n <= 4 bs) is timed
+// on a sample of the class's instances -- evenly spaced over the class, at
+// most eight per compute unit, enough to fill the device -- running
+// exactly 100 iterations per instance (tolerance 0, lambda's fixed at 1, so
+// no power method) into scratch outputs; the default block size is kept
+// unless another is at least 5% faster (near ties would otherwise flip
+// between runs).  Only the speed is measured: the shapes do not change
+// what is computed beyond the order of the block reductions.
+void autotune_batch(hprqp_batch* b, const std::vector<BInst>& hi, const std::vector<int> (&cls)[HB_NCLASS], int ncu) {
+  BOpts o = b->o;
+  o.tol = 0.0; o.max_iter = 100; o.check_every = 100; o.lamA = 1.0; o.lamQ = 1.0; o.sigma0 = 1.0;
+  o.time_ticks = 0;
+  const long long tn = std::max(1ll, b->total_n), tm = std::max(1ll, b->total_m);
+  double *sy = nullptr, *sz = nullptr, *sw = nullptr, *sx = nullptr, *hb = nullptr;
+  int *sorder = nullptr, *squeue = nullptr;
+  BInfo* sinfo = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  const auto cleanup = [&] {
+    for (void* p : {(void*)sy, (void*)sz, (void*)sw, (void*)sx, (void*)hb, (void*)sorder, (void*)squeue, (void*)sinfo})
+      if (p) hipFree(p);
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+  };
+  try {
+    HBC(hipMalloc(&sy, tm * sizeof(double)));
+    HBC(hipMalloc(&sz, tn * sizeof(double)));
+    HBC(hipMalloc(&sw, tn * sizeof(double)));
+    HBC(hipMalloc(&sx, tn * sizeof(double)));
+    HBC(hipMalloc(&sinfo, b->count * sizeof(BInfo)));
+    HBC(hipMalloc(&squeue, sizeof(int)));
+    HBC(hipMalloc(&sorder, b->count * sizeof(int)));
+    HBC(hipEventCreate(&t0));
+    HBC(hipEventCreate(&t1));
+    size_t hb_cap = 0;
+    for (int c = 0; c < HB_NCLASS; ++c) {
+      const int cnt = (int)cls[c].size();
+      if (cnt < 8) continue;
+      const int want = std::min(cnt, 8 * ncu);
+      std::vector<int> sample;
+      for (int q = 0; q < want; ++q) sample.push_back(cls[c][(size_t)q * cnt / want]);
+      HBC(hipMemcpyAsync(sorder, sample.data(), sample.size() * sizeof(int), hipMemcpyHostToDevice, b->st));
+      double best = 0.0;
+      int best_bs = b->class_bs[c];
+      for (int lb = 0; lb < HB_NCLASS; ++lb) {
+        const int bs = 64 << lb;
+        if (HB_EPT * bs < (256 << c)) continue;    // cannot hold the class
+        const int grid = std::max(1, std::min(want, batch_resident(bs, b->rank_max, ncu)));
+        const size_t need = (size_t)grid * 5 * HB_EPT * bs;
+        if (need > hb_cap) {
+          if (hb) HBC(hipFree(hb));
+          hb = nullptr;
+          HBC(hipMalloc(&hb, need * sizeof(double)));
+          hb_cap = need;
+        }
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {   // the first launch loads the code
+          k_zero_ints<<<1, 64, 0, b->st>>>(squeue, 1);
+          HBC(hipEventRecord(t0, b->st));
+          batch_launch(bs, b->rank_max, b->st, grid, b->d_insts, sorder, (int)sample.size(), squeue, o, nullptr,
+                       nullptr, nullptr, sy, sz, sw, sx, sinfo, hb);
+          HBC(hipEventRecord(t1, b->st));
+          HBC(hipEventSynchronize(t1));
+          HBC(hipEventElapsedTime(&ms, t0, t1));
+        }
+        const double us = 1e3 * ms / (100.0 * sample.size());   // per instance-iteration
+        b->class_us[c][lb] = us;
+        if (bs == b->class_bs[c]) best = best > 0.0 ? std::min(best, us) : us;
+      }
+      // the fastest, unless within 5% of the default
+      double dflt = 0.0;
+      for (int lb = 0; lb < HB_NCLASS; ++lb)
+        if ((64 << lb) == b->class_bs[c]) dflt = b->class_us[c][lb];
+      double bu = dflt;
+      for (int lb = 0; lb < HB_NCLASS; ++lb) {
+        const double us = b->class_us[c][lb];
+        if (us > 0.0 && us < 0.95 * dflt && us < bu) { bu = us; best_bs = 64 << lb; }
+      }
+      b->class_bs[c] = best_bs;
+      (void)best;
+    }
+    b->tuned = 1;
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+}
 
 void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_options* opt, hipStream_t st,
                        hprqp_batch** out) {
@@ -1163,42 +1312,59 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return hi[a].n > hi[c].n; });
     HBC(hipMalloc(&b->d_order, count * sizeof(int)));
-    HBC(hipMemcpyAsync(b->d_order, order.data(), count * sizeof(int), hipMemcpyHostToDevice, st));
-    HBC(hipMalloc(&b->d_queue, 2 * sizeof(int)));
+    HBC(hipMalloc(&b->d_queue, HB_NCLASS * sizeof(int)));
     HBC(hipMalloc(&b->d_infos, count * sizeof(BInfo)));
-    b->nbig = 0;
-    while (b->nbig < count && hi[order[b->nbig]].n > HB_NMAX_SMALL) ++b->nbig;
-    b->nsmall = count - b->nbig;
-    int dev = 0, ncu = 0;
-    HBC(hipGetDevice(&dev));
-    HBC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const auto resident = [&](const void* kern, int bs) {
-      int per_cu = 0;
-      HBC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, bs, 0));
-      return ncu * std::max(per_cu, 1);
-    };
-    if (b->nbig > 0) {
-      const int r = b->rank_max == 10 ? resident((const void*)k_batch_solve<10, HB_BS>, HB_BS)
-                                      : resident((const void*)k_batch_solve<16, HB_BS>, HB_BS);
-      b->grid_big = std::max(1, std::min(b->nbig, r));
-      HBC(hipMalloc(&b->hbuf, (size_t)b->grid_big * 5 * HB_NMAX * sizeof(double)));
-    }
-    if (b->nsmall > 0) {
-      const int r = b->rank_max == 10 ? resident((const void*)k_batch_solve<10, HB_BS / 2>, HB_BS / 2)
-                                      : resident((const void*)k_batch_solve<16, HB_BS / 2>, HB_BS / 2);
-      b->grid_small = std::max(1, std::min(b->nsmall, r));
-      HBC(hipMalloc(&b->hbuf_small, (size_t)b->grid_small * 5 * HB_NMAX_SMALL * sizeof(double)));
-    }
-    if (b->nbig > 0 && b->nsmall > 0) {
-      HBC(hipStreamCreateWithFlags(&b->st2, hipStreamNonBlocking));
-      HBC(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-      HBC(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
-    }
     HBC(hipEventCreate(&b->e0));
     HBC(hipEventCreate(&b->e1));
     HBC(hipMalloc(&b->d_qwx, count * sizeof(double)));
     HBC(hipMalloc(&b->d_t0, sizeof(long long)));
     b->o.t0 = b->d_t0;
+    int dev = 0, ncu = 0;
+    HBC(hipGetDevice(&dev));
+    HBC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    // size classes: class c holds the instances with 256 << (c - 1) < n <= 256 << c
+    std::vector<int> cls_order[HB_NCLASS];
+    for (int i : order) {
+      int c = 0;
+      while (hi[i].n > (256 << c)) ++c;
+      cls_order[c].push_back(i);
+    }
+    for (int c = 0; c < HB_NCLASS; ++c) {
+      b->class_cnt[c] = (int)cls_order[c].size();
+      b->class_bs[c] = c == HB_NCLASS - 1 ? 512 : 256;     // default shapes
+    }
+    const int bt = opt->batch_threads;
+    if (bt != 0 && bt != 64 && bt != 128 && bt != 256 && bt != 512)
+      bfail(HPRQP_ERR_ARG, "batch_threads must be 0, 64, 128, 256 or 512");
+    if (bt != 0) {
+      for (int c = 0; c < HB_NCLASS; ++c)
+        if (HB_EPT * bt >= (256 << c)) b->class_bs[c] = bt;
+    } else if (opt->spmv_autotune == 1) {
+      autotune_batch(b, hi, cls_order, ncu);
+    }
+    // one kernel per block size in use, its instances largest first
+    std::vector<int> korder;
+    b->nkern = 0;
+    for (int bs = 512; bs >= 64; bs /= 2) {
+      std::vector<int> mine;
+      for (int c = HB_NCLASS - 1; c >= 0; --c)
+        if (b->class_bs[c] == bs) mine.insert(mine.end(), cls_order[c].begin(), cls_order[c].end());
+      if (mine.empty()) continue;
+      hprqp_batch::Kern& K = b->kern[b->nkern];
+      K.bs = bs;
+      K.first = (int)korder.size();
+      K.cnt = (int)mine.size();
+      K.grid = std::max(1, std::min(K.cnt, batch_resident(bs, b->rank_max, ncu)));
+      HBC(hipMalloc(&K.hbuf, (size_t)K.grid * 5 * HB_EPT * bs * sizeof(double)));
+      if (b->nkern > 0) {
+        HBC(hipStreamCreateWithFlags(&K.st, hipStreamNonBlocking));
+        HBC(hipEventCreateWithFlags(&K.ev_join, hipEventDisableTiming));
+      }
+      korder.insert(korder.end(), mine.begin(), mine.end());
+      ++b->nkern;
+    }
+    if (b->nkern > 1) HBC(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    HBC(hipMemcpyAsync(b->d_order, korder.data(), count * sizeof(int), hipMemcpyHostToDevice, st));
     HBC(hipStreamSynchronize(st));
     *out = b;
   } catch (...) {
@@ -1211,35 +1377,20 @@ void solve_batch_impl(hprqp_batch* b, const double* y0, const double* w0, const 
                       double* w, double* x, hprqp_info* infos) {
   if (!b || !z || !w || !x || (b->total_m > 0 && !y)) bfail(HPRQP_ERR_ARG, "NULL argument");
   if (b->own_st) HBC(hipDeviceSynchronize());
-  k_zero_ints<<<1, 64, 0, b->st>>>(b->d_queue, 2);
+  k_zero_ints<<<1, 64, 0, b->st>>>(b->d_queue, HB_NCLASS);
   HBC(hipEventRecord(b->e0, b->st));
   k_stamp<<<1, 64, 0, b->st>>>(b->d_t0);
-  // one launch per class; the 256-thread kernel on the second stream when both run
-  const auto launch = [&](auto bs_tag, hipStream_t s, int grid, int first, int cnt, int* queue, double* hbuf) {
-    constexpr int BS = decltype(bs_tag)::value;
-    if (b->rank_max == 10)
-      k_batch_solve<10, BS><<<grid, BS, 0, s>>>(b->d_insts, b->d_order + first, cnt, queue, b->o, y0, w0, x0, y, z, w,
-                                                x, b->d_infos, hbuf);
-    else
-      k_batch_solve<16, BS><<<grid, BS, 0, s>>>(b->d_insts, b->d_order + first, cnt, queue, b->o, y0, w0, x0, y, z, w,
-                                                x, b->d_infos, hbuf);
-    HBC(hipGetLastError());
-  };
-  hipStream_t s_small = b->st;
-  if (b->st2) {
-    HBC(hipEventRecord(b->ev_fork, b->st));
-    HBC(hipStreamWaitEvent(b->st2, b->ev_fork, 0));
-    s_small = b->st2;
+  // one launch per block size in use, kernels 1.. on their own streams
+  if (b->nkern > 1) HBC(hipEventRecord(b->ev_fork, b->st));
+  for (int k = 0; k < b->nkern; ++k) {
+    const hprqp_batch::Kern& K = b->kern[k];
+    hipStream_t s = k == 0 ? b->st : K.st;
+    if (k > 0) HBC(hipStreamWaitEvent(s, b->ev_fork, 0));
+    batch_launch(K.bs, b->rank_max, s, K.grid, b->d_insts, b->d_order + K.first, K.cnt, b->d_queue + k, b->o, y0, w0,
+                 x0, y, z, w, x, b->d_infos, K.hbuf);
+    if (k > 0) HBC(hipEventRecord(K.ev_join, s));
   }
-  if (b->nbig > 0)
-    launch(std::integral_constant<int, HB_BS>{}, b->st, b->grid_big, 0, b->nbig, b->d_queue, b->hbuf);
-  if (b->nsmall > 0)
-    launch(std::integral_constant<int, HB_BS / 2>{}, s_small, b->grid_small, b->nbig, b->nsmall, b->d_queue + 1,
-           b->hbuf_small);
-  if (b->st2) {
-    HBC(hipEventRecord(b->ev_join, b->st2));
-    HBC(hipStreamWaitEvent(b->st, b->ev_join, 0));
-  }
+  for (int k = 1; k < b->nkern; ++k) HBC(hipStreamWaitEvent(b->st, b->kern[k].ev_join, 0));
   HBC(hipEventRecord(b->e1, b->st));
   k_batch_qwx<<<std::min(b->count, 4096), HB_QWX_BS, 0, b->st>>>(b->d_insts, b->count, w, x, b->d_qwx);
   HBC(hipGetLastError());
@@ -1287,6 +1438,18 @@ hprqp_status hprqp_batch_create(int32_t count, const hprqp_problem* probs, const
 hprqp_status hprqp_solve_batch(hprqp_batch* b, const double* y0, const double* w0, const double* x0, double* y,
                                double* z, double* w, double* x, hprqp_info* infos_host) {
   HB_GUARD(solve_batch_impl(b, y0, w0, x0, y, z, w, x, infos_host));
+}
+
+
+hprqp_status hprqp_batch_shapes(hprqp_batch* b, int32_t* class_count_host, int32_t* class_threads_host,
+                                double* class_us_host) {
+  HB_GUARD(if (!b) bfail(HPRQP_ERR_ARG, "NULL batch");
+           for (int c = 0; c < HB_NCLASS; ++c) {
+             if (class_count_host) class_count_host[c] = b->class_cnt[c];
+             if (class_threads_host) class_threads_host[c] = b->class_bs[c];
+             for (int lb = 0; lb < HB_NCLASS; ++lb)
+               if (class_us_host) class_us_host[c * HB_NCLASS + lb] = b->class_us[c][lb];
+           });
 }
 
 double hprqp_batch_last_kernel_s(hprqp_batch* b) { return b ? b->last_kernel_s : 0.0; }

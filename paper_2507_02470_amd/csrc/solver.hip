@@ -1994,6 +1994,7 @@ void hprqp_default_options(hprqp_options* o) {
   o->method = 0;
   o->kron_kernel = -1;
   o->small_path = -1;
+  o->batch_threads = 0;
 }
 
 hprqp_status hprqp_create(const hprqp_problem* prob, const hprqp_options* opt, hipStream_t stream,

@@ -42,11 +42,20 @@ def _insts(seed0=20_000):
     return [qpgen.make_portfolio(seed0 + i, n=n) for i, n in enumerate(SIZES)]
 
 
-def test_batch_iterates_match_oracle_after_50():
+@pytest.mark.parametrize("threads", [0, 64, 128, 256, 512])
+def test_batch_iterates_match_oracle_after_50(threads):
+    """Every size class (n <= 256, 512, 1024, 2048, each with sizes at its
+    edges) on every block size that can hold it: batch_threads forces one
+    block size on the classes it fits, the others keep the default."""
     BS = _B()
     qps = _insts()
-    print("batch sizes:", [q.n for q in qps], flush=True)
-    b = BS(qps, tol=0.0, max_iter=50, check_every=10)
+    print("batch sizes:", [q.n for q in qps], "threads", threads, flush=True)
+    b = BS(qps, tol=0.0, max_iter=50, check_every=10, batch_threads=threads)
+    sh = b.shapes()
+    print("shapes:", sh, flush=True)
+    want = [threads if threads and 4 * threads >= cmax else (512 if cmax == 2048 else 256)
+            for cmax in sh["class_max_n"]]
+    assert sh["threads"] == want
     r = b.solve()
     b.close()
     for i, q in enumerate(qps):
@@ -98,6 +107,31 @@ def test_batch_ranks_and_instances_without_rows(ranks):
         for name, g, ref in pairs:
             e = _rel(g, ref)
             assert e <= 1e-10, (i, q.n, q.m, name, e)
+
+
+def test_batch_autotuned_shapes():
+    """The shape autotuner: every class with 8 or more instances has every
+    fitting block size timed, the chosen one is among them (or the default),
+    and the solve with the tuned shapes matches the oracle."""
+    BS = _B()
+    sizes = [60 + 7 * i for i in range(12)] + [300 + 15 * i for i in range(10)] + \
+            [600 + 37 * i for i in range(10)] + [1100 + 80 * i for i in range(9)]
+    qps = [qpgen.make_portfolio(45_000 + i, n=n) for i, n in enumerate(sizes)]
+    b = BS(qps, tol=1e-8, max_iter=100_000, spmv_autotune=1)
+    sh = b.shapes()
+    print("tuned shapes:", sh, flush=True)
+    assert sh["instances"] == [12, 10, 10, 9]
+    for c, cmax in enumerate(sh["class_max_n"]):
+        fit = [t for t in (64, 128, 256, 512) if 4 * t >= cmax]
+        assert sorted(t for (cm, t) in sh["timed_us"] if cm == cmax) == fit
+        assert sh["threads"][c] in fit
+    r = b.solve()
+    b.close()
+    for i, q in enumerate(qps[::5]):
+        f = r.infos[5 * i]
+        o = oracle.solve(q, tol=1e-8, max_iter=100_000)
+        assert f["term"] == "solved" and o.term == "solved"
+        assert abs(f["pobj"] - o.pobj) <= 1e-6 * max(1.0, abs(o.pobj))
 
 
 def test_batch_full_solves_match_oracle():

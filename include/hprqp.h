@@ -293,7 +293,8 @@ void hprqp_destroy(hprqp_handle *h);
  * instance when lambda_A/lambda_Q <= 0, from an all-ones start); time_limit_s
  * counts from the start of hprqp_solve_batch, and an instance still running
  * then stops at its next check with HPRQP_TIME_LIMIT (0: no limit).
- * Instances are scheduled largest first. */
+ * Instances are scheduled largest first (hprqp_batch_set_priority sets
+ * another order). */
 hprqp_status hprqp_batch_create(int32_t count, const hprqp_problem *probs,
                                 const hprqp_options *opt, hipStream_t stream, hprqp_batch **out);
 
@@ -322,6 +323,16 @@ hprqp_status hprqp_batch_shapes(hprqp_batch *b, int32_t *class_count_host, int32
 
 /* Elapsed time of the last hprqp_solve_batch kernels (HIP events on `stream`
  * around them), seconds. */
+/* Queue order of the next hprqp_solve_batch calls.  A persistent kernel
+ * takes its instances from a queue; the batch ends when the last instance
+ * ends, so a long solve taken late sets the time of the whole batch.  With
+ * priority (device array of `count` floats, a predicted length of each
+ * solve, e.g. the score of hprqp_mlp_warm_start) each kernel takes its
+ * instances highest priority first (ties, and non-finite priorities last, in
+ * the default order); NULL restores the default (largest n first).  Results
+ * do not depend on the order, only the time does. */
+hprqp_status hprqp_batch_set_priority(hprqp_batch *b, const float *priority);
+
 double hprqp_batch_last_kernel_s(hprqp_batch *b);
 
 void hprqp_batch_destroy(hprqp_batch *b);

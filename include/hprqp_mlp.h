@@ -56,15 +56,40 @@ hprqp_status hprqp_mlp_loss_grad(hprqp_mlp *net, int32_t batch, const float *X, 
 hprqp_status hprqp_mlp_set_scaling(hprqp_mlp *net, const float *in_mean, const float *in_std,
                                    const float *out_mean, const float *out_std);
 
+/* Standardization from training data: the column means and standard
+ * deviations (divisor rows - 1) of X (rows x n_in) and T (rows x n_out,
+ * device, FP32), accumulated in FP64 on the device in a fixed order, set as by
+ * hprqp_mlp_set_scaling.  stats_host (may be NULL) receives them as
+ * [in_mean, in_std, out_mean, out_std] (2 n_in + 2 n_out floats). */
+hprqp_status hprqp_mlp_fit_scaling(hprqp_mlp *net, int64_t rows, const float *X, const float *T,
+                                   float *stats_host);
+
+/* Network input of `batch` family members: X[s] = [c_s (n); u_s (m)] as FP32
+ * (c: batch x n, u: batch x m, FP64, concatenated by member; X: batch x (n+m)). */
+hprqp_status hprqp_family_features(int32_t batch, int32_t n, int32_t m, const double *c, const double *u,
+                                   float *X, hipStream_t stream);
+
+/* Training targets: T[s] = [y_s (m); z_s (n); w_s (n)] as FP32 from the FP64
+ * solutions (concatenated by member), T: batch x (m + 2n).  With iters (device,
+ * batch entries, the iteration count of the solve that produced each
+ * solution; may be NULL) T has one more column, log(max(iters_s, 1)): the
+ * network then also learns the length of a member's solve. */
+hprqp_status hprqp_family_targets(int32_t batch, int32_t n, int32_t m, const double *y, const double *z,
+                                  const double *w, const int64_t *iters, float *T, hipStream_t stream);
+
 /* Warm start of HPR-QP for `batch` family members from their parameter
- * vectors X: with the prediction (y, z, w) = forward(X) (n_out = m + 2n),
- * writes the FP64 starting point y0 = y (batch x m), w0 = w and
- * x0 = Pi_C(w) = clamp(w, L, U) (batch x n each; the z part is not used by
- * Algorithm 4).  bad[s] = 1 flags a sample whose prediction is not finite:
- * the caller starts it cold instead. */
+ * vectors X: with the prediction (y, z, w) = forward(X) (n_out = m + 2n, or
+ * m + 2n + 1 with a last column that predicts the log iteration count of the
+ * member's solve), writes the FP64 starting point y0 = y (batch x m), w0 = w
+ * and x0 = Pi_C(w) = clamp(w, L, U) (batch x n each; the z part is not used
+ * by Algorithm 4).  bad[s] = 1 flags a sample whose predicted y or w is not
+ * finite: its start is written as the origin (the cold start).  score (device,
+ * batch floats, may be NULL; needs n_out = m + 2n + 1) receives the predicted
+ * log iteration count, the priority hprqp_batch_set_priority takes to start
+ * the longest solves first. */
 hprqp_status hprqp_mlp_warm_start(hprqp_mlp *net, int32_t batch, const float *X, int32_t n, int32_t m,
                                   const double *L, const double *U, double *y0, double *w0, double *x0,
-                                  int32_t *bad);
+                                  int32_t *bad, float *score);
 
 /* One Adam step (bias-corrected) on the FP32 master parameters with the
  * last gradient; refreshes the BF16 weight copies. */
@@ -78,6 +103,17 @@ hprqp_status hprqp_mlp_set_params(hprqp_mlp *net, const float *params_host);
 hprqp_status hprqp_mlp_gemm_stats(hprqp_mlp *net, double *ms_host, double *flop_host);
 
 void hprqp_mlp_destroy(hprqp_mlp *net);
+
+/* A stage tensor of the last forward / loss_grad call (exposed for tests, so
+ * that every stage can be checked with its own inputs), written to out
+ * (rows x cols FP32, device; may be NULL to query the shape): which = 0 the
+ * standardized input (BF16), 1 Z1 = W1 x + b1, 2 A1 = GELU(Z1) (BF16), 3 Z2,
+ * 4 A2 (BF16), 5 the standardized output, 6 dY = d loss / d output (FP32),
+ * 7 its BF16 copy, 8 dA2, 9 dZ2 = dA2 * GELU'(Z2), 10 its BF16 copy, 11 dA1,
+ * 12 dZ1, 13 its BF16 copy, 14 the standardized targets.  BF16 values are
+ * widened exactly.  rows_host / cols_host (may be NULL) receive the shape. */
+hprqp_status hprqp_mlp_intermediate(hprqp_mlp *net, int32_t which, float *out, int32_t *rows_host,
+                                    int32_t *cols_host);
 
 /* Plain BF16 GEMM with FP32 accumulation on the matrix cores (exposed for
  * tests): C[i*ldc + j] (+)= sum_k A[i*a_rs + k*a_cs] * B[k*b_rs + j*b_cs],

@@ -55,7 +55,7 @@ class hprqp_info(C.Structure):
 EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_residuals_noalloc",
            "hprqp_apply",
            "hprqp_power_info", "hprqp_scaling", "hprqp_kernel_stats", "hprqp_set_options", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
-           "hprqp_batch_last_kernel_s", "hprqp_batch_shapes", "hprqp_batch_destroy", "hprqp_last_error")
+           "hprqp_batch_last_kernel_s", "hprqp_batch_shapes", "hprqp_batch_set_priority", "hprqp_batch_destroy", "hprqp_last_error")
 
 _lib = None
 
@@ -94,6 +94,8 @@ def load():
         lib.hprqp_batch_last_kernel_s.restype = C.c_double
         lib.hprqp_batch_shapes.argtypes = [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         lib.hprqp_batch_shapes.restype = C.c_int
+        lib.hprqp_batch_set_priority.argtypes = [_vp, _vp]
+        lib.hprqp_batch_set_priority.restype = C.c_int
         lib.hprqp_batch_destroy.argtypes = [_vp]
         lib.hprqp_batch_destroy.restype = None
     for name in ("hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_residuals_noalloc", "hprqp_apply",

@@ -132,10 +132,14 @@ class BatchSolver:
         n + m) float32 device tensor, from the copies already on the device."""
         if self.shared is None:
             raise ValueError("shared_features needs a batch built with `shared`")
+        from .surrogate import _load
         n, m = self.shared.n, self.shared.m
-        c = self.t["c"].view(self.count, n)
-        parts = [c, self.t["u"][:self.count * m].view(self.count, m)] if m else [c]
-        return torch.cat(parts, dim=1).to(torch.float32)
+        X = torch.empty((self.count, n + m), dtype=torch.float32, device=self.device)
+        lib = _load()
+        N.check(lib.hprqp_family_features(self.count, n, m, C.c_void_p(self.t["c"].data_ptr()),
+                                          C.c_void_p(self.t["u"].data_ptr()) if m else None,
+                                          C.c_void_p(X.data_ptr()), C.c_void_p(self.stream.cuda_stream)))
+        return X
 
     def shapes(self) -> dict:
         """Size classes (n <= 256, 512, 1024, 2048) of the batch: instances,
@@ -145,6 +149,18 @@ class BatchSolver:
         N.check(self.lib.hprqp_batch_shapes(self.h, cnt, thr, us))
         return dict(class_max_n=[256, 512, 1024, 2048], instances=list(cnt), threads=list(thr),
                     timed_us={(256 << c, 64 << j): us[4 * c + j] for c in range(4) for j in range(4) if us[4 * c + j] > 0})
+
+    def set_priority(self, priority=None):
+        """Queue order of the next solves: highest priority first (a device
+        float32 tensor of `count` predicted solve lengths); None restores the
+        default order.  Changes the time of a solve, not its results."""
+        if priority is None:
+            N.check(self.lib.hprqp_batch_set_priority(self.h, None))
+            return
+        p = torch.as_tensor(priority, dtype=torch.float32, device=self.device).contiguous()
+        if p.numel() != self.count:
+            raise ValueError(f"priority needs {self.count} entries, got {p.numel()}")
+        N.check(self.lib.hprqp_batch_set_priority(self.h, C.c_void_p(p.data_ptr())))
 
     def close(self):
         if getattr(self, "h", None):

@@ -1018,6 +1018,7 @@ struct hprqp_batch {
     hipEvent_t ev_join = nullptr;
   } kern[HB_NCLASS];
   int nkern = 0;
+  std::vector<int> order_default;   // d_order as built at create
   hipEvent_t ev_fork = nullptr;
   // size classes n <= 256 << c: instances, block size, and (autotuned) the
   // mean kernel time per instance-iteration of each candidate block size
@@ -1364,6 +1365,7 @@ void batch_create_impl(int count, const hprqp_problem* probs, const hprqp_option
       ++b->nkern;
     }
     if (b->nkern > 1) HBC(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    b->order_default = korder;
     HBC(hipMemcpyAsync(b->d_order, korder.data(), count * sizeof(int), hipMemcpyHostToDevice, st));
     HBC(hipStreamSynchronize(st));
     *out = b;
@@ -1450,6 +1452,25 @@ hprqp_status hprqp_batch_shapes(hprqp_batch* b, int32_t* class_count_host, int32
              for (int lb = 0; lb < HB_NCLASS; ++lb)
                if (class_us_host) class_us_host[c * HB_NCLASS + lb] = b->class_us[c][lb];
            });
+}
+
+hprqp_status hprqp_batch_set_priority(hprqp_batch* b, const float* priority) {
+  HB_GUARD(if (!b) bfail(HPRQP_ERR_ARG, "NULL batch");
+           std::vector<int> ord = b->order_default;
+           if (priority) {
+             std::vector<float> pr(b->count);
+             HBC(hipMemcpyAsync(pr.data(), priority, b->count * sizeof(float), hipMemcpyDeviceToHost, b->st));
+             HBC(hipStreamSynchronize(b->st));
+             for (float& v : pr)
+               if (!std::isfinite(v)) v = -INFINITY;     // no usable prediction: last
+             // each kernel's queue: highest priority first, ties in the default order
+             for (int k = 0; k < b->nkern; ++k) {
+               auto first = ord.begin() + b->kern[k].first;
+               std::stable_sort(first, first + b->kern[k].cnt, [&](int a, int c) { return pr[a] > pr[c]; });
+             }
+           }
+           HBC(hipMemcpyAsync(b->d_order, ord.data(), b->count * sizeof(int), hipMemcpyHostToDevice, b->st));
+           HBC(hipStreamSynchronize(b->st)));
 }
 
 double hprqp_batch_last_kernel_s(hprqp_batch* b) { return b ? b->last_kernel_s : 0.0; }

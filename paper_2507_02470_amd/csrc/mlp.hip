@@ -129,35 +129,108 @@ __global__ void k_destandardize(int rows, int cols, const float* __restrict__ Y,
     out[t] = mean[c] + sd[c] * Y[(long long)r * ld + c];
   }
 }
-// prediction [y (m); z (n); w (n)] per sample -> FP64 warm start of HPR-QP:
-// y0 = y, w0 = w, x0 = Pi_C(w) (z is not read by the iteration).  bad[s] = 1
-// if a predicted value is not finite (the caller then starts that sample cold).
-__global__ void k_warm_start(int batch, int n, int m, const float* __restrict__ P, const double* __restrict__ L,
+// prediction [y (m); z (n); w (n) (; ell)] per sample (row length no) -> FP64
+// warm start of HPR-QP: y0 = y, w0 = w, x0 = Pi_C(w) (z is not read by the
+// iteration).  bad[s] = 1 if a predicted value of y or w is not finite: that
+// sample's start is then the origin (y0 = w0 = x0 = 0, the cold start of
+// Algorithm 4).  score (if given): the predicted length ell of each solve.
+__global__ void k_warm_start(int batch, int n, int m, int no, const float* __restrict__ P, const double* __restrict__ L,
                              const double* __restrict__ U, double* __restrict__ y0, double* __restrict__ w0,
-                             double* __restrict__ x0, int* __restrict__ bad) {
+                             double* __restrict__ x0, int* __restrict__ bad, float* __restrict__ score) {
   const int s = blockIdx.x;
   if (s >= batch) return;
-  const float* p = P + (long long)s * (m + 2 * n);
+  const float* p = P + (long long)s * no;
   int nf = 0;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    const double v = p[i];
-    if (!isfinite(v)) nf = 1;
-    y0[(long long)s * m + i] = isfinite(v) ? v : 0.0;
-  }
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const double v = p[m + n + j];
-    if (!isfinite(v)) nf = 1;
-    const double wv = isfinite(v) ? v : 0.0;
-    w0[(long long)s * n + j] = wv;
-    x0[(long long)s * n + j] = fmin(fmax(wv, L[j]), U[j]);
-  }
+  for (int i = threadIdx.x; i < m; i += blockDim.x) nf |= !isfinite(p[i]);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) nf |= !isfinite(p[m + n + j]);
   __shared__ int sbad;
   if (threadIdx.x == 0) sbad = 0;
   __syncthreads();
   if (nf) atomicOr(&sbad, 1);
   __syncthreads();
-  if (threadIdx.x == 0) bad[s] = sbad;
+  const bool cold = sbad != 0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) y0[(long long)s * m + i] = cold ? 0.0 : (double)p[i];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double wv = cold ? 0.0 : (double)p[m + n + j];
+    w0[(long long)s * n + j] = wv;
+    x0[(long long)s * n + j] = cold ? 0.0 : fmin(fmax(wv, L[j]), U[j]);
+  }
+  if (threadIdx.x == 0) {
+    bad[s] = cold ? 1 : 0;
+    if (score) score[s] = p[m + 2 * n];
+  }
 }
+
+// out (rows x cols, FP32) <- a stage tensor with leading dimension ld, FP32
+// or BF16 bits (exact widening)
+__global__ void k_export(int rows, int cols, long long ld, const float* __restrict__ f32,
+                         const uint16_t* __restrict__ b16, float* __restrict__ out) {
+  const long long total = (long long)rows * cols;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
+    const long long r = t / cols, c = t % cols;
+    out[t] = f32 ? f32[r * ld + c] : __uint_as_float((unsigned)b16[r * ld + c] << 16);
+  }
+}
+
+// Column statistics of a (rows x cols) FP32 matrix for the standardization:
+// per column, the sum (pass 0) or the sum of squared deviations from `mean`
+// (pass 1) over a chunk of rows into part[chunk][col], FP64, rows in order.
+#define HM_STAT_ROWS 1024
+__global__ void k_col_stats(long long rows, int cols, const float* __restrict__ X, const double* __restrict__ mean,
+                            double* __restrict__ part) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  const long long r0 = (long long)blockIdx.y * HM_STAT_ROWS, r1 = min(rows, r0 + HM_STAT_ROWS);
+  double s = 0.0;
+  for (long long r = r0; r < r1; ++r) {
+    const double v = X[r * cols + j];
+    s += mean ? (v - mean[j]) * (v - mean[j]) : v;
+  }
+  part[(long long)blockIdx.y * cols + j] = s;
+}
+// out[j] = sum of the chunks' partials in chunk order, divided by `div`
+// (sqrt of it when `root`): the mean (div = rows) or the standard deviation
+// (div = rows - 1)
+__global__ void k_col_finish(int chunks, int cols, const double* __restrict__ part, double div, int root,
+                             double* __restrict__ out64, float* __restrict__ out32) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += part[(long long)c * cols + j];
+  s /= div;
+  if (root) s = sqrt(s);
+  out64[j] = s;
+  out32[j] = (float)s;
+}
+
+// Network input of family members: X[s] = [c_s (n); u_s (m)] in FP32
+__global__ void k_family_features(int batch, int n, int m, const double* __restrict__ c, const double* __restrict__ u,
+                                  float* __restrict__ X) {
+  const long long total = (long long)batch * (n + m);
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
+    const long long s = t / (n + m);
+    const int k = (int)(t % (n + m));
+    X[t] = (float)(k < n ? c[s * n + k] : u[s * m + (k - n)]);
+  }
+}
+// Training targets of family members: T[s] = [y_s (m); z_s (n); w_s (n)] in
+// FP32, and with iters given a last column log(max(iters_s, 1)) (the length of
+// the solve that produced the member's solution)
+__global__ void k_family_targets(int batch, int n, int m, const double* __restrict__ y, const double* __restrict__ z,
+                                 const double* __restrict__ w, const long long* __restrict__ iters,
+                                 float* __restrict__ T) {
+  const int no = m + 2 * n + (iters ? 1 : 0);
+  const long long total = (long long)batch * no;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
+    const long long s = t / no;
+    const int k = (int)(t % no);
+    T[t] = k < m ? (float)y[s * m + k]
+         : k < m + n ? (float)z[s * n + (k - m)]
+         : k < m + 2 * n ? (float)w[s * n + (k - m - n)]
+         : (float)log((double)(iters[s] > 1 ? iters[s] : 1));
+  }
+}
+
 // dst (cols_p x rows_p) = transpose of src (rows x cols_p), zero rows beyond `rows`
 __global__ void k_transpose_bf16(int rows, int rows_p, int cols_p, const uint16_t* __restrict__ src,
                                  uint16_t* __restrict__ dst) {
@@ -288,6 +361,7 @@ struct hprqp_mlp {
   hipEvent_t ev[16] = {};
   int nev = 0;
   double last_flop = 0.0;
+  int last_batch = 0;   // batch of the last forward / loss_grad
   ~hprqp_mlp() {
     for (void* p : owned) hipFree(p);
     for (auto e : ev)
@@ -418,6 +492,7 @@ void mark(hprqp_mlp& n) { HMC(hipEventRecord(n.ev[n.nev++], n.st)); }
 
 void forward_impl(hprqp_mlp& n, int B, const float* X) {
   if (B <= 0 || B > n.maxb || !X) mfail(HPRQP_ERR_ARG, "batch out of range or NULL input");
+  n.last_batch = B;
   const int in = n.d[0], h1 = n.d[1], h2 = n.d[2], out = n.d[3];
   const int inp = n.dp[0], h1p = n.dp[1], h2p = n.dp[2], outp = n.dp[3];
   k_to_bf16_pad<<<eg((long long)B * inp), 256, 0, n.st>>>(B, in, inp, X, n.in_mean, n.in_istd, n.Xb);
@@ -493,6 +568,37 @@ void loss_grad_impl(hprqp_mlp& n, int B, const float* X, const float* T, const f
 
 }  // namespace
 
+// mean and standard deviation (divisor rows - 1) of every column of X
+// (rows x cols, device, FP32), FP64 on the device, into mean64/sd64 (device)
+// and the host arrays mean_h/sd_h
+void col_moments(hipStream_t st, long long rows, int cols, const float* X, float* mean_h, float* sd_h) {
+  const int chunks = (int)((rows + HM_STAT_ROWS - 1) / HM_STAT_ROWS);
+  double *part = nullptr, *mean = nullptr, *sd = nullptr;
+  float* f32 = nullptr;
+  const auto done = [&] {
+    for (void* p : {(void*)part, (void*)mean, (void*)sd, (void*)f32})
+      if (p) hipFree(p);
+  };
+  try {
+    HMC(hipMalloc(&part, (size_t)chunks * cols * sizeof(double)));
+    HMC(hipMalloc(&mean, cols * sizeof(double)));
+    HMC(hipMalloc(&sd, cols * sizeof(double)));
+    HMC(hipMalloc(&f32, cols * sizeof(float)));
+    const dim3 g((cols + 255) / 256, chunks);
+    k_col_stats<<<g, 256, 0, st>>>(rows, cols, X, nullptr, part);
+    k_col_finish<<<(cols + 255) / 256, 256, 0, st>>>(chunks, cols, part, (double)rows, 0, mean, f32);
+    HMC(hipMemcpyAsync(mean_h, f32, cols * sizeof(float), hipMemcpyDeviceToHost, st));
+    k_col_stats<<<g, 256, 0, st>>>(rows, cols, X, mean, part);
+    k_col_finish<<<(cols + 255) / 256, 256, 0, st>>>(chunks, cols, part, (double)std::max(1ll, rows - 1), 1, sd, f32);
+    HMC(hipMemcpyAsync(sd_h, f32, cols * sizeof(float), hipMemcpyDeviceToHost, st));
+    HMC(hipStreamSynchronize(st));
+  } catch (...) {
+    done();
+    throw;
+  }
+  done();
+}
+
 #define HM_GUARD(...)                 \
   try {                               \
     hq::g_err.clear();                \
@@ -538,15 +644,87 @@ hprqp_status hprqp_mlp_set_scaling(hprqp_mlp* n, const float* in_mean, const flo
 }
 
 hprqp_status hprqp_mlp_warm_start(hprqp_mlp* n, int32_t batch, const float* X, int32_t qn, int32_t qm, const double* L,
-                                  const double* U, double* y0, double* w0, double* x0, int32_t* bad) {
+                                  const double* U, double* y0, double* w0, double* x0, int32_t* bad, float* score) {
   HM_GUARD(
       if (!n || !L || !U || !w0 || !x0 || !bad || (qm > 0 && !y0)) mfail(HPRQP_ERR_ARG, "NULL argument");
-      if (qn <= 0 || qm < 0 || qm + 2 * qn != n->d[3]) mfail(HPRQP_ERR_SHAPE, "n_out must equal m + 2 n");
+      if (qn <= 0 || qm < 0 || (qm + 2 * qn != n->d[3] && qm + 2 * qn + 1 != n->d[3]))
+        mfail(HPRQP_ERR_SHAPE, "n_out must equal m + 2 n or m + 2 n + 1");
+      if (score && qm + 2 * qn + 1 != n->d[3]) mfail(HPRQP_ERR_SHAPE, "score needs n_out = m + 2 n + 1");
       forward_impl(*n, batch, X);
       k_destandardize<<<eg((long long)batch * n->d[3]), 256, 0, n->st>>>(batch, n->d[3], n->Y, n->dp[3], n->out_mean,
                                                                         n->out_sd, n->Yuser);
-      k_warm_start<<<batch, 256, 0, n->st>>>(batch, qn, qm, n->Yuser, L, U, y0, w0, x0, bad);
+      if (batch > 0)
+        k_warm_start<<<batch, 256, 0, n->st>>>(batch, qn, qm, n->d[3], n->Yuser, L, U, y0, w0, x0, bad, score);
+      HMC(hipGetLastError());
       HMC(hipStreamSynchronize(n->st)));
+}
+
+hprqp_status hprqp_mlp_fit_scaling(hprqp_mlp* n, int64_t rows, const float* X, const float* T, float* stats_host) {
+  HM_GUARD(
+      if (!n || !X || !T) mfail(HPRQP_ERR_ARG, "NULL argument");
+      if (rows < 2) mfail(HPRQP_ERR_SHAPE, "at least two samples are needed");
+      std::vector<float> xm(n->d[0]), xs(n->d[0]), tm(n->d[3]), ts(n->d[3]);
+      col_moments(n->st, rows, n->d[0], X, xm.data(), xs.data());
+      col_moments(n->st, rows, n->d[3], T, tm.data(), ts.data());
+      if (stats_host) {
+        float* o = stats_host;
+        for (int i = 0; i < n->d[0]; ++i) { o[i] = xm[i]; o[n->d[0] + i] = xs[i]; }
+        o += 2 * n->d[0];
+        for (int i = 0; i < n->d[3]; ++i) { o[i] = tm[i]; o[n->d[3] + i] = ts[i]; }
+      }
+      const hprqp_status st = hprqp_mlp_set_scaling(n, xm.data(), xs.data(), tm.data(), ts.data());
+      if (st != HPRQP_OK) mfail(st, hq::g_err));
+}
+
+hprqp_status hprqp_mlp_intermediate(hprqp_mlp* n, int32_t which, float* out, int32_t* rows_host, int32_t* cols_host) {
+  HM_GUARD(
+      if (!n) mfail(HPRQP_ERR_ARG, "NULL handle");
+      const int B = n->last_batch;
+      const int in = n->d[0], h1 = n->d[1], h2 = n->d[2], o = n->d[3];
+      const int inp = n->dp[0], h1p = n->dp[1], h2p = n->dp[2], op = n->dp[3];
+      struct Src { int cols; long long ld; const float* f; const uint16_t* b; };
+      Src s{};
+      switch (which) {
+        case 0: s = {in, inp, nullptr, n->Xb}; break;
+        case 1: s = {h1, h1p, n->Z1, nullptr}; break;
+        case 2: s = {h1, h1p, nullptr, n->A1b}; break;
+        case 3: s = {h2, h2p, n->Z2, nullptr}; break;
+        case 4: s = {h2, h2p, nullptr, n->A2b}; break;
+        case 5: s = {o, op, n->Y, nullptr}; break;
+        case 6: s = {o, op, n->dYf, nullptr}; break;
+        case 7: s = {o, op, nullptr, n->dYb}; break;
+        case 8: s = {h2, h2p, n->dA2, nullptr}; break;
+        case 9: s = {h2, h2p, n->dZ2f, nullptr}; break;
+        case 10: s = {h2, h2p, nullptr, n->dZ2b}; break;
+        case 11: s = {h1, h1p, n->dA1, nullptr}; break;
+        case 12: s = {h1, h1p, n->dZ1f, nullptr}; break;
+        case 13: s = {h1, h1p, nullptr, n->dZ1b}; break;
+        case 14: s = {o, o, n->Tstd, nullptr}; break;
+        default: mfail(HPRQP_ERR_ARG, "which must be in [0, 14]");
+      }
+      if (rows_host) *rows_host = B;
+      if (cols_host) *cols_host = s.cols;
+      if (out && B > 0) {
+        k_export<<<eg((long long)B * s.cols), 256, 0, n->st>>>(B, s.cols, s.ld, s.f, s.b, out);
+        HMC(hipGetLastError());
+      }
+      HMC(hipStreamSynchronize(n->st)));
+}
+
+hprqp_status hprqp_family_features(int32_t batch, int32_t n, int32_t m, const double* c, const double* u, float* X,
+                                   hipStream_t stream) {
+  HM_GUARD(if (batch < 0 || n <= 0 || m < 0 || !c || !X || (m > 0 && !u)) mfail(HPRQP_ERR_ARG, "bad arguments");
+           if (batch > 0) k_family_features<<<eg((long long)batch * (n + m)), 256, 0, stream>>>(batch, n, m, c, u, X);
+           HMC(hipGetLastError()); HMC(hipStreamSynchronize(stream)));
+}
+
+hprqp_status hprqp_family_targets(int32_t batch, int32_t n, int32_t m, const double* y, const double* z,
+                                  const double* w, const int64_t* iters, float* T, hipStream_t stream) {
+  HM_GUARD(if (batch < 0 || n <= 0 || m < 0 || !z || !w || !T || (m > 0 && !y)) mfail(HPRQP_ERR_ARG, "bad arguments");
+           if (batch > 0)
+             k_family_targets<<<eg((long long)batch * (m + 2 * n + 1)), 256, 0, stream>>>(
+                 batch, n, m, y, z, w, reinterpret_cast<const long long*>(iters), T);
+           HMC(hipGetLastError()); HMC(hipStreamSynchronize(stream)));
 }
 
 hprqp_status hprqp_mlp_loss_grad(hprqp_mlp* n, int32_t batch, const float* X, const float* T, const float* out_w,

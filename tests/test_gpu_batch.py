@@ -166,6 +166,31 @@ def test_batch_permutation_invariance_bitwise():
         assert r1.infos[p]["iters"] == r2.infos[j]["iters"]
 
 
+def test_batch_priority_order_changes_nothing_but_time():
+    """hprqp_batch_set_priority reorders each kernel's queue; every instance's
+    result and iteration count stay bit-identical (including non-finite
+    priorities, and after restoring the default order)."""
+    BS = _B()
+    qps = _insts(45_000)
+    b = BS(qps, tol=1e-8, max_iter=3000)
+    r1 = b.solve()
+    rng = np.random.default_rng(1)
+    pr = rng.standard_normal(len(qps)).astype(np.float32)
+    pr[::5] = np.nan; pr[1] = np.inf; pr[2] = -np.inf
+    outs = []
+    for p in (torch.as_tensor(pr, device="cuda"), None):
+        b.set_priority(p)
+        outs.append(b.solve())
+    with pytest.raises(ValueError):
+        b.set_priority(torch.zeros(len(qps) + 1, device="cuda"))
+    b.close()
+    for r2 in outs:
+        for j in range(len(qps)):
+            for a, c in ((r1.x[j], r2.x[j]), (r1.y[j], r2.y[j]), (r1.w[j], r2.w[j]), (r1.z[j], r2.z[j])):
+                assert np.array_equal(a, c)
+            assert r1.infos[j]["iters"] == r2.infos[j]["iters"]
+
+
 def test_batch_shared_structure_and_warm_start():
     BS = _B()
     base = qpgen.make_portfolio_family_base()

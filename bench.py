@@ -421,6 +421,35 @@ def extra_ablation(qp, dp, lamA, lamQ, steps, cpu, time_cap):
     return out
 
 
+def calibrate_copy(reps=5, mib=4096):
+    """The library's plain streaming copy of `mib` MiB (k_stream_copy2), after
+    a 256 MiB fill that evicts the caches before each run: the counter scale
+    (each run reads and writes mib MiB) and the HBM rate plain streaming
+    reaches (read + write bytes over the HIP-event time; 4 GiB, so that the
+    launch and the ramp are a small part of it)."""
+    import ctypes as C
+    import torch
+    from paper_2507_02470_amd import _native as N
+    lib = N.load()
+    a = torch.rand(mib << 17, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    flush = torch.empty(32 << 20, dtype=torch.float64, device="cuda")
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ms = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        t = C.c_double()
+        N.check(lib.hprqp_stream_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), a.numel(), st, C.byref(t)))
+        ms.append(t.value)
+    assert torch.equal(a, b)
+    nbytes = 2 * a.numel() * 8
+    del a, b, flush
+    return dict(kernel="k_stream_copy2", bytes_read=nbytes // 2, bytes_written=nbytes // 2, runs=reps,
+                best_ms=round(min(ms), 4), median_ms=round(sorted(ms)[reps // 2], 4),
+                best_GBps=round(nbytes / (min(ms) * 1e-3) / 1e9, 1),
+                median_GBps=round(nbytes / (sorted(ms)[reps // 2] * 1e-3) / 1e9, 1))
+
+
 def _rounded(st):
     """{median, min, max} of repeated timings, in seconds to 0.1 ms."""
     return {k: round(v, 4) for k, v in st.items()}
@@ -606,15 +635,10 @@ def main():
         cpu = cpu_baseline(qp, r.lambda_A, r.lambda_Q, r.sigma0, args.cpu_iters)
         log(f"cpu baseline: {cpu}")
     s.close()
+    copy_cal = None
     if args.calibrate_copy:
-        a = torch.rand(64 << 20, dtype=torch.float64, device="cuda")
-        flush = torch.empty(128 << 20, dtype=torch.float64, device="cuda").fill_(1.0)   # evict caches
-        del flush
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log("calibration copy: 536870912 bytes read, 536870912 bytes written")
-        del a, b
+        copy_cal = calibrate_copy()
+        log(f"calibration copy (hprqp_stream_copy): {copy_cal}")
     extras = None
     if not args.no_extras and args.workload == "random_large":
         extras = {}
@@ -652,6 +676,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_1e-8": tol_run,
+        "hbm_copy_calibration": copy_cal,
         "extras": extras,
     }
     print(json.dumps(out))

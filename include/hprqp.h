@@ -323,6 +323,15 @@ hprqp_status hprqp_batch_shapes(hprqp_batch *b, int32_t *class_count_host, int32
 
 /* Elapsed time of the last hprqp_solve_batch kernels (HIP events on `stream`
  * around them), seconds. */
+/* A plain streaming copy dst[i] = src[i], i < n (device arrays of doubles
+ * that do not overlap), with 16-byte loads and stores when both are 16-byte
+ * aligned.  Not part of the solver: the benchmark runs it to scale the HBM
+ * byte counters by what they read for a known number of bytes, and to
+ * measure the HBM rate plain streaming reaches.  ms_host (may be NULL)
+ * receives its duration from HIP events on `stream` (and the call then
+ * waits for the copy).  HPRQP_ERR_ARG for n < 0 or a NULL array. */
+hprqp_status hprqp_stream_copy(const double *src, double *dst, int64_t n, hipStream_t stream, double *ms_host);
+
 /* Queue order of the next hprqp_solve_batch calls.  A persistent kernel
  * takes its instances from a queue; the batch ends when the last instance
  * ends, so a long solve taken late sets the time of the whole batch.  With

@@ -55,7 +55,7 @@ class hprqp_info(C.Structure):
 EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_residuals_noalloc",
            "hprqp_apply",
            "hprqp_power_info", "hprqp_scaling", "hprqp_kernel_stats", "hprqp_set_options", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
-           "hprqp_batch_last_kernel_s", "hprqp_batch_shapes", "hprqp_batch_set_priority", "hprqp_batch_destroy", "hprqp_last_error")
+           "hprqp_batch_last_kernel_s", "hprqp_batch_shapes", "hprqp_batch_set_priority", "hprqp_stream_copy", "hprqp_batch_destroy", "hprqp_last_error")
 
 _lib = None
 
@@ -86,6 +86,8 @@ def load():
     lib.hprqp_destroy.argtypes = [_vp]
     lib.hprqp_destroy.restype = None
     lib.hprqp_last_error.restype = C.c_char_p
+    lib.hprqp_stream_copy.argtypes = [_vp, _vp, C.c_int64, _vp, C.POINTER(C.c_double)]
+    lib.hprqp_stream_copy.restype = C.c_int
     if hasattr(lib, "hprqp_batch_create"):
         lib.hprqp_batch_create.argtypes = [C.c_int32, C.POINTER(hprqp_problem), C.POINTER(hprqp_options), _vp,
                                            C.POINTER(_vp)]

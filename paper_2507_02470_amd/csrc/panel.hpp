@@ -18,7 +18,9 @@
 #include "common.hpp"
 #include "spmv.hpp"   // HQ_STREAM_CHUNK
 
+#ifndef HQ_PANELS
 #define HQ_PANELS 4
+#endif
 
 struct PanelMat {
   int rows = 0, cols = 0;

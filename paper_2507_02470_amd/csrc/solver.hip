@@ -1175,10 +1175,12 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       M.G = default_G(M.nnz, M.rows, mx, M.cols);
       M.G_np = M.G;
       M.maxlen = mx;
-      // short rows gathering from a vector larger than an XCD's L2 (4 MB): the
-      // panel-ordered product (measured 20% faster on 5e6 random gathers from an
-      // 8 MB vector, 8% slower from a 4 MB one), also under heavy epilogues
-      if (M.G == 0 && (long long)M.cols * 8 > (4ll << 20) && build_panel(h, M)) {
+      // short rows gathering from a vector larger than three quarters of an
+      // XCD's 4 MiB L2 (which the matrix streams through as well): the
+      // panel-ordered product, also under heavy epilogues (measured on 5e6
+      // random gathers: 20% faster from an 8 MB vector, 1.8% from a 4 MB one,
+      // A^T ybar of the random QP with n = 1e6, m = 5e5)
+      if (M.G == 0 && (long long)M.cols * 8 > (3ll << 20) && build_panel(h, M)) {
         M.G = HQ_G_PANEL;
         M.G_np = HQ_G_PANEL;
       }

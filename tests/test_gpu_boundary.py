@@ -99,3 +99,24 @@ def test_batch_qwx_gap_and_time_limit():
     b.close()
     assert [f["term"] for f in r.infos] == ["time_limit"] * len(qps)
     assert [f["iters"] for f in r.infos] == [100] * len(qps)
+
+
+@pytest.mark.parametrize("n,offset", [(0, 0), (1, 0), (3, 1), (1001, 0), (1001, 1), (1 << 20, 0), ((1 << 20) + 7, 1)])
+def test_stream_copy_exact(n, offset):
+    """hprqp_stream_copy (the benchmark's counter calibration): an exact copy for
+    any length, 16-byte aligned (vector path) or not (offset 1: scalar path);
+    nothing written past n; n < 0 rejected."""
+    import ctypes as C
+    from paper_2507_02470_amd import _native as N
+    lib = N.load()
+    src = torch.rand(n + offset + 8, dtype=torch.float64, device="cuda")
+    dst = torch.full((n + offset + 8,), -1.0, dtype=torch.float64, device="cuda")
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ms = C.c_double(-1.0)
+    N.check(lib.hprqp_stream_copy(C.c_void_p(src[offset:].data_ptr()), C.c_void_p(dst[offset:].data_ptr()), n, st,
+                                  C.byref(ms)))
+    torch.cuda.synchronize()
+    assert torch.equal(dst[offset:offset + n], src[offset:offset + n])
+    assert torch.all(dst[:offset] == -1.0) and torch.all(dst[offset + n:] == -1.0)
+    assert ms.value >= 0.0
+    assert lib.hprqp_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), -1, st, None) == 1

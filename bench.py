@@ -421,6 +421,42 @@ def extra_ablation(qp, dp, lamA, lamQ, steps, cpu, time_cap):
     return out
 
 
+def extra_mlp(steps=20):
+    """The warm-start network (1021 -> 512 -> 512 -> 2022, the n = 1000
+    portfolio family's) on random inputs: the forward pass at batch 512 (the
+    warm-start evaluation) and a training step (forward, backward, Adam) at
+    batch 128; GEMM time and useful FLOPs from the library's HIP events."""
+    import numpy as np
+    import torch
+    from paper_2507_02470_amd.surrogate import MLP, init_params
+    dims = (1021, 512, 512, 2022)
+    net = MLP(dims, 512, init_params(dims, 0))
+    rng = np.random.default_rng(0)
+    X = torch.as_tensor(rng.standard_normal((512, dims[0])), dtype=torch.float32, device="cuda")
+    T = torch.as_tensor(rng.standard_normal((512, dims[3])), dtype=torch.float32, device="cuda")
+    fw = []
+    for _ in range(steps + 2):
+        net.forward(X)
+        fw.append(net.gemm_stats())
+    tr = []
+    for i in range(steps + 2):
+        b0 = (i % 4) * 128
+        net.loss_grad(X[b0:b0 + 128], T[b0:b0 + 128], want_grad=False)
+        tr.append(net.gemm_stats())
+        net.adam(1e-4)
+    torch.cuda.synchronize()
+    net.close()
+    med = lambda v: sorted(v)[len(v) // 2]
+    f_ms, f_fl = med([x[0] for x in fw[2:]]), fw[-1][1]
+    t_ms, t_fl = med([x[0] for x in tr[2:]]), tr[-1][1]
+    f_tf, t_tf = f_fl / (f_ms * 1e-3) / 1e12, t_fl / (t_ms * 1e-3) / 1e12
+    return dict(dims=list(dims), forward=dict(batch=512, gemm_ms=round(f_ms, 4), tflops=round(f_tf, 2)),
+                train_step=dict(batch=128, gemm_ms=round(t_ms, 4), tflops=round(t_tf, 2)),
+                roofline=dict(bound="mfma", kernel="k_gemm_bf16 (+ k_splitk_reduce)", achieved=round(f_tf, 2),
+                              peak=BF16_PEAK_TFLOPS, unit="TFLOP/s", frac=round(f_tf / BF16_PEAK_TFLOPS, 5),
+                              traffic=None, flop_per_forward=f_fl))
+
+
 def calibrate_copy(reps=5, mib=4096):
     """The library's plain streaming copy of `mib` MiB (k_stream_copy2), after
     a 256 MiB fill that evicts the caches before each run: the counter scale
@@ -482,6 +518,7 @@ def extra_warm_cold(n_train, n_eval, epochs):
     Xe = np.stack([family_features(c, u) for (c, l, u) in held[:512]])
     sur.net.forward(Xe)
     ms, fl = sur.net.gemm_stats()
+    mlp = extra_mlp()
     # first use of the warm-start path (network, unpack, the check of its flags)
     # outside the timed comparison
     bool(sur.starts(Xe)[3].bool().any())
@@ -506,6 +543,7 @@ def extra_warm_cold(n_train, n_eval, epochs):
                                               np.maximum(1.0, np.abs(res["obj_cold"])))),
                 prediction_rel_err_w=round(res["pred_rel_err_w"], 4),
                 prediction_rel_err_y=round(res["pred_rel_err_y"], 4),
+                mlp_gemms=dict(forward=mlp["forward"], train_step=mlp["train_step"]),
                 mlp_forward_gemm=dict(batch=512, ms=round(ms, 4), tflops=round(fl / (ms * 1e-3) / 1e12, 2),
                                       bf16_mfma_util=round(fl / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 5)))
 
@@ -516,7 +554,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="random_large",
-                    choices=["random_large", "small_ccqp", "kron", "qap", "batch"])
+                    choices=["random_large", "small_ccqp", "kron", "qap", "batch", "mlp"])
     ap.add_argument("--qap-d", type=int, default=512, help="d of --workload qap (n = d^2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tol-solve", action="store_true")
@@ -556,6 +594,14 @@ def main():
     elif args.workload == "qap":
         qp = qpgen.make_qap(d=args.qap_d)
         wl = dict(workload="qap_relaxation", n=qp.n, m=qp.m, d=args.qap_d, seed=1007)
+    elif args.workload == "mlp":
+        # the warm-start network's GEMMs alone (what the rocprofv3 trace of them covers)
+        m = extra_mlp(args.steps)
+        print(json.dumps(dict(metric="BF16 MFMA TFLOP/s (warm-start network GEMMs)", value=m["forward"]["tflops"],
+                              unit="TFLOP/s", n_gpus=1, higher_is_better=True, dtype="bf16 (FP32 accumulate)",
+                              data="synthetic (random inputs, random-init weights)",
+                              config=dict(workload="mlp_1021_512_512_2022"), roofline=m["roofline"], detail=m)))
+        return
     elif args.workload == "batch":
         # the batched solver alone (what the batch leg of the extras reports)
         b = extra_batch(args.batch_count, not args.no_cpu_baseline)

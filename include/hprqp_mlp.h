@@ -117,10 +117,15 @@ hprqp_status hprqp_mlp_intermediate(hprqp_mlp *net, int32_t which, float *out, i
 
 /* Plain BF16 GEMM with FP32 accumulation on the matrix cores (exposed for
  * tests): C[i*ldc + j] (+)= sum_k A[i*a_rs + k*a_cs] * B[k*b_rs + j*b_cs],
- * A, B stored as BF16 bit patterns; accumulate = 1 adds to C. */
+ * A, B stored as BF16 bit patterns; accumulate = 1 adds to C.  split_k in
+ * [1, 64]: the K range is cut into that many slices of whole 16-steps, each
+ * slice's partial product goes to workspace (device, split_k M N floats;
+ * may be NULL when split_k = 1) and a second kernel adds the partials in slice
+ * order (deterministic).  The network's own GEMMs choose their split from
+ * the shape (enough waves to fill the CUs) and use the handle's workspace. */
 hprqp_status hprqp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A, int64_t a_rs, int64_t a_cs,
                              const uint16_t *B, int64_t b_rs, int64_t b_cs, float *C, int64_t ldc,
-                             int32_t accumulate, hipStream_t stream);
+                             int32_t accumulate, int32_t split_k, float *workspace, hipStream_t stream);
 
 #ifdef __cplusplus
 }

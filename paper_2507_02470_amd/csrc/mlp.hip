@@ -31,6 +31,29 @@ __device__ __forceinline__ float bf2f(uint16_t u) { return __builtin_bit_cast(fl
 
 static inline int rup8(int v) { return (v + 7) & ~7; }
 
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// Optional epilogue of a GEMM of the forward pass: Z = A B + bias (FP32,
+// stored in C) and, with act, its activation as BF16 (GELU for the hidden
+// layers): the same FP32 operations as a separate bias/activation pass.
+struct GemmEpi {
+  const float* bias = nullptr;
+  uint16_t* act = nullptr;
+  long long ld_act = 0;
+  int gelu_on = 0;
+};
+__device__ __forceinline__ void gemm_store(float* C, long long ldc, int row, int col, float v, int accumulate,
+                                           const GemmEpi& ep) {
+  float* p = C + (long long)row * ldc + col;
+  float z = accumulate ? *p + v : v;
+  if (ep.bias) z += ep.bias[col];
+  *p = z;
+  if (ep.act) ep.act[(long long)row * ep.ld_act + col] = f2bf(ep.gelu_on ? gelu(z) : z);
+}
+
 // ---------------------------------------------------------------------------
 // GEMM.  Block = 4 waves in a 2 x 2 arrangement, each wave a 32 x 32 tile of
 // C (one 32x32x16 MFMA per K step of 16).  Operand layout of the MFMA
@@ -40,62 +63,100 @@ static inline int rup8(int v) { return (v + 7) & ~7; }
 // A(i, k) = A[i*a_rs + k*a_cs], B(k, j) = B[k*b_rs + j*b_cs]; when a_cs == 1
 // (resp. b_rs == 1) and the row start is 16-byte aligned the 8 values come
 // from one vector load.
+// Split K: blockIdx.z takes the K range [z kper, (z + 1) kper) (kper a
+// multiple of 16) and writes its partial tile to W[z] (M x N, dense); a
+// second kernel adds the partials in the order z = 0, 1, ... (deterministic).
+// Without a split (W == nullptr) the tile goes to C directly.
 // ---------------------------------------------------------------------------
 #define HM_KUNROLL 8
-__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, long long a_rs,
-                                                  long long a_cs, const uint16_t* __restrict__ B, long long b_rs,
-                                                  long long b_cs, float* __restrict__ C, long long ldc, int accumulate) {
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, int kper, const uint16_t* __restrict__ A,
+                                                  long long a_rs, long long a_cs, const uint16_t* __restrict__ B,
+                                                  long long b_rs, long long b_cs, float* __restrict__ C, long long ldc,
+                                                  int accumulate, float* __restrict__ W, GemmEpi ep) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 31, lh = lane >> 5;
   const int i0 = blockIdx.x * 64 + (wv & 1) * 32;
   const int j0 = blockIdx.y * 64 + (wv >> 1) * 32;
   const int ia = i0 + li, jb = j0 + li;
+  const int kbeg = blockIdx.z * kper, kend = min(K, kbeg + kper);
   const bool a_vec = (a_cs == 1) && ((a_rs & 7) == 0) && ((((uintptr_t)A) & 15) == 0);
   const bool b_vec = (b_rs == 1) && ((b_cs & 7) == 0) && ((((uintptr_t)B) & 15) == 0);
   hm_f32x16 acc = {};
   auto frag_a = [&](int kb) {
     hm_u16x8 au;
-    if (a_vec && ia < M && kb + 8 <= K) {
+    if (a_vec && ia < M && kb + 8 <= kend) {
       au = *reinterpret_cast<const hm_u16x8*>(A + (long long)ia * a_rs + kb);
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) au[e] = (ia < M && kb + e < K) ? A[(long long)ia * a_rs + (long long)(kb + e) * a_cs] : 0;
+      for (int e = 0; e < 8; ++e)
+        au[e] = (ia < M && kb + e < kend) ? A[(long long)ia * a_rs + (long long)(kb + e) * a_cs] : 0;
     }
     return au;
   };
   auto frag_b = [&](int kb) {
     hm_u16x8 bu;
-    if (b_vec && jb < N && kb + 8 <= K) {
+    if (b_vec && jb < N && kb + 8 <= kend) {
       bu = *reinterpret_cast<const hm_u16x8*>(B + (long long)jb * b_cs + kb);
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) bu[e] = (jb < N && kb + e < K) ? B[(long long)(kb + e) * b_rs + (long long)jb * b_cs] : 0;
+      for (int e = 0; e < 8; ++e)
+        bu[e] = (jb < N && kb + e < kend) ? B[(long long)(kb + e) * b_rs + (long long)jb * b_cs] : 0;
     }
     return bu;
   };
-  // the fragments of HM_KUNROLL k-steps are loaded first (all in flight at
-  // once), then multiplied: the MFMA chain does not wait a load per step
-  for (int k0 = 0; k0 < K; k0 += 16 * HM_KUNROLL) {
-    hm_u16x8 au[HM_KUNROLL], bu[HM_KUNROLL];
+  // software pipeline: the fragments of the next HM_KUNROLL k-steps are
+  // loaded before the MFMAs of the current ones, so their latency overlaps
+  // the matrix-core work instead of stalling it
+  hm_u16x8 au[HM_KUNROLL], bu[HM_KUNROLL];
 #pragma unroll
-    for (int u = 0; u < HM_KUNROLL; ++u) {
-      const int kb = k0 + 16 * u + 8 * lh;
-      au[u] = frag_a(kb);
-      bu[u] = frag_b(kb);
+  for (int u = 0; u < HM_KUNROLL; ++u) {
+    const int kb = kbeg + 16 * u + 8 * lh;
+    au[u] = frag_a(kb);
+    bu[u] = frag_b(kb);
+  }
+  for (int k0 = kbeg; k0 < kend; k0 += 16 * HM_KUNROLL) {
+    const int k1 = k0 + 16 * HM_KUNROLL;
+    hm_u16x8 an[HM_KUNROLL], bn[HM_KUNROLL];
+    if (k1 < kend) {
+#pragma unroll
+      for (int u = 0; u < HM_KUNROLL; ++u) {
+        const int kb = k1 + 16 * u + 8 * lh;
+        an[u] = frag_a(kb);
+        bn[u] = frag_b(kb);
+      }
     }
 #pragma unroll
     for (int u = 0; u < HM_KUNROLL; ++u)
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(hm_bf16x8, au[u]),
                                                     __builtin_bit_cast(hm_bf16x8, bu[u]), acc, 0, 0, 0);
+    if (k1 < kend) {
+#pragma unroll
+      for (int u = 0; u < HM_KUNROLL; ++u) {
+        au[u] = an[u];
+        bu[u] = bn[u];
+      }
+    }
   }
+  float* const Wz = W ? W + (size_t)blockIdx.z * M * N : nullptr;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int row = i0 + 8 * (v >> 2) + 4 * lh + (v & 3);
     const int col = j0 + li;
     if (row < M && col < N) {
-      float* p = C + (long long)row * ldc + col;
-      *p = accumulate ? *p + acc[v] : acc[v];
+      if (Wz) Wz[(size_t)row * N + col] = acc[v];
+      else gemm_store(C, ldc, row, col, acc[v], accumulate, ep);
     }
+  }
+}
+
+// C (+)= sum over z = 0..S-1 of W[z] (M x N each), in that order, then the epilogue
+__global__ void k_splitk_reduce(int M, int N, int S, const float* __restrict__ W, float* __restrict__ C, long long ldc,
+                                int accumulate, GemmEpi ep) {
+  const long long total = (long long)M * N;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
+    float sum = W[t];
+    for (int z = 1; z < S; ++z) sum += W[(size_t)z * total + t];
+    gemm_store(C, ldc, (int)(t / N), (int)(t % N), sum, accumulate, ep);
   }
 }
 
@@ -248,22 +309,6 @@ __global__ void k_transpose_bf16(int rows, int rows_p, int cols_p, const uint16_
   }
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_d(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
-}
-
-// Z (B x N, ld) += bias; hidden layers: act (B x ld_act, BF16) = GELU(Z); else Y = Z
-__global__ void k_bias_act(int B, int N, long long ld, float* __restrict__ Z, const float* __restrict__ bias,
-                           uint16_t* __restrict__ act, long long ld_act, int gelu_on) {
-  const long long total = (long long)B * N;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
-    const int b = (int)(t / N), j = (int)(t % N);
-    const float z = Z[(long long)b * ld + j] + bias[j];
-    Z[(long long)b * ld + j] = z;
-    if (gelu_on) act[(long long)b * ld_act + j] = f2bf(gelu(z));
-  }
-}
 
 // weighted MSE: dY = 2 w (Y - T)/(B N) (FP32 and BF16 copies), per-block loss partials
 __global__ __launch_bounds__(256) void k_mse(int B, int N, const float* __restrict__ Y, long long ldy,
@@ -304,12 +349,30 @@ __global__ void k_gelu_bwd(int B, int N, const float* __restrict__ dA, long long
   }
 }
 
-// db[j] = sum_b dZ[b][j] (one thread per column, fixed order)
-__global__ void k_colsum(int B, int N, const float* __restrict__ dZ, long long ld, float* __restrict__ db) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+// db[j] = sum_b dZ[b][j]: a block of 256 threads covers 32 columns, thread
+// (g, c) summing rows g, g + 8, ... of its column in FP64, and the 8 partial
+// sums of a column are added in the order g = 0..7 (deterministic; reading
+// rows 8 at a time keeps 8 loads per column in flight)
+#define HM_CS_COLS 32
+#define HM_CS_GRP 8
+__global__ __launch_bounds__(256) void k_colsum(int B, int N, const float* __restrict__ dZ, long long ld,
+                                                float* __restrict__ db) {
+  __shared__ double part[HM_CS_GRP][HM_CS_COLS];
+  const int c = threadIdx.x % HM_CS_COLS, g = threadIdx.x / HM_CS_COLS;
+  for (int j0 = blockIdx.x * HM_CS_COLS; j0 < N; j0 += gridDim.x * HM_CS_COLS) {
+    const int j = j0 + c;
     double s = 0.0;
-    for (int b = 0; b < B; ++b) s += dZ[(long long)b * ld + j];
-    db[j] = (float)s;
+    if (j < N)
+      for (int b = g; b < B; b += HM_CS_GRP) s += dZ[(long long)b * ld + j];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < N) {
+      double t = part[0][c];
+#pragma unroll
+      for (int q = 1; q < HM_CS_GRP; ++q) t += part[q][c];
+      db[j] = (float)t;
+    }
+    __syncthreads();
   }
 }
 
@@ -354,6 +417,9 @@ struct hprqp_mlp {
   float *dYf = nullptr, *dA2 = nullptr, *dZ2f = nullptr, *dA1 = nullptr, *dZ1f = nullptr;
   uint16_t *dYb = nullptr, *dYt = nullptr, *dZ2b = nullptr, *dZ2t = nullptr, *dZ1b = nullptr, *dZ1t = nullptr;
   double* part = nullptr;
+  float* ws = nullptr;          // split-K partials of the GEMMs
+  long long ws_floats = 0;
+  int ncu = 0;
   // input / output standardization (set by hprqp_mlp_set_scaling; identity by default)
   float *in_mean = nullptr, *in_istd = nullptr, *out_mean = nullptr, *out_sd = nullptr, *out_istd = nullptr;
   float *Tstd = nullptr, *Yuser = nullptr;
@@ -398,10 +464,45 @@ int eg(long long work) {
   return (int)std::max(1LL, std::min(g, 4096LL));
 }
 
-void gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, long long a_rs, long long a_cs, const uint16_t* B,
-          long long b_rs, long long b_cs, float* C, long long ldc, int acc) {
-  dim3 grid((M + 63) / 64, (N + 63) / 64);
-  k_gemm_bf16<<<grid, 256, 0, st>>>(M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, C, ldc, acc);
+int cs_grid(int cols) { return std::max(1, std::min((cols + HM_CS_COLS - 1) / HM_CS_COLS, 4096)); }
+
+// K splits of a GEMM: doubled while the launch holds fewer than 4 waves per
+// CU, each split keeps at least 4 k-steps of 16 and the partials fit the
+// workspace (the network's GEMMs are small: a 512 x 512 output is 64 tiles,
+// 256 waves, too few to hide the fragment loads on 256 CUs)
+int gemm_splits(int M, int N, int K, int ncu, long long ws_floats) {
+  const long long waves = 4LL * ((M + 63) / 64) * ((N + 63) / 64);
+  const int ksteps = (K + 15) / 16;
+  int S = 1;
+  while (S < 8 && waves * S < 4LL * ncu && ksteps >= 8 * S && (long long)(2 * S) * M * N <= ws_floats) S *= 2;
+  return S;
+}
+
+// C (+)= A B with S K-splits (S > 1: the partials go through ws, which holds
+// at least S M N floats)
+void gemm_split(hipStream_t st, int M, int N, int K, const uint16_t* A, long long a_rs, long long a_cs,
+                const uint16_t* B, long long b_rs, long long b_cs, float* C, long long ldc, int acc, int S, float* ws,
+                const GemmEpi& ep = GemmEpi{}) {
+  const int ksteps = (K + 15) / 16;
+  if (S < 1) S = 1;
+  const int kper = 16 * ((ksteps + S - 1) / S);
+  const int Se = kper > 0 ? (K + kper - 1) / kper : 1;
+  if (Se <= 1) {
+    dim3 grid((M + 63) / 64, (N + 63) / 64, 1);
+    k_gemm_bf16<<<grid, 256, 0, st>>>(M, N, K, std::max(kper, 16), A, a_rs, a_cs, B, b_rs, b_cs, C, ldc, acc, nullptr,
+                                      ep);
+    return;
+  }
+  dim3 grid((M + 63) / 64, (N + 63) / 64, Se);
+  k_gemm_bf16<<<grid, 256, 0, st>>>(M, N, K, kper, A, a_rs, a_cs, B, b_rs, b_cs, C, ldc, acc, ws, GemmEpi{});
+  k_splitk_reduce<<<eg((long long)M * N), 256, 0, st>>>(M, N, Se, ws, C, ldc, acc, ep);
+}
+
+// a GEMM of the network: K split by gemm_splits, partials in the handle's workspace
+void gemm(hprqp_mlp& n, int M, int N, int K, const uint16_t* A, long long a_rs, long long a_cs, const uint16_t* B,
+          long long b_rs, long long b_cs, float* C, long long ldc, int acc, const GemmEpi& ep = GemmEpi{}) {
+  gemm_split(n.st, M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, C, ldc, acc, gemm_splits(M, N, K, n.ncu, n.ws_floats), n.ws,
+             ep);
 }
 
 void refresh_weights(hprqp_mlp& n) {
@@ -464,6 +565,15 @@ void create_impl(const int32_t dims[4], int32_t max_batch, const float* params_h
     n->dZ1b = malloc_dev<uint16_t>(*n, B * n->dp[1]);
     n->dZ1t = malloc_dev<uint16_t>(*n, B * n->dp[1]);
     n->part = malloc_dev<double>(*n, 4096);
+    {
+      int dev = 0;
+      HMC(hipGetDevice(&dev));
+      HMC(hipDeviceGetAttribute(&n->ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      // split-K partials: gemm_splits only splits launches of fewer than 4
+      // waves per CU, whose partials stay well below this; beyond it, fewer splits
+      n->ws_floats = 2LL * n->ncu * 4096 * 4;
+      n->ws = malloc_dev<float>(*n, (size_t)n->ws_floats);
+    }
     n->in_mean = malloc_dev<float>(*n, n->d[0]);
     n->in_istd = malloc_dev<float>(*n, n->d[0]);
     n->out_mean = malloc_dev<float>(*n, n->d[3]);
@@ -498,17 +608,15 @@ void forward_impl(hprqp_mlp& n, int B, const float* X) {
   k_to_bf16_pad<<<eg((long long)B * inp), 256, 0, n.st>>>(B, in, inp, X, n.in_mean, n.in_istd, n.Xb);
   n.nev = 0;
   mark(n);
-  gemm(n.st, B, h1, inp, n.Xb, inp, 1, n.Wb[0], 1, inp, n.Z1, h1p, 0);
+  // each layer: Z = W x + b, then the hidden layers' GELU to BF16, in the GEMM's epilogue
+  gemm(n, B, h1, inp, n.Xb, inp, 1, n.Wb[0], 1, inp, n.Z1, h1p, 0, GemmEpi{n.P + n.off_b[0], n.A1b, h1p, 1});
   mark(n);
-  k_bias_act<<<eg((long long)B * h1), 256, 0, n.st>>>(B, h1, h1p, n.Z1, n.P + n.off_b[0], n.A1b, h1p, 1);
   mark(n);
-  gemm(n.st, B, h2, h1p, n.A1b, h1p, 1, n.Wb[1], 1, h1p, n.Z2, h2p, 0);
+  gemm(n, B, h2, h1p, n.A1b, h1p, 1, n.Wb[1], 1, h1p, n.Z2, h2p, 0, GemmEpi{n.P + n.off_b[1], n.A2b, h2p, 1});
   mark(n);
-  k_bias_act<<<eg((long long)B * h2), 256, 0, n.st>>>(B, h2, h2p, n.Z2, n.P + n.off_b[1], n.A2b, h2p, 1);
   mark(n);
-  gemm(n.st, B, out, h2p, n.A2b, h2p, 1, n.Wb[2], 1, h2p, n.Y, outp, 0);
+  gemm(n, B, out, h2p, n.A2b, h2p, 1, n.Wb[2], 1, h2p, n.Y, outp, 0, GemmEpi{n.P + n.off_b[2], nullptr, 0, 0});
   mark(n);
-  k_bias_act<<<eg((long long)B * out), 256, 0, n.st>>>(B, out, outp, n.Y, n.P + n.off_b[2], nullptr, 0, 0);
   n.last_flop = 2.0 * B * ((double)inp * h1 + (double)h1p * h2 + (double)h2p * out);
 }
 
@@ -536,24 +644,24 @@ void loss_grad_impl(hprqp_mlp& n, int B, const float* X, const float* T, const f
   float* G = n.G;
   mark(n);
   // layer 3
-  gemm(n.st, out, h2, Bp, n.dYt, Bp, 1, n.A2t, 1, Bp, G + n.off_W[2], h2, 0);          // dW3 = dY^T A2
-  k_colsum<<<eg(out), 256, 0, n.st>>>(B, out, n.dYf, outp, G + n.off_b[2]);
-  gemm(n.st, B, h2, outp, n.dYb, outp, 1, n.Wt[2], 1, outp, n.dA2, h2p, 0);             // dA2 = dY W3
+  gemm(n, out, h2, Bp, n.dYt, Bp, 1, n.A2t, 1, Bp, G + n.off_W[2], h2, 0);          // dW3 = dY^T A2
+  k_colsum<<<cs_grid(out), 256, 0, n.st>>>(B, out, n.dYf, outp, G + n.off_b[2]);
+  gemm(n, B, h2, outp, n.dYb, outp, 1, n.Wt[2], 1, outp, n.dA2, h2p, 0);             // dA2 = dY W3
   mark(n);
   k_gelu_bwd<<<eg((long long)B * h2), 256, 0, n.st>>>(B, h2, n.dA2, h2p, n.Z2, h2p, n.dZ2f, n.dZ2b, h2p);
   tr(n.dZ2b, n.dZ2t, h2p);
   mark(n);
   // layer 2
-  gemm(n.st, h2, h1, Bp, n.dZ2t, Bp, 1, n.A1t, 1, Bp, G + n.off_W[1], h1, 0);          // dW2 = dZ2^T A1
-  k_colsum<<<eg(h2), 256, 0, n.st>>>(B, h2, n.dZ2f, h2p, G + n.off_b[1]);
-  gemm(n.st, B, h1, h2p, n.dZ2b, h2p, 1, n.Wt[1], 1, h2p, n.dA1, h1p, 0);              // dA1 = dZ2 W2
+  gemm(n, h2, h1, Bp, n.dZ2t, Bp, 1, n.A1t, 1, Bp, G + n.off_W[1], h1, 0);          // dW2 = dZ2^T A1
+  k_colsum<<<cs_grid(h2), 256, 0, n.st>>>(B, h2, n.dZ2f, h2p, G + n.off_b[1]);
+  gemm(n, B, h1, h2p, n.dZ2b, h2p, 1, n.Wt[1], 1, h2p, n.dA1, h1p, 0);              // dA1 = dZ2 W2
   mark(n);
   k_gelu_bwd<<<eg((long long)B * h1), 256, 0, n.st>>>(B, h1, n.dA1, h1p, n.Z1, h1p, n.dZ1f, n.dZ1b, h1p);
   tr(n.dZ1b, n.dZ1t, h1p);
   mark(n);
   // layer 1
-  gemm(n.st, h1, in, Bp, n.dZ1t, Bp, 1, n.Xt, 1, Bp, G + n.off_W[0], in, 0);           // dW1 = dZ1^T X
-  k_colsum<<<eg(h1), 256, 0, n.st>>>(B, h1, n.dZ1f, h1p, G + n.off_b[0]);
+  gemm(n, h1, in, Bp, n.dZ1t, Bp, 1, n.Xt, 1, Bp, G + n.off_W[0], in, 0);           // dW1 = dZ1^T X
+  k_colsum<<<cs_grid(h1), 256, 0, n.st>>>(B, h1, n.dZ1f, h1p, G + n.off_b[0]);
   mark(n);
   n.last_flop = fwd_flop + 2.0 * ((double)out * h2 * Bp + (double)B * h2 * outp + (double)h2 * h1 * Bp +
                                   (double)B * h1 * h2p + (double)h1 * in * Bp);
@@ -767,9 +875,12 @@ void hprqp_mlp_destroy(hprqp_mlp* n) { delete n; }
 
 hprqp_status hprqp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int64_t a_rs, int64_t a_cs,
                              const uint16_t* B, int64_t b_rs, int64_t b_cs, float* C, int64_t ldc, int32_t accumulate,
-                             hipStream_t stream) {
+                             int32_t split_k, float* workspace, hipStream_t stream) {
   HM_GUARD(if (M < 0 || N < 0 || K < 0 || !A || !B || !C) mfail(HPRQP_ERR_ARG, "bad GEMM arguments");
-           if (M > 0 && N > 0) gemm(stream, M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, C, ldc, accumulate);
+           if (split_k < 1 || split_k > 64) mfail(HPRQP_ERR_ARG, "split_k must be in [1, 64]");
+           if (split_k > 1 && !workspace) mfail(HPRQP_ERR_ARG, "split_k > 1 needs a workspace of split_k M N floats");
+           if (M > 0 && N > 0)
+             gemm_split(stream, M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, C, ldc, accumulate, split_k, workspace);
            HMC(hipGetLastError()); HMC(hipStreamSynchronize(stream)));
 }
 

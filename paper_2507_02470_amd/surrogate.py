@@ -45,7 +45,7 @@ def _load():
         lib.hprqp_mlp_destroy.argtypes = [_vp]
         lib.hprqp_mlp_destroy.restype = None
         lib.hprqp_gemm_bf16.argtypes = [C.c_int32, C.c_int32, C.c_int32, _vp, C.c_int64, C.c_int64, _vp, C.c_int64,
-                                        C.c_int64, _vp, C.c_int64, C.c_int32, _vp]
+                                        C.c_int64, _vp, C.c_int64, C.c_int32, C.c_int32, _vp, _vp]
         for f in ("hprqp_mlp_create", "hprqp_mlp_forward", "hprqp_mlp_loss_grad", "hprqp_mlp_adam",
                   "hprqp_mlp_get_params", "hprqp_mlp_set_params", "hprqp_mlp_set_scaling", "hprqp_mlp_warm_start",
                   "hprqp_mlp_gemm_stats", "hprqp_gemm_bf16", "hprqp_mlp_fit_scaling", "hprqp_mlp_intermediate", "hprqp_family_features",
@@ -181,11 +181,13 @@ class MLP:
 
 
 def gemm_bf16(A_bits: torch.Tensor, a_rs, a_cs, B_bits: torch.Tensor, b_rs, b_cs, M, N_, K, C_out: torch.Tensor,
-              ldc, accumulate=False):
-    """Raw BF16 GEMM of the library (inputs: int16 tensors holding BF16 bits)."""
+              ldc, accumulate=False, split_k=1):
+    """Raw BF16 GEMM of the library (inputs: int16 tensors holding BF16 bits);
+    split_k > 1 cuts K into that many slices through a workspace."""
     lib = _load()
+    ws = torch.empty(max(1, split_k * M * N_), dtype=torch.float32, device=C_out.device) if split_k > 1 else None
     N.check(lib.hprqp_gemm_bf16(M, N_, K, _p(A_bits), a_rs, a_cs, _p(B_bits), b_rs, b_cs, _p(C_out), ldc,
-                                int(accumulate), _vp(torch.cuda.current_stream().cuda_stream)))
+                                int(accumulate), int(split_k), _p(ws), _vp(torch.cuda.current_stream().cuda_stream)))
 
 
 # ---------------------------------------------------------------------------

@@ -38,11 +38,18 @@ def _bits(a):
     return t.view(torch.int16).cuda(), t.to(torch.float64).numpy()
 
 
-@pytest.mark.parametrize("M,N,K,transA,transB", [(64, 64, 16, 0, 0), (100, 37, 51, 0, 0), (1, 2021, 512, 0, 1),
-                                                 (256, 512, 1024, 0, 0), (513, 129, 24, 1, 1), (33, 65, 1000, 1, 0)])
-def test_gemm_bf16_against_numpy(M, N, K, transA, transB):
+@pytest.mark.parametrize("M,N,K,transA,transB,split", [(64, 64, 16, 0, 0, 1), (100, 37, 51, 0, 0, 1),
+                                                       (1, 2021, 512, 0, 1, 1), (256, 512, 1024, 0, 0, 1),
+                                                       (513, 129, 24, 1, 1, 1), (33, 65, 1000, 1, 0, 1),
+                                                       (512, 512, 1021, 0, 1, 4), (100, 37, 51, 0, 0, 3),
+                                                       (128, 512, 2024, 1, 0, 8), (33, 65, 1000, 1, 1, 64),
+                                                       (70, 90, 17, 0, 0, 2)])
+def test_gemm_bf16_against_numpy(M, N, K, transA, transB, split):
+    """The GEMM, with K split into `split` slices or not, within the
+    recursive-summation bound; accumulate adds to C; split results are the
+    same on every call (fixed-order reduction)."""
     from paper_2507_02470_amd.surrogate import gemm_bf16
-    rng = np.random.default_rng(M * 7 + N)
+    rng = np.random.default_rng(M * 7 + N + split)
     A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N))
     if transA:   # A stored as K x M (A(i,k) = At[k, i])
         Ab, Ar = _bits(A.T.copy()); a_rs, a_cs = 1, M
@@ -55,11 +62,21 @@ def test_gemm_bf16_against_numpy(M, N, K, transA, transB):
     Ae = Ar.T if transA else Ar
     Be = Br.T if transB else Br
     Cout = torch.zeros((M, N), dtype=torch.float32, device="cuda")
-    gemm_bf16(Ab, a_rs, a_cs, Bb, b_rs, b_cs, M, N, K, Cout, N)
+    gemm_bf16(Ab, a_rs, a_cs, Bb, b_rs, b_cs, M, N, K, Cout, N, split_k=split)
     ref = Ae @ Be
     bound = K * 2.0 ** -24 * (np.abs(Ae) @ np.abs(Be)) + 1e-30
-    err = np.abs(Cout.cpu().numpy().astype(np.float64) - ref)
+    C1 = Cout.cpu().numpy().astype(np.float64)
+    err = np.abs(C1 - ref)
     assert np.all(err <= bound), float((err / bound).max())
+    C0 = rng.standard_normal((M, N)).astype(np.float32)
+    Cacc = torch.as_tensor(C0, device="cuda")
+    gemm_bf16(Ab, a_rs, a_cs, Bb, b_rs, b_cs, M, N, K, Cacc, N, accumulate=True, split_k=split)
+    ref2 = C0.astype(np.float64) + ref
+    bound2 = (K + 1) * 2.0 ** -24 * (np.abs(Ae) @ np.abs(Be) + np.abs(C0)) + 1e-30
+    assert np.all(np.abs(Cacc.cpu().numpy().astype(np.float64) - ref2) <= bound2)
+    Cagain = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+    gemm_bf16(Ab, a_rs, a_cs, Bb, b_rs, b_cs, M, N, K, Cagain, N, split_k=split)
+    assert torch.equal(Cagain, Cout)
 
 
 DIMS = (1021, 512, 512, 2021)

@@ -88,21 +88,56 @@ def read_traffic(kernel: str, workload: str):
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(qp, lam_A, lam_Q, sigma0, iters, budget_s=20.0):
+def host_lambdas(qp):
+    """Upper bounds of lambda_1(A A^T) and lambda_1(Q) from the host copy of
+    the data alone (no GPU result): ||A||_1 ||A||_inf, and for Q its largest
+    absolute row sum (CSR, symmetric), ||B||_inf ||C||_inf (+ ||S||_inf +
+    ||T||_inf) for a Kronecker Q, max d + ||F||_F^2 for diag(d) + F F^T, or
+    ||Ahat||_1 ||Ahat||_inf for Ahat^T Ahat.  The oracle's timed iterations
+    take them as its lambda's: the cost of an iteration does not depend on
+    them."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    def n1ninf(rp, ci, v, rows, cols):
+        M = abs(sp.csr_matrix((v, ci, rp), shape=(rows, cols)))
+        return float(np.asarray(M.sum(axis=0)).max(initial=0.0) * np.asarray(M.sum(axis=1)).max(initial=0.0))
+
+    lam_A = n1ninf(qp.a_rowptr, qp.a_col, qp.a_val, qp.m, qp.n) if qp.m else 0.0
+    if qp.qkind == "csr":
+        Qm = abs(sp.csr_matrix((qp.q_val, qp.q_col, qp.q_rowptr), shape=(qp.n, qp.n)))
+        lam_Q = float(np.asarray(Qm.sum(axis=1)).max(initial=0.0))
+    elif qp.qkind == "kron":
+        inf = lambda M: float(np.abs(np.asarray(M)).sum(axis=1).max())
+        lam_Q = inf(qp.kron_B) * inf(qp.kron_C)
+        for M in (qp.kron_S, qp.kron_T):
+            if M is not None:
+                lam_Q += inf(M)
+    elif qp.qkind == "lowrank":
+        lam_Q = float(np.max(qp.lr_d) + np.sum(np.asarray(qp.lr_F) ** 2))
+    elif qp.qkind == "gram":
+        lam_Q = n1ninf(qp.gram_rowptr, qp.gram_col, qp.gram_val, qp.gram_p, qp.n)
+    else:
+        lam_Q = 0.0
+    return max(lam_A, 0.0), max(lam_Q, 0.0)
+
+
+def cpu_baseline(qp, iters, budget_s=20.0):
     """The oracle as it stands, single thread, on the first `iters` iterations
-    (fewer when two iterations show that `iters` would exceed `budget_s`)."""
+    (fewer when two iterations show that `iters` would exceed `budget_s`), with
+    the lambda's of host_lambdas and its own sigma0 rule."""
     import oracle
+    lam_A, lam_Q = host_lambdas(qp)
     t0 = time.perf_counter()
-    oracle.solve(qp, tol=0.0, max_iter=2, check_every=T_CHECK, lambda_A=lam_A, lambda_Q=lam_Q, sigma0=sigma0)
+    oracle.solve(qp, tol=0.0, max_iter=2, check_every=T_CHECK, lambda_A=lam_A, lambda_Q=lam_Q)
     per_it = (time.perf_counter() - t0) / 2
     iters = int(max(2, min(iters, budget_s / max(per_it, 1e-9))))
     t0 = time.perf_counter()
-    r = oracle.solve(qp, tol=0.0, max_iter=iters, check_every=T_CHECK, lambda_A=lam_A, lambda_Q=lam_Q,
-                     sigma0=sigma0)
+    r = oracle.solve(qp, tol=0.0, max_iter=iters, check_every=T_CHECK, lambda_A=lam_A, lambda_Q=lam_Q)
     dt = time.perf_counter() - t0
     return dict(value=r.iters / dt, unit="iterations/s", cores=1, kind="oracle",
                 sample=f"first {r.iters} iterations of the same instance (single-threaded FP64 C, "
-                       f"lambda's and sigma0 given), {dt:.1f} s")
+                       f"lambda's from host-side bounds of the data), {dt:.1f} s")
 
 
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 MFMA, published
@@ -142,8 +177,8 @@ def extra_kron(steps, cpu):
     if cpu:
         import oracle
         t0 = time.perf_counter()
-        ro = oracle.solve(qp, tol=0.0, max_iter=3, check_every=T_CHECK, lambda_A=r.lambda_A, lambda_Q=r.lambda_Q,
-                          sigma0=r.sigma0)
+        la, lq = host_lambdas(qp)
+        ro = oracle.solve(qp, tol=0.0, max_iter=3, check_every=T_CHECK, lambda_A=la, lambda_Q=lq)
         out["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
     s.close()
     return out
@@ -188,8 +223,8 @@ def extra_qap(dims, steps, cpu, time_cap):
         if cpu and d <= 256:
             import oracle
             t0 = time.perf_counter()
-            ro = oracle.solve(qp, tol=0.0, max_iter=3, check_every=T_CHECK, lambda_A=r.lambda_A,
-                              lambda_Q=r.lambda_Q, sigma0=r.sigma0)
+            la, lq = host_lambdas(qp)
+            ro = oracle.solve(qp, tol=0.0, max_iter=3, check_every=T_CHECK, lambda_A=la, lambda_Q=lq)
             o["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
         s.close()
         out[f"d{d}"] = o
@@ -232,14 +267,19 @@ def extra_precond(qp_large, dp_large, cpu):
     return out
 
 
-def extra_lasso(steps, cpu):
-    """Lasso 1/2||Ahat x - bhat||^2 + lambda ||x||_1 (Section 4.4) at the first size
-    of the paper's random Lasso table (p = 1e4 rows, q = 5e5 variables), Ahat with
-    1% N(0,1) entries, lambda = ||Ahat^T bhat||_inf / 5; Q = Ahat^T Ahat matrix-free."""
+def extra_lasso(steps, cpu, p=10_000, q=500_000, per_row=0, time_cap=60.0):
+    """Lasso 1/2||Ahat x - bhat||^2 + lambda ||x||_1 (Section 4.4) of the paper's
+    random Lasso table, lambda = ||Ahat^T bhat||_inf / 5; Q = Ahat^T Ahat
+    matrix-free.  Default: its first size (p = 1e4 rows, q = 5e5 variables)
+    with 1% N(0,1) entries; per_row > 0: Ahat built row by row with that many
+    entries per row (the larger sizes, e.g. p = 2e5, q = 5e6, 1000 per row)."""
     import torch
     import qpgen
     from paper_2507_02470_amd.solver import DeviceProblem, Solver
-    qp = qpgen.make_lasso(seed=1006, p=10_000, q=500_000, density=0.01)
+    if per_row > 0:
+        qp = qpgen.make_lasso_rows(seed=1008, p=p, q=q, per_row=per_row)
+    else:
+        qp = qpgen.make_lasso(seed=1006, p=p, q=q, density=0.01)
     nnz = int(qp.gram_rowptr[-1])
     dp = DeviceProblem(qp)
     s = Solver(dp, power_start_Q=qpgen.power_start(qp.n), check_every=T_CHECK, tol=0.0, max_iter=T_CHECK,
@@ -261,15 +301,16 @@ def extra_lasso(steps, cpu):
                iterations_per_s=round(r.iters / dt, 1), us_per_iteration=round(dt / r.iters * 1e6, 2),
                q_product=dict(avg_us=round(q_us, 2), algorithmic_bytes=q_bytes,
                               GBps=round(q_bytes / (q_us * 1e-6) / 1e9, 1)))
-    s.set_options(tol=1e-8, max_iter=2_000_000, profile_kernels=0, time_limit_s=60.0)
+    s.set_options(tol=1e-8, max_iter=2_000_000, profile_kernels=0, time_limit_s=time_cap)
     rt = s.solve()
     out["time_to_1e-8"] = dict(term=rt.term, iterations=rt.iters, restarts=rt.restarts, kkt=rt.kkt,
-                               time_s=round(rt.t_setup_s + rt.t_solve_s, 4), pobj=rt.pobj)
+                               time_s=round(rt.t_setup_s + rt.t_solve_s, 4), pobj=rt.pobj, time_cap_s=time_cap)
     s.close()
     if cpu:
         import oracle
         t0 = time.perf_counter()
-        ro = oracle.solve(qp, tol=0.0, max_iter=5, check_every=T_CHECK, lambda_Q=rt.lambda_Q, sigma0=rt.sigma0)
+        la, lq = host_lambdas(qp)
+        ro = oracle.solve(qp, tol=0.0, max_iter=5, check_every=T_CHECK, lambda_A=la, lambda_Q=lq)
         out["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
     return out
 
@@ -554,8 +595,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="random_large",
-                    choices=["random_large", "small_ccqp", "kron", "qap", "batch", "mlp"])
+                    choices=["random_large", "small_ccqp", "kron", "qap", "batch", "mlp", "lasso"])
     ap.add_argument("--qap-d", type=int, default=512, help="d of --workload qap (n = d^2)")
+    ap.add_argument("--lasso-p", type=int, default=10_000, help="rows of Ahat, --workload lasso")
+    ap.add_argument("--lasso-q", type=int, default=500_000, help="variables, --workload lasso")
+    ap.add_argument("--lasso-per-row", type=int, default=0,
+                    help="entries per row of Ahat (0: 1%% density), --workload lasso")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tol-solve", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
@@ -594,6 +639,15 @@ def main():
     elif args.workload == "qap":
         qp = qpgen.make_qap(d=args.qap_d)
         wl = dict(workload="qap_relaxation", n=qp.n, m=qp.m, d=args.qap_d, seed=1007)
+    elif args.workload == "lasso":
+        la = extra_lasso(args.steps, not args.no_cpu_baseline, args.lasso_p, args.lasso_q, args.lasso_per_row,
+                         args.tol_time_limit)
+        print(json.dumps(dict(metric="HPR-QP iterations/s (FP64, Lasso, Q = Ahat^T Ahat matrix-free)",
+                              value=la["iterations_per_s"], unit="iterations/s", n_gpus=1, higher_is_better=True,
+                              dtype="f64", data="synthetic (seeded random Lasso)",
+                              config=dict(workload="lasso", p=la["p"], q=la["q"], nnz=la["nnz"]),
+                              roofline=None, cpu_baseline=None, detail=la)))
+        return
     elif args.workload == "mlp":
         # the warm-start network's GEMMs alone (what the rocprofv3 trace of them covers)
         m = extra_mlp(args.steps)
@@ -678,7 +732,7 @@ def main():
         log(f"to 1e-8: {tol_run}")
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(qp, r.lambda_A, r.lambda_Q, r.sigma0, args.cpu_iters)
+        cpu = cpu_baseline(qp, args.cpu_iters)
         log(f"cpu baseline: {cpu}")
     s.close()
     copy_cal = None

@@ -11,6 +11,6 @@ shares no code with it.
 * ``mlp.py``         -- numpy FP64 forward/backward of the warm-start MLP.
 """
 from .oracle import (  # noqa: F401
-    build_oracle, solve, residuals, apply_Q, apply_A, apply_AT, power, sigma0,
+    build_oracle, solve, residuals, apply_Q, apply_Q_kron_factored, apply_A, apply_AT, power, sigma0,
     thetas, mnorm2, sigma_argmin, restart_test, alpha3_next, scaling, primal_step, primal_mnorm2, OracleResult, TERM_NAMES,
 )

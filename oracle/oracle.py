@@ -265,6 +265,23 @@ def apply_AT(qp, y):
     return _apply("orc_apply_AT", qp, y if qp.m else np.zeros(1), qp.n)
 
 
+def apply_Q_kron_factored(qp, x):
+    """The Kronecker operator of Section 4.5 through numpy matrix products:
+    Q vec(X) = vec(C X B^T) - vec(S X) - vec(X T^T), X the s x p matrix whose
+    columns are the consecutive blocks of x (vec stacks columns).  The same
+    definition as orc_apply_Q (pinned to it at small sizes); for sizes at
+    which the C oracle's plain loops take minutes per product (d = 2048)."""
+    B, Cm = np.asarray(qp.kron_B, dtype=np.float64), np.asarray(qp.kron_C, dtype=np.float64)
+    p, s = B.shape[0], Cm.shape[0]
+    X = np.asarray(x, dtype=np.float64).reshape(p, s).T
+    out = Cm @ X @ B.T
+    if getattr(qp, "kron_S", None) is not None:
+        out -= np.asarray(qp.kron_S, dtype=np.float64) @ X
+    if getattr(qp, "kron_T", None) is not None:
+        out -= X @ np.asarray(qp.kron_T, dtype=np.float64).T
+    return np.ascontiguousarray(out.T).ravel()
+
+
 def power(qp, which: str, start, maxit=5000, tol=1e-6):
     M = _Marshal(qp)
     s = np.ascontiguousarray(start, dtype=np.float64)

@@ -426,6 +426,37 @@ def rescale(qp: QP, seed: int, decades: float = 2.0) -> QP:
     return out
 
 
+def make_lasso_rows(seed: int = 1008, p: int = 200_000, q: int = 5_000_000, per_row: int = 1000,
+                    lam_frac: float = 0.2) -> QP:
+    """The random Lasso of make_lasso at the sizes of the paper's large random
+    Lasso table (p = 2e5 .. 6e5 rows, q = 5e6 .. 1e7 columns), built row by
+    row so that it fits in memory and time: every row of Ahat holds `per_row`
+    columns drawn uniformly (repeats dropped, so slightly fewer) with N(0, 1)
+    values; bhat, x_true and lambda as in make_lasso.  The paper does not
+    print the density; 1000 per row (2e8 nonzeros at p = 2e5) is what its
+    run times on the A100 allow (a denser Ahat would not fit its 80 GB)."""
+    rng = np.random.default_rng(seed)
+    cols = rng.integers(0, q, size=(p, per_row), dtype=np.int32)
+    cols.sort(axis=1)
+    keep = np.ones(cols.shape, dtype=bool)
+    keep[:, 1:] = cols[:, 1:] != cols[:, :-1]
+    rp = np.zeros(p + 1, dtype=np.int64)
+    np.cumsum(keep.sum(axis=1), out=rp[1:])
+    ci = cols[keep]
+    del cols, keep
+    vv = rng.standard_normal(ci.size)
+    Ah = sp.csr_matrix((vv, ci, rp.astype(np.int32)), shape=(p, q))
+    xt = np.where(rng.random(q) < 0.5, 0.0, rng.standard_normal(q) / np.sqrt(q))
+    bh = Ah @ xt + rng.standard_normal(p)
+    g = np.asarray(Ah.T @ bh).ravel()
+    return QP(n=q, m=0, qkind="gram", c=-g, L=np.full(q, -np.inf), U=np.full(q, np.inf),
+              a_rowptr=np.zeros(1, dtype=np.int32), a_col=np.zeros(0, dtype=np.int32),
+              a_val=np.zeros(0), l=np.zeros(0), u=np.zeros(0),
+              gram_rowptr=rp.astype(np.int32), gram_col=ci, gram_val=vv, gram_p=p,
+              l1_weight=lam_frac * np.abs(g).max(),
+              meta=dict(workload="lasso", seed=seed, p=p, q=q, per_row=per_row, bhat=bh))
+
+
 def make_lasso(seed: int = 1005, p: int = 200, q: int = 600, density: float = 0.15,
                lam_frac: float = 0.2) -> QP:
     """Lasso  min 1/2 ||Ahat x - bhat||^2 + lambda ||x||_1  (Section 4.4) as the

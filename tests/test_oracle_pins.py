@@ -44,6 +44,33 @@ def test_operators_match_scipy_and_kron():
     np.testing.assert_allclose(oracle.apply_Q(pq, xp), pq.Q_dense() @ xp, rtol=1e-12, atol=1e-14)
 
 
+def test_factored_kronecker_operator_matches_np_kron_and_the_c_oracle():
+    """oracle.apply_Q_kron_factored (numpy products, for the d = 2048 QAP
+    relaxation): against np.kron of the dense Q = B (x) C - I (x) S - T (x) I
+    (Section 4.5) with unsymmetric factors of different sizes, so that a
+    transposed factor or a wrong vec order shows, and against the C oracle's
+    orc_apply_Q on the QAP relaxation itself."""
+    rng = np.random.default_rng(17)
+    p, s = 5, 3
+    B, Cm = rng.standard_normal((p, p)), rng.standard_normal((s, s))
+    S, T = rng.standard_normal((s, s)), rng.standard_normal((p, p))
+    for withS, withT in ((False, False), (True, False), (False, True), (True, True)):
+        kq = qpgen.QP(n=p * s, m=0, qkind="kron", c=np.zeros(p * s), L=np.zeros(p * s), U=np.ones(p * s),
+                      a_rowptr=np.zeros(1, np.int32), a_col=np.zeros(0, np.int32), a_val=np.zeros(0),
+                      l=np.zeros(0), u=np.zeros(0), kron_B=B, kron_C=Cm,
+                      kron_S=S if withS else None, kron_T=T if withT else None)
+        Qd = np.kron(B, Cm) - (np.kron(np.eye(p), S) if withS else 0) - (np.kron(T, np.eye(s)) if withT else 0)
+        x = rng.standard_normal(p * s)
+        np.testing.assert_allclose(oracle.apply_Q_kron_factored(kq, x), Qd @ x, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(oracle.apply_Q_kron_factored(kq, x), oracle.apply_Q(kq, x), rtol=1e-12,
+                                   atol=1e-12)
+    for d in (7, 40):
+        qp = qpgen.make_qap(seed=50 + d, d=d)
+        x = rng.standard_normal(qp.n)
+        ref = oracle.apply_Q(qp, x)
+        assert np.max(np.abs(oracle.apply_Q_kron_factored(qp, x) - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
 # ---------------------------------------------------------------------------
 # Power method (Section 4.1, parameter setting)
 # ---------------------------------------------------------------------------

@@ -22,7 +22,9 @@
 #include "epilogues.hpp"
 #include "epilogues_primal.hpp"
 
+#ifndef HQ_SMALL_BS
 #define HQ_SMALL_BS 1024
+#endif
 #define HQ_SMALL_LDS (150 * 1024)
 
 struct SmallMat {

@@ -182,7 +182,7 @@ __device__ __forceinline__ void panel_fetch(const PanelMat& M, int rb, int p, in
 // see panel_launch_shape: one group per workgroup whenever the whole grid is
 // resident, since a late workgroup would gather from a panel the others have
 // left)
-template <class Epi, int BPB>
+template <class Epi, int BPB, bool GS = false>
 __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double* __restrict__ xin, Epi epi,
                                                         const DevParams* __restrict__ prm, int j, RedOut red) {
   constexpr int NR = Epi::NR;
@@ -195,7 +195,8 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
   for (int s = 0; s < (NR > 0 ? NR : 1); ++s) acc[s] = 0.0;
   const int nblk = (M.rows + HQ_BLOCK - 1) / HQ_BLOCK;
   const int t = threadIdx.x;
-  for (int g = blockIdx.x; g * BPB < nblk; g += gridDim.x) {
+  // one group of row blocks [g BPB, g BPB + BPB) of this workgroup
+  auto group = [&](const int g) {
     const int rb0 = g * BPB;
     double sum[BPB];
 #pragma unroll
@@ -270,6 +271,13 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
       const int rb = rb0 + q;
       if (rb < nblk && t < min(HQ_BLOCK, M.rows - rb * HQ_BLOCK)) e(rb * HQ_BLOCK + t, sum[q], acc);
     }
+  };
+  // GS: groups in grid-stride order (matrices too tall for one group per
+  // resident workgroup); else the one group blockIdx.x
+  if constexpr (GS) {
+    for (int g = blockIdx.x; g * BPB < nblk; g += gridDim.x) group(g);
+  } else {
+    if ((int)blockIdx.x * BPB < nblk) group(blockIdx.x);
   }
   if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
 }

@@ -406,7 +406,12 @@ void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, 
       case 1: k_csr_panel<Epi, 1><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
       case 2: k_csr_panel<Epi, 2><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
       case 3: k_csr_panel<Epi, 3><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
-      default: k_csr_panel<Epi, 4><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;
+      default:
+        if ((long long)sh.grid * 4 >= (M.rows + HQ_BLOCK - 1) / HQ_BLOCK)
+          k_csr_panel<Epi, 4><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red);
+        else   // more row blocks than 4 per resident workgroup: grid-stride groups
+          k_csr_panel<Epi, 4, true><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red);
+        break;
     }
     return;
   }

@@ -607,9 +607,9 @@ def main():
     ap.add_argument("--tol-time-limit", type=float, default=120.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the Kronecker, batch and warm-start workloads")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default SpMV kernel choice")
-    ap.add_argument("--calibrate-copy", action="store_true", default=True,
-                    help="run the library's streaming copy after the timed region (the default): the counter scale "
-                         "and the HBM rate plain streaming reaches")
+    ap.add_argument("--calibrate-copy", action="store_true", default=None,
+                    help="run the library's streaming copy after the timed region (the default for the random QP): "
+                         "the counter scale and the HBM rate plain streaming reaches")
     ap.add_argument("--no-calibrate-copy", dest="calibrate_copy", action="store_false")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--train-samples", type=int, default=50_000)
@@ -738,6 +738,8 @@ def main():
         log(f"cpu baseline: {cpu}")
     s.close()
     copy_cal = None
+    if args.calibrate_copy is None:
+        args.calibrate_copy = args.workload == "random_large"
     if args.calibrate_copy:
         copy_cal = calibrate_copy()
         log(f"calibration copy (hprqp_stream_copy): {copy_cal}")

@@ -996,8 +996,11 @@ int default_G(long long nnz, int rows, int maxlen, int cols) {
   const double avg = rows > 0 ? (double)nnz / rows : 1.0;
   (void)cols;
   if (avg <= 32.0 && maxlen <= 4096) return 0;
+  // up to one wave per row for rows of up to 4096 entries on average (the
+  // Kronecker QP's A, 300 per row: 64 lanes 7.5 us, 128 8.9 us, 256 9.3 us)
+  const int cap = avg <= 4096.0 ? 64 : HQ_BLOCK;
   int G = 1;
-  while (G < HQ_BLOCK && G * 2 <= avg) G *= 2;
+  while (G < cap && G * 2 <= avg) G *= 2;
   return G;
 }
 

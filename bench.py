@@ -122,10 +122,29 @@ def host_lambdas(qp):
     return max(lam_A, 0.0), max(lam_Q, 0.0)
 
 
-def cpu_baseline(qp, iters, budget_s=20.0):
+def host_cpu():
+    """The host the oracle runs on: CPU model, logical CPUs, and the CPUs this
+    process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return dict(model=model, logical_cpus=os.cpu_count(), usable_cpus=usable)
+
+
+def oracle_rate(qp, iters=200, budget_s=20.0):
     """The oracle as it stands, single thread, on the first `iters` iterations
     (fewer when two iterations show that `iters` would exceed `budget_s`), with
-    the lambda's of host_lambdas and its own sigma0 rule."""
+    the lambda's of host_lambdas and its own sigma0 rule: (iterations, seconds)."""
     import oracle
     lam_A, lam_Q = host_lambdas(qp)
     t0 = time.perf_counter()
@@ -134,9 +153,14 @@ def cpu_baseline(qp, iters, budget_s=20.0):
     iters = int(max(2, min(iters, budget_s / max(per_it, 1e-9))))
     t0 = time.perf_counter()
     r = oracle.solve(qp, tol=0.0, max_iter=iters, check_every=T_CHECK, lambda_A=lam_A, lambda_Q=lam_Q)
-    dt = time.perf_counter() - t0
-    return dict(value=r.iters / dt, unit="iterations/s", cores=1, kind="oracle",
-                sample=f"first {r.iters} iterations of the same instance (single-threaded FP64 C, "
+    return r.iters, time.perf_counter() - t0
+
+
+def cpu_baseline(qp, iters, budget_s=20.0):
+    """oracle_rate as the bench line's cpu_baseline, with the host it ran on."""
+    n, dt = oracle_rate(qp, iters, budget_s)
+    return dict(value=n / dt, unit="iterations/s", cores=1, kind="oracle", host=host_cpu(),
+                sample=f"first {n} iterations of the same instance (single-threaded FP64 C, "
                        f"lambda's from host-side bounds of the data), {dt:.1f} s")
 
 
@@ -175,11 +199,9 @@ def extra_kron(steps, cpu):
     out["time_to_1e-8"] = dict(term=rt.term, iterations=rt.iters, kkt=rt.kkt,
                                time_s=round(rt.t_setup_s + rt.t_solve_s, 4))
     if cpu:
-        import oracle
-        t0 = time.perf_counter()
-        la, lq = host_lambdas(qp)
-        ro = oracle.solve(qp, tol=0.0, max_iter=3, check_every=T_CHECK, lambda_A=la, lambda_Q=lq)
-        out["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
+        n_it, dt_o = oracle_rate(qp)
+        out["cpu_oracle_iterations_per_s"] = round(n_it / dt_o, 3)
+        out["cpu_oracle_sample"] = dict(iterations=n_it, seconds=round(dt_o, 2), cores=1, host=host_cpu())
     s.close()
     return out
 
@@ -221,11 +243,9 @@ def extra_qap(dims, steps, cpu, time_cap):
                                   time_s=round(rt.t_setup_s + rt.t_solve_s, 3), time_cap_s=time_cap,
                                   relaxation_bound=rt.pobj + float(qp.meta["s"].sum() + qp.meta["t"].sum())))
         if cpu and d <= 256:
-            import oracle
-            t0 = time.perf_counter()
-            la, lq = host_lambdas(qp)
-            ro = oracle.solve(qp, tol=0.0, max_iter=3, check_every=T_CHECK, lambda_A=la, lambda_Q=lq)
-            o["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
+            n_it, dt_o = oracle_rate(qp)
+            o["cpu_oracle_iterations_per_s"] = round(n_it / dt_o, 3)
+            o["cpu_oracle_sample"] = dict(iterations=n_it, seconds=round(dt_o, 2), cores=1)
         s.close()
         out[f"d{d}"] = o
         log(f"qap d={d}: {o}")
@@ -307,11 +327,9 @@ def extra_lasso(steps, cpu, p=10_000, q=500_000, per_row=0, time_cap=60.0):
                                time_s=round(rt.t_setup_s + rt.t_solve_s, 4), pobj=rt.pobj, time_cap_s=time_cap)
     s.close()
     if cpu:
-        import oracle
-        t0 = time.perf_counter()
-        la, lq = host_lambdas(qp)
-        ro = oracle.solve(qp, tol=0.0, max_iter=5, check_every=T_CHECK, lambda_A=la, lambda_Q=lq)
-        out["cpu_oracle_iterations_per_s"] = round(ro.iters / (time.perf_counter() - t0), 3)
+        n_it, dt_o = oracle_rate(qp)
+        out["cpu_oracle_iterations_per_s"] = round(n_it / dt_o, 3)
+        out["cpu_oracle_sample"] = dict(iterations=n_it, seconds=round(dt_o, 2), cores=1)
     return out
 
 
@@ -376,7 +394,7 @@ def extra_batch(count, cpu):
         tc = time.perf_counter() - t0
         cores = os.cpu_count() or 1
         out["cpu_oracle"] = dict(instances_per_s=round(len(sample) / tc, 2),
-                                 instance_iterations_per_s=round(its / tc, 1), cores=1,
+                                 instance_iterations_per_s=round(its / tc, 1), cores=1, host=host_cpu(),
                                  sample=f"{len(sample)} instances stratified by n, solved one after another",
                                  projected_all_cores=dict(instances_per_s=round(cores * len(sample) / tc, 1),
                                                           cores=cores, kind="projected (independent instances)"))
@@ -603,7 +621,7 @@ def main():
                     help="entries per row of Ahat (0: 1%% density), --workload lasso")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tol-solve", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--tol-time-limit", type=float, default=120.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the Kronecker, batch and warm-start workloads")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default SpMV kernel choice")

@@ -212,6 +212,42 @@ hprqp_status hprqp_create(const hprqp_problem *prob, const hprqp_options *opt,
 hprqp_status hprqp_solve(hprqp_handle *h, const double *y0, const double *w0, const double *x0,
                          double *y, double *z, double *w, double *x, hprqp_info *info);
 
+/* The state of Algorithm 4 at the start of an outer epoch (Algorithm 5:
+ * restart index r, the first inner iterate u^{r,0}, sigma_r, the total
+ * iteration count k at that point, and the restart-test state of
+ * Section 4.1: the merit at the first restart, which the sigma update and
+ * the alpha3 tightening compare against, and the current alpha3).  All
+ * other quantities of an epoch (anchors, A^T y, Q w, the merit at t = 0)
+ * are recomputed from these exactly, so a solve resumed from this state
+ * repeats the iterations that followed it bit for bit.  y (m), w, x (n)
+ * are DEVICE arrays owned by the caller, in the handle's internal
+ * variables (scaled when the handle is preconditioned), so the state is
+ * meant for a handle made from the same problem with the same create
+ * options. */
+typedef struct {
+  int64_t k;           /* iterations done before the epoch                         */
+  int32_t restarts;    /* r                                                        */
+  int32_t reserved;
+  double sigma;        /* sigma_r                                                  */
+  double R0ref;        /* merit at the first restart; negative before it           */
+  double alpha3;       /* current alpha3 of eq:restart_3                           */
+  double *y, *w, *x;   /* u^{r,0}: y (m), w, x (n)                                 */
+} hprqp_state;
+
+/* hprqp_solve (method 0 only; HPRQP_ERR_UNSUPPORTED otherwise) with
+ * checkpoint and resume.  resume (may be NULL: the origin as start, k = 0)
+ * starts the solve from a saved epoch start instead of a warm start; its
+ * k must be below options.max_iter, which counts the iterations of both
+ * solves together.  save (may be NULL) receives the state at the start of
+ * the last epoch of this solve (its arrays must be given).  A solve
+ * stopped by max_iter or the time limit and resumed from its saved state
+ * returns what one uninterrupted solve returns (the same iterates and
+ * info, apart from the timings), since it redoes the partial epoch from
+ * its start.  info->iters is the total k, restarts the total r; the check
+ * log of the resumed solve holds the checks after the saved k. */
+hprqp_status hprqp_solve_resume(hprqp_handle *h, const hprqp_state *resume, hprqp_state *save, double *y,
+                                double *z, double *w, double *x, hprqp_info *info);
+
 /* Replaces the per-solve options of a handle (tol, max_iter, time limit,
  * check_every, alpha's, restart/sigma switches, graph use, trace/log
  * buffers, kernel timing).  The setup-time choices made by hprqp_create

@@ -52,7 +52,13 @@ class hprqp_info(C.Structure):
                 ("t_precond_s", C.c_double), ("qwx_gap", C.c_double)]
 
 
-EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_residuals", "hprqp_residuals_noalloc",
+class hprqp_state(C.Structure):
+    _fields_ = [("k", C.c_int64), ("restarts", C.c_int32), ("reserved", C.c_int32), ("sigma", C.c_double),
+                ("R0ref", C.c_double), ("alpha3", C.c_double), ("y", C.c_void_p), ("w", C.c_void_p),
+                ("x", C.c_void_p)]
+
+
+EXPORTS = ("hprqp_default_options", "hprqp_create", "hprqp_solve", "hprqp_solve_resume", "hprqp_residuals", "hprqp_residuals_noalloc",
            "hprqp_apply",
            "hprqp_power_info", "hprqp_scaling", "hprqp_kernel_stats", "hprqp_set_options", "hprqp_destroy", "hprqp_batch_create", "hprqp_solve_batch",
            "hprqp_batch_last_kernel_s", "hprqp_batch_shapes", "hprqp_batch_set_priority", "hprqp_stream_copy", "hprqp_batch_destroy", "hprqp_last_error")
@@ -72,6 +78,9 @@ def load():
     lib.hprqp_default_options.restype = None
     lib.hprqp_create.argtypes = [C.POINTER(hprqp_problem), C.POINTER(hprqp_options), _vp, C.POINTER(_vp)]
     lib.hprqp_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(hprqp_info)]
+    lib.hprqp_solve_resume.argtypes = [_vp, C.POINTER(hprqp_state), C.POINTER(hprqp_state), _vp, _vp, _vp, _vp,
+                                       C.POINTER(hprqp_info)]
+    lib.hprqp_solve_resume.restype = C.c_int
     lib.hprqp_residuals.argtypes = [_vp, _vp, _vp, _vp, _vp, C.POINTER(hprqp_info)]
     lib.hprqp_residuals_noalloc.argtypes = [C.POINTER(hprqp_problem), _vp, _vp, _vp, _vp, C.POINTER(hprqp_info), _vp]
     lib.hprqp_apply.argtypes = [_vp, C.c_int32, _vp, _vp]

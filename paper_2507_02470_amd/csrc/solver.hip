@@ -1320,7 +1320,8 @@ void trace_row(hprqp_handle& h, double* row) {
 }
 
 void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const double* x0, double* yo, double* zo,
-                double* wo, double* xo, hprqp_info* info) {
+                double* wo, double* xo, hprqp_info* info, const hprqp_state* rs = nullptr,
+                hprqp_state* sv = nullptr) {
   const double tstart = now_s();
   if (h.own_st) HQC(hipDeviceSynchronize());   // inputs written on other streams
   for (int kind = 0; kind < 4; ++kind) { h.prof_ms[kind] = 0.0; h.prof_n[kind] = 0; }
@@ -1330,16 +1331,32 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
   const bool tracing = o.trace_iters > 0 && o.trace_host;
   if (!yo && m > 0) fail(HPRQP_ERR_ARG, "output y required");
   if (!zo || !wo || !xo) fail(HPRQP_ERR_ARG, "outputs z, w, x required");
-  // a warm start in the given variables enters scaled: y/E, w/D, x/D
-  if (m > 0) copy_or_zero(h, m, y0, h.y, h.pre ? h.iEs : nullptr);
-  copy_or_zero(h, n, w0, h.w, h.pre ? h.iDs : nullptr);
-  copy_or_zero(h, n, x0, h.x, h.pre ? h.iDs : nullptr);
+  if (sv && ((m > 0 && !sv->y) || !sv->w || !sv->x)) fail(HPRQP_ERR_ARG, "save: arrays y, w, x required");
   double sigma = h.sigma0;
-  write_params(h, sigma, 0);
-  reset_epoch(h);
   long long k = 0, t = 0;
   int r = 0, term = -1, nlog = 0;
   double alpha3 = o.alpha3, R0ref = -1.0, Rr0 = -1.0, Rprev = -1.0, R = 0.0;
+  if (rs) {
+    // an epoch start saved by an earlier solve, already in the internal variables
+    if ((m > 0 && !rs->y) || !rs->w || !rs->x) fail(HPRQP_ERR_ARG, "resume: arrays y, w, x required");
+    if (rs->k < 0 || rs->k >= o.max_iter) fail(HPRQP_ERR_ARG, "resume: k must lie in [0, max_iter)");
+    if (rs->restarts < 0 || !(rs->sigma > 0.0) || !std::isfinite(rs->sigma) || !(rs->alpha3 > 0.0) ||
+        !std::isfinite(rs->R0ref))
+      fail(HPRQP_ERR_ARG, "resume: restarts >= 0, finite sigma > 0, alpha3 > 0 and finite R0ref required");
+    if (m > 0) copy_or_zero(h, m, rs->y, h.y);
+    copy_or_zero(h, n, rs->w, h.w);
+    copy_or_zero(h, n, rs->x, h.x);
+    k = rs->k; r = rs->restarts; sigma = rs->sigma; alpha3 = rs->alpha3; R0ref = rs->R0ref;
+  } else {
+    // a warm start in the given variables enters scaled: y/E, w/D, x/D
+    if (m > 0) copy_or_zero(h, m, y0, h.y, h.pre ? h.iEs : nullptr);
+    copy_or_zero(h, n, w0, h.w, h.pre ? h.iDs : nullptr);
+    copy_or_zero(h, n, x0, h.x, h.pre ? h.iDs : nullptr);
+  }
+  write_params(h, sigma, 0);
+  reset_epoch(h);
+  // the state at the start of the current epoch (its point is the anchor ya, wa, xa)
+  hprqp_state ep{k, r, 0, sigma, R0ref, alpha3, nullptr, nullptr, nullptr};
   Resid res{};
   const int rowlen = 2 * m + 4 * n;
   long long seg = 0;
@@ -1429,6 +1446,7 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
       Rprev = -1.0;
       r += 1;
       restarted = 1;
+      ep = hprqp_state{k, r, 0, sigma, R0ref, alpha3, nullptr, nullptr, nullptr};
     }
     if (tracing && k <= o.trace_iters) trace_row(h, o.trace_host + (size_t)(k - 1) * rowlen);
     if (o.check_log_host && nlog < o.log_cap) {
@@ -1445,7 +1463,14 @@ void solve_impl(hprqp_handle& h, const double* y0, const double* w0, const doubl
   copy_or_zero(h, n, h.zbo, zo, h.pre ? h.iDs : nullptr);
   copy_or_zero(h, n, h.wbar, wo, h.pre ? h.Ds : nullptr);
   copy_or_zero(h, n, h.xbo, xo, h.pre ? h.Ds : nullptr);
+  if (sv) {
+    if (m > 0) copy_or_zero(h, m, h.ya, sv->y);
+    copy_or_zero(h, n, h.wa, sv->w);
+    copy_or_zero(h, n, h.xa, sv->x);
+    ep.y = sv->y; ep.w = sv->w; ep.x = sv->x;
+  }
   HQC(hipStreamSynchronize(h.st));
+  if (sv) *sv = ep;
   if (info) {
     const double tsolve = now_s() - tstart;
     info->term = term; info->iters = k; info->restarts = r; info->n_log = nlog;
@@ -2023,6 +2048,13 @@ hprqp_status hprqp_solve(hprqp_handle* h, const double* y0, const double* w0, co
   HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle");
            if (h->opt.method == 0) hq::solve_impl(*h, y0, w0, x0, y, z, w, x, info);
            else hq::solve_primal_impl(*h, y0, w0, x0, y, z, w, x, info));
+}
+
+hprqp_status hprqp_solve_resume(hprqp_handle* h, const hprqp_state* resume, hprqp_state* save, double* y, double* z,
+                                double* w, double* x, hprqp_info* info) {
+  HQ_GUARD(if (!h) hq::fail(HPRQP_ERR_ARG, "NULL handle");
+           if (h->opt.method != 0) hq::fail(HPRQP_ERR_UNSUPPORTED, "resume: method 0 (HPR-QP) only");
+           hq::solve_impl(*h, nullptr, nullptr, nullptr, y, z, w, x, info, resume, save));
 }
 
 hprqp_status hprqp_residuals(hprqp_handle* h, const double* y, const double* z, const double* w, const double* x,

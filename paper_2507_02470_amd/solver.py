@@ -132,10 +132,26 @@ class Result:
     qwx_gap: float = float("nan")
     trace: np.ndarray | None = None
     check_log: np.ndarray | None = None
+    state: "State | None" = None
 
     @property
     def kkt(self) -> float:
         return max(self.eta_p, self.eta_d, self.eta_gap)
+
+
+@dataclass
+class State:
+    """Start of the last epoch of a solve (restart index, first inner iterate
+    in the handle's internal variables, sigma, total iteration count and the
+    restart-test state): Solver.solve(resume=state) continues from it exactly."""
+    k: int
+    restarts: int
+    sigma: float
+    R0ref: float
+    alpha3: float
+    y: torch.Tensor
+    w: torch.Tensor
+    x: torch.Tensor
 
 
 class Solver:
@@ -190,15 +206,39 @@ class Solver:
         except Exception:
             pass
 
-    def solve(self, y0=None, w0=None, x0=None) -> Result:
+    def solve(self, y0=None, w0=None, x0=None, resume: State | None = None, checkpoint: bool = False) -> Result:
+        """Algorithm 4 from the warm start (y0, w0, x0), or from a saved
+        epoch start (resume); checkpoint=True also returns the start of the
+        last epoch as Result.state (HPR-QP, method 0)."""
         n, m = self.dp.n, self.dp.m
         f64 = dict(dtype=torch.float64, device=self.device)
         y = torch.empty(max(m, 1), **f64)
         z = torch.empty(n, **f64); w = torch.empty(n, **f64); x = torch.empty(n, **f64)
         info = N.hprqp_info()
-        ins = [None if a is None else torch.as_tensor(a, **f64).contiguous() for a in (y0, w0, x0)]
-        N.check(self.lib.hprqp_solve(self.h, _ptr(ins[0]), _ptr(ins[1]), _ptr(ins[2]), _ptr(y), _ptr(z),
-                                     _ptr(w), _ptr(x), C.byref(info)))
+        state = None
+        if resume is None and not checkpoint:
+            ins = [None if a is None else torch.as_tensor(a, **f64).contiguous() for a in (y0, w0, x0)]
+            N.check(self.lib.hprqp_solve(self.h, _ptr(ins[0]), _ptr(ins[1]), _ptr(ins[2]), _ptr(y), _ptr(z),
+                                         _ptr(w), _ptr(x), C.byref(info)))
+        else:
+            if any(a is not None for a in (y0, w0, x0)):
+                raise ValueError("a solve with resume or checkpoint starts from the origin or the resumed state")
+            rs = None
+            if resume is not None:
+                held = [torch.as_tensor(a, **f64).contiguous() for a in (resume.y, resume.w, resume.x)]
+                rs = N.hprqp_state(k=resume.k, restarts=resume.restarts, sigma=resume.sigma, R0ref=resume.R0ref,
+                                   alpha3=resume.alpha3, y=_ptr(held[0]) if m else None, w=_ptr(held[1]),
+                                   x=_ptr(held[2]))
+            sv = None
+            if checkpoint:
+                sy = torch.empty(max(m, 1), **f64); sw = torch.empty(n, **f64); sx = torch.empty(n, **f64)
+                sv = N.hprqp_state(y=_ptr(sy), w=_ptr(sw), x=_ptr(sx))
+            N.check(self.lib.hprqp_solve_resume(self.h, None if rs is None else C.byref(rs),
+                                                None if sv is None else C.byref(sv), _ptr(y), _ptr(z), _ptr(w),
+                                                _ptr(x), C.byref(info)))
+            if checkpoint:
+                state = State(k=int(sv.k), restarts=int(sv.restarts), sigma=sv.sigma, R0ref=sv.R0ref,
+                              alpha3=sv.alpha3, y=sy[:m], w=sw, x=sx)
         return Result(y=y[:m], z=z, w=w, x=x, term=N.TERM[info.term], iters=int(info.iters),
                       restarts=int(info.restarts), sigma=info.sigma, sigma0=info.sigma0,
                       lambda_A=info.lambda_A, lambda_Q=info.lambda_Q, eta_p=info.eta_p, eta_d=info.eta_d,
@@ -206,7 +246,7 @@ class Solver:
                       t_setup_s=info.t_setup_s, t_solve_s=info.t_solve_s, t_precond_s=info.t_precond_s,
                       qwx_gap=info.qwx_gap,
                       trace=None if self.trace is None else self.trace.copy(),
-                      check_log=None if self.log is None else self.log[:info.n_log].copy())
+                      check_log=None if self.log is None else self.log[:info.n_log].copy(), state=state)
 
     def residuals(self, y, z, x, w=None) -> dict:
         f64 = dict(dtype=torch.float64, device=self.device)

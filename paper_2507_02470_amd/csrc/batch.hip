@@ -128,6 +128,7 @@ struct BShared {
   int np;
   double ctrl[8];
   int inst;
+  BOpts opt;                         // the options, for the out-of-line check decision
 };
 
 // DPP move of a double (both 32-bit halves with the same control); lanes
@@ -445,10 +446,13 @@ __device__ __forceinline__ void halpern(BShared<BS>& S, int i, double rho, bool 
 // line: it runs once per check and its golden section needs registers the
 // iteration does not.
 template <int BS>
-__device__ __noinline__ void check_decision(BShared<BS>& S, const BOpts& o, double eta_p, double eta_d, double eta_gap,
+__device__ __noinline__ void check_decision(BShared<BS>& S, double eta_p, double eta_d, double eta_gap,
                                             double R, double Rr0, double Rprev, long long t, long long k, double lamA,
                                             double lamQ, double thy, double thw, double thq, double th2, double th3,
                                             double sigma, double alpha3, double R0ref) {
+  // (read from the LDS copy: a reference to the kernel argument itself would
+  // make the compiler keep a copy of it in scratch memory)
+  const BOpts& o = S.opt;
   const double kkt = fmax(eta_p, fmax(eta_d, eta_gap));
   int tm = -1, rs = 0;
   if (isnan(kkt) || isnan(R)) tm = HPRQP_NUMERICAL;
@@ -493,6 +497,7 @@ __global__ __launch_bounds__(BS, BCfg<BS>::MIN_BLOCKS) void k_batch_solve(const 
   __shared__ BShared<BS> S;
   const int tid = threadIdx.x;
   int par = 0;
+  if (tid == 0) S.opt = o;   // read after the queue's barriers below
   // the block's check buffer: xbar, wbar, Q wbar, A^T ybar, zbar (entries owned per thread)
   double* const Hx = hbuf + (size_t)blockIdx.x * 5 * NM;
   double* const Hw = Hx + NM;
@@ -790,7 +795,7 @@ __global__ __launch_bounds__(BS, BCfg<BS>::MIN_BLOCKS) void k_batch_solve(const 
       }
       // decisions (thread 0, FP64), broadcast through LDS
       if (tid == 0)
-        check_decision(S, o, eta_p, eta_d, eta_gap, R, Rr0, Rprev, t, k, lamA, lamQ, th[0], th[1], th[2], th[3], th[4],
+        check_decision(S, eta_p, eta_d, eta_gap, R, Rr0, Rprev, t, k, lamA, lamQ, th[0], th[1], th[2], th[3], th[4],
                        sigma, alpha3, R0ref);
       __syncthreads();
       term = (int)S.ctrl[0];

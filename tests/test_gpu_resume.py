@@ -35,6 +35,8 @@ CASES = {
     "small_ccqp": (lambda: qpgen.make_small_ccqp(), {}),
     # the multi-kernel path on a preconditioned handle (state in scaled variables)
     "random_precond": (lambda: qpgen.make_random_large(seed=1011, n=20_000, m=10_000), dict(precondition=1)),
+    # m = 0 (no y in the state) with the matrix-free Gram Q and phi = lambda ||x||_1
+    "lasso_m0": (lambda: qpgen.make_lasso(seed=1012, p=300, q=900), {}),
 }
 
 
@@ -118,3 +120,24 @@ def test_resume_rejects_bad_states():
     with pytest.raises(HPRQPError, match="method 0"):
         p.solve(checkpoint=True)
     p.close()
+
+
+def test_resume_after_a_time_limit():
+    """A solve stopped by the time limit at its first check, resumed without
+    one, ends where the uninterrupted solve ends."""
+    DP, Solver = _S()
+    qp = qpgen.make_small_ccqp()
+    dp = DP(qp)
+    s = Solver(dp, tol=1e-8, max_iter=400_000)
+    full = s.solve()
+    assert full.term == "solved" and full.restarts >= 1
+    s.set_options(time_limit_s=1e-9)
+    part = s.solve(checkpoint=True)
+    assert part.term == "time_limit" and part.iters == 100
+    assert part.state.k == 0 and part.state.restarts == 0      # still in the first epoch
+    s.set_options(time_limit_s=0.0)
+    res = s.solve(resume=part.state)
+    assert res.term == full.term and res.iters == full.iters and res.restarts == full.restarts
+    for a, b in ((res.y, full.y), (res.z, full.z), (res.w, full.w), (res.x, full.x)):
+        assert _same(a, b)
+    s.close()

@@ -239,7 +239,8 @@ typedef struct {
  * starts the solve from a saved epoch start instead of a warm start; its
  * k must be below options.max_iter, which counts the iterations of both
  * solves together.  save (may be NULL) receives the state at the start of
- * the last epoch of this solve (its arrays must be given).  A solve
+ * the last epoch of this solve (its arrays must be given; they may be those
+ * of resume, for a checkpoint kept in place, but not the output arrays).  A solve
  * stopped by max_iter or the time limit and resumed from its saved state
  * returns what one uninterrupted solve returns (the same iterates and
  * info, apart from the timings), since it redoes the partial epoch from

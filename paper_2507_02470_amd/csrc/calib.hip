@@ -57,8 +57,10 @@ extern "C" hprqp_status hprqp_stream_copy(const double* src, double* dst, int64_
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return calib_fail(HPRQP_ERR_HIP, "no device");
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ms_host && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+  if (ms_host && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+    if (e0) hipEventDestroy(e0);
     return calib_fail(HPRQP_ERR_HIP, "hipEventCreate failed");
+  }
   if (e0) hipEventRecord(e0, stream);
   if (n > 0) {
     const bool vec = ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);

@@ -62,7 +62,7 @@ def kernel_bytes(qp) -> dict:
 # sources of the single-instance solver's kernels and launches (the batched
 # solver and the MLP do not enter the dominant kernel)
 SOLVER_SOURCES = ("common.hpp", "spmv.hpp", "epilogues.hpp", "epilogues_primal.hpp", "qops.hpp", "small.hpp",
-                  "panel.hpp", "solver.hip")
+                  "panel.hpp", "split.hpp", "solver.hip")
 
 
 def src_hash() -> str:

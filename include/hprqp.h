@@ -136,7 +136,9 @@ typedef struct {
                                  the same order by a persistent grid; an extra copy of the
                                  matrix; rows of at most 4096 nonzeros, else the default);
                                  1, 2, 4, ..., 256: that many lanes per row, for every
-                                 matrix; -1                                               */
+                                 matrix; -100 - g (g = 1, 2, 4, ..., 64): g lanes per row
+                                 gathering from an LDS copy of the input vector (at most
+                                 14336 columns, else g lanes from memory); -1             */
   int32_t method;             /* 0: HPR-QP (Algorithm 4 on the restricted Wolfe dual).
                                  1, 2: HPR applied to the primal reformulations of
                                  Appendix A, the baselines of Table 1: 1 = Algorithm 6 on
@@ -304,7 +306,10 @@ hprqp_status hprqp_scaling(hprqp_handle *h, double *D, double *E);
  * launches of product i, i = 0: Q xhat (with its epilogue), 1: A v, 2: A^T ybar,
  * 3: Q A^T(ybar - y) with the Halpern epilogue (methods 1, 2: 0 = Q x or Q v,
  * 1 = A x, 2 = A^T(2 ybar - y), 3 unused).  Also reports the
- * lanes-per-row choice of A, A^T and Q (g_host[3], may be NULL). */
+ * kernel choice of A, A^T and Q (g_host[3], may be NULL): g > 0 lanes per row,
+ * 0 the CSR-stream kernel, -1 its variant gathering from LDS, -3 the
+ * panel-ordered product, -100 - g the row-split kernel with g lanes gathering
+ * from LDS. */
 hprqp_status hprqp_kernel_stats(hprqp_handle *h, double *avg_ms_host, int64_t *launches_host, int32_t *g_host);
 
 void hprqp_destroy(hprqp_handle *h);

@@ -149,6 +149,7 @@ __device__ __forceinline__ double neg_conj_phi(double z, double lam, double L, d
 // vector being gathered from L2
 __device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ int ld_stream(const int* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ unsigned short ld_stream(const unsigned short* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
 static inline int hq_grid(long long work, int per_block) {

@@ -18,6 +18,7 @@
 #include "spmv.hpp"
 #include "precond.hpp"
 #include "panel.hpp"
+#include "split.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -238,6 +239,7 @@ struct Mat {
   int maxlen = -1;    // longest row (-1: not measured)
   PanelMat pm;        // panel-ordered copy (pm.pp == nullptr: not built)
   int G_np = 0;       // kernel used in place of the panel-ordered one under a heavy epilogue
+  SplitMat sm;        // column-split copy (sm.off == nullptr: not built)
 };
 
 #define HQ_PROF_ITERS 64
@@ -364,6 +366,54 @@ inline void check_red_grid(long long grid, const RedOut& red) {
 #define HQ_G_XLDS (-1)
 // Lanes-per-row code of the panel-ordered product (Mat::pm built).
 #define HQ_G_PANEL (-3)
+// Lanes-per-row codes HQ_G_XROW - g: the row-split kernel with g <= 64 lanes
+// per row gathering from an LDS copy of the vector (k_csr_xrow).
+#define HQ_G_XROW (-100)
+inline bool is_xrow(int G) { return G < HQ_G_XROW; }
+// Lanes-per-row code of the column-split product (Mat::sm built).
+#define HQ_G_SPLIT (-4)
+
+template <class Epi>
+void launch_split(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
+  const SplitMat& S = M.sm;
+  k_split_partial<<<S.np * S.nrb, HQ_BLOCK, 0, h.st>>>(S, x);
+  const int rgrid = (S.rows + HQ_SPLIT_RED_ROWS - 1) / HQ_SPLIT_RED_ROWS;
+  check_red_grid(rgrid, red);
+  k_split_reduce<Epi><<<rgrid, 4 * HQ_SPLIT_RED_ROWS, 0, h.st>>>(S.rows, S.np, S.partial, epi, h.dprm, j, red);
+}
+
+template <int G, class Epi>
+void launch_xrow_g(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
+  constexpr int BS = HQ_XLDS_BLOCK;
+  static bool attr_set = false;   // one per instantiation: dynamic LDS above 64 KB must be enabled
+  if (!attr_set) {
+    HQC(hipFuncSetAttribute((const void*)k_csr_xrow<G, Epi>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(HQ_XLDS_MAX * sizeof(double))));
+    attr_set = true;
+  }
+  const size_t lds = (size_t)M.cols * sizeof(double);
+  // persistent grid: as many blocks as fit on the CUs at this LDS size
+  const size_t per_block = lds + 16 * 16 * sizeof(double) + 2048;
+  const int per_cu = std::max(1, (int)((160 * 1024) / per_block));
+  const long long groups = ((long long)M.rows + BS / G - 1) / (BS / G);
+  const int grid = (int)std::max(1ll, std::min(groups, (long long)std::min(h.ncu * per_cu, HQ_GRID_CAP)));
+  check_red_grid(grid, red);
+  k_csr_xrow<G, Epi><<<grid, BS, lds, h.st>>>(M.rows, M.rp, M.ci, M.v, x, epi, h.dprm, j, red, M.cols);
+}
+
+template <class Epi>
+void launch_csr_xrow(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
+  if (M.cols > HQ_XLDS_MAX) fail(HPRQP_ERR_UNSUPPORTED, "LDS-gather kernel: vector too long");
+  switch (HQ_G_XROW - M.G) {
+    case 1: launch_xrow_g<1>(h, M, x, epi, j, red); break;
+    case 2: launch_xrow_g<2>(h, M, x, epi, j, red); break;
+    case 4: launch_xrow_g<4>(h, M, x, epi, j, red); break;
+    case 8: launch_xrow_g<8>(h, M, x, epi, j, red); break;
+    case 16: launch_xrow_g<16>(h, M, x, epi, j, red); break;
+    case 32: launch_xrow_g<32>(h, M, x, epi, j, red); break;
+    default: launch_xrow_g<64>(h, M, x, epi, j, red); break;
+  }
+}
 
 template <class Epi>
 void launch_csr_xlds(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
@@ -387,6 +437,8 @@ void launch_csr_xlds(hprqp_handle& h, const Mat& M, const double* x, const Epi& 
 template <class Epi>
 void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
   if (M.G == HQ_G_XLDS) { launch_csr_xlds(h, M, x, epi, j, red); return; }
+  if (is_xrow(M.G)) { launch_csr_xrow(h, M, x, epi, j, red); return; }
+  if (M.G == HQ_G_SPLIT) { launch_split(h, M, x, epi, j, red); return; }
   if (M.G == HQ_G_PANEL) {
     // row blocks per workgroup: the fewest for which the whole grid is
     // resident, by the occupancy of the instantiation that would run (the
@@ -875,9 +927,47 @@ bool build_panel(hprqp_handle& h, Mat& M, bool any_size = false) {
   return true;
 }
 
+// Column-split copy of M (split.hpp); false when the matrix does not have the
+// shape it serves: a vector too long for LDS, and rows long enough that the
+// per-(panel, row) starts and partial sums stay small beside the matrix (at
+// least 8 nonzeros per row and panel on average)
+bool build_split(hprqp_handle& h, Mat& M) {
+  if (M.sm.off) return true;
+  if (M.rows == 0 || M.nnz == 0 || M.cols <= HQ_XLDS_MAX) return false;
+  const long long np = (M.cols + HQ_SPLIT_PW - 1) / HQ_SPLIT_PW;
+  const long long cells = np * M.rows;
+  if (cells * 8 > M.nnz || cells + 1 >= (1ll << 31)) return false;
+  int* cnt = nullptr;
+  HQC(hipMalloc(&cnt, sizeof(int) * (size_t)cells));
+  HQC(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)cells, h.st));   // (setup, never captured)
+  k_split_count<<<hq_grid(M.rows, 256), 256, 0, h.st>>>(M.rows, M.rp, M.ci, cnt);
+  std::vector<int> hc((size_t)cells), ho((size_t)cells + 1, 0);
+  HQC(hipMemcpyAsync(hc.data(), cnt, sizeof(int) * (size_t)cells, hipMemcpyDeviceToHost, h.st));
+  HQC(hipStreamSynchronize(h.st));
+  for (long long c = 0; c < cells; ++c) ho[c + 1] = ho[c] + hc[c];
+  if (ho[cells] != M.nnz) { hipFree(cnt); fail(HPRQP_ERR_HIP, "column-split layout: nonzero count mismatch"); }
+  int* off = h.dalloc<int>((size_t)cells + 1);
+  unsigned short* lci = h.dalloc<unsigned short>((size_t)M.nnz);
+  double* sv = h.dalloc<double>((size_t)M.nnz);
+  double* part = h.dalloc<double>((size_t)cells);
+  HQC(hipMemcpyAsync(off, ho.data(), sizeof(int) * ((size_t)cells + 1), hipMemcpyHostToDevice, h.st));
+  HQC(hipMemcpyAsync(cnt, ho.data(), sizeof(int) * (size_t)cells, hipMemcpyHostToDevice, h.st));   // cursors
+  k_split_scatter<<<hq_grid(M.rows, 256), 256, 0, h.st>>>(M.rows, M.rp, M.ci, M.v, cnt, lci, sv);
+  HQC(hipStreamSynchronize(h.st));
+  hipFree(cnt);
+  SplitMat S;
+  S.rows = M.rows; S.cols = M.cols; S.np = (int)np;
+  S.off = off; S.lci = lci; S.v = sv; S.partial = part;
+  S.nrb = (M.rows + HQ_SPLIT_ROWS - 1) / HQ_SPLIT_ROWS;
+  if ((long long)S.np * S.nrb >= (1ll << 31)) return false;
+  M.sm = S;
+  return true;
+}
+
 void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   if (M.rows == 0 || M.nnz == 0) return;
-  const int Gs[] = {0, HQ_G_XLDS, HQ_G_PANEL, 2, 4, 8, 16, 32, 64, 128, 256};
+  const int Gs[] = {0, HQ_G_XLDS, HQ_G_PANEL, HQ_G_SPLIT, 2, 4, 8, 16, 32, 64, 128, 256,
+                    HQ_G_XROW - 2, HQ_G_XROW - 4, HQ_G_XROW - 8, HQ_G_XROW - 16, HQ_G_XROW - 32, HQ_G_XROW - 64};
   hipEvent_t e0, e1;
   HQC(hipEventCreate(&e0));
   HQC(hipEventCreate(&e1));
@@ -889,10 +979,13 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
   for (int G : Gs) {
     // the CSR-stream kernels add a row serially: not candidates for very long rows
     if ((G == 0 || G == HQ_G_XLDS) && M.maxlen > 4096 && G0 != 0) continue;
-    if (G == HQ_G_XLDS && M.cols > HQ_XLDS_MAX) continue;
+    if ((G == HQ_G_XLDS || is_xrow(G)) && M.cols > HQ_XLDS_MAX) continue;
+    const int lanes = is_xrow(G) ? HQ_G_XROW - G : G;   // lanes per row of a row-split kernel
     if (G == HQ_G_PANEL && (M.maxlen > 4096 || !build_panel(h, M))) continue;
+    if (G == HQ_G_SPLIT && !build_split(h, M)) continue;
     // row-split groups much wider than the rows only idle their lanes: skip them
-    if (G > 1 && M.maxlen >= 0 && M.maxlen <= 4096 && (double)G > 4.0 * ((double)M.nnz / M.rows) && G > 8)
+    if (lanes > 1 && M.maxlen >= 0 && M.maxlen <= 4096 && (double)lanes > 4.0 * ((double)M.nnz / M.rows) &&
+        lanes > 8)
       continue;
     M.G = G;
     launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
@@ -904,7 +997,7 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
     HQC(hipEventElapsedTime(&ms, e0, e1));
     if (G == G0) t_default = ms;
     if (ms < best) { best = ms; bestG = G; }
-    if (G != HQ_G_PANEL && ms < best_np) { best_np = ms; bestG_np = G; }
+    if (G != HQ_G_PANEL && G != HQ_G_SPLIT && ms < best_np) { best_np = ms; bestG_np = G; }
   }
   M.G = best < 0.95f * t_default ? bestG : G0;
   M.G_np = best_np < 0.95f * t_default ? bestG_np : G0;
@@ -1183,6 +1276,21 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       M.G = default_G(M.nnz, M.rows, mx, M.cols);
       M.G_np = M.G;
       M.maxlen = mx;
+      if (M.G > 0 && M.cols <= HQ_XLDS_MAX && M.rows >= 65536) {
+        // many long rows over a vector that fits LDS: the row-split kernel
+        // gathering from LDS, about six nonzeros per lane (the Lasso's
+        // Ahat^T, 100 per row: 173 us with 16 lanes against 350 us through
+        // the L2 and 250 us with 64 lanes from LDS)
+        const double avg = (double)M.nnz / M.rows;
+        int g = 1;
+        while (g < HQ_WAVE && 6.0 * 2 * g <= avg) g *= 2;
+        M.G = HQ_G_XROW - g;
+        M.G_np = M.G;
+      } else if (M.G > 0 && build_split(h, M)) {
+        // few long rows over a vector too long for LDS: the column-split
+        // product (the Lasso's Ahat, 5000 per row: 145 us against 326 us)
+        M.G = HQ_G_SPLIT;
+      }
       // short rows gathering from a vector larger than three quarters of an
       // XCD's 4 MiB L2 (which the matrix streams through as well): the
       // panel-ordered product, also under heavy epilogues (measured on 5e6
@@ -1239,21 +1347,46 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
       h.kron_mode = kk == 0 ? 0 : 1;
       h.kron_groups = kk == 0 ? 1 : kk;
     }
-    if (opt->spmv_lanes == -3) {
+    if (opt->spmv_lanes == HQ_G_SPLIT) {
+      // the column-split product wherever its layout applies, else the default kernel
+      for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT})
+        if (build_split(h, *M)) { M->G_np = M->G; M->G = HQ_G_SPLIT; }
+    } else if (opt->spmv_lanes == -3) {
       // panel-ordered products wherever the layout applies, else the default kernel
       for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT})
         if (M->rows > 0 && M->maxlen <= 4096 && build_panel(h, *M, true)) { M->G_np = M->G; M->G = HQ_G_PANEL; }
     } else if (opt->spmv_lanes >= 0 || opt->spmv_lanes == -2) {
       const int g = opt->spmv_lanes == -2 ? HQ_G_XLDS : opt->spmv_lanes;
       if (g != HQ_G_XLDS && (g > HQ_BLOCK || (g & (g - 1)) != 0))
-        fail(HPRQP_ERR_ARG, "spmv_lanes must be -3, -2, -1, 0 or a power of 2 <= 256");
+        fail(HPRQP_ERR_ARG, "spmv_lanes must be -4, -3, -2, -1, 0, a power of 2 <= 256 or -100 - g (g <= 64)");
       for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT}) {
         M->G = (g == HQ_G_XLDS && M->cols > HQ_XLDS_MAX) ? 0 : g;   // the LDS copy needs a small vector
         M->G_np = M->G;
       }
+    } else if (opt->spmv_lanes < HQ_G_XROW) {
+      const int g = HQ_G_XROW - opt->spmv_lanes;
+      if (g > HQ_WAVE || (g & (g - 1)) != 0)
+        fail(HPRQP_ERR_ARG, "spmv_lanes below -100 must be -100 - g with g a power of 2 <= 64");
+      for (Mat* M : {&h.A, &h.AT, &h.Q, &h.G, &h.GT}) {
+        // the LDS copy needs a small vector: the row-split kernel with g lanes otherwise
+        M->G = M->cols > HQ_XLDS_MAX ? g : opt->spmv_lanes;
+        M->G_np = M->G;
+      }
     } else if (opt->spmv_lanes != -1) {
-      fail(HPRQP_ERR_ARG, "spmv_lanes must be -3, -2, -1, 0 or a power of 2 <= 256");
+      fail(HPRQP_ERR_ARG, "spmv_lanes must be -4, -3, -2, -1, 0, a power of 2 <= 256 or -100 - g (g <= 64)");
     }
+    // the operators as given (hprqp_apply, and the residuals of a preconditioned
+    // handle) take the kernel chosen for the method's copy: the same arrays
+    // without preconditioning; with it the unscaled arrays have the same
+    // structure, but the panel-ordered copy holds scaled values
+    auto inherit = [&](Mat& M0, const Mat& M) {
+      if (!h.pre) { M0 = M; return; }
+      const auto layout = [](int G) { return G == HQ_G_PANEL || G == HQ_G_SPLIT; };
+      M0.maxlen = M.maxlen;
+      M0.G = layout(M.G) ? (layout(M.G_np) ? 0 : M.G_np) : M.G;
+      M0.G_np = M0.G;
+    };
+    inherit(h.A0, h.A); inherit(h.AT0, h.AT); inherit(h.Q0, h.Q);
     if (opt->lambda_A > 0) h.lamA = opt->lambda_A;
     else if (m > 0) {
       h.powA_est = power_method(h, 0, opt->power_start_A, 5000, 1e-6, &h.powA_it);

@@ -1,0 +1,158 @@
+// split.hpp -- column-split CSR products for matrices with few, long rows
+// over a vector too large for LDS (the Lasso's Ahat: p rows of thousands of
+// nonzeros, q >> p columns).
+//
+// A row-split kernel gathers every nonzero's x entry through the L2 at the
+// rate of its random 8-byte requests.  Here the columns are cut into panels
+// of HQ_SPLIT_PW columns and the matrix is stored panel by panel, each panel
+// a CSR over all rows (rows in order, a row's entries in their CSR order,
+// columns as 16-bit offsets into the panel).  A workgroup owns one panel and a
+// block of rows: it copies the panel's slice of x into LDS once, gathers from
+// there, and writes one partial sum per row and panel; a second kernel adds a
+// row's partials in panel order (four fixed segments, combined in a fixed
+// order) and runs the epilogue.  Deterministic: inside a panel a row's
+// entries are added in CSR order, then the panels' sums as stated.
+#pragma once
+#include "common.hpp"
+
+#define HQ_SPLIT_PW 2048        // columns per panel (16 KB of LDS)
+#define HQ_SPLIT_RED_ROWS 64    // rows per workgroup of the reduction
+
+struct SplitMat {
+  int rows = 0, cols = 0;
+  int np = 0;                        // panels
+  int nrb = 0;                       // row blocks (of HQ_SPLIT_ROWS rows) per panel
+  const int* off = nullptr;          // np * rows + 1 starts: panel p, row r at off[p * rows + r]
+  const unsigned short* lci = nullptr;   // column - p * HQ_SPLIT_PW
+  const double* v = nullptr;
+  double* partial = nullptr;         // np * rows partial sums
+};
+
+// The layout is built by two per-row steps, run by one thread per row on the
+// device and by the host layout test on the CPU.
+//
+// Step 1, row r: how many of its nonzeros fall in each panel,
+// cnt[p * rows + r] (zeroed beforehand).  Consecutive entries of one panel
+// are counted together.
+__host__ __device__ inline void split_count_row(int r, int rows, const int* rp, const int* ci, int* cnt) {
+  int p = -1, run = 0;
+  for (int k = rp[r]; k < rp[r + 1]; ++k) {
+    const int q = ci[k] / HQ_SPLIT_PW;
+    if (q != p) {
+      if (run) cnt[(size_t)p * rows + r] += run;
+      p = q;
+      run = 0;
+    }
+    ++run;
+  }
+  if (run) cnt[(size_t)p * rows + r] += run;
+}
+
+// Step 2, row r: its entries into their panels in CSR order; cur holds the
+// next free position of every (panel, row), initialised to the starts off.
+__host__ __device__ inline void split_scatter_row(int r, int rows, const int* rp, const int* ci, const double* v,
+                                                  int* cur, unsigned short* lci, double* sv) {
+  int p = -1, pos = 0;
+  for (int k = rp[r]; k < rp[r + 1]; ++k) {
+    const int q = ci[k] / HQ_SPLIT_PW;
+    if (q != p) {
+      if (p >= 0) cur[(size_t)p * rows + r] = pos;
+      p = q;
+      pos = cur[(size_t)p * rows + r];
+    }
+    lci[pos] = (unsigned short)(ci[k] - q * HQ_SPLIT_PW);
+    sv[pos] = v[k];
+    ++pos;
+  }
+  if (p >= 0) cur[(size_t)p * rows + r] = pos;
+}
+
+__global__ void k_split_count(int rows, const int* __restrict__ rp, const int* __restrict__ ci, int* cnt) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x)
+    split_count_row(r, rows, rp, ci, cnt);
+}
+
+__global__ void k_split_scatter(int rows, const int* __restrict__ rp, const int* __restrict__ ci,
+                                const double* __restrict__ v, int* cur, unsigned short* lci, double* sv) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x)
+    split_scatter_row(r, rows, rp, ci, v, cur, lci, sv);
+}
+
+// Partial sums: workgroup b takes panel b % np and the HQ_SPLIT_ROWS rows of
+// row block b / np.  Inside a panel the rows are short (tens of nonzeros), so
+// the block's entries -- one contiguous range of the layout -- are streamed
+// as by the CSR-stream kernel: coalesced loads, products staged in LDS, then
+// every thread adds up its rows' products in order (RPT rows per thread).
+#define HQ_SPLIT_RPT 4
+#define HQ_SPLIT_ROWS (HQ_BLOCK * HQ_SPLIT_RPT)
+__global__ __launch_bounds__(HQ_BLOCK) void k_split_partial(SplitMat S, const double* __restrict__ x) {
+  constexpr int CH = 2048;   // products staged per step
+  __shared__ double xs[HQ_SPLIT_PW];
+  __shared__ double prod[CH];
+  __shared__ int srp[HQ_SPLIT_ROWS + 1];
+  const int t = threadIdx.x;
+  const int p = blockIdx.x % S.np, rb = blockIdx.x / S.np;
+  const int cx = p * HQ_SPLIT_PW, nc = min(HQ_SPLIT_PW, S.cols - cx);
+  for (int i = t; i < nc; i += HQ_BLOCK) xs[i] = x[cx + i];
+  const int r0 = rb * HQ_SPLIT_ROWS, nr = min(HQ_SPLIT_ROWS, S.rows - r0);
+  // (row r0 + nr ends at the next row's start, or at the next panel's first)
+  const int* __restrict__ offp = S.off + (size_t)p * S.rows + r0;
+  for (int i = t; i <= nr; i += HQ_BLOCK) srp[i] = offp[i];
+  __syncthreads();
+  const int kb = srp[0], ke = srp[nr];
+  double sum[HQ_SPLIT_RPT];
+#pragma unroll
+  for (int q = 0; q < HQ_SPLIT_RPT; ++q) sum[q] = 0.0;
+  for (int c0 = kb; c0 < ke; c0 += CH) {   // same trip count in every thread
+    const int c1 = min(ke, c0 + CH);
+#pragma unroll 8
+    for (int k = c0 + t; k < c1; k += HQ_BLOCK) prod[k - c0] = ld_stream(S.v + k) * xs[ld_stream(S.lci + k)];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < HQ_SPLIT_RPT; ++q) {
+      const int i = t + q * HQ_BLOCK;
+      if (i < nr) {
+        const int lo = max(srp[i], c0), hi = min(srp[i + 1], c1);
+        for (int k = lo; k < hi; ++k) sum[q] += prod[k - c0];
+      }
+    }
+    __syncthreads();   // prod is rewritten by the next step
+  }
+  double* __restrict__ part = S.partial + (size_t)p * S.rows + r0;
+#pragma unroll
+  for (int q = 0; q < HQ_SPLIT_RPT; ++q) {
+    const int i = t + q * HQ_BLOCK;
+    if (i < nr) part[i] = sum[q];
+  }
+}
+
+// Row sums from the partials (panel order: four segments of the panel range,
+// each added in order, then combined as ((s0 + s1) + s2) + s3), and the epilogue.
+template <class Epi>
+__global__ __launch_bounds__(4 * HQ_SPLIT_RED_ROWS) void k_split_reduce(int rows, int np,
+                                                                        const double* __restrict__ partial, Epi epi,
+                                                                        const DevParams* __restrict__ prm, int j,
+                                                                        RedOut red) {
+  constexpr int NR = Epi::NR;
+  __shared__ double seg_sum[4][HQ_SPLIT_RED_ROWS];
+  const int lr = threadIdx.x % HQ_SPLIT_RED_ROWS, seg = threadIdx.x / HQ_SPLIT_RED_ROWS;
+  const int row = blockIdx.x * HQ_SPLIT_RED_ROWS + lr;
+  const int p0 = (int)((long long)seg * np / 4), p1 = (int)((long long)(seg + 1) * np / 4);
+  double s = 0.0;
+  if (row < rows) {
+#pragma unroll 4
+    for (int p = p0; p < p1; ++p) s += partial[(size_t)p * rows + row];
+  }
+  seg_sum[seg][lr] = s;
+  __syncthreads();
+  Epi e = epi;
+  e.setup(prm, j);
+  double acc[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int q = 0; q < (NR > 0 ? NR : 1); ++q) acc[q] = 0.0;
+  if (seg == 0 && row < rows) {
+    const double t = ((seg_sum[0][lr] + seg_sum[1][lr]) + seg_sum[2][lr]) + seg_sum[3][lr];
+    e(row, t, acc);
+  }
+  if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
+}

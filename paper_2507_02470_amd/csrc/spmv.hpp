@@ -119,6 +119,47 @@ __global__ __launch_bounds__(BS) void k_csr_stream(int nrows, const int* __restr
   if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
 }
 
+// Row-split kernel (as k_csr, G <= 64 lanes per row) gathering from an LDS
+// copy of the input vector (at most HQ_XLDS_MAX entries): for rows of tens to
+// hundreds of nonzeros over a small vector (the Lasso's Ahat^T, p columns),
+// where the stream kernel would add each long row serially.  Persistent
+// 1024-thread blocks copy the vector once, then take rows in grid-stride
+// order; the summation order is that of k_csr<G>.
+template <int G, class Epi>
+__global__ __launch_bounds__(HQ_XLDS_BLOCK) void k_csr_xrow(int nrows, const int* __restrict__ rowptr,
+                                                            const int* __restrict__ col,
+                                                            const double* __restrict__ val,
+                                                            const double* __restrict__ xin, Epi epi,
+                                                            const DevParams* __restrict__ prm, int j, RedOut red,
+                                                            int ncols) {
+  static_assert(G >= 1 && G <= HQ_WAVE && (HQ_WAVE % G) == 0, "lanes per row");
+  constexpr int BS = HQ_XLDS_BLOCK;
+  constexpr int RPB = BS / G;
+  constexpr int NR = Epi::NR;
+  extern __shared__ double xs[];
+  const int gl = threadIdx.x % G;
+  const int gi = threadIdx.x / G;
+  Epi e = epi;
+  e.setup(prm, j);
+  double acc[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int s = 0; s < (NR > 0 ? NR : 1); ++s) acc[s] = 0.0;
+  for (int i = threadIdx.x; i < ncols; i += BS) xs[i] = xin[i];
+  __syncthreads();
+  for (long long r0 = (long long)blockIdx.x * RPB; r0 < nrows; r0 += (long long)gridDim.x * RPB) {
+    const long long row = r0 + gi;
+    double sum = 0.0;
+    if (row < nrows) {
+      const int b = rowptr[row], en = rowptr[row + 1];
+#pragma unroll 4
+      for (int k = b + gl; k < en; k += G) sum += ld_stream(val + k) * xs[ld_stream(col + k)];
+    }
+    if constexpr (G > 1) sum = group_sum<G>(sum);
+    if (row < nrows && gl == 0) e((int)row, sum, acc);
+  }
+  if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
+}
+
 // Elementwise driver: epi(i, q_i) with a precomputed / zero q.
 template <class Epi>
 __global__ __launch_bounds__(HQ_BLOCK) void k_elem(int n, const double* __restrict__ q, Epi epi,

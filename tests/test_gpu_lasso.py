@@ -105,6 +105,37 @@ def test_full_solves_and_lasso_optimality():
             assert np.abs(g[~on]).max() <= lam * (1 + 1e-6)
 
 
+def test_benchmark_size_kernels_match_oracle():
+    """The benchmark's Lasso (p = 1e4, q = 5e5, 5e7 nonzeros) runs its Ahat x
+    product on the column-split layout and Ahat^T t on the row-split kernel
+    gathering from LDS by default: the Q operator against the oracle's, then
+    three iterations with a check after each against the oracle.  lambda_Q is
+    the host bound ||Ahat||_1 ||Ahat||_inf >= lambda_max(Ahat^T Ahat) on both
+    sides (the power method would cost the oracle minutes here)."""
+    import time
+    DP, Solver = _S()
+    t0 = time.time()
+    qp = qpgen.make_lasso(seed=1006, p=10_000, q=500_000, density=0.01)
+    Ah = qp.Ahat_scipy()
+    lamQ = float(abs(Ah).sum(axis=0).max() * abs(Ah).sum(axis=1).max())
+    print(f"lasso built ({time.time() - t0:.1f} s)", flush=True)
+    dp = DP(qp)
+    K = 3
+    s = Solver(dp, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=1, log_cap=K)
+    x = np.random.default_rng(4).standard_normal(qp.n)
+    got = s.apply("Q", x).cpu().numpy()
+    ref = oracle.apply_Q(qp, x)
+    assert _max_rel(got, ref) < 1e-13
+    rg = s.solve()
+    s.close()
+    print(f"gpu done ({time.time() - t0:.1f} s)", flush=True)
+    ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=1, lambda_Q=lamQ, log_cap=K)
+    print(f"oracle done ({time.time() - t0:.1f} s)", flush=True)
+    np.testing.assert_allclose(rg.check_log[:, 2:6], ro.check_log[:, 2:6], rtol=1e-9, atol=1e-15)
+    for name in ("w", "x", "z"):
+        assert _max_rel(getattr(rg, name).cpu().numpy(), getattr(ro, name)) <= 1e-10, name
+
+
 def test_batch_rejects_l1():
     from paper_2507_02470_amd.batch import BatchSolver
     from paper_2507_02470_amd._native import HPRQPError

@@ -55,7 +55,8 @@ def test_operators_csr_kron_lowrank():
         print("operators:", qp.meta.get("workload"), qp.n, qp.m, flush=True)
         x = rng.standard_normal(qp.n); y = rng.standard_normal(qp.m)
         dp = DP(qp)
-        for lanes in (-1, 0, -2, -3):    # default, CSR-stream, gathering from LDS, panel-ordered
+        # default, CSR-stream, gathering from LDS, panel-ordered, row-split from LDS (1, 4, 64 lanes)
+        for lanes in (-1, 0, -2, -3, -101, -104, -164):
             s = Solver(dp, lambda_A=1.0, lambda_Q=1.0, spmv_lanes=lanes)
             Qd = qp.Q_dense() if qp.n <= 4000 else None
             ref_q = Qd @ x
@@ -87,7 +88,8 @@ def test_operators_large_csr_all_lane_groups():
     assert _max_rel(s.apply("Q", x).cpu().numpy(), ref) < 1e-13
     s.close()
     dp = DP(qp)
-    for g in (-3, 0, 1, 2, 4, 8, 16, 32, 64, 128, 256):
+    # (-116: a vector over the LDS limit, so 16 lanes gathering from memory)
+    for g in (-3, 0, 1, 2, 4, 8, 16, 32, 64, 128, 256, -116):
         s = Solver(dp, lambda_Q=1.0, spmv_lanes=g)
         assert _max_rel(s.apply("Q", x).cpu().numpy(), ref) < 1e-13, g
         s.close()
@@ -103,13 +105,66 @@ def test_long_rows_and_every_kernel_in_the_iteration():
     ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_Q=lamQ, trace_iters=K)
     to = split_trace(ro.trace, qp.n, qp.m)
     dp = DP(qp)
-    for g in (-3, -2, 0, 1, 8, 64, 128, 256):
+    for g in (-3, -2, 0, 1, 8, 64, 128, 256, -108, -164):
         s = Solver(dp, lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K, spmv_lanes=g)
         rg = s.solve()
         s.close()
         tg = split_trace(rg.trace, qp.n, qp.m)
         for name in ("w", "x", "wbar", "xbar"):
             assert _max_rel(tg[name][K - 1], to[name][K - 1]) <= 1e-10, (g, name)
+
+
+def test_column_split_product():
+    """The column-split product (spmv_lanes = -4): a wide matrix with long rows
+    whose columns come in random order, with repeats and an empty row, against
+    scipy; then a Lasso whose Ahat is wider than the LDS limit through 30
+    iterations against the oracle."""
+    DP, Solver = _S()
+    rng = np.random.default_rng(7)
+    m, n = 300, 60_001
+    lens = rng.integers(1500, 2500, size=m)
+    lens[5] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    cols = rng.integers(0, n, size=int(rp[-1])).astype(np.int32)     # unsorted, repeats possible
+    vals = rng.standard_normal(cols.size)
+    qp = qpgen.QP(n=n, m=m, qkind="zero", c=np.zeros(n), L=-np.ones(n), U=np.ones(n),
+                  a_rowptr=rp, a_col=cols, a_val=vals, l=-np.ones(m), u=np.ones(m))
+    A = sp.csr_matrix((vals, cols, rp), shape=(m, n))
+    x = rng.standard_normal(n)
+    s = Solver(DP(qp), lambda_A=1.0, spmv_lanes=-4, small_path=0)
+    assert s.kernel_stats()["lanes_per_row"]["A"] == -4
+    assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13
+    s.close()
+
+    qp = qpgen.make_lasso(seed=9, p=40, q=20_000, density=0.3)     # 6000 nonzeros per row of Ahat
+    lamQ = 1.01 * oracle.power(qp, "Q", qpgen.power_start(qp.n), maxit=5000, tol=1e-10)[0]
+    K = 30
+    ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_Q=lamQ, trace_iters=K)
+    to = split_trace(ro.trace, qp.n, qp.m)
+    s = Solver(DP(qp), lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K, spmv_lanes=-4)
+    rg = s.solve()
+    s.close()
+    tg = split_trace(rg.trace, qp.n, qp.m)
+    for name in ("w", "x", "wbar", "xbar"):
+        assert _max_rel(tg[name][K - 1], to[name][K - 1]) <= 1e-10, name
+
+
+def test_lds_row_split_codes():
+    """spmv_lanes = -100 - g selects the row-split kernel gathering from LDS
+    (reported back by kernel_stats); other codes below -100 are rejected."""
+    from paper_2507_02470_amd._native import HPRQPError
+    DP, Solver = _S()
+    qp = qpgen.make_small_ccqp(seed=21, n=2500, m=900, nb=300, density=0.004)
+    dp = DP(qp)
+    for bad in (-103, -228, -100):
+        with pytest.raises(HPRQPError):
+            Solver(dp, lambda_A=1.0, lambda_Q=1.0, spmv_lanes=bad)
+    s = Solver(dp, lambda_A=1.0, lambda_Q=1.0, spmv_lanes=-132, max_iter=10, small_path=0)
+    s.solve()
+    assert s.kernel_stats()["lanes_per_row"] == dict(A=-132, AT=-132, Q=-132)
+    x = np.random.default_rng(2).standard_normal(qp.n)
+    assert _max_rel(s.apply("Q", x).cpu().numpy(), qp.Q_dense() @ x) < 1e-13
+    s.close()
 
 
 def test_panel_layout_falls_back_when_a_chunk_is_too_large():

@@ -376,7 +376,18 @@ inline bool is_xrow(int G) { return G < HQ_G_XROW; }
 template <class Epi>
 void launch_split(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, int j, const RedOut& red) {
   const SplitMat& S = M.sm;
-  k_split_partial<<<S.np * S.nrb, HQ_BLOCK, 0, h.st>>>(S, x);
+  const size_t lds = (size_t)S.pw * sizeof(double);
+  if (S.pw == HQ_SPLIT_PW) {
+    k_split_partial<HQ_BLOCK><<<S.np * S.nrb, HQ_BLOCK, lds, h.st>>>(S, x);
+  } else {
+    static bool attr_set = false;   // dynamic LDS above 64 KB must be enabled
+    if (!attr_set) {
+      HQC(hipFuncSetAttribute((const void*)k_split_partial<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(HQ_SPLIT_PW_WIDE * sizeof(double))));
+      attr_set = true;
+    }
+    k_split_partial<1024><<<S.np * S.nrb, 1024, lds, h.st>>>(S, x);
+  }
   const int rgrid = (S.rows + HQ_SPLIT_RED_ROWS - 1) / HQ_SPLIT_RED_ROWS;
   check_red_grid(rgrid, red);
   k_split_reduce<Epi><<<rgrid, 4 * HQ_SPLIT_RED_ROWS, 0, h.st>>>(S.rows, S.np, S.partial, epi, h.dprm, j, red);
@@ -929,18 +940,43 @@ bool build_panel(hprqp_handle& h, Mat& M, bool any_size = false) {
 
 // Column-split copy of M (split.hpp); false when the matrix does not have the
 // shape it serves: a vector too long for LDS, and rows long enough that the
-// per-(panel, row) starts and partial sums stay small beside the matrix (at
-// least 8 nonzeros per row and panel on average)
+// per-(panel, row) starts and partial sums stay small beside the matrix: on
+// average at least 8 nonzeros per row in a panel of 2,048 columns, else at
+// least 2 in a panel of 16,384
 bool build_split(hprqp_handle& h, Mat& M) {
   if (M.sm.off) return true;
   if (M.rows == 0 || M.nnz == 0 || M.cols <= HQ_XLDS_MAX) return false;
-  const long long np = (M.cols + HQ_SPLIT_PW - 1) / HQ_SPLIT_PW;
-  const long long cells = np * M.rows;
-  if (cells * 8 > M.nnz || cells + 1 >= (1ll << 31)) return false;
+  int pw = 0;
+  long long np = 0, cells = 0;
+  for (int w : {HQ_SPLIT_PW, HQ_SPLIT_PW_WIDE}) {
+    np = (M.cols + w - 1) / w;
+    cells = np * M.rows;
+    if (cells * (w == HQ_SPLIT_PW ? 8 : 2) <= M.nnz) { pw = w; break; }
+  }
+  if (!pw || cells + 1 >= (1ll << 31)) return false;
+  // workgroups per panel: one pass of 1,024 rows each for the narrow panels; for
+  // the wide ones (one workgroup per CU) as few as keep the copies of x under an
+  // eighth of the matrix's bytes, chosen to fill the last round of workgroups
+  int nrb = (M.rows + HQ_SPLIT_ROWS - 1) / HQ_SPLIT_ROWS;
+  if (pw == HQ_SPLIT_PW_WIDE) {
+    const long long cap = std::max(1ll, (M.nnz * 10) / (8ll * 8 * M.cols));
+    const int most = (int)std::min<long long>(std::min<long long>(cap, 16), nrb);
+    double best = -1.0;
+    int pick = 1;
+    for (int r = 1; r <= most; ++r) {
+      const long long blocks = np * r, rounds = (blocks + h.ncu - 1) / h.ncu;
+      const double fill = (double)blocks / (double)(rounds * h.ncu);
+      if (fill > best + 1e-9) { best = fill; pick = r; }
+    }
+    nrb = pick;
+  }
+  const int rpb = (int)((((long long)M.rows + nrb - 1) / nrb + HQ_SPLIT_ROWS - 1) / HQ_SPLIT_ROWS) * HQ_SPLIT_ROWS;
+  nrb = (M.rows + rpb - 1) / rpb;
+  if (np * nrb >= (1ll << 31)) return false;
   int* cnt = nullptr;
   HQC(hipMalloc(&cnt, sizeof(int) * (size_t)cells));
   HQC(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)cells, h.st));   // (setup, never captured)
-  k_split_count<<<hq_grid(M.rows, 256), 256, 0, h.st>>>(M.rows, M.rp, M.ci, cnt);
+  k_split_count<<<hq_grid(M.rows, 256), 256, 0, h.st>>>(M.rows, pw, M.rp, M.ci, cnt);
   std::vector<int> hc((size_t)cells), ho((size_t)cells + 1, 0);
   HQC(hipMemcpyAsync(hc.data(), cnt, sizeof(int) * (size_t)cells, hipMemcpyDeviceToHost, h.st));
   HQC(hipStreamSynchronize(h.st));
@@ -952,14 +988,12 @@ bool build_split(hprqp_handle& h, Mat& M) {
   double* part = h.dalloc<double>((size_t)cells);
   HQC(hipMemcpyAsync(off, ho.data(), sizeof(int) * ((size_t)cells + 1), hipMemcpyHostToDevice, h.st));
   HQC(hipMemcpyAsync(cnt, ho.data(), sizeof(int) * (size_t)cells, hipMemcpyHostToDevice, h.st));   // cursors
-  k_split_scatter<<<hq_grid(M.rows, 256), 256, 0, h.st>>>(M.rows, M.rp, M.ci, M.v, cnt, lci, sv);
+  k_split_scatter<<<hq_grid(M.rows, 256), 256, 0, h.st>>>(M.rows, pw, M.rp, M.ci, M.v, cnt, lci, sv);
   HQC(hipStreamSynchronize(h.st));
   hipFree(cnt);
   SplitMat S;
-  S.rows = M.rows; S.cols = M.cols; S.np = (int)np;
+  S.rows = M.rows; S.cols = M.cols; S.pw = pw; S.np = (int)np; S.rpb = rpb; S.nrb = nrb;
   S.off = off; S.lci = lci; S.v = sv; S.partial = part;
-  S.nrb = (M.rows + HQ_SPLIT_ROWS - 1) / HQ_SPLIT_ROWS;
-  if ((long long)S.np * S.nrb >= (1ll << 31)) return false;
   M.sm = S;
   return true;
 }
@@ -1286,9 +1320,13 @@ void create_impl(const hprqp_problem* P, const hprqp_options* opt, hipStream_t s
         while (g < HQ_WAVE && 6.0 * 2 * g <= avg) g *= 2;
         M.G = HQ_G_XROW - g;
         M.G_np = M.G;
-      } else if (M.G > 0 && build_split(h, M)) {
-        // few long rows over a vector too long for LDS: the column-split
-        // product (the Lasso's Ahat, 5000 per row: 145 us against 326 us)
+      } else if (M.G > 0 && (long long)M.cols * 8 > (3ll << 20) && build_split(h, M)) {
+        // long rows over a vector larger than three quarters of an XCD's L2:
+        // the column-split product (the Lasso's Ahat, 1e4 rows of 5000 over a
+        // 4 MB vector: 145 us against 326 us; 2e5 rows of 1000 over 40 MB:
+        // 1.30 ms against 3.0 ms panel-ordered).  Over a vector that stays in
+        // the L2 its partial sums cost more than the gathers (Ahat^T of the
+        // latter, 5e6 rows of 40 over 1.6 MB: 1.59 ms against 1.18 ms)
         M.G = HQ_G_SPLIT;
       }
       // short rows gathering from a vector larger than three quarters of an

@@ -4,7 +4,7 @@
 //
 // A row-split kernel gathers every nonzero's x entry through the L2 at the
 // rate of its random 8-byte requests.  Here the columns are cut into panels
-// of HQ_SPLIT_PW columns and the matrix is stored panel by panel, each panel
+// of pw columns and the matrix is stored panel by panel, each panel
 // a CSR over all rows (rows in order, a row's entries in their CSR order,
 // columns as 16-bit offsets into the panel).  A workgroup owns one panel and a
 // block of rows: it copies the panel's slice of x into LDS once, gathers from
@@ -15,15 +15,18 @@
 #pragma once
 #include "common.hpp"
 
-#define HQ_SPLIT_PW 2048        // columns per panel (16 KB of LDS)
+#define HQ_SPLIT_PW 2048        // columns per panel, denser matrices (16 KB of LDS)
+#define HQ_SPLIT_PW_WIDE 16384  // columns per panel, sparser ones (128 KB of LDS)
 #define HQ_SPLIT_RED_ROWS 64    // rows per workgroup of the reduction
+#define HQ_SPLIT_ROWS 1024      // rows per pass of a workgroup
 
 struct SplitMat {
   int rows = 0, cols = 0;
+  int pw = HQ_SPLIT_PW;              // columns per panel
   int np = 0;                        // panels
-  int nrb = 0;                       // row blocks (of HQ_SPLIT_ROWS rows) per panel
+  int rpb = 0, nrb = 0;              // rows per workgroup (a multiple of HQ_SPLIT_ROWS), row blocks per panel
   const int* off = nullptr;          // np * rows + 1 starts: panel p, row r at off[p * rows + r]
-  const unsigned short* lci = nullptr;   // column - p * HQ_SPLIT_PW
+  const unsigned short* lci = nullptr;   // column - p * pw
   const double* v = nullptr;
   double* partial = nullptr;         // np * rows partial sums
 };
@@ -34,10 +37,10 @@ struct SplitMat {
 // Step 1, row r: how many of its nonzeros fall in each panel,
 // cnt[p * rows + r] (zeroed beforehand).  Consecutive entries of one panel
 // are counted together.
-__host__ __device__ inline void split_count_row(int r, int rows, const int* rp, const int* ci, int* cnt) {
+__host__ __device__ inline void split_count_row(int r, int rows, int pw, const int* rp, const int* ci, int* cnt) {
   int p = -1, run = 0;
   for (int k = rp[r]; k < rp[r + 1]; ++k) {
-    const int q = ci[k] / HQ_SPLIT_PW;
+    const int q = ci[k] / pw;
     if (q != p) {
       if (run) cnt[(size_t)p * rows + r] += run;
       p = q;
@@ -50,79 +53,86 @@ __host__ __device__ inline void split_count_row(int r, int rows, const int* rp, 
 
 // Step 2, row r: its entries into their panels in CSR order; cur holds the
 // next free position of every (panel, row), initialised to the starts off.
-__host__ __device__ inline void split_scatter_row(int r, int rows, const int* rp, const int* ci, const double* v,
-                                                  int* cur, unsigned short* lci, double* sv) {
+__host__ __device__ inline void split_scatter_row(int r, int rows, int pw, const int* rp, const int* ci,
+                                                  const double* v, int* cur, unsigned short* lci, double* sv) {
   int p = -1, pos = 0;
   for (int k = rp[r]; k < rp[r + 1]; ++k) {
-    const int q = ci[k] / HQ_SPLIT_PW;
+    const int q = ci[k] / pw;
     if (q != p) {
       if (p >= 0) cur[(size_t)p * rows + r] = pos;
       p = q;
       pos = cur[(size_t)p * rows + r];
     }
-    lci[pos] = (unsigned short)(ci[k] - q * HQ_SPLIT_PW);
+    lci[pos] = (unsigned short)(ci[k] - q * pw);
     sv[pos] = v[k];
     ++pos;
   }
   if (p >= 0) cur[(size_t)p * rows + r] = pos;
 }
 
-__global__ void k_split_count(int rows, const int* __restrict__ rp, const int* __restrict__ ci, int* cnt) {
+__global__ void k_split_count(int rows, int pw, const int* __restrict__ rp, const int* __restrict__ ci, int* cnt) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x)
-    split_count_row(r, rows, rp, ci, cnt);
+    split_count_row(r, rows, pw, rp, ci, cnt);
 }
 
-__global__ void k_split_scatter(int rows, const int* __restrict__ rp, const int* __restrict__ ci,
+__global__ void k_split_scatter(int rows, int pw, const int* __restrict__ rp, const int* __restrict__ ci,
                                 const double* __restrict__ v, int* cur, unsigned short* lci, double* sv) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x)
-    split_scatter_row(r, rows, rp, ci, v, cur, lci, sv);
+    split_scatter_row(r, rows, pw, rp, ci, v, cur, lci, sv);
 }
 
-// Partial sums: workgroup b takes panel b % np and the HQ_SPLIT_ROWS rows of
-// row block b / np.  Inside a panel the rows are short (tens of nonzeros), so
-// the block's entries -- one contiguous range of the layout -- are streamed
-// as by the CSR-stream kernel: coalesced loads, products staged in LDS, then
-// every thread adds up its rows' products in order (RPT rows per thread).
-#define HQ_SPLIT_RPT 4
-#define HQ_SPLIT_ROWS (HQ_BLOCK * HQ_SPLIT_RPT)
-__global__ __launch_bounds__(HQ_BLOCK) void k_split_partial(SplitMat S, const double* __restrict__ x) {
-  constexpr int CH = 2048;   // products staged per step
-  __shared__ double xs[HQ_SPLIT_PW];
+// Partial sums: workgroup b takes panel b % np and the rpb rows of row block
+// b / np, HQ_SPLIT_ROWS at a time.  Inside a panel the rows are short (a few
+// to tens of nonzeros), so each pass's entries -- one contiguous range of the
+// layout -- are streamed as by the CSR-stream kernel: coalesced loads,
+// products staged in LDS, then every thread adds up its rows' products in
+// order.  BS = 256 for the narrow panels (several workgroups per CU), 1024 for
+// the wide ones (one workgroup per CU, its 128 KB copy of x in LDS).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_split_partial(SplitMat S, const double* __restrict__ x) {
+  static_assert(HQ_SPLIT_ROWS % BS == 0, "rows per pass");
+  constexpr int RPT = HQ_SPLIT_ROWS / BS;   // rows per thread and pass
+  constexpr int CH = 2048;                  // products staged per step
+  extern __shared__ double xs[];            // S.pw entries
   __shared__ double prod[CH];
   __shared__ int srp[HQ_SPLIT_ROWS + 1];
   const int t = threadIdx.x;
   const int p = blockIdx.x % S.np, rb = blockIdx.x / S.np;
-  const int cx = p * HQ_SPLIT_PW, nc = min(HQ_SPLIT_PW, S.cols - cx);
-  for (int i = t; i < nc; i += HQ_BLOCK) xs[i] = x[cx + i];
-  const int r0 = rb * HQ_SPLIT_ROWS, nr = min(HQ_SPLIT_ROWS, S.rows - r0);
-  // (row r0 + nr ends at the next row's start, or at the next panel's first)
-  const int* __restrict__ offp = S.off + (size_t)p * S.rows + r0;
-  for (int i = t; i <= nr; i += HQ_BLOCK) srp[i] = offp[i];
-  __syncthreads();
-  const int kb = srp[0], ke = srp[nr];
-  double sum[HQ_SPLIT_RPT];
+  const int cx = p * S.pw, nc = min(S.pw, S.cols - cx);
+  for (int i = t; i < nc; i += BS) xs[i] = x[cx + i];
+  const int* __restrict__ offp = S.off + (size_t)p * S.rows;
+  double* __restrict__ part = S.partial + (size_t)p * S.rows;
+  const int rend = min(S.rows, (rb + 1) * S.rpb);
+  for (int r0 = rb * S.rpb; r0 < rend; r0 += HQ_SPLIT_ROWS) {
+    const int nr = min(HQ_SPLIT_ROWS, rend - r0);
+    // (row r0 + nr - 1 ends at the next row's start, or at the next panel's first)
+    for (int i = t; i <= nr; i += BS) srp[i] = offp[r0 + i];
+    __syncthreads();   // also orders the copy of x before the first pass
+    const int kb = srp[0], ke = srp[nr];
+    double sum[RPT];
 #pragma unroll
-  for (int q = 0; q < HQ_SPLIT_RPT; ++q) sum[q] = 0.0;
-  for (int c0 = kb; c0 < ke; c0 += CH) {   // same trip count in every thread
-    const int c1 = min(ke, c0 + CH);
+    for (int q = 0; q < RPT; ++q) sum[q] = 0.0;
+    for (int c0 = kb; c0 < ke; c0 += CH) {   // same trip count in every thread
+      const int c1 = min(ke, c0 + CH);
 #pragma unroll 8
-    for (int k = c0 + t; k < c1; k += HQ_BLOCK) prod[k - c0] = ld_stream(S.v + k) * xs[ld_stream(S.lci + k)];
-    __syncthreads();
+      for (int k = c0 + t; k < c1; k += BS) prod[k - c0] = ld_stream(S.v + k) * xs[ld_stream(S.lci + k)];
+      __syncthreads();
 #pragma unroll
-    for (int q = 0; q < HQ_SPLIT_RPT; ++q) {
-      const int i = t + q * HQ_BLOCK;
-      if (i < nr) {
-        const int lo = max(srp[i], c0), hi = min(srp[i + 1], c1);
-        for (int k = lo; k < hi; ++k) sum[q] += prod[k - c0];
+      for (int q = 0; q < RPT; ++q) {
+        const int i = t + q * BS;
+        if (i < nr) {
+          const int lo = max(srp[i], c0), hi = min(srp[i + 1], c1);
+          for (int k = lo; k < hi; ++k) sum[q] += prod[k - c0];
+        }
       }
+      __syncthreads();   // prod is rewritten by the next step
     }
-    __syncthreads();   // prod is rewritten by the next step
-  }
-  double* __restrict__ part = S.partial + (size_t)p * S.rows + r0;
 #pragma unroll
-  for (int q = 0; q < HQ_SPLIT_RPT; ++q) {
-    const int i = t + q * HQ_BLOCK;
-    if (i < nr) part[i] = sum[q];
+    for (int q = 0; q < RPT; ++q) {
+      const int i = t + q * BS;
+      if (i < nr) part[r0 + i] = sum[q];
+    }
+    __syncthreads();   // srp is rewritten by the next pass
   }
 }
 

@@ -19,7 +19,7 @@ static int failures = 0;
     }                                                           \
   } while (0)
 
-static void check_layout(int rows, int cols, int maxlen, bool shuffle, unsigned seed) {
+static void check_layout(int rows, int cols, int maxlen, bool shuffle, unsigned seed, int pw) {
   std::mt19937_64 rng(seed);
   std::vector<int> rp(rows + 1, 0), ci;
   std::vector<double> v;
@@ -32,10 +32,10 @@ static void check_layout(int rows, int cols, int maxlen, bool shuffle, unsigned 
     rp[r + 1] = (int)ci.size();
   }
   const int nnz = rp[rows];
-  const int np = (cols + HQ_SPLIT_PW - 1) / HQ_SPLIT_PW;
+  const int np = (cols + pw - 1) / pw;
   const size_t cells = (size_t)np * rows;
   std::vector<int> cnt(cells, 0);
-  for (int r = 0; r < rows; ++r) split_count_row(r, rows, rp.data(), ci.data(), cnt.data());
+  for (int r = 0; r < rows; ++r) split_count_row(r, rows, pw, rp.data(), ci.data(), cnt.data());
   std::vector<int> off(cells + 1, 0);
   for (size_t c = 0; c < cells; ++c) off[c + 1] = off[c] + cnt[c];
   CHECK(off[cells] == nnz, "counts sum to %d, nnz %d", off[cells], nnz);
@@ -43,31 +43,35 @@ static void check_layout(int rows, int cols, int maxlen, bool shuffle, unsigned 
   std::vector<unsigned short> lci(nnz + 2, 0xBEEF);
   std::vector<double> sv(nnz + 2, -1.0);
   std::vector<int> cur(off.begin(), off.end() - 1);
-  for (int r = 0; r < rows; ++r) split_scatter_row(r, rows, rp.data(), ci.data(), v.data(), cur.data(), lci.data() + 1, sv.data() + 1);
+  for (int r = 0; r < rows; ++r) split_scatter_row(r, rows, pw, rp.data(), ci.data(), v.data(), cur.data(), lci.data() + 1,
+                                             sv.data() + 1);
   CHECK(lci[0] == 0xBEEF && lci[nnz + 1] == 0xBEEF, "scatter wrote outside the arrays");
   for (size_t c = 0; c < cells; ++c) CHECK(cur[c] == off[c + 1], "cell %zu: cursor %d, end %d", c, cur[c], off[c + 1]);
   for (int p = 0; p < np; ++p)
     for (int r = 0; r < rows; ++r) {
       std::vector<int> want;
       for (int k = rp[r]; k < rp[r + 1]; ++k)
-        if (ci[k] / HQ_SPLIT_PW == p) want.push_back(k);
+        if (ci[k] / pw == p) want.push_back(k);
       const int b = off[(size_t)p * rows + r], e = off[(size_t)p * rows + r + 1];
       CHECK(e - b == (int)want.size(), "panel %d row %d: %d entries, want %zu", p, r, e - b, want.size());
       for (int q = 0; q < (int)want.size() && q < e - b; ++q) {
         const int k = want[q];
-        CHECK(lci[1 + b + q] == ci[k] - p * HQ_SPLIT_PW && sv[1 + b + q] == v[k],
+        CHECK(lci[1 + b + q] == ci[k] - p * pw && sv[1 + b + q] == v[k],
               "panel %d row %d entry %d: (%d, %g) want (%d, %g)", p, r, q, (int)lci[1 + b + q], sv[1 + b + q],
-              ci[k] - p * HQ_SPLIT_PW, v[k]);
+              ci[k] - p * pw, v[k]);
       }
     }
 }
 
 int main() {
-  check_layout(1, 5000, 3000, false, 1);
-  check_layout(37, 20000, 2500, true, 2);      // random order and repeats
-  check_layout(200, 9 * HQ_SPLIT_PW + 17, 900, false, 3);   // ragged last panel
-  check_layout(300, 14337, 60, true, 4);
-  check_layout(5, 70000, 0, false, 5);         // empty rows
+  for (int pw : {HQ_SPLIT_PW, HQ_SPLIT_PW_WIDE}) {
+    check_layout(1, 5000, 3000, false, 1, pw);
+    check_layout(37, 20000, 2500, true, 2, pw);      // random order and repeats
+    check_layout(200, 9 * pw + 17, 900, false, 3, pw);   // ragged last panel
+    check_layout(300, 14337, 60, true, 4, pw);
+    check_layout(5, 70000, 0, false, 5, pw);         // empty rows
+    check_layout(3000, 65536 * 3, 400, true, 6, pw);
+  }
   if (failures) { std::printf("%d failures\n", failures); return 1; }
   std::printf("OK\n");
   return 0;

@@ -135,18 +135,36 @@ def test_column_split_product():
     assert s.kernel_stats()["lanes_per_row"]["A"] == -4
     assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13
     s.close()
-
-    qp = qpgen.make_lasso(seed=9, p=40, q=20_000, density=0.3)     # 6000 nonzeros per row of Ahat
-    lamQ = 1.01 * oracle.power(qp, "Q", qpgen.power_start(qp.n), maxit=5000, tol=1e-10)[0]
-    K = 30
-    ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_Q=lamQ, trace_iters=K)
-    to = split_trace(ro.trace, qp.n, qp.m)
-    s = Solver(DP(qp), lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K, spmv_lanes=-4)
-    rg = s.solve()
+    # sparser rows over a vector beyond the L2: the wide panels (16,384
+    # columns, 1024-thread workgroups, two passes of 1,024 rows in each
+    # workgroup), chosen by default
+    m, n = 2000, 600_003
+    lens = rng.integers(100, 200, size=m)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    cols = rng.integers(0, n, size=int(rp[-1])).astype(np.int32)
+    vals = rng.standard_normal(cols.size)
+    qp = qpgen.QP(n=n, m=m, qkind="zero", c=np.zeros(n), L=-np.ones(n), U=np.ones(n),
+                  a_rowptr=rp, a_col=cols, a_val=vals, l=-np.ones(m), u=np.ones(m))
+    A = sp.csr_matrix((vals, cols, rp), shape=(m, n))
+    x = rng.standard_normal(n)
+    s = Solver(DP(qp), lambda_A=1.0, small_path=0)
+    assert s.kernel_stats()["lanes_per_row"]["A"] == -4
+    assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13
     s.close()
-    tg = split_trace(rg.trace, qp.n, qp.m)
-    for name in ("w", "x", "wbar", "xbar"):
-        assert _max_rel(tg[name][K - 1], to[name][K - 1]) <= 1e-10, name
+
+    # Lasso, narrow panels (6000 nonzeros per row of Ahat) and wide ones (150)
+    for qp in (qpgen.make_lasso(seed=9, p=40, q=20_000, density=0.3),
+               qpgen.make_lasso_rows(seed=10, p=2_000, q=200_000, per_row=150)):
+        lamQ = 1.01 * oracle.power(qp, "Q", qpgen.power_start(qp.n), maxit=5000, tol=1e-10)[0]
+        K = 30
+        ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=10, lambda_Q=lamQ, trace_iters=K)
+        to = split_trace(ro.trace, qp.n, qp.m)
+        s = Solver(DP(qp), lambda_Q=lamQ, tol=0.0, max_iter=K, check_every=10, trace_iters=K, spmv_lanes=-4)
+        rg = s.solve()
+        s.close()
+        tg = split_trace(rg.trace, qp.n, qp.m)
+        for name in ("w", "x", "wbar", "xbar"):
+            assert _max_rel(tg[name][K - 1], to[name][K - 1]) <= 1e-10, (qp.gram_p, name)
 
 
 def test_lds_row_split_codes():

@@ -200,7 +200,9 @@ void hprqp_default_options(hprqp_options *opt);
  * an explicit CSR on the device (rows of A^T ordered by row of A, so every
  * product is deterministic), runs the power method when lambda_A/lambda_Q
  * are not given (Section 4.1), computes sigma0 and allocates the workspace
- * (about 34 n + 15 m doubles plus A^T).  The problem arrays are borrowed.
+ * (about 34 n + 15 m doubles plus A^T, plus a reordered copy of each matrix
+ * whose product runs on the panel-ordered or column-split layout, and the
+ * latter's per-panel partial sums).  The problem arrays are borrowed.
  * Returns HPRQP_ERR_BOUNDS / HPRQP_ERR_SHAPE on invalid data. */
 hprqp_status hprqp_create(const hprqp_problem *prob, const hprqp_options *opt,
                           hipStream_t stream, hprqp_handle **out);

@@ -388,7 +388,7 @@ void launch_split(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi
     }
     k_split_partial<1024><<<S.np * S.nrb, 1024, lds, h.st>>>(S, x);
   }
-  const int rgrid = (S.rows + HQ_SPLIT_RED_ROWS - 1) / HQ_SPLIT_RED_ROWS;
+  const int rgrid = std::min((S.rows + HQ_SPLIT_RED_ROWS - 1) / HQ_SPLIT_RED_ROWS, HQ_PCAP);
   check_red_grid(rgrid, red);
   k_split_reduce<Epi><<<rgrid, 4 * HQ_SPLIT_RED_ROWS, 0, h.st>>>(S.rows, S.np, S.partial, epi, h.dprm, j, red);
 }

@@ -137,7 +137,9 @@ __global__ __launch_bounds__(BS) void k_split_partial(SplitMat S, const double* 
 }
 
 // Row sums from the partials (panel order: four segments of the panel range,
-// each added in order, then combined as ((s0 + s1) + s2) + s3), and the epilogue.
+// each added in order, then combined as ((s0 + s1) + s2) + s3), and the
+// epilogue.  Workgroups take groups of HQ_SPLIT_RED_ROWS rows in grid-stride
+// order (the grid is capped, so a reduction's partials fit their slots).
 template <class Epi>
 __global__ __launch_bounds__(4 * HQ_SPLIT_RED_ROWS) void k_split_reduce(int rows, int np,
                                                                         const double* __restrict__ partial, Epi epi,
@@ -146,23 +148,27 @@ __global__ __launch_bounds__(4 * HQ_SPLIT_RED_ROWS) void k_split_reduce(int rows
   constexpr int NR = Epi::NR;
   __shared__ double seg_sum[4][HQ_SPLIT_RED_ROWS];
   const int lr = threadIdx.x % HQ_SPLIT_RED_ROWS, seg = threadIdx.x / HQ_SPLIT_RED_ROWS;
-  const int row = blockIdx.x * HQ_SPLIT_RED_ROWS + lr;
   const int p0 = (int)((long long)seg * np / 4), p1 = (int)((long long)(seg + 1) * np / 4);
-  double s = 0.0;
-  if (row < rows) {
-#pragma unroll 4
-    for (int p = p0; p < p1; ++p) s += partial[(size_t)p * rows + row];
-  }
-  seg_sum[seg][lr] = s;
-  __syncthreads();
   Epi e = epi;
   e.setup(prm, j);
   double acc[NR > 0 ? NR : 1];
 #pragma unroll
   for (int q = 0; q < (NR > 0 ? NR : 1); ++q) acc[q] = 0.0;
-  if (seg == 0 && row < rows) {
-    const double t = ((seg_sum[0][lr] + seg_sum[1][lr]) + seg_sum[2][lr]) + seg_sum[3][lr];
-    e(row, t, acc);
+  const int groups = (rows + HQ_SPLIT_RED_ROWS - 1) / HQ_SPLIT_RED_ROWS;
+  for (int g = blockIdx.x; g < groups; g += gridDim.x) {   // same trip count in every thread
+    const int row = g * HQ_SPLIT_RED_ROWS + lr;
+    double s = 0.0;
+    if (row < rows) {
+#pragma unroll 4
+      for (int p = p0; p < p1; ++p) s += partial[(size_t)p * rows + row];
+    }
+    seg_sum[seg][lr] = s;
+    __syncthreads();
+    if (seg == 0 && row < rows) {
+      const double t = ((seg_sum[0][lr] + seg_sum[1][lr]) + seg_sum[2][lr]) + seg_sum[3][lr];
+      e(row, t, acc);
+    }
+    __syncthreads();   // seg_sum is rewritten by the next group
   }
   if (red.active) block_reduce_store<NR, Epi::MAXMASK>(acc, red);
 }

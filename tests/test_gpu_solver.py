@@ -167,6 +167,42 @@ def test_column_split_product():
             assert _max_rel(tg[name][K - 1], to[name][K - 1]) <= 1e-10, (qp.gram_p, name)
 
 
+def test_column_split_with_more_row_groups_than_partial_slots():
+    """A (300,000 x 20,000, 10 per row) and A^T on the column-split layout
+    (wide panels): the row sums of A take 4,688 groups of 64 rows, more than a
+    reduction slot's 4,096 partials, so the summing kernel walks them in
+    grid-stride order.  Ten iterations of an LP with checks every 5 against the
+    oracle (the checks reduce through that kernel)."""
+    DP, Solver = _S()
+    rng = np.random.default_rng(11)
+    m, n = 300_000, 20_000
+    rows = np.repeat(np.arange(m), 10)
+    cols = rng.integers(0, n, size=rows.size)
+    A = sp.csr_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(m, n))
+    x0 = rng.uniform(0, 1, n)
+    ax = A @ x0
+    l = np.where(np.arange(m) % 2 == 0, ax, -np.inf)
+    u = ax + rng.uniform(0, 1, m)
+    qp = qpgen.QP(n=n, m=m, qkind="zero", c=rng.standard_normal(n), L=np.zeros(n), U=np.full(n, 2.0),
+                  a_rowptr=A.indptr.astype(np.int32), a_col=A.indices.astype(np.int32), a_val=A.data.copy(),
+                  l=l, u=u)
+    lamA = 1.01 * oracle.power(qp, "A", qpgen.power_start(m), maxit=5000, tol=1e-10)[0]
+    K = 10
+    ro = oracle.solve(qp, tol=0.0, max_iter=K, check_every=5, lambda_A=lamA, lambda_Q=0.0, log_cap=4)
+    s = Solver(DP(qp), lambda_A=lamA, lambda_Q=0.0, tol=0.0, max_iter=K, check_every=5, log_cap=4,
+               spmv_lanes=-4, small_path=0)
+    g = s.kernel_stats()["lanes_per_row"]
+    assert g["A"] == -4 and g["AT"] == -4, g
+    x = rng.standard_normal(n)
+    assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13
+    rg = s.solve()
+    s.close()
+    np.testing.assert_array_equal(rg.check_log[:, 7], ro.check_log[:, 7])
+    np.testing.assert_allclose(rg.check_log[:, 2:6], ro.check_log[:, 2:6], rtol=1e-9, atol=1e-15)
+    for name in ("y", "z", "w", "x"):
+        assert _max_rel(getattr(rg, name).cpu().numpy(), getattr(ro, name)) <= 1e-10, name
+
+
 def test_lds_row_split_codes():
     """spmv_lanes = -100 - g selects the row-split kernel gathering from LDS
     (reported back by kernel_stats); other codes below -100 are rejected."""

@@ -123,10 +123,14 @@ __global__ void k_panel_scatter(int rows, int cols, const int* __restrict__ rp, 
 // workgroups as are resident, each walking its groups in grid-stride order
 // (so the workgroups still move through the panels together, group by group).
 // The grid never exceeds HQ_PCAP, the block partials one reduction slot holds.
+// min_bpb starts the search higher: the product with the prefetching epilogue
+// runs fastest with 4 row blocks per workgroup (random QP, n = 1e6: Q d +
+// Halpern 58.6 us against 62.0 us with the resident 3; its longer chain of
+// prefetched chunks per workgroup), the plain products with the fewest.
 struct PanelShape { int bpb, grid; };
-inline PanelShape panel_launch_shape(int rows, int ncu, const int per_cu[5]) {
+inline PanelShape panel_launch_shape(int rows, int ncu, const int per_cu[5], int min_bpb = 1) {
   const long long nblk = (rows + HQ_BLOCK - 1) / HQ_BLOCK;
-  for (int b = 1; b <= 4; ++b) {
+  for (int b = min_bpb; b <= 4; ++b) {
     const long long g = (nblk + b - 1) / b;
     if (g <= (long long)ncu * per_cu[b] && g <= HQ_PCAP) return {b, (int)(g > 0 ? g : 1)};
   }
@@ -148,6 +152,17 @@ inline PanelShape panel_launch_shape(int rows, int ncu, const int per_cu[5]) {
 template <class E, class = void> struct panel_prefetch : std::false_type {};
 template <class E>
 struct panel_prefetch<E, std::void_t<decltype(E::PANEL_PREFETCH)>> : std::bool_constant<E::PANEL_PREFETCH> {};
+
+// Optional preload of epilogue operands: an epilogue type with a Pre struct,
+// preload(i) and operator()(i, q, acc, pre) has its row-wise loads issued at
+// the start of the last panel, so that they arrive during that panel's
+// gathers instead of after the row sums.
+template <class E, class = void> struct panel_preload : std::false_type {};
+template <class E>
+struct panel_preload<E, std::void_t<typename E::Pre>> : std::true_type {};
+struct PanelNoPre {};
+template <class E, bool PL> struct panel_pre_t { using type = PanelNoPre; };
+template <class E> struct panel_pre_t<E, true> { using type = typename E::Pre; };
 
 #define HQ_PANEL_PF 4                               // prefetched elements per thread
 #define HQ_PANEL_PASS (HQ_PANEL_PF * HQ_BLOCK)      // elements per LDS pass
@@ -187,6 +202,7 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
                                                         const DevParams* __restrict__ prm, int j, RedOut red) {
   constexpr int NR = Epi::NR;
   constexpr bool PF = panel_prefetch<Epi>::value;
+  constexpr bool PL = PF && panel_preload<Epi>::value;
   __shared__ double prod[PF ? HQ_PANEL_PASS : HQ_STREAM_CHUNK];
   Epi e = epi;
   e.setup(prm, j);
@@ -199,6 +215,7 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
   auto group = [&](const int g) {
     const int rb0 = g * BPB;
     double sum[BPB];
+    [[maybe_unused]] typename panel_pre_t<Epi, PL>::type pre[BPB];
 #pragma unroll
     for (int q = 0; q < BPB; ++q) sum[q] = 0.0;
     if constexpr (PF) {
@@ -207,6 +224,15 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
       PanelChunk cur;
       panel_fetch(M, rb0, 0, t, cur);
       for (int p = 0; p < HQ_PANELS; ++p) {
+        if constexpr (PL) {
+          if (p == HQ_PANELS - 1) {
+#pragma unroll
+            for (int q = 0; q < BPB; ++q) {
+              const int rb = rb0 + q;
+              if (rb < nblk && t < min(HQ_BLOCK, M.rows - rb * HQ_BLOCK)) pre[q] = e.preload(rb * HQ_BLOCK + t);
+            }
+          }
+        }
 #pragma unroll
         for (int q = 0; q < BPB; ++q) {
           if (q < nq) {
@@ -269,7 +295,10 @@ __global__ __launch_bounds__(HQ_BLOCK) void k_csr_panel(PanelMat M, const double
 #pragma unroll
     for (int q = 0; q < BPB; ++q) {
       const int rb = rb0 + q;
-      if (rb < nblk && t < min(HQ_BLOCK, M.rows - rb * HQ_BLOCK)) e(rb * HQ_BLOCK + t, sum[q], acc);
+      if (rb < nblk && t < min(HQ_BLOCK, M.rows - rb * HQ_BLOCK)) {
+        if constexpr (PL) e(rb * HQ_BLOCK + t, sum[q], acc, pre[q]);
+        else e(rb * HQ_BLOCK + t, sum[q], acc);
+      }
     }
   };
   // GS: groups in grid-stride order (matrices too tall for one group per

@@ -463,7 +463,7 @@ void launch_csr(hprqp_handle& h, const Mat& M, const double* x, const Epi& epi, 
         per_cu[b] = std::max(per_cu[b], 1);
       }
     }
-    const PanelShape sh = panel_launch_shape(M.rows, h.ncu, per_cu);
+    const PanelShape sh = panel_launch_shape(M.rows, h.ncu, per_cu, panel_prefetch<Epi>::value ? 4 : 1);
     check_red_grid(sh.grid, red);
     switch (sh.bpb) {
       case 1: k_csr_panel<Epi, 1><<<sh.grid, HQ_BLOCK, 0, h.st>>>(M.pm, x, epi, h.dprm, j, red); break;

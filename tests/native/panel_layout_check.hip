@@ -79,8 +79,9 @@ static void check_layout(int rows, int cols, int maxlen, bool shuffle, unsigned 
   }
 }
 
-static void check_shape(long long rows, int ncu, const int per_cu[5]) {
-  const PanelShape sh = panel_launch_shape((int)rows, ncu, per_cu);
+static void check_shape(long long rows, int ncu, const int per_cu[5], int min_bpb = 1) {
+  const PanelShape sh = panel_launch_shape((int)rows, ncu, per_cu, min_bpb);
+  CHECK(sh.bpb >= min_bpb, "rows %lld: bpb %d below %d", rows, sh.bpb, min_bpb);
   const long long nblk = (rows + HQ_BLOCK - 1) / HQ_BLOCK;
   CHECK(sh.grid >= 1 && sh.grid <= HQ_PCAP, "rows %lld: grid %d", rows, sh.grid);
   CHECK(sh.bpb >= 1 && sh.bpb <= 4, "rows %lld: bpb %d", rows, sh.bpb);
@@ -107,6 +108,7 @@ int main() {
   const int occ_a[5] = {0, 8, 8, 6, 4}, occ_b[5] = {0, 2, 2, 1, 1};
   const long long rows[] = {1, 255, 256, 257, 1000000, 4194304, 4194305, 5000000, 20000000, 100000000};
   for (long long r : rows) {
+    check_shape(r, 256, occ_a, 4);   // the prefetching epilogue's shape
     check_shape(r, 256, occ_a);
     check_shape(r, 256, occ_b);
     check_shape(r, 1, occ_b);

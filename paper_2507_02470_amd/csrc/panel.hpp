@@ -149,6 +149,9 @@ inline PanelShape panel_launch_shape(int rows, int ncu, const int per_cu[5], int
 // 62.5 to 59.6 us, but slows the plain products down (A v 46 -> 52 us, the
 // power method's Q product 41 -> 43 us), whose resident workgroups already
 // hide that latency and whose early loads then only compete with the gathers.
+// An epilogue that prefetches also gets four row blocks per workgroup
+// (panel_launch_shape), with which the Q xhat product gains slightly
+// (46.4 -> 45.9 us) and A v, A^T ybar still lose (47.3 -> 48.9, 48.5 us).
 template <class E, class = void> struct panel_prefetch : std::false_type {};
 template <class E>
 struct panel_prefetch<E, std::void_t<decltype(E::PANEL_PREFETCH)>> : std::bool_constant<E::PANEL_PREFETCH> {};

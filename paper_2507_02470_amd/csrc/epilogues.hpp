@@ -6,7 +6,6 @@
 // ATy = A^T y and Qw = Q w_Q are carried through the Halpern step instead of
 // being recomputed (they are reset from exact products at every restart).
 #pragma once
-#include <type_traits>
 #include "common.hpp"
 
 // out_i = q_i
@@ -90,13 +89,10 @@ struct EpiAT {
 //   acc[0..5] = <dw,Q dw>, <Q dw, A^T dy>, |dx|^2, <A^T dy, Q A^T dy>, <A^T dy, dx>, <Q dw, dx>
 //     with A^T dy = -d, Q A^T dy = -q2, dx = xbar - xh;
 //   acc[6..8] (checks) with D = ubar - u_a: <Dw, Q Dw>, <Q Dw, e>, |Dx|^2.
-// The panel-ordered product loads the first HQ_EPI_PRELOAD operands of the
-// epilogue below (the Halpern anchors wa, Qwa, xa) at the start of its last
-// panel (random QP, n = 1e6: 58.1 against 58.6 us; more operands gain nothing
-// more and take registers).
-#ifndef HQ_EPI_PRELOAD
-#define HQ_EPI_PRELOAD 3
-#endif
+// The panel-ordered product loads the Halpern anchors (wa, Qwa, xa) of the
+// epilogue below at the start of its last panel (Pre, preload; random QP,
+// n = 1e6: 58.1 against 58.6 us; preloading more operands gains nothing more
+// and takes registers).  The other products load them in the epilogue.
 struct EpiQ2 {
   double *xh, *w, *Qw, *XB, *ZB;
   const double *q1, *d, *wa, *Qwa, *xa, *ATy, *c, *L, *U, *e;
@@ -111,38 +107,28 @@ struct EpiQ2 {
     IterScalars s; s.load(p, j);
     sigma = s.sigma; sQ = s.sQ; kappa = s.kappa; rho = s.rho;
   }
-#if HQ_EPI_PRELOAD
   // operands loaded early by the panel-ordered product (before its last panel)
-  struct Pre { double v[HQ_EPI_PRELOAD]; };
+  struct Pre { double wa, Qwa, xa; };
   __device__ __forceinline__ Pre preload(int i) const {
-    Pre r;
-    const double* src[6] = {wa, Qwa, xa, c, q1, ATy};
-#pragma unroll
-    for (int s = 0; s < HQ_EPI_PRELOAD; ++s) r.v[s] = ld_stream(src[s] + i);
-    return r;
+    return Pre{ld_stream(wa + i), ld_stream(Qwa + i), ld_stream(xa + i)};
   }
-  __device__ __forceinline__ void operator()(int i, double q2, double* acc) const { (*this)(i, q2, acc, preload(i)); }
   __device__ __forceinline__ void operator()(int i, double q2, double* acc, const Pre& pf) const {
-    // operand s: the preloaded value when s < HQ_EPI_PRELOAD, else loaded here
-    auto opnd = [&](auto s, const double* a) {
-      constexpr int k = decltype(s)::value;
-      if constexpr (k < HQ_EPI_PRELOAD) return pf.v[k];
-      else return ld_stream(a + i);
-    };
-    using I0 = std::integral_constant<int, 0>; using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>; using I3 = std::integral_constant<int, 3>;
-    using I4 = std::integral_constant<int, 4>; using I5 = std::integral_constant<int, 5>;
-    const double wai = opnd(I0{}, wa), Qwai = opnd(I1{}, Qwa), xai = opnd(I2{}, xa);
-    const double ci = opnd(I3{}, c), q1i = opnd(I4{}, q1), atyi = opnd(I5{}, ATy);
-#else
+    apply(i, q2, acc, [&](double& a, double& b, double& c3) { a = pf.wa; b = pf.Qwa; c3 = pf.xa; });
+  }
   __device__ __forceinline__ void operator()(int i, double q2, double* acc) const {
-    const double wai = ld_stream(wa + i), Qwai = ld_stream(Qwa + i), xai = ld_stream(xa + i);
-    const double ci = ld_stream(c + i), q1i = ld_stream(q1 + i), atyi = ld_stream(ATy + i);
-#endif
+    apply(i, q2, acc, [&](double& a, double& b, double& c3) {
+      a = ld_stream(wa + i); b = ld_stream(Qwa + i); c3 = ld_stream(xa + i);
+    });
+  }
+  // anchors(wa_i, Qwa_i, xa_i) supplies the Halpern anchors of entry i
+  template <class Anchors>
+  __device__ __forceinline__ void apply(int i, double q2, double* acc, Anchors anchors) const {
     const double xhi = ld_stream(xh + i), wi = ld_stream(w + i), Qwi = ld_stream(Qw + i), di = d[i];
     const double inv = 1.0 / (1.0 + sQ);
     const double wb = (sQ * wi + xhi) * inv + kappa * di;
-    const double Qwb = (sQ * Qwi + q1i) * inv + kappa * q2;
+    const double Qwb = (sQ * Qwi + ld_stream(q1 + i)) * inv + kappa * q2;
+    double wai, Qwai, xai;
+    anchors(wai, Qwai, xai);
     if (want_r || check || trace) {
       const double xb = XB[i];
       if (want_r) {
@@ -162,7 +148,7 @@ struct EpiQ2 {
     const double Qwn = rho * Qwai + (1.0 - rho) * (2.0 * Qwb - Qwi);
     st_stream(w + i, wn); st_stream(Qw + i, Qwn);
     if (trace) x[i] = xn;
-    const double rz = xn + sigma * (-Qwn + atyi - ci);
+    const double rz = xn + sigma * (-Qwn + ld_stream(ATy + i) - ld_stream(c + i));
     const double xbn = prox_phi(rz, sigma * l1, ld_stream(L + i), ld_stream(U + i));
     xh[i] = 2.0 * xbn - xn;                                  // gathered next by Q-apply #1
     if (xb_next) { XB[i] = xbn; ZB[i] = (xbn - rz) / sigma; }

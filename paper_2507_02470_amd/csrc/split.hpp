@@ -86,36 +86,77 @@ __global__ void k_split_scatter(int rows, int pw, const int* __restrict__ rp, co
 // to tens of nonzeros), so each pass's entries -- one contiguous range of the
 // layout -- are streamed as by the CSR-stream kernel: coalesced loads,
 // products staged in LDS, then every thread adds up its rows' products in
-// order.  BS = 256 for the narrow panels (several workgroups per CU), 1024 for
-// the wide ones (one workgroup per CU, its 128 KB copy of x in LDS).
+// order.  The loads run one step ahead: a chunk's entries are fetched while the
+// previous chunk is summed (the first chunk of the next pass during the last of
+// this one), and the next pass's row starts during this pass.  BS = 256 for
+// the narrow panels (several workgroups per CU), 1024 for the wide ones (one
+// workgroup per CU, its 128 KB copy of x in LDS).
 template <int BS>
 __global__ __launch_bounds__(BS) void k_split_partial(SplitMat S, const double* __restrict__ x) {
   static_assert(HQ_SPLIT_ROWS % BS == 0, "rows per pass");
   constexpr int RPT = HQ_SPLIT_ROWS / BS;   // rows per thread and pass
   constexpr int CH = 2048;                  // products staged per step
+  constexpr int E = CH / BS;                // entries per thread and step
   extern __shared__ double xs[];            // S.pw entries
   __shared__ double prod[CH];
   __shared__ int srp[HQ_SPLIT_ROWS + 1];
   const int t = threadIdx.x;
   const int p = blockIdx.x % S.np, rb = blockIdx.x / S.np;
+  const int rbeg = rb * S.rpb, rend = min(S.rows, rbeg + S.rpb);
+  if (rbeg >= rend) return;                 // (the whole workgroup)
   const int cx = p * S.pw, nc = min(S.pw, S.cols - cx);
-  for (int i = t; i < nc; i += BS) xs[i] = x[cx + i];
   const int* __restrict__ offp = S.off + (size_t)p * S.rows;
   double* __restrict__ part = S.partial + (size_t)p * S.rows;
-  const int rend = min(S.rows, (rb + 1) * S.rpb);
-  for (int r0 = rb * S.rpb; r0 < rend; r0 += HQ_SPLIT_ROWS) {
-    const int nr = min(HQ_SPLIT_ROWS, rend - r0);
-    // (row r0 + nr - 1 ends at the next row's start, or at the next panel's first)
-    for (int i = t; i <= nr; i += BS) srp[i] = offp[r0 + i];
-    __syncthreads();   // also orders the copy of x before the first pass
-    const int kb = srp[0], ke = srp[nr];
+  // row starts of the pass from row r (rows r .. r + n - 1, and the end)
+  int sr[RPT], sr_end;
+  auto load_starts = [&](int r, int n) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) sr[q] = t + q * BS < n ? offp[r + t + q * BS] : 0;
+    sr_end = offp[r + n];   // (the next row's start, or the next panel's first)
+  };
+  auto store_starts = [&](int n) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (t + q * BS < n) srp[t + q * BS] = sr[q];
+    if (t == 0) srp[n] = sr_end;
+  };
+  // the entries [a, b) of one step, E per thread
+  int ci[E];
+  double v[E];
+  auto fetch = [&](int a, int b) {
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int k = a + t + u * BS;
+      ci[u] = k < b ? (int)ld_stream(S.lci + k) : 0;
+      v[u] = k < b ? ld_stream(S.v + k) : 0.0;
+    }
+  };
+  int r0 = rbeg, nr = min(HQ_SPLIT_ROWS, rend - r0);
+  load_starts(r0, nr);
+  for (int i = t; i < nc; i += BS) xs[i] = x[cx + i];
+  store_starts(nr);
+  __syncthreads();
+  int kb = srp[0], ke = srp[nr];
+  fetch(kb, min(ke, kb + CH));
+  for (;;) {   // passes; the same trip counts in every thread
+    const int r1 = r0 + HQ_SPLIT_ROWS;
+    const bool more = r1 < rend;
+    const int nr1 = more ? min(HQ_SPLIT_ROWS, rend - r1) : 0;
+    if (more) load_starts(r1, nr1);
     double sum[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) sum[q] = 0.0;
-    for (int c0 = kb; c0 < ke; c0 += CH) {   // same trip count in every thread
+    for (int c0 = kb; c0 < ke; c0 += CH) {
       const int c1 = min(ke, c0 + CH);
-#pragma unroll 8
-      for (int k = c0 + t; k < c1; k += BS) prod[k - c0] = ld_stream(S.v + k) * xs[ld_stream(S.lci + k)];
+      int cc[E];
+      double cv[E];
+#pragma unroll
+      for (int u = 0; u < E; ++u) { cc[u] = ci[u]; cv[u] = v[u]; }
+      if (c1 < ke) fetch(c1, min(ke, c1 + CH));
+      else if (more) fetch(ke, min(sr_end, ke + CH));   // the next pass's first step
+#pragma unroll
+      for (int u = 0; u < E; ++u)
+        if (c0 + t + u * BS < c1) prod[t + u * BS] = cv[u] * xs[cc[u]];
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
@@ -127,12 +168,17 @@ __global__ __launch_bounds__(BS) void k_split_partial(SplitMat S, const double* 
       }
       __syncthreads();   // prod is rewritten by the next step
     }
+    if (kb == ke && more) fetch(ke, min(sr_end, ke + CH));   // a pass without entries fetched nothing
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int i = t + q * BS;
       if (i < nr) part[r0 + i] = sum[q];
     }
-    __syncthreads();   // srp is rewritten by the next pass
+    if (!more) break;
+    __syncthreads();     // every thread has read this pass's row starts
+    store_starts(nr1);
+    __syncthreads();
+    r0 = r1; nr = nr1; kb = ke; ke = srp[nr];
   }
 }
 

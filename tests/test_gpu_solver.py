@@ -151,6 +151,22 @@ def test_column_split_product():
     assert s.kernel_stats()["lanes_per_row"]["A"] == -4
     assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13
     s.close()
+    # three passes of 1,024 rows per workgroup, the middle one without entries in
+    # every panel but the first (its rows' columns all lie in the first 16,384)
+    m = 3000
+    lens = rng.integers(100, 200, size=m)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    cols = rng.integers(0, n, size=int(rp[-1])).astype(np.int32)
+    mid = slice(int(rp[1024]), int(rp[2048]))
+    cols[mid] = rng.integers(0, 16_384, size=mid.stop - mid.start)
+    vals = rng.standard_normal(cols.size)
+    qp = qpgen.QP(n=n, m=m, qkind="zero", c=np.zeros(n), L=-np.ones(n), U=np.ones(n),
+                  a_rowptr=rp, a_col=cols, a_val=vals, l=-np.ones(m), u=np.ones(m))
+    A = sp.csr_matrix((vals, cols, rp), shape=(m, n))
+    s = Solver(DP(qp), lambda_A=1.0, small_path=0)
+    assert s.kernel_stats()["lanes_per_row"]["A"] == -4
+    assert _max_rel(s.apply("A", x).cpu().numpy(), A @ x) < 1e-13
+    s.close()
 
     # Lasso, narrow panels (6000 nonzeros per row of Ahat) and wide ones (150)
     for qp in (qpgen.make_lasso(seed=9, p=40, q=20_000, density=0.3),

@@ -135,6 +135,12 @@ typedef struct {
                                  panel-ordered product (columns cut into 4 panels walked in
                                  the same order by a persistent grid; an extra copy of the
                                  matrix; rows of at most 4096 nonzeros, else the default);
+                                 -4: the column-split product (a copy of the matrix in
+                                 column panels, each workgroup gathering from its panel's
+                                 slice of the vector in LDS, per-panel partial sums added
+                                 in panel order; matrices with more than 14336 columns and
+                                 on average at least 8 nonzeros per row in a 2048-column
+                                 panel or 2 in a 16384-column one, else the default);
                                  1, 2, 4, ..., 256: that many lanes per row, for every
                                  matrix; -100 - g (g = 1, 2, 4, ..., 64): g lanes per row
                                  gathering from an LDS copy of the input vector (at most

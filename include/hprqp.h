@@ -316,8 +316,8 @@ hprqp_status hprqp_scaling(hprqp_handle *h, double *D, double *E);
  * 1 = A x, 2 = A^T(2 ybar - y), 3 unused).  Also reports the
  * kernel choice of A, A^T and Q (g_host[3], may be NULL): g > 0 lanes per row,
  * 0 the CSR-stream kernel, -1 its variant gathering from LDS, -3 the
- * panel-ordered product, -100 - g the row-split kernel with g lanes gathering
- * from LDS. */
+ * panel-ordered product, -4 the column-split product, -100 - g the row-split
+ * kernel with g lanes gathering from LDS. */
 hprqp_status hprqp_kernel_stats(hprqp_handle *h, double *avg_ms_host, int64_t *launches_host, int32_t *g_host);
 
 void hprqp_destroy(hprqp_handle *h);

@@ -1023,12 +1023,25 @@ void autotune_csr(hprqp_handle& h, Mat& M, const double* x, double* out) {
       continue;
     M.G = G;
     launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
+    // one timed launch first: a candidate already twice as slow as the best
+    // so far is not timed further (its single launch, times 5, stands in;
+    // large matrices spend most of create here otherwise)
+    float ms = 0, ms1 = 0;
     HQC(hipEventRecord(e0, h.st));
-    for (int r = 0; r < 5; ++r) launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
+    launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
     HQC(hipEventRecord(e1, h.st));
     HQC(hipEventSynchronize(e1));
-    float ms = 0;
-    HQC(hipEventElapsedTime(&ms, e0, e1));
+    HQC(hipEventElapsedTime(&ms1, e0, e1));
+    if (G != G0 && 5.0f * ms1 > 2.0f * best) {
+      ms = 5.0f * ms1;
+    } else {
+      HQC(hipEventRecord(e0, h.st));
+      for (int r = 0; r < 4; ++r) launch_csr(h, M, x, EpiStore{out}, 0, no_red(h));
+      HQC(hipEventRecord(e1, h.st));
+      HQC(hipEventSynchronize(e1));
+      HQC(hipEventElapsedTime(&ms, e0, e1));
+      ms += ms1;
+    }
     if (G == G0) t_default = ms;
     if (ms < best) { best = ms; bestG = G; }
     if (G != HQ_G_PANEL && G != HQ_G_SPLIT && ms < best_np) { best_np = ms; bestG_np = G; }
